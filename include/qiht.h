@@ -1,0 +1,244 @@
+/*
+ * qiht.h -- C ABI of the MI355X (gfx950) hot path of low-precision
+ * normalized Iterative Hard Thresholding (QIHT).
+ *
+ * Method: N. M. Guerel, K. Kara, A. Stojanov, T. Smith, T. Lemmin,
+ * D. Alistarh, M. Pueschel, C. Zhang, "Compressive Sensing Using Iterative
+ * Hard Thresholding with Low Precision Data Representation: Theory and
+ * Applications", IEEE Trans. Signal Process. 68 (2020), arXiv:1802.04907.
+ *
+ * Problem (Sec. I-A, Eq. CS_model and Eq. cost_function): given y = Phi x + e
+ * with Phi an M x N real or complex matrix, find x minimizing
+ * |y - Phi x|^2 subject to |x|_0 <= s.  QIHT (Sec. III-A, Algorithm 2)
+ * runs normalized IHT (Algorithm 1) on stochastically quantized copies of
+ * Phi and y: x+ = H_s(x + mu Q1^T (y_hat - Q2 x)) with two independent
+ * quantizations Q1, Q2 of Phi ("double sampling").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Array arguments are DEVICE pointers (memory of the current HIP device)
+ *    unless marked "host".  The caller owns every buffer it passes; a
+ *    qiht_qmatrix owns the device codes it holds until qiht_qmatrix_free.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is ordered on that stream.  Entry points that return results in
+ *    host memory (qiht_info, scales) synchronize that stream before
+ *    returning.
+ *  - Every entry point validates its arguments on the host before touching
+ *    the device.  On any error it returns a non-zero qiht_status, leaves
+ *    the caller's outputs untouched, and stores a message retrievable with
+ *    qiht_last_error() (thread-local).  No C++ exception crosses the ABI.
+ *  - Not thread-safe on one qiht_qmatrix; distinct handles may be used
+ *    from distinct threads.
+ */
+#ifndef QIHT_H_
+#define QIHT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QIHT_OK = 0,
+    QIHT_ERR_INVALID_ARG = 1,   /* bad size, null pointer, s out of range */
+    QIHT_ERR_UNSUPPORTED = 2,   /* bit width or dtype not implemented      */
+    QIHT_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                */
+    QIHT_ERR_DEVICE = 4,        /* no usable device, or a HIP call failed  */
+    QIHT_ERR_NUMERIC = 5        /* NaN or Inf in the input data           */
+} qiht_status;
+
+typedef enum {
+    QIHT_F64 = 0,   /* double                                   */
+    QIHT_F32 = 1,   /* float                                    */
+    QIHT_C64 = 2,   /* complex float, interleaved (re, im)      */
+    QIHT_C128 = 3   /* complex double, interleaved (re, im)     */
+} qiht_dtype;
+
+/* Why a solve stopped (qiht_info.reason). */
+enum {
+    QIHT_REASON_CONVERGED = 1,  /* |x^n - x^(n-1)| <= tol |x^n|            */
+    QIHT_REASON_MAX_ITERS = 2,  /* iteration cap reached                    */
+    QIHT_REASON_STATIONARY = 3  /* gradient vanished on the support         */
+};
+
+/* Opaque quantized measurement matrix: packed codes of one or two
+ * realizations plus the max-abs scale. */
+typedef struct qiht_qmatrix qiht_qmatrix;
+
+/*
+ * Solver parameters.  Algorithm 2 inputs: iteration count n* (max_iters),
+ * the step-size tuning parameters k and c (Sec. II-A: on a support change
+ * the step must satisfy mu <= (1 - c)|dx|^2/|Phi dx|^2, otherwise
+ * mu <- mu / (k (1 - c)), with k > 1/(1 - c)).
+ */
+typedef struct {
+    int32_t max_iters;       /* n*; >= 1                                    */
+    double tol;              /* stop when |x^n - x^(n-1)| <= tol |x^n|;
+                                0 disables (the paper gives only n*)        */
+    double k;                /* shrink parameter, k > 1/(1-c); default 2    */
+    double c;                /* step test margin, 0 <= c < 1; default 0.01  */
+    int32_t max_backtracks;  /* shrinks per iteration (>= 0); default 32    */
+    int32_t mu_mode;         /* 0: mu = |g_G|^2/((Q1_G g_G).(Q2_G g_G))
+                                   (Algorithm 2); 1: |g_G|^2/|Q1_G g_G|^2   */
+    const float* x0;         /* optional warm start x (device, n floats);
+                                NULL = x0 = 0 and G0 = supp H_s(Q1^T y_hat) */
+    const int32_t* support0; /* warm-start support (device, s ascending
+                                indices); required iff x0 != NULL           */
+} qiht_params;
+
+typedef struct {
+    int32_t iterations;        /* completed iterations                       */
+    int32_t reason;            /* QIHT_REASON_*                              */
+    int32_t backtracks;        /* total step shrinks                         */
+    int32_t capped_iterations; /* iterations that hit max_backtracks         */
+    double mu_last;            /* accepted step of the last iteration        */
+    double status_flags;       /* reserved, 0                                */
+} qiht_info;
+
+/* Fill `p` (host) with the defaults: max_iters 300, tol 1e-8, k 2, c 0.01,
+ * max_backtracks 32, mu_mode 0, no warm start. */
+void qiht_default_params(qiht_params* p);
+
+/*
+ * Quantize the measurement matrix: Q(Phi, b) of Sec. III-A.
+ *
+ *   Phi is M x N, row-major with leading dimension ld >= N (elements), on
+ *   the device, of dtype F32, F64, C64 or C128.  Complex input is treated
+ *   as the real matrix [Re Phi; Im Phi] of 2M rows (real unknown x).
+ *   The scale c = max |Phi_ij| over the (stacked) matrix; values are mapped
+ *   to [-1, 1] by 1/c and rounded at random to one of the two neighbouring
+ *   levels q_k = -1 + 2k/(2^b - 1), up with probability equal to the
+ *   fractional position (unbiased: E[Q(v)] = v).
+ *
+ *   bits: 1, 2, 4 or 8 (packed codes), or 32 (plain FP32 copy, no
+ *   randomness; realizations is then forced to 1 and Q1 = Q2).
+ *   realizations: 1 (Q1 = Q2, single sampling) or 2 (independent Q1 for
+ *   Phi^T and Q2 for Phi: double sampling, Sec. III-A).
+ *   seed: 64-bit Philox4x32-10 key.  Element e (column-major index over
+ *   the stacked rows) of realization r draws word e & 3 of the block with
+ *   counter (e >> 2, stream 0, r); code = i + [u < f 2^32] with
+ *   p = (v + c)(2^b - 1)/(2c) in FP64, i = floor(p) clamped to
+ *   [0, 2^b - 2], f = p - i.
+ *
+ *   *out receives a new handle (free with qiht_qmatrix_free).  Errors:
+ *   INVALID_ARG (null, m/n < 1, ld < n), UNSUPPORTED (bits/dtype),
+ *   NUMERIC (NaN/Inf in Phi), OUT_OF_MEMORY, DEVICE.  Synchronizes stream.
+ */
+qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n,
+                                 int64_t ld, qiht_dtype dtype, int bits,
+                                 int realizations, uint64_t seed,
+                                 void* stream, qiht_qmatrix** out);
+
+/*
+ * Quantize the observation vector: Q(y, b) of Sec. III-A, one realization
+ * on Philox stream 1 (counter (e >> 2, 1, 0)), same rounding rule as the
+ * matrix.  y has m entries of dtype F32/F64 (real) or C64/C128 (complex,
+ * stacked [Re y; Im y], 2m rows) on the device.
+ *
+ *   yhat_out (device, rows doubles): the dequantized FP64 values
+ *            c (2k/(2^b - 1) - 1); for bits = 32 the FP32-rounded y.
+ *   codes_out (device, rows bytes, optional, bits <= 8): the codes.
+ *   scale_out (host, optional): the scale c (0 for bits = 32).
+ *   bits: 1..8 or 32.  Synchronizes stream.
+ */
+qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype,
+                                 int bits, uint64_t seed, void* stream,
+                                 double* yhat_out, uint8_t* codes_out,
+                                 double* scale_out);
+
+/*
+ * Shape of a quantized matrix (host outputs, each optional): stacked row
+ * count, column count, bit width, realizations, scale c, and the byte
+ * stride between packed columns in device memory.
+ */
+qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows,
+                              int64_t* n, int* bits, int* realizations,
+                              double* scale, int64_t* col_bytes);
+
+/*
+ * Copy one realization's codes to host memory, unpacked: rows x n bytes,
+ * column-major (byte j*rows + i is the code of element (i, j)).  For
+ * bits = 32 the buffer receives rows x n floats instead.  For inspection
+ * and tests; the device layout is private.
+ */
+qiht_status qiht_qmatrix_export_codes(const qiht_qmatrix* q, int realization,
+                                      void* host_out);
+
+/* Release a handle (NULL is a no-op). */
+void qiht_qmatrix_free(qiht_qmatrix* q);
+
+/*
+ * Solve one instance with QIHT (Algorithm 2 on the fixed realizations held
+ * by q; Algorithm 1 when q has bits = 32).  Per iteration, on the GPU:
+ *   r = y_hat - Q2_G x_G           (FP64 gather over the s support columns)
+ *   g = Q1^T r                     (full pass over the packed codes, FP32)
+ *   mu = |g_G|^2/((Q1_G g_G).(Q2_G g_G))          (Eq. step_size, FP64)
+ *   x' = H_s(x + mu g)             (top-s, ties to the lower index)
+ *   if supp x' != G: backtrack while mu > (1-c)|dx|^2/|Q1 dx|^2 (FP64)
+ *   stop on tol or max_iters.
+ *
+ *   yhat: device, rows doubles (from qiht_quantize_vector).
+ *   s: 1 <= s <= min(rows, n) (Theorem on QIHT requires s <= M).
+ *   x_out: device, n floats, the final x (zero off the support).
+ *   support_out: device, s int32, the final support in ascending order.
+ *   info: host, optional.  Synchronizes stream.
+ */
+qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat,
+                            int64_t s, const qiht_params* p, float* x_out,
+                            int32_t* support_out, qiht_info* info,
+                            void* stream);
+
+/* One problem of a batch. */
+typedef struct {
+    const qiht_qmatrix* q;
+    const double* yhat;      /* device, rows doubles           */
+    int64_t s;
+    float* x_out;            /* device, n floats               */
+    int32_t* support_out;    /* device, s int32                */
+} qiht_problem;
+
+/*
+ * Solve `count` independent problems of possibly different sizes in one
+ * sequence of batched launches (each phase of an iteration is one launch
+ * covering every unfinished problem).  Problems must share the bit width.
+ * infos: host array of `count` (optional).  Same semantics per problem as
+ * qiht_niht_solve; the warm start in p is not supported here (must be
+ * NULL).  Synchronizes stream.
+ */
+qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
+                                    const qiht_params* p, qiht_info* infos,
+                                    void* stream);
+
+/*
+ * One evaluation of the gradient pair at a given sparse x:
+ *   r = y_hat - Q2_G x_G (FP64 accumulation, rounded to FP32 for the pass)
+ *   g = Q1^T r (FP32)
+ * x: device, n floats, zero outside `support` (device, s int32 ascending).
+ * g_out: device, n floats.  r_out: device, rows floats (optional).
+ * This is the dense pair of Algorithm 2's first line, exposed for parity
+ * tests and profiling.
+ */
+qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat,
+                          const float* x, const int32_t* support, int64_t s,
+                          float* g_out, float* r_out, void* stream);
+
+/*
+ * H_s selection alone (Sec. I-A): the indices of the s entries of a
+ * (device, n floats) largest in magnitude, ties to the lower index,
+ * written ascending to support_out (device, s int32).  0 <= s <= n.
+ */
+qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s,
+                                int32_t* support_out, void* stream);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* qiht_last_error(void);
+
+/* Library version string. */
+const char* qiht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QIHT_H_ */

@@ -25,7 +25,8 @@ Readings where the paper is silent, ambiguous or garbled (listed in the design doc)
 * N2: iteration n evaluates g at x^[n-1] (Algorithm 2 prints x^[n] inside
   the gradient, which does not exist yet).
 * N3: if the step-size denominator is <= 0 or not finite, use
-  |Phi1_G g_G|^2; if |g_G| = 0 stop (reason STATIONARY).
+  |Phi1_G g_G|^2; if |g_G| = 0, or that fallback is 0 as well, stop
+  (reason STATIONARY).
 * N4: H_s ties go to the lower index; the new support is the selected index
   set (always s indices, even if some selected values are zero).
 * N5/N6: the "x^[n] = x^[n-1]" lines of the accept branches are read as
@@ -95,6 +96,8 @@ def step_size(g, support, phi1, phi2, mu_mode="cross"):
         den = float(u @ u)
     if not (np.isfinite(den) and den > 0.0):
         den = float(u @ u)
+    if not den > 0.0:
+        return None, num, den
     return num / den, num, den
 
 

@@ -58,11 +58,14 @@ def level_values(bits, odd=False):
     return 2.0 * k / (L - 1) - 1.0
 
 
-def quantize(v, bits, seed, stream, realization, odd=False, e_offset=0):
+def quantize(v, bits, seed, stream, realization, odd=False, e_offset=0,
+             scale=None):
     """Quantize a 1-D array of values given in element order.
 
     Returns (codes, c): integer codes in [0, l-1] and the max-abs scale c.
     The dequantized value of code k is c * (2k/(l-1) - 1).
+    ``e_offset`` is the element index of v[0]; ``scale`` supplies c when v
+    is only a slice of the quantized matrix (default: max |v|).
     """
     v = np.asarray(v, dtype=np.float64).reshape(-1)
     L = num_levels(bits, odd)
@@ -71,7 +74,7 @@ def quantize(v, bits, seed, stream, realization, odd=False, e_offset=0):
         return codes, 0.0
     if not np.all(np.isfinite(v)):
         raise ValueError("non-finite input to the quantizer")
-    c = float(np.max(np.abs(v)))
+    c = float(np.max(np.abs(v))) if scale is None else float(scale)
     if c == 0.0:
         return codes, 0.0
     K = (L - 1) / (2.0 * c)

@@ -1,0 +1,217 @@
+"""MI355X (gfx950) hot path of low-precision normalized IHT (QIHT).
+
+Guerel et al., "Compressive Sensing Using Iterative Hard Thresholding with
+Low Precision Data Representation: Theory and Applications", IEEE TSP 68
+(2020), arXiv:1802.04907.
+
+This module is a thin binding of the C ABI in ``include/qiht.h``
+(``libqiht.so``, built from ``csrc/``): it only marshals arguments.  Every
+step of the path runs in the HIP kernels; PyTorch supplies device memory
+and the current stream.  If the library is missing, calls raise -- there is
+no CPU fallback.
+
+Functions keep the C names without the ``qiht_`` prefix:
+``quantize_matrix``, ``quantize_vector``, ``niht_solve``,
+``niht_solve_batched``, ``gradient``, ``hard_threshold``, ``last_error``.
+"""
+
+import ctypes as C
+
+from . import _lib
+
+__all__ = ["QihtError", "QMatrix", "quantize_matrix", "quantize_vector",
+           "niht_solve", "niht_solve_batched", "gradient", "hard_threshold",
+           "last_error", "version", "library_path"]
+
+library_path = _lib.LIB_PATH
+
+
+class QihtError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        self.status_name = _lib.STATUS_NAMES.get(status, str(status))
+        super().__init__(f"qiht {self.status_name}: {message}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(status):
+    if status != _lib.QIHT_OK:
+        raise QihtError(status, last_error())
+
+
+def last_error():
+    return _lib.load().qiht_last_error().decode()
+
+
+def version():
+    return _lib.load().qiht_version().decode()
+
+
+def _stream(stream=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    table = {torch.float64: "f64", torch.float32: "f32",
+             torch.complex64: "c64", torch.complex128: "c128"}
+    if t.dtype not in table:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _lib.DTYPE[table[t.dtype]]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class QMatrix:
+    """Handle on quantized measurement-matrix codes held in device memory."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+        rows, n, cb = C.c_int64(), C.c_int64(), C.c_int64()
+        bits, real = C.c_int(), C.c_int()
+        scale = C.c_double()
+        _check(_lib.load().qiht_qmatrix_info(self._h, C.byref(rows), C.byref(n),
+                                             C.byref(bits), C.byref(real),
+                                             C.byref(scale), C.byref(cb)))
+        self.rows, self.n, self.bits = rows.value, n.value, bits.value
+        self.realizations, self.scale, self.col_bytes = real.value, scale.value, cb.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export_codes(self, realization=0):
+        """Codes of one realization as a (rows, n) numpy array (host)."""
+        import numpy as np
+        if self.bits == 32:
+            out = np.empty((self.n, self.rows), dtype=np.float32)
+        else:
+            out = np.empty((self.n, self.rows), dtype=np.uint8)
+        _check(_lib.load().qiht_qmatrix_export_codes(
+            self._h, int(realization), out.ctypes.data_as(C.c_void_p)))
+        return out.T
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.load().qiht_qmatrix_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def quantize_matrix(phi, bits, realizations=2, seed=0, stream=None):
+    """Q(Phi, b): ``phi`` is an (m, n) CUDA tensor, row-major (stride (ld, 1))."""
+    if phi.dim() != 2 or phi.stride(1) != 1 or not phi.is_cuda:
+        raise ValueError("phi must be a 2-D row-major CUDA tensor")
+    m, n = phi.shape
+    out = C.c_void_p()
+    _check(_lib.load().qiht_quantize_matrix(
+        _ptr(phi), m, n, phi.stride(0), _dtype_code(phi), int(bits),
+        int(realizations), C.c_uint64(int(seed) & (2**64 - 1)), _stream(stream),
+        C.byref(out)))
+    return QMatrix(out.value)
+
+
+def quantize_vector(y, bits, seed=0, stream=None, want_codes=False):
+    """Q(y, b) -> (y_hat FP64 CUDA tensor of the stacked rows, codes, scale)."""
+    torch = _torch()
+    if y.dim() != 1 or not y.is_contiguous() or not y.is_cuda:
+        raise ValueError("y must be a contiguous 1-D CUDA tensor")
+    rows = y.numel() * (2 if y.is_complex() else 1)
+    yhat = torch.empty(rows, dtype=torch.float64, device=y.device)
+    codes = torch.empty(rows, dtype=torch.uint8, device=y.device) if want_codes else None
+    scale = C.c_double()
+    _check(_lib.load().qiht_quantize_vector(
+        _ptr(y), y.numel(), _dtype_code(y), int(bits),
+        C.c_uint64(int(seed) & (2**64 - 1)), _stream(stream), _ptr(yhat),
+        _ptr(codes), C.byref(scale)))
+    return yhat, codes, scale.value
+
+
+def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=None):
+    p = _lib.QihtParams()
+    _lib.load().qiht_default_params(C.byref(p))
+    p.max_iters, p.tol, p.k, p.c = int(max_iters), float(tol), float(k), float(c)
+    p.max_backtracks, p.mu_mode = int(max_backtracks), int(mu_mode)
+    p.x0 = None if x0 is None else x0.data_ptr()
+    p.support0 = None if support0 is None else support0.data_ptr()
+    return p
+
+
+def _info_dict(inf):
+    return dict(iterations=inf.iterations, reason=_lib.REASONS.get(inf.reason, inf.reason),
+                backtracks=inf.backtracks, capped_iterations=inf.capped_iterations,
+                mu_last=inf.mu_last)
+
+
+def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
+               mu_mode=0, x0=None, support0=None, stream=None):
+    """QIHT solve -> (x FP32 CUDA tensor, support int32 CUDA tensor, info dict)."""
+    torch = _torch()
+    x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
+    sup = torch.empty(int(s), dtype=torch.int32, device=yhat.device)
+    if x0 is not None:
+        x0 = x0.to(dtype=torch.float32).contiguous()
+        support0 = support0.to(dtype=torch.int32).contiguous()
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0)
+    inf = _lib.QihtInfo()
+    _check(_lib.load().qiht_niht_solve(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
+                                       _ptr(sup), C.byref(inf), _stream(stream)))
+    return x, sup, _info_dict(inf)
+
+
+def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
+                       max_backtracks=32, mu_mode=0, stream=None):
+    """Batched solve; ``problems`` is a list of (QMatrix, yhat, s).
+
+    Returns a list of (x, support, info)."""
+    torch = _torch()
+    cnt = len(problems)
+    arr = (_lib.QihtProblem * cnt)()
+    outs = []
+    for i, (q, yhat, s) in enumerate(problems):
+        x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
+        sup = torch.empty(int(s), dtype=torch.int32, device=yhat.device)
+        outs.append((x, sup))
+        arr[i] = _lib.QihtProblem(q.handle.value, yhat.data_ptr(), int(s),
+                                  x.data_ptr(), sup.data_ptr())
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode)
+    infos = (_lib.QihtInfo * cnt)()
+    _check(_lib.load().qiht_niht_solve_batched(cnt, arr, C.byref(p), infos, _stream(stream)))
+    return [(x, sup, _info_dict(infos[i])) for i, (x, sup) in enumerate(outs)]
+
+
+def gradient(q, yhat, x, support, stream=None):
+    """(g, r): r = y_hat - Q2_G x_G and g = Q1^T r at a sparse x."""
+    torch = _torch()
+    g = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
+    r = torch.empty(q.rows, dtype=torch.float32, device=yhat.device)
+    s = 0 if support is None else support.numel()
+    xs = None if x is None else x.to(torch.float32).contiguous()
+    ss = None if support is None else support.to(torch.int32).contiguous()
+    _check(_lib.load().qiht_gradient(q.handle, _ptr(yhat), _ptr(xs), _ptr(ss), s, _ptr(g),
+                                     _ptr(r), _stream(stream)))
+    return g, r
+
+
+def hard_threshold(a, s, stream=None):
+    """H_s support (ascending int32 CUDA tensor) of a float32 CUDA vector."""
+    torch = _torch()
+    a = a.to(torch.float32).contiguous()
+    out = torch.empty(int(s), dtype=torch.int32, device=a.device)
+    _check(_lib.load().qiht_hard_threshold(_ptr(a), a.numel(), int(s), _ptr(out),
+                                           _stream(stream)))
+    return out

@@ -1,0 +1,361 @@
+// C ABI of libqiht: argument validation, handle management and dispatch to
+// the quantization and solver launchers.  Every entry point checks its
+// arguments on the host before touching the device and reports errors as
+// status codes plus a thread-local message; no exception crosses the ABI.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qiht_internal.h"
+
+namespace qiht {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+qiht_status fail(qiht_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+qiht_status hip_fail(hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(QIHT_ERR_OUT_OF_MEMORY, m);
+    return fail(QIHT_ERR_DEVICE, m);
+}
+
+namespace {
+
+bool bits_ok_matrix(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 32; }
+bool bits_ok_vector(int b) { return (b >= 1 && b <= 8) || b == 32; }
+bool dtype_ok(int d) { return d >= QIHT_F64 && d <= QIHT_C128; }
+bool is_complex(qiht_dtype d) { return d == QIHT_C64 || d == QIHT_C128; }
+
+qiht_status need_device(int* dev) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1) {
+        (void)hipGetLastError();
+        return fail(QIHT_ERR_DEVICE, "no HIP device available");
+    }
+    QIHT_HIP(hipGetDevice(dev));
+    return QIHT_OK;
+}
+
+qiht_status check_params(const qiht_params* p) {
+    if (!p) return fail(QIHT_ERR_INVALID_ARG, "params is NULL");
+    if (p->max_iters < 1) return fail(QIHT_ERR_INVALID_ARG, "max_iters must be >= 1");
+    if (!(p->c >= 0.0 && p->c < 1.0)) return fail(QIHT_ERR_INVALID_ARG, "need 0 <= c < 1");
+    if (!(p->k > 1.0 / (1.0 - p->c)))
+        return fail(QIHT_ERR_INVALID_ARG, "need k > 1/(1 - c)");
+    if (p->max_backtracks < 0) return fail(QIHT_ERR_INVALID_ARG, "max_backtracks must be >= 0");
+    if (p->mu_mode != 0 && p->mu_mode != 1) return fail(QIHT_ERR_INVALID_ARG, "mu_mode is 0 or 1");
+    if (std::isnan(p->tol)) return fail(QIHT_ERR_INVALID_ARG, "tol is NaN");
+    if ((p->x0 == nullptr) != (p->support0 == nullptr))
+        return fail(QIHT_ERR_INVALID_ARG, "x0 and support0 go together");
+    return QIHT_OK;
+}
+
+SolveArgs to_args(const qiht_params* p) {
+    SolveArgs a;
+    a.max_iters = p->max_iters;
+    a.tol = p->tol;
+    a.k = p->k;
+    a.c = p->c;
+    a.max_backtracks = p->max_backtracks;
+    a.mu_mode = p->mu_mode;
+    return a;
+}
+
+qiht_status check_problem(const qiht_qmatrix* q, const double* yhat, int64_t s, const void* x_out,
+                          const void* sup_out) {
+    if (!q) return fail(QIHT_ERR_INVALID_ARG, "quantized matrix is NULL");
+    if (!yhat) return fail(QIHT_ERR_INVALID_ARG, "yhat is NULL");
+    if (!x_out || !sup_out) return fail(QIHT_ERR_INVALID_ARG, "output pointer is NULL");
+    if (s < 1 || s > q->rows || s > q->n)
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= s <= min(rows, n)");
+    if (q->n > (1LL << 31) - 1 || q->rows > (1LL << 31) - 1)
+        return fail(QIHT_ERR_UNSUPPORTED, "dimension above 2^31 - 1");
+    return QIHT_OK;
+}
+
+// Copy a device support list to the host and check it is strictly
+// increasing inside [0, n).
+qiht_status check_support(const int32_t* dev_sup, int64_t s, int64_t n, hipStream_t st) {
+    if (s == 0) return QIHT_OK;
+    std::vector<int32_t> h(static_cast<size_t>(s));
+    QIHT_HIP(hipMemcpyAsync(h.data(), dev_sup, sizeof(int32_t) * s, hipMemcpyDeviceToHost, st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    for (int64_t t = 0; t < s; ++t) {
+        if (h[t] < 0 || h[t] >= n) return fail(QIHT_ERR_INVALID_ARG, "support index out of range");
+        if (t > 0 && h[t] <= h[t - 1])
+            return fail(QIHT_ERR_INVALID_ARG, "support must be strictly increasing");
+    }
+    return QIHT_OK;
+}
+
+}  // namespace
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+}  // namespace qiht
+
+using namespace qiht;
+
+extern "C" {
+
+void qiht_default_params(qiht_params* p) {
+    if (!p) return;
+    p->max_iters = 300;
+    p->tol = 1e-8;
+    p->k = 2.0;
+    p->c = 0.01;
+    p->max_backtracks = 32;
+    p->mu_mode = 0;
+    p->x0 = nullptr;
+    p->support0 = nullptr;
+}
+
+const char* qiht_last_error(void) { return last_error_cstr(); }
+
+const char* qiht_version(void) { return "qiht-gfx950 0.1"; }
+
+qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t ld,
+                                 qiht_dtype dtype, int bits, int realizations, uint64_t seed,
+                                 void* stream, qiht_qmatrix** out) try {
+    set_error("");
+    if (!phi || !out) return fail(QIHT_ERR_INVALID_ARG, "phi or out is NULL");
+    if (m < 1 || n < 1) return fail(QIHT_ERR_INVALID_ARG, "need m >= 1 and n >= 1");
+    if (ld < n) return fail(QIHT_ERR_INVALID_ARG, "need ld >= n");
+    if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
+    if (!bits_ok_matrix(bits)) return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8 or 32");
+    if (realizations != 1 && realizations != 2)
+        return fail(QIHT_ERR_INVALID_ARG, "realizations must be 1 or 2");
+    const int64_t rows = is_complex(dtype) ? 2 * m : m;
+    if (rows > (1LL << 31) - 1 || n > (1LL << 31) - 1)
+        return fail(QIHT_ERR_UNSUPPORTED, "dimension above 2^31 - 1");
+    const int64_t cb = column_bytes(rows, bits);
+    if (cb > (int64_t(1) << 40) / n) return fail(QIHT_ERR_INVALID_ARG, "matrix too large");
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double c = 0.0;
+    s0 = device_absmax(phi, dtype, m, n, ld, st, &c);
+    if (s0 != QIHT_OK) return s0;
+    const int R = (bits == 32) ? 1 : realizations;
+    qiht_qmatrix* q = new qiht_qmatrix();
+    q->device = dev;
+    q->m = m;
+    q->n = n;
+    q->rows = rows;
+    q->bits = bits;
+    q->realizations = R;
+    q->col_bytes = cb;
+    q->rows_pad = rows_in_bytes(cb, bits);
+    q->scale = (bits == 32) ? 0.0 : c;
+    if (bits != 32 && c > 0.0) {
+        const double L = static_cast<double>(1 << bits);
+        q->alpha = 2.0 * c / (L - 1.0);
+        q->beta = -c;
+    }
+    const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&q->codes[0]), bytes * R);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete q;
+        return fail(QIHT_ERR_OUT_OF_MEMORY, "code allocation failed");
+    }
+    q->codes[1] = (R == 2) ? q->codes[0] + bytes : q->codes[0];
+    const double K = (bits == 32 || c == 0.0) ? 0.0 : ((1 << bits) - 1) / (2.0 * c);
+    s0 = launch_quantize_matrix(phi, dtype, m, n, ld, bits, R, seed, c, K, q, st);
+    if (s0 == QIHT_OK) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s0 = hip_fail(e, "quantize");
+    }
+    if (s0 != QIHT_OK) {
+        (void)hipFree(q->codes[0]);
+        delete q;
+        return s0;
+    }
+    *out = q;
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype, int bits,
+                                 uint64_t seed, void* stream, double* yhat_out,
+                                 uint8_t* codes_out, double* scale_out) try {
+    set_error("");
+    if (!y || !yhat_out) return fail(QIHT_ERR_INVALID_ARG, "y or yhat_out is NULL");
+    if (m < 1) return fail(QIHT_ERR_INVALID_ARG, "need m >= 1");
+    if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
+    if (!bits_ok_vector(bits)) return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1..8 or 32");
+    if (bits == 32 && codes_out) return fail(QIHT_ERR_INVALID_ARG, "no codes for bits = 32");
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double c = 0.0;
+    s0 = device_absmax(y, dtype, 1, m, m, st, &c);
+    if (s0 != QIHT_OK) return s0;
+    double* lev = nullptr;
+    double K = 0.0;
+    if (bits != 32) {
+        const int L = 1 << bits;
+        std::vector<double> h(L);
+        for (int k = 0; k < L; ++k) h[k] = c * (2.0 * k / static_cast<double>(L - 1) - 1.0);
+        K = c > 0.0 ? (L - 1) / (2.0 * c) : 0.0;
+        QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&lev), sizeof(double) * L, st));
+        QIHT_HIP(hipMemcpyAsync(lev, h.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
+    }
+    s0 = launch_quantize_vector(y, dtype, m, bits, seed, c, K, lev, yhat_out, codes_out, st);
+    if (lev) (void)hipFreeAsync(lev, st);
+    hipError_t e = hipStreamSynchronize(st);
+    if (s0 != QIHT_OK) return s0;
+    if (e != hipSuccess) return hip_fail(e, "quantize_vector");
+    if (scale_out) *scale_out = (bits == 32) ? 0.0 : c;
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows, int64_t* n, int* bits,
+                              int* realizations, double* scale, int64_t* col_bytes) {
+    if (!q) return fail(QIHT_ERR_INVALID_ARG, "handle is NULL");
+    if (rows) *rows = q->rows;
+    if (n) *n = q->n;
+    if (bits) *bits = q->bits;
+    if (realizations) *realizations = q->realizations;
+    if (scale) *scale = q->scale;
+    if (col_bytes) *col_bytes = q->col_bytes;
+    return QIHT_OK;
+}
+
+qiht_status qiht_qmatrix_export_codes(const qiht_qmatrix* q, int realization,
+                                      void* host_out) try {
+    set_error("");
+    if (!q || !host_out) return fail(QIHT_ERR_INVALID_ARG, "handle or output is NULL");
+    if (realization < 0 || realization > 1) return fail(QIHT_ERR_INVALID_ARG, "realization is 0 or 1");
+    const size_t bytes = static_cast<size_t>(q->col_bytes) * static_cast<size_t>(q->n);
+    std::vector<uint8_t> packed(bytes);
+    QIHT_HIP(hipMemcpy(packed.data(), q->codes[realization], bytes, hipMemcpyDeviceToHost));
+    const int64_t rows = q->rows;
+    if (q->bits == 32) {
+        float* o = static_cast<float*>(host_out);
+        for (int64_t j = 0; j < q->n; ++j)
+            std::memcpy(o + j * rows, packed.data() + j * q->col_bytes, sizeof(float) * rows);
+        return QIHT_OK;
+    }
+    uint8_t* o = static_cast<uint8_t*>(host_out);
+    const int b = q->bits;
+    const uint32_t mask = (1u << b) - 1u;
+    for (int64_t j = 0; j < q->n; ++j) {
+        const uint8_t* col = packed.data() + j * q->col_bytes;
+        for (int64_t i = 0; i < rows; ++i) {
+            const int64_t bit = i * b;
+            o[j * rows + i] = static_cast<uint8_t>((col[bit >> 3] >> (bit & 7)) & mask);
+        }
+    }
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+void qiht_qmatrix_free(qiht_qmatrix* q) {
+    if (!q) return;
+    if (q->codes[0]) (void)hipFree(q->codes[0]);
+    delete q;
+}
+
+qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat, int64_t s,
+                            const qiht_params* p, float* x_out, int32_t* support_out,
+                            qiht_info* info, void* stream) try {
+    set_error("");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    s0 = check_problem(q, yhat, s, x_out, support_out);
+    if (s0 != QIHT_OK) return s0;
+    int dev = 0;
+    s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    if (p->support0) {
+        s0 = check_support(p->support0, s, q->n, static_cast<hipStream_t>(stream));
+        if (s0 != QIHT_OK) return s0;
+    }
+    ProblemIn in{q, yhat, s, x_out, support_out, p->x0, p->support0};
+    qiht_info tmp;
+    s0 = run_solve(&in, 1, to_args(p), &tmp, static_cast<hipStream_t>(stream));
+    if (s0 != QIHT_OK) return s0;
+    if (info) *info = tmp;
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
+                                    const qiht_params* p, qiht_info* infos,
+                                    void* stream) try {
+    set_error("");
+    if (count < 1 || !probs) return fail(QIHT_ERR_INVALID_ARG, "empty batch");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    if (p->x0) return fail(QIHT_ERR_INVALID_ARG, "warm start is not supported in a batch");
+    std::vector<ProblemIn> in(count);
+    for (int i = 0; i < count; ++i) {
+        s0 = check_problem(probs[i].q, probs[i].yhat, probs[i].s, probs[i].x_out,
+                           probs[i].support_out);
+        if (s0 != QIHT_OK) return fail(s0, "problem " + std::to_string(i) + ": " + last_error_cstr());
+        if (probs[i].q->bits != probs[0].q->bits)
+            return fail(QIHT_ERR_UNSUPPORTED, "problems of a batch must share the bit width");
+        in[i] = ProblemIn{probs[i].q, probs[i].yhat, probs[i].s, probs[i].x_out,
+                          probs[i].support_out, nullptr, nullptr};
+    }
+    int dev = 0;
+    s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    std::vector<qiht_info> tmp(count);
+    s0 = run_solve(in.data(), count, to_args(p), tmp.data(), static_cast<hipStream_t>(stream));
+    if (s0 != QIHT_OK) return s0;
+    if (infos) std::memcpy(infos, tmp.data(), sizeof(qiht_info) * count);
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat, const float* x,
+                          const int32_t* support, int64_t s, float* g_out, float* r_out,
+                          void* stream) try {
+    set_error("");
+    if (!q || !yhat || !g_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    if (s < 0 || s > q->n) return fail(QIHT_ERR_INVALID_ARG, "need 0 <= s <= n");
+    if (s > 0 && (!x || !support)) return fail(QIHT_ERR_INVALID_ARG, "x and support needed for s > 0");
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    s0 = check_support(support, s, q->n, static_cast<hipStream_t>(stream));
+    if (s0 != QIHT_OK) return s0;
+    return run_gradient(q, yhat, x, support, s, g_out, r_out, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* support_out,
+                                void* stream) try {
+    set_error("");
+    if (!a || !support_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1 || s < 0 || s > n) return fail(QIHT_ERR_INVALID_ARG, "need n >= 1, 0 <= s <= n");
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    return run_hard_threshold(a, n, s, support_out, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+}  // extern "C"

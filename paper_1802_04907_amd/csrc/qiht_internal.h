@@ -1,0 +1,108 @@
+// Internal declarations shared by the translation units of libqiht.
+// Not part of the public ABI (see include/qiht.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/qiht.h"
+
+// ---------------------------------------------------------------------------
+// Quantized matrix handle.
+//
+// Device layout: column-major, one column after another, each column padded
+// to `col_bytes` (a multiple of 256 bytes).  Within a column, code of row i
+// sits in byte (i * bits) / 8 at bit offset (i * bits) % 8 (little-endian
+// within the byte).  Padding rows hold code 0 and are never read as data:
+// every kernel masks rows >= rows.  bits == 32 stores plain floats.
+// ---------------------------------------------------------------------------
+struct qiht_qmatrix {
+    int device = 0;
+    int64_t m = 0;         // rows of the caller's Phi
+    int64_t n = 0;         // columns
+    int64_t rows = 0;      // m, or 2m for complex input ([Re; Im])
+    int bits = 0;          // 1, 2, 4, 8 or 32
+    int realizations = 0;  // 1 or 2
+    double scale = 0.0;    // c = max |Phi_ij| (0 for bits 32)
+    double alpha = 0.0;    // dequantized value = alpha * code + beta
+    double beta = 0.0;
+    int64_t col_bytes = 0; // stride between columns
+    int64_t rows_pad = 0;  // rows covered by col_bytes
+    uint8_t* codes[2] = {nullptr, nullptr};  // codes[1] == codes[0] if R == 1
+};
+
+namespace qiht {
+
+// Error reporting (thread-local message behind qiht_last_error).
+void set_error(const std::string& msg);
+qiht_status fail(qiht_status st, const std::string& msg);
+qiht_status hip_fail(hipError_t e, const char* what);
+
+#define QIHT_HIP(call)                                                    \
+    do {                                                                  \
+        hipError_t _e = (call);                                           \
+        if (_e != hipSuccess) return ::qiht::hip_fail(_e, #call);         \
+    } while (0)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Bytes per column for a given row count and bit width (multiple of 256).
+inline int64_t column_bytes(int64_t rows, int bits) {
+    int64_t raw = (bits == 32) ? rows * 4 : (rows * bits + 7) / 8;
+    if (raw < 1) raw = 1;
+    return round_up(raw, 256);
+}
+
+inline int64_t rows_in_bytes(int64_t col_bytes, int bits) {
+    return bits == 32 ? col_bytes / 4 : col_bytes * 8 / bits;
+}
+
+// ---- quantization (quantize.hip) ----
+// Max-abs of a row-major (complex: interleaved) matrix, and a NaN/Inf flag.
+qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
+                          int64_t n, int64_t ld, hipStream_t st,
+                          double* c_out);
+qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
+                                   int64_t n, int64_t ld, int bits, int R,
+                                   uint64_t seed, double c, double K,
+                                   qiht_qmatrix* q, hipStream_t st);
+qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
+                                   int bits, uint64_t seed, double c,
+                                   double K, const double* levels_dev,
+                                   double* yhat, uint8_t* codes,
+                                   hipStream_t st);
+
+// ---- solver (solve.hip) ----
+struct SolveArgs {
+    int32_t max_iters;
+    double tol;
+    double k;
+    double c;
+    int32_t max_backtracks;
+    int32_t mu_mode;
+};
+
+struct ProblemIn {
+    const qiht_qmatrix* q;
+    const double* yhat;
+    int64_t s;
+    float* x_out;
+    int32_t* support_out;
+    const float* x0;
+    const int32_t* support0;
+};
+
+qiht_status run_solve(const ProblemIn* probs, int count, const SolveArgs& a,
+                      qiht_info* infos, hipStream_t st);
+
+qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat,
+                         const float* x, const int32_t* support, int64_t s,
+                         float* g_out, float* r_out, hipStream_t st);
+
+qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s,
+                               int32_t* support_out, hipStream_t st);
+
+}  // namespace qiht

@@ -1,0 +1,279 @@
+// Stochastic quantization of the measurement matrix and the observation
+// vector (Sec. III-A): max-abs scaling, then unbiased randomized rounding to
+// one of 2^b equispaced levels in [-1, 1], driven by Philox4x32-10 so that
+// every element's coin is a pure function of (seed, stream, realization,
+// element index).
+//
+// This file is compiled with -ffp-contract=off: the FP64 position
+// p = (v + c) * K, its floor and its fractional part must be the exact
+// IEEE results of those three operations, so the codes are reproducible
+// bit for bit by any other IEEE implementation of the same rule.
+#include <algorithm>
+#include <cstring>
+
+#include "philox_dev.h"
+#include "qiht_internal.h"
+
+namespace qiht {
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+
+// One stochastic rounding decision.  L levels; c the scale; K = (L-1)/(2c)
+// (0 when c == 0, which sends every value to code 0).
+__device__ __forceinline__ uint32_t quantize_one(double v, double c, double K,
+                                                 int L, uint32_t u) {
+#pragma clang fp contract(off)
+    const double t = v + c;
+    const double p = t * K;
+    double fi = floor(p);
+    fi = fmin(fmax(fi, 0.0), static_cast<double>(L - 2));
+    const double f = p - fi;
+    const uint32_t up = (static_cast<double>(u) < f * kTwo32) ? 1u : 0u;
+    return static_cast<uint32_t>(fi) + up;
+}
+
+// Element (i, j) of the stacked real view of a row-major matrix.
+template <typename T, int NC>
+__device__ __forceinline__ double load_stacked(const T* src, int64_t m,
+                                               int64_t ld, int64_t i,
+                                               int64_t j) {
+    if constexpr (NC == 1) {
+        return static_cast<double>(src[i * ld + j]);
+    } else {
+        const int64_t ii = i < m ? i : i - m;
+        const int part = i < m ? 0 : 1;
+        return static_cast<double>(src[(ii * ld + j) * 2 + part]);
+    }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_absmax(const T* __restrict__ src,
+                                                int64_t m, int64_t n,
+                                                int64_t ld,
+                                                unsigned long long* out,
+                                                int* bad) {
+    double mx = 0.0;
+    int nonfinite = 0;
+    const int64_t row_len = n * NC;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+        const T* row = src + i * ld * NC;
+        for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x +
+                         threadIdx.x;
+             t < row_len; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+            const double v = static_cast<double>(row[t]);
+            if (!isfinite(v)) nonfinite = 1;
+            mx = fmax(mx, fabs(v));
+        }
+    }
+    __shared__ double sh[256];
+    __shared__ int shbad;
+    if (threadIdx.x == 0) shbad = 0;
+    __syncthreads();
+    if (nonfinite) shbad = 1;
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // Non-negative doubles order like their bit patterns.
+        atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(sh[0])));
+        if (shbad) atomicOr(bad, 1);
+    }
+}
+
+// One thread = one column j and one 16-byte chunk of that column (the codes
+// of RPC consecutive rows), for every realization.  Lanes of a wave take 64
+// consecutive columns, so the row-major source is read in coalesced rows.
+template <int BITS, typename T, int NC>
+__global__ __launch_bounds__(256) void k_quantize(
+    const T* __restrict__ src, int64_t m, int64_t n, int64_t ld, int64_t rows,
+    int64_t col_bytes, int64_t nchunks, double c, double K, uint32_t k0,
+    uint32_t k1, int R, uint8_t* __restrict__ out0,
+    uint8_t* __restrict__ out1) {
+    constexpr int RPC = (BITS == 32) ? 4 : 128 / BITS;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int64_t chunk = static_cast<int64_t>(blockIdx.y) * 4 + wave;
+    if (j >= n || chunk >= nchunks) return;
+    const int64_t i0 = chunk * RPC;
+    const size_t off = static_cast<size_t>(j) * col_bytes + chunk * 16;
+
+    if constexpr (BITS == 32) {
+        float vals[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + q;
+            vals[q] = i < rows ? static_cast<float>(load_stacked<T, NC>(src, m, ld, i, j))
+                               : 0.0f;
+        }
+        *reinterpret_cast<float4*>(out0 + off) =
+            make_float4(vals[0], vals[1], vals[2], vals[3]);
+    } else {
+        constexpr int L = 1 << BITS;
+        PhiloxStream s0{k0, k1, 0u, 0u};
+        PhiloxStream s1{k0, k1, 0u, 1u};
+        uint32_t w0[4] = {0u, 0u, 0u, 0u};
+        uint32_t w1[4] = {0u, 0u, 0u, 0u};
+        const uint64_t ebase = static_cast<uint64_t>(j) * rows;
+#pragma unroll 4
+        for (int q = 0; q < RPC; ++q) {
+            const int64_t i = i0 + q;
+            if (i >= rows) break;
+            const double v = load_stacked<T, NC>(src, m, ld, i, j);
+            const uint64_t e = ebase + i;
+            const int bit = q * BITS;
+            w0[bit >> 5] |= quantize_one(v, c, K, L, s0.word(e)) << (bit & 31);
+            if (R > 1)
+                w1[bit >> 5] |= quantize_one(v, c, K, L, s1.word(e)) << (bit & 31);
+        }
+        *reinterpret_cast<uint4*>(out0 + off) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
+        if (R > 1)
+            *reinterpret_cast<uint4*>(out1 + off) = make_uint4(w1[0], w1[1], w1[2], w1[3]);
+    }
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_quantize_vec(
+    const T* __restrict__ y, int64_t m, int64_t rows, int bits, double c,
+    double K, uint32_t k0, uint32_t k1, const double* __restrict__ levels,
+    double* __restrict__ yhat, uint8_t* __restrict__ codes) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const double v = load_stacked<T, NC>(y, m, 1, i, 0);
+    if (bits == 32) {
+        yhat[i] = static_cast<double>(static_cast<float>(v));
+        return;
+    }
+    PhiloxStream s{k0, k1, 1u, 0u};
+    const uint32_t code = quantize_one(v, c, K, 1 << bits, s.word(static_cast<uint64_t>(i)));
+    yhat[i] = levels[code];
+    if (codes) codes[i] = static_cast<uint8_t>(code);
+}
+
+template <typename T, int NC>
+qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
+                     hipStream_t st, double* c_out) {
+    unsigned long long* d_max = nullptr;
+    int* d_bad = nullptr;
+    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_max), 16, st));
+    d_bad = reinterpret_cast<int*>(d_max + 1);
+    QIHT_HIP(hipMemsetAsync(d_max, 0, 16, st));
+    const int64_t row_len = n * NC;
+    dim3 grid(static_cast<unsigned>(std::min<int64_t>((row_len + 255) / 256, 64)),
+              static_cast<unsigned>(std::min<int64_t>(m, 2048)));
+    hipLaunchKernelGGL((k_absmax<T, NC>), grid, dim3(256), 0, st,
+                       static_cast<const T*>(src), m, n, ld, d_max, d_bad);
+    QIHT_HIP(hipGetLastError());
+    unsigned long long h[2] = {0, 0};
+    QIHT_HIP(hipMemcpyAsync(h, d_max, 16, hipMemcpyDeviceToHost, st));
+    QIHT_HIP(hipFreeAsync(d_max, st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    int bad = 0;
+    std::memcpy(&bad, &h[1], sizeof(int));
+    if (bad) return fail(QIHT_ERR_NUMERIC, "input contains NaN or Inf");
+    double c;
+    std::memcpy(&c, &h[0], sizeof(double));
+    *c_out = c;
+    return QIHT_OK;
+}
+
+template <int BITS, typename T, int NC>
+void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
+              uint64_t seed, double c, double K, qiht_qmatrix* q,
+              hipStream_t st) {
+    const int64_t nchunks = q->col_bytes / 16;
+    dim3 grid(static_cast<unsigned>((n + 63) / 64),
+              static_cast<unsigned>((nchunks + 3) / 4));
+    hipLaunchKernelGGL((k_quantize<BITS, T, NC>), grid, dim3(256), 0, st,
+                       static_cast<const T*>(src), m, n, ld, q->rows,
+                       q->col_bytes, nchunks, c, K,
+                       static_cast<uint32_t>(seed),
+                       static_cast<uint32_t>(seed >> 32), R, q->codes[0],
+                       q->codes[1]);
+}
+
+template <typename T, int NC>
+qiht_status dispatch_bits(int bits, const void* src, int64_t m, int64_t n,
+                          int64_t ld, int R, uint64_t seed, double c, double K,
+                          qiht_qmatrix* q, hipStream_t st) {
+    switch (bits) {
+        case 1: launch_q<1, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        case 2: launch_q<2, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        case 4: launch_q<4, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        case 8: launch_q<8, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        case 32: launch_q<32, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        default: return fail(QIHT_ERR_UNSUPPORTED, "unsupported bit width");
+    }
+    QIHT_HIP(hipGetLastError());
+    return QIHT_OK;
+}
+
+}  // namespace
+
+qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
+                          int64_t n, int64_t ld, hipStream_t st,
+                          double* c_out) {
+    switch (dt) {
+        case QIHT_F32: return absmax_t<float, 1>(src, m, n, ld, st, c_out);
+        case QIHT_F64: return absmax_t<double, 1>(src, m, n, ld, st, c_out);
+        case QIHT_C64: return absmax_t<float, 2>(src, m, n, ld, st, c_out);
+        case QIHT_C128: return absmax_t<double, 2>(src, m, n, ld, st, c_out);
+    }
+    return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
+}
+
+qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
+                                   int64_t n, int64_t ld, int bits, int R,
+                                   uint64_t seed, double c, double K,
+                                   qiht_qmatrix* q, hipStream_t st) {
+    switch (dt) {
+        case QIHT_F32: return dispatch_bits<float, 1>(bits, src, m, n, ld, R, seed, c, K, q, st);
+        case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, q, st);
+        case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
+        case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
+    }
+    return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
+}
+
+qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
+                                   int bits, uint64_t seed, double c,
+                                   double K, const double* levels_dev,
+                                   double* yhat, uint8_t* codes,
+                                   hipStream_t st) {
+    const bool cplx = (dt == QIHT_C64 || dt == QIHT_C128);
+    const int64_t rows = cplx ? 2 * m : m;
+    dim3 grid(static_cast<unsigned>((rows + 255) / 256));
+    const uint32_t k0 = static_cast<uint32_t>(seed);
+    const uint32_t k1 = static_cast<uint32_t>(seed >> 32);
+    switch (dt) {
+        case QIHT_F32:
+            hipLaunchKernelGGL((k_quantize_vec<float, 1>), grid, dim3(256), 0, st,
+                               static_cast<const float*>(y), m, rows, bits, c, K, k0, k1,
+                               levels_dev, yhat, codes);
+            break;
+        case QIHT_F64:
+            hipLaunchKernelGGL((k_quantize_vec<double, 1>), grid, dim3(256), 0, st,
+                               static_cast<const double*>(y), m, rows, bits, c, K, k0, k1,
+                               levels_dev, yhat, codes);
+            break;
+        case QIHT_C64:
+            hipLaunchKernelGGL((k_quantize_vec<float, 2>), grid, dim3(256), 0, st,
+                               static_cast<const float*>(y), m, rows, bits, c, K, k0, k1,
+                               levels_dev, yhat, codes);
+            break;
+        case QIHT_C128:
+            hipLaunchKernelGGL((k_quantize_vec<double, 2>), grid, dim3(256), 0, st,
+                               static_cast<const double*>(y), m, rows, bits, c, K, k0, k1,
+                               levels_dev, yhat, codes);
+            break;
+    }
+    QIHT_HIP(hipGetLastError());
+    return QIHT_OK;
+}
+
+}  // namespace qiht

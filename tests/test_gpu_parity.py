@@ -1,0 +1,317 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (stated per test):
+* codes: bit-exact, every element, both realizations;
+* H_s supports: exact (same FP32 input on both sides, ties to the lower
+  index);
+* gradient g: |g_gpu - g_orc| <= 1e-5 max(|g_orc|, 1e-3 |g0|) with the oracle
+  evaluated in FP64 at the GPU's x (teacher forcing);
+* solves: identical final supports, |x_gpu - x_orc| / |x_orc| <= 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1802_04907_amd as qiht  # noqa: E402
+import workloads  # noqa: E402
+from oracle import niht  # noqa: E402
+from oracle import quantizer as qz  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _oracle_mats(p, bits, realizations=2):
+    c1, s1 = qz.quantize_matrix(p.phi, bits, p.seed, 0)
+    if bits == 32:
+        q1 = c1
+        q2 = c1
+    else:
+        q1 = qz.dequantize(c1, s1, bits)
+        if realizations == 2:
+            c2, _ = qz.quantize_matrix(p.phi, bits, p.seed, 1)
+            q2 = qz.dequantize(c2, s1, bits)
+        else:
+            q2 = q1
+    yh = qz.dequantized_vector(p.y, 8 if bits != 32 else 32, p.seed)
+    return q1, q2, yh
+
+
+def _gpu_problem(p, bits, realizations=2, ybits=None):
+    ybits = ybits if ybits is not None else (8 if bits != 32 else 32)
+    q = qiht.quantize_matrix(_t(p.phi), bits, realizations, p.seed)
+    yhat, _, _ = qiht.quantize_vector(_t(p.y), ybits, p.seed)
+    return q, yhat
+
+
+# ---------------------------------------------------------------- codes
+CODE_CASES = [
+    (37, 50, 4, np.float32, 2),
+    (300, 129, 8, np.float64, 2),
+    (1000, 67, 2, np.float32, 2),
+    (513, 33, 1, np.float64, 2),
+    (129, 65, 4, np.float32, 1),
+    (256, 1024, 8, np.float64, 2),
+    (3, 1, 8, np.float64, 2),
+]
+
+
+@pytest.mark.parametrize("m,n,bits,dt,R", CODE_CASES)
+def test_codes_bit_exact(m, n, bits, dt, R):
+    say(f"codes m={m} n={n} bits={bits} dt={dt.__name__} R={R}")
+    rng = np.random.default_rng(m * 1000 + n)
+    phi = rng.standard_normal((m, n)).astype(dt)
+    q = qiht.quantize_matrix(_t(phi), bits, R, seed=12345 + m)
+    for r in range(R):
+        want, c = qz.quantize_matrix(phi, bits, 12345 + m, r)
+        got = q.export_codes(r)
+        assert got.shape == want.shape
+        np.testing.assert_array_equal(got, want.astype(np.uint8))
+        assert q.scale == c
+
+
+def test_codes_complex_and_strided():
+    rng = np.random.default_rng(5)
+    a = (rng.standard_normal((45, 70)) + 1j * rng.standard_normal((45, 70))).astype(np.complex64)
+    q = qiht.quantize_matrix(_t(a), 4, 2, seed=77)
+    assert q.rows == 90
+    for r in range(2):
+        want, c = qz.quantize_matrix(a, 4, 77, r)
+        np.testing.assert_array_equal(q.export_codes(r), want.astype(np.uint8))
+    # a row-major view with leading dimension > n
+    big = rng.standard_normal((40, 100)).astype(np.float32)
+    view = _t(big)[:, 10:73]
+    q2 = qiht.quantize_matrix(view, 2, 2, seed=3)
+    want, _ = qz.quantize_matrix(big[:, 10:73], 2, 3, 1)
+    np.testing.assert_array_equal(q2.export_codes(1), want.astype(np.uint8))
+
+
+def test_fp32_path_is_plain_copy():
+    rng = np.random.default_rng(9)
+    phi = rng.standard_normal((77, 40))
+    q = qiht.quantize_matrix(_t(phi), 32, 2, seed=0)
+    assert q.realizations == 1
+    np.testing.assert_array_equal(q.export_codes(0), phi.astype(np.float32))
+
+
+def test_zero_matrix_codes():
+    q = qiht.quantize_matrix(torch.zeros(20, 30, device=DEV), 4, 2, seed=1)
+    assert q.scale == 0.0
+    assert np.all(q.export_codes(0) == 0) and np.all(q.export_codes(1) == 0)
+
+
+def test_nan_rejected():
+    phi = torch.ones(8, 8, device=DEV)
+    phi[3, 4] = float("nan")
+    with pytest.raises(qiht.QihtError) as e:
+        qiht.quantize_matrix(phi, 4, 2, seed=1)
+    assert e.value.status_name == "NUMERIC"
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 8, 32])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_vector_exact(bits, cplx):
+    rng = np.random.default_rng(bits)
+    y = rng.standard_normal(1001)
+    if cplx:
+        y = y + 1j * rng.standard_normal(1001)
+    yhat, codes, scale = qiht.quantize_vector(_t(y), bits, seed=42, want_codes=bits != 32)
+    want = qz.dequantized_vector(y, bits, 42)
+    np.testing.assert_array_equal(yhat.cpu().numpy(), want)
+    if bits != 32:
+        wc, c = qz.quantize_vector(y, bits, 42)
+        np.testing.assert_array_equal(codes.cpu().numpy(), wc.astype(np.uint8))
+        assert scale == c
+
+
+# ---------------------------------------------------------------- H_s
+@pytest.mark.parametrize("n", [1, 5, 1000, 1025, 32768, 40000])
+def test_hard_threshold_exact(n):
+    rng = np.random.default_rng(n)
+    a = rng.integers(-4, 5, size=n).astype(np.float32)          # ties and zeros
+    b = (rng.standard_normal(n) * 10.0 ** rng.integers(-3, 3, size=n)).astype(np.float32)
+    for vec in (a, b):
+        for s in sorted({0, 1, max(1, n // 64), n // 2, n}):
+            say(f"H_s n={n} s={s}")
+            got = qiht.hard_threshold(_t(vec), s).cpu().numpy()
+            want = niht.hard_threshold_support(vec.astype(np.float64), s)
+            np.testing.assert_array_equal(got, want)
+
+
+def test_hard_threshold_nan():
+    a = torch.ones(100, device=DEV)
+    a[7] = float("nan")
+    with pytest.raises(qiht.QihtError):
+        qiht.hard_threshold(a, 5)
+
+
+# ---------------------------------------------------------------- gradient
+GRAD_CASES = [
+    (256, 1024, 16, 8, False),
+    (2000, 3000, 40, 4, False),
+    (1500, 700, 30, 2, False),
+    (777, 901, 12, 1, False),
+    (5000, 1200, 20, 32, False),    # two FP32 slabs
+    (4500, 1300, 25, 4, True),      # complex: 9000 stacked rows, two slabs
+]
+
+
+@pytest.mark.parametrize("m,n,s,bits,cplx", GRAD_CASES)
+def test_gradient_teacher_forced(m, n, s, bits, cplx):
+    say(f"gradient m={m} n={n} s={s} bits={bits} cplx={cplx}")
+    if cplx:
+        p = workloads.interferometry(n_vis=m, side=int(np.sqrt(n)) + 1, s=s, seed=1)
+    else:
+        p = workloads.gaussian(m, n, s, 1e-3, seed=m + n)
+    q, yhat = _gpu_problem(p, bits)
+    q1, q2, yh = _oracle_mats(p, bits)
+    np.testing.assert_array_equal(yhat.cpu().numpy(), yh)
+    g0_gpu, r0 = qiht.gradient(q, yhat, None, None)
+    g0 = q1.T @ yh
+    tol = lambda ref: 1e-5 * max(np.linalg.norm(ref), 1e-3 * np.linalg.norm(g0))  # noqa: E731
+    assert np.linalg.norm(g0_gpu.cpu().numpy() - g0) <= tol(g0)
+    np.testing.assert_array_equal(r0.cpu().numpy(), yh.astype(np.float32))
+    rng = np.random.default_rng(0)
+    for trial in range(3):
+        nn = q.n
+        sup = np.sort(rng.choice(nn, s, replace=False)).astype(np.int32)
+        x = np.zeros(nn, dtype=np.float32)
+        x[sup] = rng.standard_normal(s).astype(np.float32)
+        g, r = qiht.gradient(q, yhat, _t(x), _t(sup))
+        r_or = yh - q2 @ x.astype(np.float64)
+        g_or = q1.T @ r_or
+        rg = r.cpu().numpy()
+        assert np.all(np.abs(rg - r_or) <= 2.0 ** -23 * np.abs(r_or) + 1e-30)
+        assert np.linalg.norm(g.cpu().numpy() - g_or) <= tol(g_or), trial
+
+
+# ---------------------------------------------------------------- solves
+def _compare_solve(p, bits, max_iters=300, tol=1e-8, mu_mode=0, realizations=2,
+                   rel=1e-4):
+    q, yhat = _gpu_problem(p, bits, realizations)
+    x, sup, info = qiht.niht_solve(q, yhat, p.s, max_iters=max_iters, tol=tol,
+                                   mu_mode=mu_mode)
+    q1, q2, yh = _oracle_mats(p, bits, realizations)
+    ref = niht.qiht_solve(q1, q2, yh, p.s, max_iters=max_iters, tol=tol,
+                          mu_mode="cross" if mu_mode == 0 else "same")
+    gs = sup.cpu().numpy()
+    np.testing.assert_array_equal(gs, ref.support)
+    xg = x.cpu().numpy().astype(np.float64)
+    assert np.count_nonzero(np.delete(xg, gs)) == 0
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    say(f"  support identical, rel err {err:.2e}, gpu {info}, oracle it {ref.iterations}"
+        f" reason {ref.reason}")
+    assert err <= rel
+    return x, sup, info, ref
+
+
+def test_solve_config1():
+    say("solve config1")
+    p = workloads.config1(0)
+    _compare_solve(p, 8, 300, 1e-8)
+
+
+@pytest.mark.parametrize("bits", [2, 4, 8, 32])
+@pytest.mark.parametrize("mu_mode", [0, 1])
+def test_solve_bits_and_step_modes(bits, mu_mode):
+    say(f"solve bits={bits} mu_mode={mu_mode}")
+    p = workloads.gaussian(300, 900, 6 if bits == 2 else 12, 1e-3, seed=bits)
+    _compare_solve(p, bits, 300, 1e-7, mu_mode)
+
+
+def test_solve_single_realization():
+    p = workloads.gaussian(250, 600, 10, 1e-3, seed=21)
+    _compare_solve(p, 8, 300, 1e-8, realizations=1)
+
+
+def test_solve_complex_interferometry():
+    say("solve complex")
+    p = workloads.interferometry(n_vis=700, side=24, s=6, snr_db=30, seed=2)
+    _compare_solve(p, 4, 300, 1e-7)
+
+
+def test_teacher_forced_iterations_config1():
+    """One GPU iteration at a time (warm start), each checked against the
+    oracle's iteration from the very same state."""
+    p = workloads.config1(0)
+    q, yhat = _gpu_problem(p, 8)
+    q1, q2, yh = _oracle_mats(p, 8)
+    x = np.zeros(p.n)
+    sup = niht.initial_support(q1, yh, p.s)
+    for it in range(40):
+        xg, sg, info = qiht.niht_solve(q, yhat, p.s, max_iters=1, tol=-1.0,
+                                       x0=_t(x.astype(np.float32)),
+                                       support0=_t(sup.astype(np.int32)))
+        ref = niht.qiht_iteration(q1, q2, yh, x.astype(np.float32).astype(np.float64),
+                                  sup, p.s)
+        gsup = sg.cpu().numpy()
+        np.testing.assert_array_equal(gsup, ref.support, err_msg=f"iteration {it}")
+        assert info["backtracks"] == ref.backtracks
+        xn = xg.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(xn - ref.x) <= 1e-5 * np.linalg.norm(ref.x), it
+        assert abs(info["mu_last"] - ref.mu) <= 1e-5 * ref.mu, it
+        x, sup = xn, gsup.astype(np.int64)
+
+
+def test_determinism_bitwise():
+    p = workloads.gaussian(400, 1500, 20, 1e-3, seed=7)
+    q, yhat = _gpu_problem(p, 4)
+    a = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
+    b = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_batched_uneven_matches_oracle():
+    probs = workloads.batch_uneven(count=5, m_lo=200, m_hi=900, seed=3)
+    gpu = []
+    for p in probs:
+        q, yhat = _gpu_problem(p, 4)
+        gpu.append((q, yhat, p.s))
+    res = qiht.niht_solve_batched(gpu, max_iters=300, tol=1e-7)
+    for p, (x, sup, info) in zip(probs, res):
+        q1, q2, yh = _oracle_mats(p, 4)
+        ref = niht.qiht_solve(q1, q2, yh, p.s, max_iters=300, tol=1e-7)
+        np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
+        err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        say(f"  batch m={p.m} err {err:.1e} {info}")
+        assert err <= 1e-4
+
+
+# ---------------------------------------------------------------- edges
+def test_full_support_s_equals_n():
+    p = workloads.gaussian(60, 20, 20, 1e-3, seed=4)
+    _compare_solve(p, 8, 400, 1e-9)
+
+
+def test_s_one_and_tiny_m():
+    p = workloads.gaussian(5, 40, 1, 0.0, seed=8)
+    _compare_solve(p, 8, 100, 1e-9)
+
+
+def test_zero_observation_is_stationary():
+    p = workloads.gaussian(50, 100, 3, 0.0, seed=1)
+    q = qiht.quantize_matrix(_t(p.phi), 4, 2, p.seed)
+    yhat = torch.zeros(50, dtype=torch.float64, device=DEV)
+    x, sup, info = qiht.niht_solve(q, yhat, 3)
+    assert info["reason"] == "stationary" and info["iterations"] == 0
+    assert torch.count_nonzero(x) == 0
+    np.testing.assert_array_equal(sup.cpu().numpy(), [0, 1, 2])
+
+
+def test_invalid_s_rejected_on_device_handle():
+    p = workloads.gaussian(30, 40, 3, 0.0, seed=1)
+    q, yhat = _gpu_problem(p, 4)
+    with pytest.raises(qiht.QihtError):
+        qiht.niht_solve(q, yhat, 41)
+    with pytest.raises(qiht.QihtError):
+        qiht.niht_solve(q, yhat, 0)
