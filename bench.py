@@ -1,0 +1,270 @@
+"""Benchmark of the QIHT hot path on one MI355X.
+
+Workload (the memory-bound GEMV-pair roofline case): real Gaussian Phi of
+8192 x 32768 (FP32, N(0, 1/8192)), x 512-sparse with N(0, 1) nonzeros, noise
+sigma 1e-3, seed 0.  One step = quantize Phi (two realizations) and y, then a
+200-iteration QIHT solve (all steps of the path), with the inputs already
+resident in HBM.  Headline bit width: 4-bit Phi / 8-bit y.
+
+Prints ONE JSON line.  Extra fields:
+  roofline      the dominant kernel (g = Q1^T r) from HIP events recorded on
+                its launch stream during the timed steps
+  cpu_baseline  the CPU oracle timed on a bounded sample of the workload
+  sweep         b = 32 / 8 / 4 / 2: iterations/s of the solve, pass GB/s,
+                error floors, time to 90% support recovery and to an equal
+                recovery error
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M, N, S, SIGMA, SEED, ITERS = 8192, 32768, 512, 1e-3, 0, 200
+PEAK_HBM_GBPS = 8000.0
+METRIC = "NIHT iterations/s + HBM GB/s, b=8/4/2-bit vs FP32 at equal recovery error"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fullpass_traffic_config2.md")
+PASS_SOURCE = os.path.join(ROOT, "paper_1802_04907_amd", "csrc", "pass.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pass_bytes(rows, n, bits):
+    """Algorithmic bytes of one g = Q1^T r launch: the codes once, r once,
+    g written once."""
+    codes = rows * n * (32 if bits == 32 else bits) / 8.0
+    return codes + rows * 4.0 + n * 4.0
+
+
+def source_hash():
+    with open(PASS_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(bits):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None when absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = source_hash()
+    h, val = None, None
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line.startswith("source_hash:"):
+            h = line.split(":", 1)[1].strip()
+        if line.startswith(f"traffic_bytes_per_launch_b{bits}:"):
+            val = float(line.split(":", 1)[1])
+    return val if (h == want and val is not None) else None
+
+
+def one_step(qiht, phi_d, y_d, bits, profile=True, **kw):
+    ybits = 32 if bits == 32 else 8
+    q = qiht.quantize_matrix(phi_d, bits, 2, SEED)
+    yhat, _, _ = qiht.quantize_vector(y_d, ybits, SEED)
+    x, sup, info = qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0, profile=profile, **kw)
+    q.free()
+    return info
+
+
+def recovery(x, sup, x_true, true_sup):
+    err = float(np.linalg.norm(x - x_true) / np.linalg.norm(x_true))
+    rec = len(np.intersect1d(sup, true_sup)) / len(true_sup)
+    return err, rec
+
+
+def trajectory(qiht, torch, q, yhat, x_true, true_sup, total, chunk):
+    """Recovery error and support recovery every `chunk` iterations
+    (warm-started chunks continue the same iteration exactly)."""
+    out = []
+    x, sup, _ = qiht.niht_solve(q, yhat, S, max_iters=chunk, tol=-1.0)
+    done = chunk
+    while True:
+        xs, ss = x.cpu().numpy().astype(np.float64), sup.cpu().numpy()
+        out.append((done,) + recovery(xs, ss, x_true, true_sup))
+        if done >= total:
+            break
+        x, sup, _ = qiht.niht_solve(q, yhat, S, max_iters=chunk, tol=-1.0, x0=x, support0=sup)
+        done += chunk
+    return out
+
+
+def first_reach(traj, pred):
+    for it, err, rec in traj:
+        if pred(err, rec):
+            return it
+    return None
+
+
+def cpu_baseline(p, ncols=4096, iters=10):
+    """Oracle (plain NumPy FP64) on the first `ncols` columns of the same
+    workload; per-iteration time scaled to the full width (cost is linear in
+    n: two dense matrix-vector products per iteration)."""
+    from oracle import niht, quantizer as qz
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    phi = np.ascontiguousarray(p.phi[:, :ncols])
+    s = max(1, S * ncols // N)
+    t0 = time.perf_counter()
+    c1, sc = qz.quantize_matrix(phi, 4, SEED, 0)
+    c2, _ = qz.quantize_matrix(phi, 4, SEED, 1)
+    q1 = qz.dequantize(c1, sc, 4)
+    q2 = qz.dequantize(c2, sc, 4)
+    yh = qz.dequantized_vector(p.y, 8, SEED)
+    tq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    niht.qiht_solve(q1, q2, yh, s, max_iters=iters, tol=-1.0)
+    ti = (time.perf_counter() - t0) / iters
+    full_iter_s = ti * (N / ncols)
+    return {
+        "value": round(1.0 / full_iter_s, 3), "unit": "iterations/s",
+        "cores": int(threads), "kind": "oracle",
+        "sample": (f"oracle QIHT (4-bit Phi, 8-bit y) on rows 8192 x first {ncols} of "
+                   f"{N} columns, s={s}, {iters} iterations = {ti * 1e3:.1f} ms/iteration, "
+                   f"scaled x{N // ncols} to the full width; oracle quantization of the "
+                   f"sample took {tq:.1f} s and is not in the value"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--bits", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the column sharding it would use is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1802_04907_amd as qiht
+    import workloads
+
+    dev = torch.device("cuda:0")
+    log("generating workload ...")
+    p = workloads.config2(SEED)
+    phi_d = torch.from_numpy(p.phi).to(dev)
+    y_d = torch.from_numpy(p.y).to(dev)
+    torch.cuda.synchronize()
+
+    bits = args.bits
+    log(f"warmup {args.warmup} steps, bits {bits}")
+    for _ in range(args.warmup):
+        one_step(qiht, phi_d, y_d, bits)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(one_step(qiht, phi_d, y_d, bits))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = ITERS * args.steps / elapsed
+    pass_ms = sum(i["pass_ms"] for i in infos)
+    launches = sum(i["pass_launches"] for i in infos)
+    avg_s = pass_ms / launches / 1e3
+    bpl = pass_bytes(M, N, bits)
+    achieved = bpl / avg_s / 1e9
+    traffic = measured_traffic(bits)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"Gaussian Phi {M}x{N} FP32 N(0,1/{M}), s={S}, sigma_e={SIGMA}, "
+                                f"{bits}-bit Phi (2 realizations) / "
+                                f"{32 if bits == 32 else 8}-bit y; step = quantize + "
+                                f"{ITERS} QIHT iterations"),
+                   "m": M, "n": N, "s": S, "bits": bits, "iterations_per_step": ITERS,
+                   "codes_storage": f"u{bits}" if bits != 32 else "f32"},
+        "roofline": {"bound": "hbm", "kernel": "k_fullpass (g = Q1^T r)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic,
+                     "bytes_per_launch": bpl, "avg_launch_us": round(avg_s * 1e6, 3),
+                     "launches_timed": launches},
+    }
+    log(json.dumps(out["roofline"]))
+
+    if not args.no_sweep:
+        sweep = {}
+        true_sup = p.support
+        for b in (32, 8, 4, 2):
+            log(f"sweep b={b}")
+            one_step(qiht, phi_d, y_d, b)
+            torch.cuda.synchronize()
+            ybits = 32 if b == 32 else 8
+            q = qiht.quantize_matrix(phi_d, b, 2, SEED)
+            yhat, _, _ = qiht.quantize_vector(y_d, ybits, SEED)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            tot_ms, tot_l = 0.0, 0
+            for _ in range(reps):
+                _, _, inf = qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0, profile=True)
+                tot_ms += inf["pass_ms"]
+                tot_l += inf["pass_launches"]
+            torch.cuda.synchronize()
+            its = ITERS * reps / (time.perf_counter() - t0)
+            traj = trajectory(qiht, torch, q, yhat, p.x_true, true_sup, ITERS, 5)
+            q.free()
+            avg = tot_ms / tot_l / 1e3
+            sweep[str(b)] = {
+                "solve_iterations_per_s": round(its, 1),
+                "pass_avg_us": round(avg * 1e6, 2),
+                "pass_GBps": round(pass_bytes(M, N, b) / avg / 1e9, 1),
+                "final_rel_err": traj[-1][1], "final_support_recovery": traj[-1][2],
+                "iters_to_90pct_support": first_reach(traj, lambda e, r: r >= 0.9),
+                "trajectory_every_5": [(t, round(e, 5), round(r, 4)) for t, e, r in traj],
+            }
+        # equal recovery error: e* = 1.05 x max(floor_b, floor_32)
+        f32 = sweep["32"]
+        for b in ("8", "4", "2"):
+            d = sweep[b]
+            e_star = 1.05 * max(d["final_rel_err"], f32["final_rel_err"])
+            it_b = first_reach([tuple(v) for v in d["trajectory_every_5"]], lambda e, r: e <= e_star)
+            it_32 = first_reach([tuple(v) for v in f32["trajectory_every_5"]],
+                                lambda e, r: e <= e_star)
+            d["equal_error_target"] = e_star
+            d["time_to_target_ms"] = None if it_b is None else round(it_b / d["solve_iterations_per_s"] * 1e3, 3)
+            f32_t = None if it_32 is None else it_32 / f32["solve_iterations_per_s"] * 1e3
+            d["fp32_time_to_target_ms"] = None if f32_t is None else round(f32_t, 3)
+            d["speedup_vs_fp32_at_equal_error"] = (
+                None if (it_b is None or f32_t is None) else round(f32_t / d["time_to_target_ms"], 3))
+            t90b = d["iters_to_90pct_support"]
+            t90f = f32["iters_to_90pct_support"]
+            d["speedup_vs_fp32_to_90pct_support"] = (
+                None if (t90b is None or t90f is None) else
+                round((t90f / f32["solve_iterations_per_s"]) / (t90b / d["solve_iterations_per_s"]), 3))
+        if os.environ.get("QIHT_BENCH_TRAJ") is None:
+            for d in sweep.values():
+                d.pop("trajectory_every_5", None)
+        out["sweep"] = sweep
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle sample) ...")
+        out["cpu_baseline"] = cpu_baseline(p)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -75,7 +75,9 @@ typedef struct qiht_qmatrix qiht_qmatrix;
 typedef struct {
     int32_t max_iters;       /* n*; >= 1                                    */
     double tol;              /* stop when |x^n - x^(n-1)| <= tol |x^n|;
-                                0 disables (the paper gives only n*)        */
+                                tol < 0 disables the test (the paper gives
+                                only n*); tol = 0 stops at an exact fixed
+                                point                                       */
     double k;                /* shrink parameter, k > 1/(1-c); default 2    */
     double c;                /* step test margin, 0 <= c < 1; default 0.01  */
     int32_t max_backtracks;  /* shrinks per iteration (>= 0); default 32    */
@@ -85,6 +87,8 @@ typedef struct {
                                 NULL = x0 = 0 and G0 = supp H_s(Q1^T y_hat) */
     const int32_t* support0; /* warm-start support (device, s ascending
                                 indices); required iff x0 != NULL           */
+    int32_t profile;         /* 1: time every full-pass launch with HIP
+                                events on `stream` (qiht_info.pass_ms)      */
 } qiht_params;
 
 typedef struct {
@@ -93,11 +97,14 @@ typedef struct {
     int32_t backtracks;        /* total step shrinks                         */
     int32_t capped_iterations; /* iterations that hit max_backtracks         */
     double mu_last;            /* accepted step of the last iteration        */
-    double status_flags;       /* reserved, 0                                */
+    double pass_ms;            /* profile = 1: summed event time of the
+                                  g = Q1^T r launches (0 otherwise)          */
+    int32_t pass_launches;     /* number of those launches                   */
+    int32_t reserved;
 } qiht_info;
 
 /* Fill `p` (host) with the defaults: max_iters 300, tol 1e-8, k 2, c 0.01,
- * max_backtracks 32, mu_mode 0, no warm start. */
+ * max_backtracks 32, mu_mode 0, no warm start, profile 0. */
 void qiht_default_params(qiht_params* p);
 
 /*
@@ -226,7 +233,8 @@ qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat,
 /*
  * H_s selection alone (Sec. I-A): the indices of the s entries of a
  * (device, n floats) largest in magnitude, ties to the lower index,
- * written ascending to support_out (device, s int32).  0 <= s <= n.
+ * written ascending to support_out (device, s int32; may be NULL when
+ * s = 0).  0 <= s <= n.
  */
 qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s,
                                 int32_t* support_out, void* stream);

@@ -141,11 +141,13 @@ def quantize_vector(y, bits, seed=0, stream=None, want_codes=False):
     return yhat, codes, scale.value
 
 
-def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=None):
+def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=None,
+            profile=False):
     p = _lib.QihtParams()
     _lib.load().qiht_default_params(C.byref(p))
     p.max_iters, p.tol, p.k, p.c = int(max_iters), float(tol), float(k), float(c)
     p.max_backtracks, p.mu_mode = int(max_backtracks), int(mu_mode)
+    p.profile = 1 if profile else 0
     p.x0 = None if x0 is None else x0.data_ptr()
     p.support0 = None if support0 is None else support0.data_ptr()
     return p
@@ -154,11 +156,11 @@ def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=Non
 def _info_dict(inf):
     return dict(iterations=inf.iterations, reason=_lib.REASONS.get(inf.reason, inf.reason),
                 backtracks=inf.backtracks, capped_iterations=inf.capped_iterations,
-                mu_last=inf.mu_last)
+                mu_last=inf.mu_last, pass_ms=inf.pass_ms, pass_launches=inf.pass_launches)
 
 
 def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
-               mu_mode=0, x0=None, support0=None, stream=None):
+               mu_mode=0, x0=None, support0=None, stream=None, profile=False):
     """QIHT solve -> (x FP32 CUDA tensor, support int32 CUDA tensor, info dict)."""
     torch = _torch()
     x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
@@ -166,7 +168,7 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
     if x0 is not None:
         x0 = x0.to(dtype=torch.float32).contiguous()
         support0 = support0.to(dtype=torch.int32).contiguous()
-    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0)
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0, profile)
     inf = _lib.QihtInfo()
     _check(_lib.load().qiht_niht_solve(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
                                        _ptr(sup), C.byref(inf), _stream(stream)))

@@ -16,13 +16,15 @@ REASONS = {1: "converged", 2: "max_iters", 3: "stationary"}
 class QihtParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("tol", C.c_double), ("k", C.c_double),
                 ("c", C.c_double), ("max_backtracks", C.c_int32),
-                ("mu_mode", C.c_int32), ("x0", C.c_void_p), ("support0", C.c_void_p)]
+                ("mu_mode", C.c_int32), ("x0", C.c_void_p), ("support0", C.c_void_p),
+                ("profile", C.c_int32)]
 
 
 class QihtInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("reason", C.c_int32),
                 ("backtracks", C.c_int32), ("capped_iterations", C.c_int32),
-                ("mu_last", C.c_double), ("status_flags", C.c_double)]
+                ("mu_last", C.c_double), ("pass_ms", C.c_double),
+                ("pass_launches", C.c_int32), ("reserved", C.c_int32)]
 
 
 class QihtProblem(C.Structure):

@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 PER_FILE = {"quantize.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "quantize.hip", "solve.hip"]
+SOURCES = ["api.hip", "quantize.hip", "gather.hip", "pass.hip", "select.hip", "solve_host.hip"]
 
 
 def hipcc():

@@ -69,6 +69,7 @@ SolveArgs to_args(const qiht_params* p) {
     a.c = p->c;
     a.max_backtracks = p->max_backtracks;
     a.mu_mode = p->mu_mode;
+    a.profile = p->profile;
     return a;
 }
 
@@ -118,6 +119,7 @@ void qiht_default_params(qiht_params* p) {
     p->mu_mode = 0;
     p->x0 = nullptr;
     p->support0 = nullptr;
+    p->profile = 0;
 }
 
 const char* qiht_last_error(void) { return last_error_cstr(); }
@@ -348,8 +350,9 @@ qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat, const float
 qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* support_out,
                                 void* stream) try {
     set_error("");
-    if (!a || !support_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    if (!a || (!support_out && s > 0)) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
     if (n < 1 || s < 0 || s > n) return fail(QIHT_ERR_INVALID_ARG, "need n >= 1, 0 <= s <= n");
+    if (s == 0) return QIHT_OK;
     int dev = 0;
     qiht_status s0 = need_device(&dev);
     if (s0 != QIHT_OK) return s0;

@@ -83,6 +83,7 @@ struct SolveArgs {
     double c;
     int32_t max_backtracks;
     int32_t mu_mode;
+    int32_t profile;
 };
 
 struct ProblemIn {

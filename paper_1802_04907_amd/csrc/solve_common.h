@@ -1,0 +1,218 @@
+// Device-side data structures and helpers shared by the solver kernels
+// (gather.hip, pass.hip, select.hip) and their host orchestration
+// (solve_host.hip).
+#pragma once
+
+#include <cstdint>
+
+#include "qiht_internal.h"
+
+namespace qiht {
+
+constexpr int kSelectThreads = 1024;  // one workgroup per H_s proposal
+constexpr int kGatherThreads = 256;   // column gathers
+constexpr int kPassThreads = 256;     // full pass
+constexpr int kSpec = 4;              // step sizes proposed at once
+constexpr int kMaxSelectN = kSelectThreads * 64;
+constexpr int kGatherCpg = 64;        // listed columns per gather workgroup
+
+// Per-problem control state (device memory).
+struct SolveState {
+    int32_t done;
+    int32_t iter;       // completed iterations
+    int32_t reason;
+    int32_t phase;      // 0 normal, 2 sequential backtracking pending
+    int32_t total_bt;
+    int32_t capped;
+    int32_t err;        // NaN met in a selection
+    int32_t base_k;     // first shrink index still to be examined
+    double mu;          // step of this iteration before any shrink
+    double mu_last;     // accepted step of the last iteration
+};
+
+// One proposal x' = H_s(x + mu_k g), k = shrink count.
+struct CandMeta {
+    int32_t changed;    // support differs from the current one
+    int32_t dcount;     // entries where x' differs from x
+    int32_t k;          // shrink count of this proposal
+    int32_t pad;
+    double mu;          // mu / (k(1-c))^k
+    double dx2;         // |x' - x|^2
+    double xn2;         // |x'|^2
+    double omega;       // |x' - x|^2 / |Q1 (x' - x)|^2 (when needed)
+};
+
+struct ProbDev {
+    const uint8_t* q1;
+    const uint8_t* q2;
+    int64_t col_bytes;
+    int32_t rows;
+    int32_t n;
+    int32_t s;
+    int32_t nrb;        // 256-byte row blocks per column
+    int32_t nslab;      // full-pass row slabs
+    int32_t gmax;       // column groups reserved per gather set
+    double alpha;       // dequantized value = alpha * code + beta
+    double beta;
+    float alpha_f;
+    float pad_f;
+    const double* yhat;
+    float* r32;         // residual, rows_pad (zero beyond rows)
+    float* g;           // gradient, n
+    float* gpart;       // nslab * n slab partials (nslab > 1)
+    float* x;           // current iterate, dense n
+    int32_t* sup;       // current support, s ascending
+    int32_t* csup;      // kSpec * s proposal supports
+    float* cval;        // kSpec * s proposal values on their supports
+    int32_t* dlist;     // kSpec * 2s indices where a proposal differs from x
+    double* dw;         // kSpec * 2s the differences
+    CandMeta* meta;     // kSpec
+    double* part1;      // gather partials [set][group][row] (x2 for two matrices)
+    double* wsum1;      // [set][group]
+    double* part2;      // [set][row block] (x2)
+    unsigned* cnt1;     // [set][row block] arrivals of column groups
+    unsigned* cnt2;     // [set] arrivals of row blocks
+    unsigned* cnt3;     // arrivals of sets
+    SolveState* st;
+};
+
+struct Task {
+    int32_t p, slab, c0, c1;
+};
+
+enum { G_R = 0, G_MU = 1, G_OMEGA = 2 };
+enum { SEL_RAW = 0, SEL_INIT = 1, SEL_STEP = 2 };
+
+// ---------------------------------------------------------------------------
+// Block helpers (fixed reduction orders: results are bitwise reproducible).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive prefix sum in thread order; *total (optional) gets the sum.
+template <int NT>
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[wv] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t t = sh[w];
+        if (w < wv) before += t;
+        all += t;
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + x - v;
+}
+
+// Step after k shrinks: k successive divisions, the same rounding sequence
+// as applying mu <- mu / (k(1-c)) k times.
+__device__ __forceinline__ double shrunk_mu(double mu, double shrink, int k) {
+    for (int i = 0; i < k; ++i) mu = mu / shrink;
+    return mu;
+}
+
+// ---------------------------------------------------------------------------
+// Code unpacking: a 32-bit word holds 32/BITS codes, code q at bit q*BITS.
+// ---------------------------------------------------------------------------
+template <int BITS>
+__device__ __forceinline__ uint32_t code_at(uint32_t w, int q) {
+    return (w >> (q * BITS)) & ((1u << BITS) - 1u);
+}
+
+// Launchers (defined in the kernel files).
+void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxrb, int gmax,
+                   const SolveArgs& a, int zero_x, hipStream_t st);
+void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,
+                 hipStream_t st);
+void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
+void launch_propose(int cpt, const ProbDev* P, int count, const SolveArgs& a, int mode,
+                    hipStream_t st);
+void launch_fallback(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
+                     hipStream_t st);
+void launch_hard_threshold(int cpt, const float* a, int n, int s, int32_t* out, int* err,
+                           hipStream_t st);
+
+// Device-side commit of proposal `t` (called by one whole workgroup of
+// `nt` threads): x and the support take the proposal's values, the state
+// records the iteration and the stop test.
+template <int NT>
+__device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bool capped) {
+    SolveState* st = pd.st;
+    const CandMeta m = pd.meta[t];
+    const int32_t* cs = pd.csup + static_cast<size_t>(t) * pd.s;
+    const float* cv = pd.cval + static_cast<size_t>(t) * pd.s;
+    for (int i = threadIdx.x; i < pd.s; i += NT) pd.x[pd.sup[i]] = 0.0f;
+    __syncthreads();
+    __threadfence_block();
+    for (int i = threadIdx.x; i < pd.s; i += NT) {
+        pd.x[cs[i]] = cv[i];
+        pd.sup[i] = cs[i];
+    }
+    if (threadIdx.x == 0) {
+        st->iter += 1;
+        st->mu_last = m.mu;
+        st->total_bt += m.k;
+        st->capped += capped ? 1 : 0;
+        st->phase = 0;
+        st->base_k = 0;
+        if (a.tol >= 0.0 && m.dx2 <= a.tol * a.tol * m.xn2) {
+            st->done = 1;
+            st->reason = QIHT_REASON_CONVERGED;
+        } else if (st->iter >= a.max_iters) {
+            st->done = 1;
+            st->reason = QIHT_REASON_MAX_ITERS;
+        }
+    }
+    __syncthreads();
+}
+
+// The acceptance rule of the step-size test applied to proposals
+// base .. base + kSpec - 1 (meta[t] holds shrink count base + t).  Returns
+// the slot to accept, or -1 if every examined proposal is rejected and more
+// shrinks remain; *capped tells that the accepted slot hit max_backtracks.
+__device__ __forceinline__ int choose_proposal(const ProbDev& pd, const SolveArgs& a,
+                                               bool* capped) {
+    *capped = false;
+    for (int t = 0; t < kSpec; ++t) {
+        const CandMeta& m = pd.meta[t];
+        if (!m.changed) return t;
+        if (m.mu <= (1.0 - a.c) * m.omega) return t;
+        if (m.k >= a.max_backtracks) {
+            *capped = true;
+            return t;
+        }
+    }
+    return -1;
+}
+
+}  // namespace qiht

@@ -1,0 +1,393 @@
+// Host orchestration of the QIHT solve: workspace layout, the per-iteration
+// launch sequence, and the entry points behind qiht_niht_solve,
+// qiht_niht_solve_batched, qiht_gradient and qiht_hard_threshold.
+//
+// All control state lives on the device; the host only enqueues launches
+// and, every kChunk iterations, reads the stop flags back.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "solve_common.h"
+
+namespace qiht {
+namespace {
+
+constexpr int kChunk = 16;  // iterations enqueued between stop-flag reads
+
+struct InfoDev {
+    int32_t iterations, reason, backtracks, capped, err, pad;
+    double mu_last;
+};
+
+__global__ void k_warm_start(const ProbDev* __restrict__ P, const float* const* x0s) {
+    const ProbDev& pd = P[blockIdx.x];
+    const float* x0 = x0s[blockIdx.x];
+    for (int i = threadIdx.x; i < pd.s; i += blockDim.x) pd.x[pd.sup[i]] = x0[pd.sup[i]];
+}
+
+__global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
+                           int32_t* const* souts, InfoDev* infos) {
+    const ProbDev& pd = P[blockIdx.y];
+    const SolveState* st = pd.st;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < pd.n; j += gridDim.x * blockDim.x)
+        xouts[blockIdx.y][j] = pd.x[j];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < pd.s; t += gridDim.x * blockDim.x)
+        souts[blockIdx.y][t] = pd.sup[t];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        InfoDev inf;
+        inf.iterations = st->iter;
+        inf.reason = st->done ? st->reason : QIHT_REASON_MAX_ITERS;
+        inf.backtracks = st->total_bt;
+        inf.capped = st->capped;
+        inf.err = st->err;
+        inf.pad = 0;
+        inf.mu_last = st->mu_last;
+        infos[blockIdx.y] = inf;
+    }
+}
+
+int select_cpt(int64_t n) {
+    int cpt = 1;
+    while (static_cast<int64_t>(cpt) * kSelectThreads < n) cpt *= 2;
+    return cpt;
+}
+
+// Chunks per lane of a full-pass row slab: enough to cover the column, at
+// most 128 residual rows per lane (BITS chunks; 16 for FP32).
+int pass_cpl(int bits, int64_t col_bytes) {
+    const int64_t chunks = col_bytes / 16;
+    const int maxc = bits == 32 ? 16 : bits;
+    int c = 1;
+    while (c < maxc && static_cast<int64_t>(c) * 64 < chunks) c *= 2;
+    return c;
+}
+
+struct Carver {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count) {
+        off = (off + 255) / 256 * 256;
+        const size_t o = off;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return o;
+    }
+};
+
+struct Layout {
+    size_t r32, g, gpart, x, sup, csup, cval, dlist, dw, meta, part1, wsum1, part2, cnt1, cnt2,
+        cnt3, st;
+};
+
+struct Plan {
+    std::vector<ProbDev> host;
+    std::vector<Layout> lay;
+    std::vector<Task> tasks;
+    int bits = 0, cpl = 1, cpt = 1, maxrb = 1, maxg = 1;
+    bool any_slab = false;
+    size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
+    size_t x0ptr_off = 0;
+};
+
+qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
+    pl.bits = in[0].q->bits;
+    int64_t max_cb = 0, max_n = 0;
+    for (int i = 0; i < count; ++i) {
+        max_cb = std::max(max_cb, in[i].q->col_bytes);
+        max_n = std::max(max_n, in[i].q->n);
+    }
+    if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    pl.cpl = pass_cpl(pl.bits, max_cb);
+    pl.cpt = select_cpt(max_n);
+    const int64_t slab_chunks = 64LL * pl.cpl;
+    Carver cv;
+    pl.lay.resize(count);
+    pl.host.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const qiht_qmatrix* q = in[i].q;
+        const int64_t s = in[i].s;
+        const int64_t chunks = q->col_bytes / 16;
+        const int nslab = static_cast<int>((chunks + slab_chunks - 1) / slab_chunks);
+        const int nrb = static_cast<int>(q->col_bytes / 256);
+        const int gmax = static_cast<int>((2 * s + kGatherCpg - 1) / kGatherCpg);
+        pl.maxrb = std::max(pl.maxrb, nrb);
+        pl.maxg = std::max(pl.maxg, gmax);
+        pl.any_slab = pl.any_slab || nslab > 1;
+        Layout& L = pl.lay[i];
+        L.r32 = cv.take<float>(q->rows_pad);
+        L.g = cv.take<float>(q->n);
+        L.gpart = cv.take<float>(nslab > 1 ? static_cast<size_t>(nslab) * q->n : 1);
+        L.x = cv.take<float>(q->n);
+        L.sup = cv.take<int32_t>(s);
+        L.csup = cv.take<int32_t>(kSpec * s);
+        L.cval = cv.take<float>(kSpec * s);
+        L.dlist = cv.take<int32_t>(kSpec * 2 * s);
+        L.dw = cv.take<double>(kSpec * 2 * s);
+        L.meta = cv.take<CandMeta>(kSpec);
+        L.part1 = cv.take<double>(static_cast<size_t>(kSpec) * gmax * q->rows_pad);
+        L.wsum1 = cv.take<double>(static_cast<size_t>(kSpec) * gmax);
+        L.part2 = cv.take<double>(static_cast<size_t>(kSpec) * nrb * 2);
+        L.cnt1 = cv.take<unsigned>(static_cast<size_t>(kSpec) * nrb);
+        L.cnt2 = cv.take<unsigned>(kSpec);
+        L.cnt3 = cv.take<unsigned>(1);
+        L.st = cv.take<SolveState>(1);
+        ProbDev& p = pl.host[i];
+        std::memset(&p, 0, sizeof(p));
+        p.q1 = q->codes[0];
+        p.q2 = q->codes[1];
+        p.col_bytes = q->col_bytes;
+        p.rows = static_cast<int32_t>(q->rows);
+        p.n = static_cast<int32_t>(q->n);
+        p.s = static_cast<int32_t>(s);
+        p.nrb = nrb;
+        p.nslab = nslab;
+        p.gmax = gmax;
+        p.alpha = q->alpha;
+        p.beta = q->beta;
+        p.alpha_f = static_cast<float>(q->alpha);
+        p.yhat = in[i].yhat;
+        // full-pass tasks: about 256 KB of codes per workgroup, at least
+        // ~256 workgroups per problem when the problem is small
+        const int64_t slab_bytes = std::min<int64_t>(q->col_bytes, slab_chunks * 16);
+        const int64_t tc_bw = std::max<int64_t>(8, (256 * 1024) / std::max<int64_t>(slab_bytes, 1));
+        const int64_t tc = std::max<int64_t>(8, std::min<int64_t>(tc_bw, (q->n + 255) / 256));
+        for (int sl = 0; sl < nslab; ++sl)
+            for (int64_t c0 = 0; c0 < q->n; c0 += tc)
+                pl.tasks.push_back(Task{i, sl, static_cast<int32_t>(c0),
+                                        static_cast<int32_t>(std::min<int64_t>(q->n, c0 + tc))});
+    }
+    pl.probs_off = cv.take<ProbDev>(count);
+    pl.tasks_off = cv.take<Task>(pl.tasks.size());
+    pl.xptr_off = cv.take<float*>(count);
+    pl.sptr_off = cv.take<int32_t*>(count);
+    pl.x0ptr_off = cv.take<const float*>(count);
+    pl.info_off = cv.take<InfoDev>(count);
+    pl.bytes = cv.off;
+    return QIHT_OK;
+}
+
+void bind(Plan& pl, uint8_t* base) {
+    for (size_t i = 0; i < pl.host.size(); ++i) {
+        ProbDev& p = pl.host[i];
+        const Layout& L = pl.lay[i];
+        p.r32 = reinterpret_cast<float*>(base + L.r32);
+        p.g = reinterpret_cast<float*>(base + L.g);
+        p.gpart = reinterpret_cast<float*>(base + L.gpart);
+        p.x = reinterpret_cast<float*>(base + L.x);
+        p.sup = reinterpret_cast<int32_t*>(base + L.sup);
+        p.csup = reinterpret_cast<int32_t*>(base + L.csup);
+        p.cval = reinterpret_cast<float*>(base + L.cval);
+        p.dlist = reinterpret_cast<int32_t*>(base + L.dlist);
+        p.dw = reinterpret_cast<double*>(base + L.dw);
+        p.meta = reinterpret_cast<CandMeta*>(base + L.meta);
+        p.part1 = reinterpret_cast<double*>(base + L.part1);
+        p.wsum1 = reinterpret_cast<double*>(base + L.wsum1);
+        p.part2 = reinterpret_cast<double*>(base + L.part2);
+        p.cnt1 = reinterpret_cast<unsigned*>(base + L.cnt1);
+        p.cnt2 = reinterpret_cast<unsigned*>(base + L.cnt2);
+        p.cnt3 = reinterpret_cast<unsigned*>(base + L.cnt3);
+        p.st = reinterpret_cast<SolveState*>(base + L.st);
+    }
+}
+
+// HIP events around every full-pass launch (profile mode).
+struct PassTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    ~PassTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    void mark(hipStream_t st) {
+        if (!on) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        ev.push_back(e);
+        (void)hipEventRecord(e, st);
+    }
+    double total_ms() const {
+        double t = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+    int launches() const { return static_cast<int>(ev.size() / 2); }
+};
+
+struct Workspace {
+    uint8_t* base = nullptr;
+    hipStream_t st = nullptr;
+    ~Workspace() {
+        if (base) (void)hipFreeAsync(base, st);
+    }
+};
+
+void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
+                       const SolveArgs& a, int zero_x, hipStream_t st, PassTimer* tm) {
+    launch_gather(G_R, pl.bits, dP, count, pl.maxrb, pl.maxg, a, zero_x, st);
+    if (tm) tm->mark(st);
+    launch_pass(pl.bits, pl.cpl, dP, dT, static_cast<int>(pl.tasks.size()), st);
+    if (tm) tm->mark(st);
+    if (pl.any_slab) launch_slab_reduce(dP, count, st);
+}
+
+void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
+                        const SolveArgs& a, bool reuse_gradient, hipStream_t st, PassTimer* tm) {
+    if (!reuse_gradient) gradient_launches(pl, dP, dT, count, a, 0, st, tm);
+    launch_gather(G_MU, pl.bits, dP, count, pl.maxrb, pl.maxg, a, 0, st);
+    launch_propose(pl.cpt, dP, count, a, SEL_STEP, st);
+    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxrb, pl.maxg, a, 0, st);
+    launch_fallback(pl.bits, pl.cpt, dP, count, a, st);
+}
+
+qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
+                  ProbDev** dP, Task** dT) {
+    qiht_status s0 = make_plan(in, count, pl);
+    if (s0 != QIHT_OK) return s0;
+    ws.st = st;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws.base), pl.bytes, st);
+    if (e != hipSuccess || ws.base == nullptr) {
+        ws.base = nullptr;
+        (void)hipGetLastError();
+        return fail(QIHT_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+    }
+    bind(pl, ws.base);
+    QIHT_HIP(hipMemsetAsync(ws.base, 0, pl.bytes, st));
+    *dP = reinterpret_cast<ProbDev*>(ws.base + pl.probs_off);
+    *dT = reinterpret_cast<Task*>(ws.base + pl.tasks_off);
+    QIHT_HIP(hipMemcpyAsync(*dP, pl.host.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice,
+                            st));
+    QIHT_HIP(hipMemcpyAsync(*dT, pl.tasks.data(), sizeof(Task) * pl.tasks.size(),
+                            hipMemcpyHostToDevice, st));
+    return QIHT_OK;
+}
+
+}  // namespace
+
+qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_info* infos,
+                      hipStream_t st) {
+    Plan pl;
+    Workspace ws;
+    ProbDev* dP = nullptr;
+    Task* dT = nullptr;
+    qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT);
+    if (s0 != QIHT_OK) return s0;
+    std::vector<float*> xo(count);
+    std::vector<int32_t*> so(count);
+    std::vector<const float*> x0(count);
+    bool warm = false;
+    for (int i = 0; i < count; ++i) {
+        xo[i] = in[i].x_out;
+        so[i] = in[i].support_out;
+        x0[i] = in[i].x0;
+        if (in[i].x0) {
+            warm = true;
+            QIHT_HIP(hipMemcpyAsync(pl.host[i].sup, in[i].support0, sizeof(int32_t) * pl.host[i].s,
+                                    hipMemcpyDeviceToDevice, st));
+        }
+    }
+    float** dxo = reinterpret_cast<float**>(ws.base + pl.xptr_off);
+    int32_t** dso = reinterpret_cast<int32_t**>(ws.base + pl.sptr_off);
+    const float** dx0 = reinterpret_cast<const float**>(ws.base + pl.x0ptr_off);
+    QIHT_HIP(hipMemcpyAsync(dxo, xo.data(), sizeof(float*) * count, hipMemcpyHostToDevice, st));
+    QIHT_HIP(hipMemcpyAsync(dso, so.data(), sizeof(int32_t*) * count, hipMemcpyHostToDevice, st));
+    QIHT_HIP(hipMemcpyAsync(dx0, x0.data(), sizeof(float*) * count, hipMemcpyHostToDevice, st));
+
+    PassTimer timer;
+    timer.on = a.profile != 0;
+    if (warm) {
+        // x0 restricted to its support (x is zero elsewhere)
+        hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
+    } else {
+        // x0 = 0; G0 = supp H_s(Q1^T y_hat); iteration 1 reuses g0.
+        gradient_launches(pl, dP, dT, count, a, 1, st, &timer);
+        launch_propose(pl.cpt, dP, count, a, SEL_INIT, st);
+    }
+    QIHT_HIP(hipGetLastError());
+
+    std::vector<SolveState> hs(count);
+    for (int it = 1; it <= a.max_iters;) {
+        const int end = std::min(a.max_iters, it + kChunk - 1);
+        for (; it <= end; ++it) iteration_launches(pl, dP, dT, count, a, it == 1 && !warm, st, &timer);
+        QIHT_HIP(hipGetLastError());
+        if (it > a.max_iters) break;
+        for (int i = 0; i < count; ++i)
+            QIHT_HIP(hipMemcpyAsync(&hs[i], pl.host[i].st, sizeof(SolveState),
+                                    hipMemcpyDeviceToHost, st));
+        QIHT_HIP(hipStreamSynchronize(st));
+        bool all_done = true;
+        for (int i = 0; i < count; ++i) all_done = all_done && hs[i].done;
+        if (all_done) break;
+    }
+
+    InfoDev* dinf = reinterpret_cast<InfoDev*>(ws.base + pl.info_off);
+    hipLaunchKernelGGL(k_finalize, dim3(32, count), dim3(256), 0, st, dP, dxo, dso, dinf);
+    QIHT_HIP(hipGetLastError());
+    std::vector<InfoDev> hinf(count);
+    QIHT_HIP(hipMemcpyAsync(hinf.data(), dinf, sizeof(InfoDev) * count, hipMemcpyDeviceToHost,
+                            st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    bool nan = false;
+    for (int i = 0; i < count; ++i) {
+        nan = nan || hinf[i].err;
+        if (infos) {
+            infos[i].iterations = hinf[i].iterations;
+            infos[i].reason = hinf[i].reason;
+            infos[i].backtracks = hinf[i].backtracks;
+            infos[i].capped_iterations = hinf[i].capped;
+            infos[i].mu_last = hinf[i].mu_last;
+            infos[i].pass_ms = timer.total_ms();
+            infos[i].pass_launches = timer.launches();
+            infos[i].reserved = 0;
+        }
+    }
+    if (nan) return fail(QIHT_ERR_NUMERIC, "NaN met in the iterate");
+    return QIHT_OK;
+}
+
+qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float* x,
+                         const int32_t* support, int64_t s, float* g_out, float* r_out,
+                         hipStream_t st) {
+    ProblemIn in{q, yhat, std::max<int64_t>(s, 1), nullptr, nullptr, x, support};
+    Plan pl;
+    Workspace ws;
+    ProbDev* dP = nullptr;
+    Task* dT = nullptr;
+    qiht_status s0 = setup(&in, 1, pl, ws, st, &dP, &dT);
+    if (s0 != QIHT_OK) return s0;
+    const ProbDev& h = pl.host[0];
+    if (s > 0) {
+        QIHT_HIP(hipMemcpyAsync(h.sup, support, sizeof(int32_t) * s, hipMemcpyDeviceToDevice, st));
+        const float** dx0 = reinterpret_cast<const float**>(ws.base + pl.x0ptr_off);
+        QIHT_HIP(hipMemcpyAsync(dx0, &x, sizeof(float*), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_warm_start, dim3(1), dim3(256), 0, st, dP, dx0);
+    }
+    SolveArgs a{1, -1.0, 2.0, 0.01, 0, 0, 0};
+    gradient_launches(pl, dP, dT, 1, a, s == 0 ? 1 : 0, st, nullptr);
+    QIHT_HIP(hipGetLastError());
+    QIHT_HIP(hipMemcpyAsync(g_out, h.g, sizeof(float) * h.n, hipMemcpyDeviceToDevice, st));
+    if (r_out)
+        QIHT_HIP(hipMemcpyAsync(r_out, h.r32, sizeof(float) * h.rows, hipMemcpyDeviceToDevice, st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    return QIHT_OK;
+}
+
+qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* support_out,
+                               hipStream_t st) {
+    if (n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    int* err = nullptr;
+    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&err), sizeof(int), st));
+    QIHT_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
+    launch_hard_threshold(select_cpt(n), a, static_cast<int>(n), static_cast<int>(s), support_out,
+                          err, st);
+    QIHT_HIP(hipGetLastError());
+    int herr = 0;
+    QIHT_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+    QIHT_HIP(hipFreeAsync(err, st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    if (herr) return fail(QIHT_ERR_NUMERIC, "NaN in the input of H_s");
+    return QIHT_OK;
+}
+
+}  // namespace qiht

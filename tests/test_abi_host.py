@@ -60,7 +60,7 @@ def test_default_params(lib):
     lib.qiht_default_params(C.byref(p))
     assert (p.max_iters, p.tol, p.k, p.c, p.max_backtracks, p.mu_mode) == \
         (300, 1e-8, 2.0, 0.01, 32, 0)
-    assert p.x0 is None and p.support0 is None
+    assert p.x0 is None and p.support0 is None and p.profile == 0
 
 
 def test_quantize_matrix_validation(lib):
