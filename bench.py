@@ -146,6 +146,12 @@ def main():
     ap.add_argument("--bits", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="only quantize the workload and evaluate the gradient pair 5 times "
+                         "(short run for rocprofv3 counter passes on the full-pass kernel)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 3 times (known bytes, for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -158,6 +164,15 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 << 28, "bytes_written": 4 << 28,
+                          "launches": 3}))
+        return
     log("generating workload ...")
     p = workloads.config2(SEED)
     phi_d = torch.from_numpy(p.phi).to(dev)
@@ -165,6 +180,15 @@ def main():
     torch.cuda.synchronize()
 
     bits = args.bits
+    if args.profile_pass:
+        q = qiht.quantize_matrix(phi_d, bits, 2, SEED)
+        yhat, _, _ = qiht.quantize_vector(y_d, 32 if bits == 32 else 8, SEED)
+        for _ in range(5):
+            qiht.gradient(q, yhat, None, None)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "bits": bits, "launches": 5,
+                          "bytes_per_launch": pass_bytes(M, N, bits)}))
+        return
     log(f"warmup {args.warmup} steps, bits {bits}")
     for _ in range(args.warmup):
         one_step(qiht, phi_d, y_d, bits)

@@ -100,7 +100,8 @@ typedef struct {
     double pass_ms;            /* profile = 1: summed event time of the
                                   g = Q1^T r launches (0 otherwise)          */
     int32_t pass_launches;     /* number of those launches                   */
-    int32_t reserved;
+    int32_t full_selects;      /* H_s proposals that ranked all n entries
+                                  (the rest ranked the histogram candidates) */
 } qiht_info;
 
 /* Fill `p` (host) with the defaults: max_iters 300, tol 1e-8, k 2, c 0.01,

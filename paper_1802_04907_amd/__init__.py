@@ -156,7 +156,8 @@ def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=Non
 def _info_dict(inf):
     return dict(iterations=inf.iterations, reason=_lib.REASONS.get(inf.reason, inf.reason),
                 backtracks=inf.backtracks, capped_iterations=inf.capped_iterations,
-                mu_last=inf.mu_last, pass_ms=inf.pass_ms, pass_launches=inf.pass_launches)
+                mu_last=inf.mu_last, pass_ms=inf.pass_ms, pass_launches=inf.pass_launches,
+                full_selects=inf.full_selects)
 
 
 def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,

@@ -24,7 +24,7 @@ class QihtInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("reason", C.c_int32),
                 ("backtracks", C.c_int32), ("capped_iterations", C.c_int32),
                 ("mu_last", C.c_double), ("pass_ms", C.c_double),
-                ("pass_launches", C.c_int32), ("reserved", C.c_int32)]
+                ("pass_launches", C.c_int32), ("full_selects", C.c_int32)]
 
 
 class QihtProblem(C.Structure):

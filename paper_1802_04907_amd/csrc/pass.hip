@@ -1,5 +1,7 @@
 // The full pass g = Q1^T r of the QIHT iteration: the one launch that reads
 // every packed code of Q1, and the bandwidth-bound kernel of the path.
+#include <hip/hip_ext.h>
+
 #include "solve_common.h"
 
 namespace qiht {
@@ -93,6 +95,14 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     }
     const float bsum = static_cast<float>(pd.beta * wave_sum(sr));
     float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
+    // Histogram of the top 11 bits of |g_j| (exponent and 3 mantissa bits)
+    // for the threshold search of the H_s proposals; built where g is final.
+    const bool hist = pd.nslab == 1;
+    __shared__ uint32_t lh[2048];
+    if (hist) {
+        for (int b = threadIdx.x; b < 2048; b += kPassThreads) lh[b] = 0u;
+        __syncthreads();
+    }
     const uint8_t* base = pd.q1 + static_cast<size_t>(chunk0) * 16;
 
     for (int j = tk.c0 + wv; j < tk.c1; j += 8) {
@@ -120,9 +130,20 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
         const float sa = wave_sum(a0 + a1);
         const float sb = wave_sum(b0 + b1);
         if (lane == 0) {
-            out[j] = (BITS == 32) ? sa : fmaf(pd.alpha_f, sa, bsum);
-            if (has2) out[j2] = (BITS == 32) ? sb : fmaf(pd.alpha_f, sb, bsum);
+            const float ga = (BITS == 32) ? sa : fmaf(pd.alpha_f, sa, bsum);
+            out[j] = ga;
+            if (hist) atomicAdd(&lh[(__float_as_uint(ga) & 0x7FFFFFFFu) >> 20], 1u);
+            if (has2) {
+                const float gb = (BITS == 32) ? sb : fmaf(pd.alpha_f, sb, bsum);
+                out[j2] = gb;
+                if (hist) atomicAdd(&lh[(__float_as_uint(gb) & 0x7FFFFFFFu) >> 20], 1u);
+            }
         }
+    }
+    if (hist) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < 2048; b += kPassThreads)
+            if (lh[b]) atomicAdd(&pd.hist[b], lh[b]);
     }
 }
 
@@ -133,17 +154,24 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__
         float s = 0.f;
         for (int sl = 0; sl < pd.nslab; ++sl) s += pd.gpart[static_cast<size_t>(sl) * pd.n + j];
         pd.g[j] = s;
+        atomicAdd(&pd.hist[(__float_as_uint(s) & 0x7FFFFFFFu) >> 20], 1u);
     }
 }
 
 template <int BITS>
-void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st) {
+void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
+                   hipEvent_t ev0, hipEvent_t ev1) {
     switch (cpl) {
-#define QIHT_PASS_CASE(C)                                                                  \
-    case C:                                                                                \
-        if constexpr (C <= (BITS == 32 ? 16 : BITS))                                       \
-            hipLaunchKernelGGL((k_fullpass<BITS, C>), dim3(ntasks), dim3(kPassThreads), 0, \
-                               st, P, T);                                                  \
+#define QIHT_PASS_CASE(C)                                                                   \
+    case C:                                                                                 \
+        if constexpr (C <= (BITS == 32 ? 16 : BITS)) {                                      \
+            if (ev0)                                                                        \
+                hipExtLaunchKernelGGL((k_fullpass<BITS, C>), dim3(ntasks), dim3(kPassThreads), \
+                                      0, st, ev0, ev1, 0, P, T);                            \
+            else                                                                            \
+                hipLaunchKernelGGL((k_fullpass<BITS, C>), dim3(ntasks), dim3(kPassThreads), \
+                                   0, st, P, T);                                            \
+        }                                                                                   \
         break;
         QIHT_PASS_CASE(1)
         QIHT_PASS_CASE(2)
@@ -157,13 +185,14 @@ void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStre
 
 }  // namespace
 
-void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st) {
+void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1) {
     switch (bits) {
-        case 1: launch_pass_b<1>(cpl, P, T, ntasks, st); break;
-        case 2: launch_pass_b<2>(cpl, P, T, ntasks, st); break;
-        case 4: launch_pass_b<4>(cpl, P, T, ntasks, st); break;
-        case 8: launch_pass_b<8>(cpl, P, T, ntasks, st); break;
-        default: launch_pass_b<32>(cpl, P, T, ntasks, st); break;
+        case 1: launch_pass_b<1>(cpl, P, T, ntasks, st, ev0, ev1); break;
+        case 2: launch_pass_b<2>(cpl, P, T, ntasks, st, ev0, ev1); break;
+        case 4: launch_pass_b<4>(cpl, P, T, ntasks, st, ev0, ev1); break;
+        case 8: launch_pass_b<8>(cpl, P, T, ntasks, st, ev0, ev1); break;
+        default: launch_pass_b<32>(cpl, P, T, ntasks, st, ev0, ev1); break;
     }
 }
 

@@ -53,17 +53,27 @@ __global__ __launch_bounds__(256) void k_absmax(const T* __restrict__ src,
                                                 int64_t ld,
                                                 unsigned long long* out,
                                                 int* bad) {
+    // Rows blockIdx.y, +gridDim.y, ...; within a row, four independent
+    // loads per thread per step.  One atomic per workgroup.
     double mx = 0.0;
     int nonfinite = 0;
     const int64_t row_len = n * NC;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
         const T* row = src + i * ld * NC;
-        for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x +
-                         threadIdx.x;
-             t < row_len; t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-            const double v = static_cast<double>(row[t]);
-            if (!isfinite(v)) nonfinite = 1;
-            mx = fmax(mx, fabs(v));
+        for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+             t0 < row_len; t0 += 4 * step) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t t = t0 + u * step;
+                v[u] = t < row_len ? static_cast<double>(row[t]) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!isfinite(v[u])) nonfinite = 1;
+                mx = fmax(mx, fabs(v[u]));
+            }
         }
     }
     __shared__ double sh[256];
@@ -164,8 +174,9 @@ qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
     d_bad = reinterpret_cast<int*>(d_max + 1);
     QIHT_HIP(hipMemsetAsync(d_max, 0, 16, st));
     const int64_t row_len = n * NC;
-    dim3 grid(static_cast<unsigned>(std::min<int64_t>((row_len + 255) / 256, 64)),
-              static_cast<unsigned>(std::min<int64_t>(m, 2048)));
+    const int64_t gx = std::min<int64_t>((row_len + 1023) / 1024, 16);
+    const int64_t gy = std::min<int64_t>(m, std::max<int64_t>(1, 4096 / gx));
+    dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(gy));
     hipLaunchKernelGGL((k_absmax<T, NC>), grid, dim3(256), 0, st,
                        static_cast<const T*>(src), m, n, ld, d_max, d_bad);
     QIHT_HIP(hipGetLastError());

@@ -1,34 +1,48 @@
-// H_s proposals of the QIHT iteration (Sec. I-A hard threshold, Sec. II-A
-// step-size rule).
+// H_s proposals and the step-size test of the QIHT iteration (Sec. I-A hard
+// threshold; Sec. II-A and Algorithm 2: normalized step, support-change
+// test, shrinking by k(1-c)).
 //
-// One workgroup builds one proposal x' = H_s(x + mu_k g) with
-// mu_k = mu / (k(1-c))^k: an exact radix select of the s-th largest |a|
-// (31-bit keys; digits of 11, 10 and 10 bits counted in LDS histograms),
-// ties at the threshold resolved to the lowest indices, and an
-// order-preserving compaction built from wave ballots, so the support comes
-// out ascending.  Thread t owns indices t, t + 1024, ..., so every global
-// load is coalesced; wave w of round e covers indices [1024e + 64w, +64),
-// which makes (round, wave, lane) index order.
+// k_propose: one workgroup per proposal x'_k = H_s(x + mu_k g) with
+// mu_k = mu / (k(1-c))^k, k = 0 .. kSpec-1 side by side (speculative
+// backtracking).  Each workgroup first finishes mu = |g_G|^2 / (Q1_G g_G).
+// (Q2_G g_G) from the gather partials, in workgroup order.
 //
-// k_propose runs kSpec proposals (k = 0 .. kSpec-1) side by side, one
-// workgroup each; the omega gather then applies the step test to all of
-// them at once (speculative backtracking: the accepted proposal is the one
-// the sequential rule would reach).  k_fallback continues sequentially, in
-// one workgroup, in the rare case that every speculative proposal is
-// rejected.
+// Selection, fast path: off the current support G, a_j = mu g_j, so the
+// order of |a_j| there does not depend on mu.  The full pass counts |g_j| in
+// a 2048-bin histogram of its top 11 bits; with G's entries removed, the bin
+// B of the s-th largest |g_j| off G gives a threshold t = lo(B)(1 - 2^-20).
+// An entry off G with |g_j| < t has FP32 |a_j| strictly below at least s
+// entries off G, for any mu (round-to-nearest moves a product by at most
+// 2^-24 relative), so the top s of G plus {j off G : |g_j| >= t} is the top
+// s of all n.  That candidate set (usually a few thousand entries) is ranked
+// exactly: radix select of the s-th largest |a| (31-bit keys, digits of 11,
+// 10, 10 bits in LDS histograms), ties at the threshold to the lowest
+// indices through an index bitmap, and the support written ascending by an
+// ordered scan of the selection bitmap.  Full path (candidate set too large,
+// or a plain H_s call): the same rank over all n keys held in registers.
+//
+// k_decide: the test mu_k <= (1-c)|x'_k - x|^2 / |Q1 (x'_k - x)|^2 applied in
+// order k = 0, 1, ... (a proposal keeping the support is accepted at once);
+// the first accepted proposal is committed.  If all kSpec proposals fail,
+// the same workgroup continues one shrink at a time.
 #include "solve_common.h"
 
 namespace qiht {
 namespace {
 
+constexpr int kBmWords = kMaxSelectN / 32;
+
 struct SelShared {
     uint32_t hist[2048];
-    uint32_t cnt[kSelectThreads];   // per (round, wave) counts, then bases
-    uint32_t bm_old[kMaxSelectN / 32];
-    uint32_t bm_new[kMaxSelectN / 32];
+    uint32_t cnt[kSelectThreads];
+    uint32_t bm_old[kBmWords];   // current support
+    uint32_t bm_new[kBmWords];   // selected set
+    uint32_t bm_tie[kBmWords];   // candidates equal to the threshold key
+    uint32_t ckey[kCandCap];
+    int32_t cidx[kCandCap];
     uint32_t scan[16];
-    uint32_t bin, krem;
-    int changed;
+    uint32_t bin, krem, ncand;
+    int changed, overflow;
     double red[16];
 };
 
@@ -39,18 +53,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Exclusive scan of S.cnt[0 .. CPT*16) in place (index order).
-template <int CPT>
-__device__ void scan_round_wave_counts(SelShared& S) {
-    constexpr int NC = CPT * 16;
-    uint32_t v = threadIdx.x < NC ? S.cnt[threadIdx.x] : 0u;
-    const uint32_t before = block_excl_scan<kSelectThreads>(v, S.scan, nullptr);
-    if (threadIdx.x < NC) S.cnt[threadIdx.x] = before;
-    __syncthreads();
-}
-
-// The value whose magnitude is ranked: a_j = x_j + mu g_j (FP32, fused), or
-// g_j (initial support), or an input vector.
 template <int MODE>
 __device__ __forceinline__ float value_at(const float* a_in, const float* g, const float* x,
                                           float muf, int j) {
@@ -59,15 +61,70 @@ __device__ __forceinline__ float value_at(const float* a_in, const float* g, con
     return fmaf(muf, g[j], x[j]);
 }
 
-// Builds one proposal.  Outputs: out_sup (ascending, s entries), and for
-// SEL_STEP out_val (values on out_sup), the changed flag against old_sup,
-// the difference list (union of old and new supports, ascending, with
-// FP64 differences) and |x' - x|^2, |x'|^2 into *meta (written by thread 0).
+// One radix digit step: bins of `hist` (nb bins, counts already in place)
+// scanned from the top; finds the bin holding the krem-th largest key.
+__device__ void find_bin(SelShared& S, int nb, uint32_t& prefix, uint32_t& krem, int width) {
+    const int tid = threadIdx.x;
+    const int PB = nb / kSelectThreads;  // 1 or 2
+    const uint32_t c0 = S.hist[nb - 1 - tid * PB];
+    const uint32_t c1 = PB > 1 ? S.hist[nb - 2 - tid * PB] : 0u;
+    const uint32_t above = block_excl_scan<kSelectThreads>(c0 + c1, S.scan, nullptr);
+    if (krem > 0) {
+        if (above < krem && krem <= above + c0) {
+            S.bin = static_cast<uint32_t>(nb - 1 - tid * PB);
+            S.krem = krem - above;
+        } else if (PB > 1 && above + c0 < krem && krem <= above + c0 + c1) {
+            S.bin = static_cast<uint32_t>(nb - 2 - tid * PB);
+            S.krem = krem - above - c0;
+        }
+    }
+    __syncthreads();
+    if (krem > 0) {
+        prefix = (prefix << width) | S.bin;
+        krem = S.krem;
+    }
+    __syncthreads();
+}
+
+// Writes the support (ascending) from the selection bitmap, the values on
+// it, and compares with the old support.  Returns through S.changed.
+template <int MODE>
+__device__ void emit_support(int n, int s, const float* a_in, const float* g, const float* x,
+                             float muf, const int32_t* old_sup, int32_t* out_sup, float* out_val,
+                             SelShared& S) {
+    const int tid = threadIdx.x;
+    const int words = (n + 31) / 32;
+    const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
+    const int w0 = tid * wpt;
+    uint32_t c = 0;
+    for (int w = w0; w < min(words, w0 + wpt); ++w) c += __popc(S.bm_new[w]);
+    uint32_t pos = block_excl_scan<kSelectThreads>(c, S.scan, nullptr);
+    int changed = 0;
+    for (int w = w0; w < min(words, w0 + wpt); ++w) {
+        uint32_t u = S.bm_new[w];
+        while (u) {
+            const int b = __ffs(u) - 1;
+            u &= u - 1;
+            const int j = w * 32 + b;
+            if (pos < static_cast<uint32_t>(s)) {
+                out_sup[pos] = j;
+                if (MODE == SEL_STEP) {
+                    out_val[pos] = value_at<MODE>(a_in, g, x, muf, j);
+                    if (old_sup[pos] != j) changed = 1;
+                }
+            }
+            ++pos;
+        }
+    }
+    if (changed) S.changed = 1;
+    __syncthreads();
+}
+
+// Rank over keys held in registers (thread t owns t, t + 1024, ...): the
+// full path.  Sets the selection bitmap S.bm_new.
 template <int CPT, int MODE>
-__device__ void propose_core(int n, int s, const float* a_in, const float* g, const float* x,
-                             float muf, const int32_t* old_sup, int32_t* out_sup,
-                             float* out_val, int32_t* dlist, double* dw, CandMeta* meta,
-                             int k, double mu, SelShared& S, int* err) {
+__device__ void select_full(int n, int s, const float* a_in, const float* g, const float* x,
+                            float muf, SelShared& S, int* err) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     uint32_t key[CPT];
@@ -82,8 +139,6 @@ __device__ void propose_core(int n, int s, const float* a_in, const float* g, co
         }
     }
     if (bad) atomicOr(err, 1);
-
-    // ---- radix select of the s-th largest key ----
     uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
 #pragma unroll
     for (int pass = 0; pass < 3; ++pass) {
@@ -102,30 +157,11 @@ __device__ void propose_core(int n, int s, const float* a_in, const float* g, co
             }
         }
         __syncthreads();
-        const int PB = nb / kSelectThreads;  // bins per thread, descending
-        uint32_t c0 = S.hist[nb - 1 - tid * PB];
-        uint32_t c1 = PB > 1 ? S.hist[nb - 2 - tid * PB] : 0u;
-        const uint32_t above = block_excl_scan<kSelectThreads>(c0 + c1, S.scan, nullptr);
-        if (krem > 0) {
-            if (above < krem && krem <= above + c0) {
-                S.bin = static_cast<uint32_t>(nb - 1 - tid * PB);
-                S.krem = krem - above;
-            } else if (PB > 1 && above + c0 < krem && krem <= above + c0 + c1) {
-                S.bin = static_cast<uint32_t>(nb - 2 - tid * PB);
-                S.krem = krem - above - c0;
-            }
-        }
-        __syncthreads();
-        if (krem > 0) {
-            prefix = (prefix << width) | S.bin;
-            krem = S.krem;
-        }
-        __syncthreads();
+        find_bin(S, nb, prefix, krem, width);
     }
-    const uint32_t T = prefix;   // the s-th largest key (s > 0)
-    const uint32_t need = krem;  // keys equal to T that are taken
-
-    // ---- ranks of the ties at T, in index order ----
+    const uint32_t T = prefix;
+    const uint32_t need = krem;
+    // ties at T ranked in index order: (round, wave, lane) is index order
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
         const int j = tid + kSelectThreads * e;
@@ -133,64 +169,183 @@ __device__ void propose_core(int n, int s, const float* a_in, const float* g, co
         if (lane == 0) S.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
     }
     __syncthreads();
-    scan_round_wave_counts<CPT>(S);
-    uint64_t take = 0;
+    {
+        constexpr int NC = CPT * 16;
+        const uint32_t v = tid < NC ? S.cnt[tid] : 0u;
+        const uint32_t before = block_excl_scan<kSelectThreads>(v, S.scan, nullptr);
+        if (tid < NC) S.cnt[tid] = before;
+        __syncthreads();
+    }
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
         const int j = tid + kSelectThreads * e;
         const bool tie = s > 0 && j < n && key[e] == T;
         const uint64_t b = __ballot(tie);
         const uint32_t rank = S.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
-        const bool sel = s > 0 && j < n && (key[e] > T || (tie && rank < need));
-        take |= static_cast<uint64_t>(sel) << e;
+        if (s > 0 && j < n && (key[e] > T || (tie && rank < need)))
+            atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
-    // ---- output positions of the selected indices ----
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const uint64_t b = __ballot((take >> e) & 1ull);
-        if (lane == 0) S.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
-    }
-    if (tid == 0) S.changed = 0;
-    if (MODE == SEL_STEP) {
-        for (int w = tid; w < (n + 31) / 32; w += kSelectThreads) {
-            S.bm_old[w] = 0u;
-            S.bm_new[w] = 0u;
+}
+
+// Fast path over the support and the histogram candidates; returns false
+// (and selects nothing) when the candidate set does not fit in LDS.
+// Appends (key, index) to the LDS candidate list; one LDS atomic per wave.
+__device__ __forceinline__ void push_candidate(bool pred, uint32_t key, int j, SelShared& S) {
+    const uint64_t b = __ballot(pred);
+    if (b == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(static_cast<long long>(b)) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&S.ncand, static_cast<uint32_t>(__popcll(b)));
+    base = __shfl(base, leader, 64);
+    if (pred) {
+        const uint32_t c = base + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
+        if (c < static_cast<uint32_t>(kCandCap)) {
+            S.ckey[c] = key;
+            S.cidx[c] = j;
         }
     }
-    __syncthreads();
-    scan_round_wave_counts<CPT>(S);
-    int changed = 0;
+}
+
+template <int CPT, int MODE>
+__device__ bool select_fast(int n, int s, const float* g, const float* x, float muf,
+                            const int32_t* old_sup, int nsup, const uint32_t* ghist,
+                            SelShared& S, int* err) {
+    const int tid = threadIdx.x;
+    // every |g_j| this thread owns, loaded up front (independent loads)
+    float gv[CPT];
 #pragma unroll
     for (int e = 0; e < CPT; ++e) {
         const int j = tid + kSelectThreads * e;
-        const bool sel = (take >> e) & 1ull;
-        const uint64_t b = __ballot(sel);
-        if (sel) {
-            const uint32_t pos = S.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
-            if (pos < static_cast<uint32_t>(s)) {
-                out_sup[pos] = j;
-                if (MODE == SEL_STEP) {
-                    out_val[pos] = value_at<MODE>(a_in, g, x, muf, j);
-                    if (old_sup[pos] != j) changed = 1;
-                    atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
-                }
+        gv[e] = j < n ? g[j] : 0.0f;
+    }
+    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = ghist[b];
+    if (tid == 0) {
+        S.ncand = 0;
+        S.overflow = 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < nsup; i += kSelectThreads)
+        atomicSub(&S.hist[abs_key(g[old_sup[i]]) >> 20], 1u);
+    __syncthreads();
+    // bin of the s-th largest |g| off the support
+    const int off_count = n - nsup;
+    float thr = 0.0f;
+    if (off_count > s) {
+        uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
+        find_bin(S, 2048, prefix, krem, 11);
+        thr = __uint_as_float(prefix << 20) * (1.0f - 0x1p-20f);
+        if (!(thr >= 0x1p-100f)) return false;  // keep clear of subnormal products
+    }
+    // collect candidates: the support, and off-support entries above thr
+    int bad = 0;
+    for (int i0 = 0; i0 < nsup; i0 += kSelectThreads) {
+        const int i = i0 + tid;
+        const bool in = i < nsup;
+        const int j = in ? old_sup[i] : 0;
+        const uint32_t k = in ? abs_key(value_at<MODE>(nullptr, g, x, muf, j)) : 0u;
+        if (k > 0x7F800000u) bad = 1;
+        push_candidate(in, k, j, S);
+    }
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int j = tid + kSelectThreads * e;
+        const bool in = j < n && fabsf(gv[e]) >= thr && !((S.bm_old[j >> 5] >> (j & 31)) & 1u);
+        // off the support x_j = 0, so a_j = fma(mu, g_j, 0)
+        const uint32_t k = in ? abs_key((MODE == SEL_STEP) ? fmaf(muf, gv[e], 0.0f) : gv[e]) : 0u;
+        if (k > 0x7F800000u) bad = 1;
+        push_candidate(in, k, j, S);
+    }
+    if (bad) atomicOr(err, 1);
+    __syncthreads();
+    const uint32_t nc = S.ncand;
+    if (nc > static_cast<uint32_t>(kCandCap)) return false;
+    // exact rank among the candidates
+    uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
+#pragma unroll
+    for (int pass = 0; pass < 3; ++pass) {
+        const int width = pass == 0 ? 11 : 10;
+        const int sh = pass == 0 ? 20 : (pass == 1 ? 10 : 0);
+        const int nb = 1 << width;
+        const int hsh = sh + width;
+        for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
+        __syncthreads();
+        if (krem > 0) {
+            for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+                const uint32_t k = S.ckey[c];
+                if (pass == 0 || (k >> hsh) == prefix) atomicAdd(&S.hist[(k >> sh) & (nb - 1)], 1u);
             }
         }
-    }
-    if (MODE != SEL_STEP) {
         __syncthreads();
-        return;
+        find_bin(S, nb, prefix, krem, width);
     }
-    if (changed) S.changed = 1;
-    for (int i = tid; i < s; i += kSelectThreads) {
-        const int j = old_sup[i];
+    const uint32_t T = prefix;
+    const uint32_t need = krem;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.ckey[c];
+        const int j = S.cidx[c];
+        if (s > 0 && k > T) atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
+        else if (s > 0 && k == T) atomicOr(&S.bm_tie[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+    // the `need` lowest-index ties
+    const int words = (n + 31) / 32;
+    const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
+    const int w0 = tid * wpt;
+    uint32_t cnt = 0;
+    for (int w = w0; w < min(words, w0 + wpt); ++w) cnt += __popc(S.bm_tie[w]);
+    uint32_t rank = block_excl_scan<kSelectThreads>(cnt, S.scan, nullptr);
+    for (int w = w0; w < min(words, w0 + wpt); ++w) {
+        uint32_t u = S.bm_tie[w];
+        while (u) {
+            const int b = __ffs(u) - 1;
+            u &= u - 1;
+            if (rank < need) S.bm_new[w] |= 1u << b;
+            ++rank;
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// One complete proposal into `slot` (SEL_STEP) or the initial support
+// (SEL_INIT, written to pd.sup).  Thread 0 writes the slot's CandMeta.
+template <int CPT, int MODE>
+__device__ void propose(const ProbDev& pd, int slot, int k, double mu, SelShared& S) {
+    const int tid = threadIdx.x;
+    const int n = pd.n, s = pd.s;
+    const int words = (n + 31) / 32;
+    const float muf = static_cast<float>(mu);
+    const int nsup = (MODE == SEL_STEP) ? s : 0;
+    for (int w = tid; w < words; w += kSelectThreads) {
+        S.bm_old[w] = 0u;
+        S.bm_new[w] = 0u;
+        S.bm_tie[w] = 0u;
+    }
+    if (tid == 0) S.changed = 0;
+    __syncthreads();
+    for (int i = tid; i < nsup; i += kSelectThreads) {
+        const int j = pd.sup[i];
         atomicOr(&S.bm_old[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
-
-    // ---- difference list over old and new supports, |dx|^2, |x'|^2 ----
-    const int words = (n + 31) / 32;
+    if (!select_fast<CPT, MODE>(n, s, pd.g, pd.x, muf, pd.sup, nsup, pd.hist, S, &pd.st->err)) {
+        if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
+        for (int w = tid; w < words; w += kSelectThreads) S.bm_new[w] = 0u;
+        __syncthreads();
+        select_full<CPT, MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
+    }
+    if (MODE == SEL_INIT) {
+        emit_support<MODE>(n, s, nullptr, pd.g, nullptr, muf, nullptr, pd.sup, nullptr, S);
+        return;
+    }
+    int32_t* out_sup = pd.csup + static_cast<size_t>(slot) * s;
+    float* out_val = pd.cval + static_cast<size_t>(slot) * s;
+    int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
+    double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
+    emit_support<MODE>(n, s, nullptr, pd.g, pd.x, muf, pd.sup, out_sup, out_val, S);
+    // difference list over the union of old and new supports, ascending
     const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
     const int w0 = tid * wpt;
     uint32_t cnt = 0;
@@ -205,8 +360,8 @@ __device__ void propose_core(int n, int s, const float* a_in, const float* g, co
             const int b = __ffs(u) - 1;
             u &= u - 1;
             const int j = w * 32 + b;
-            const float xo = x[j];
-            const float xn = ((nw >> b) & 1u) ? value_at<MODE>(a_in, g, x, muf, j) : 0.0f;
+            const float xo = pd.x[j];
+            const float xn = ((nw >> b) & 1u) ? value_at<MODE>(nullptr, pd.g, pd.x, muf, j) : 0.0f;
             const double d = static_cast<double>(xn) - static_cast<double>(xo);
             dlist[pos] = j;
             dw[pos] = d;
@@ -227,19 +382,31 @@ __device__ void propose_core(int n, int s, const float* a_in, const float* g, co
         m.dx2 = dx2;
         m.xn2 = xn2;
         m.omega = 0.0;
-        *meta = m;
+        pd.meta[slot] = m;
     }
     __syncthreads();
 }
 
-template <int CPT>
-__device__ void propose_slot(const ProbDev& pd, int slot, int k, double mu, SelShared& S) {
-    propose_core<CPT, SEL_STEP>(pd.n, pd.s, nullptr, pd.g, pd.x, static_cast<float>(mu), pd.sup,
-                                pd.csup + static_cast<size_t>(slot) * pd.s,
-                                pd.cval + static_cast<size_t>(slot) * pd.s,
-                                pd.dlist + static_cast<size_t>(slot) * 2 * pd.s,
-                                pd.dw + static_cast<size_t>(slot) * 2 * pd.s, &pd.meta[slot], k,
-                                mu, S, &pd.st->err);
+// mu = |g_G|^2 / ((Q1_G g_G).(Q2_G g_G)) from the gather partials (fixed
+// order); falls back to |Q1_G g_G|^2 when the cross term is not positive.
+// Returns a negative value when the iteration is stationary.
+__device__ double step_from_partials(const ProbDev& pd, SelShared& S) {
+    double gg = 0.0, uv = 0.0, uu = 0.0;
+    for (int i = threadIdx.x; i < pd.s; i += kSelectThreads) {
+        const double v = static_cast<double>(pd.g[pd.sup[i]]);
+        gg += v * v;
+    }
+    for (int b = threadIdx.x; b < pd.nwg; b += kSelectThreads) {
+        uv += pd.part_mu[2 * b + 0];
+        uu += pd.part_mu[2 * b + 1];
+    }
+    const double num = block_sum<kSelectThreads>(gg, S.red);
+    uv = block_sum<kSelectThreads>(uv, S.red);
+    uu = block_sum<kSelectThreads>(uu, S.red);
+    double den = uv;
+    if (!(den > 0.0) || !isfinite(den)) den = uu;
+    if (!(num > 0.0) || !(den > 0.0) || !isfinite(num / den)) return -1.0;
+    return num / den;
 }
 
 template <int CPT>
@@ -250,13 +417,20 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     __shared__ SelShared S;
     if (st->done) return;
     if (mode == SEL_INIT) {
-        propose_core<CPT, SEL_INIT>(pd.n, pd.s, nullptr, pd.g, nullptr, 1.0f, nullptr, pd.sup,
-                                    nullptr, nullptr, nullptr, nullptr, 0, 1.0, S, &st->err);
+        propose<CPT, SEL_INIT>(pd, 0, 0, 1.0, S);
         return;
     }
+    const double mu0 = step_from_partials(pd, S);
+    if (mu0 < 0.0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->done = 1;
+            st->reason = QIHT_REASON_STATIONARY;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->mu = mu0;
     const int k = blockIdx.x;  // shrink count of this proposal
-    const double mu = shrunk_mu(st->mu, a.k * (1.0 - a.c), k);
-    propose_slot<CPT>(pd, k, k, mu, S);
+    propose<CPT, SEL_STEP>(pd, k, k, shrunk_mu(mu0, a.k * (1.0 - a.c), k), S);
 }
 
 // |Q1 dx|^2 of slot 0's difference list, by one workgroup.
@@ -294,42 +468,70 @@ __device__ double omega_den_block(const ProbDev& pd, int dcount, double* red) {
     return block_sum<kSelectThreads>(tot, red);
 }
 
-// Sequential continuation of the step test from shrink count base_k, one
-// workgroup per problem (only when all kSpec speculative proposals failed).
 template <int BITS, int CPT>
-__global__ __launch_bounds__(kSelectThreads) void k_fallback(const ProbDev* __restrict__ P,
-                                                             SolveArgs a) {
+__global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __restrict__ P,
+                                                           SolveArgs a) {
     const ProbDev& pd = P[blockIdx.x];
     SolveState* st = pd.st;
     __shared__ SelShared S;
-    if (st->done || st->phase != 2) return;
-    const double shrink = a.k * (1.0 - a.c);
-    for (int k = st->base_k;; ++k) {
-        const double mu = shrunk_mu(st->mu, shrink, k);
-        propose_slot<CPT>(pd, 0, k, mu, S);
-        const CandMeta m = pd.meta[0];
-        bool accept = !m.changed;
-        bool capped = false;
-        if (!accept) {
-            const double den = omega_den_block<BITS>(pd, m.dcount, S.red);
-            const double omega = den > 0.0 ? m.dx2 / den : INFINITY;
-            accept = mu <= (1.0 - a.c) * omega;
-            if (!accept && k >= a.max_backtracks) capped = accept = true;
+    if (st->done) return;
+    int pick = -1;
+    bool capped = false;
+    for (int t = 0; t < kSpec; ++t) {
+        const CandMeta m = pd.meta[t];
+        if (!m.changed) {
+            pick = t;
+            break;
         }
-        if (accept) {
-            commit_proposal<kSelectThreads>(pd, 0, a, capped);
-            return;
+        double den = 0.0;
+        for (int b = threadIdx.x; b < pd.nwg; b += kSelectThreads)
+            den += pd.part_om[static_cast<size_t>(t) * pd.nwg + b];
+        den = block_sum<kSelectThreads>(den, S.red);
+        const double omega = den > 0.0 ? m.dx2 / den : INFINITY;
+        if (m.mu <= (1.0 - a.c) * omega) {
+            pick = t;
+            break;
         }
-        __syncthreads();
+        if (m.k >= a.max_backtracks) {
+            pick = t;
+            capped = true;
+            break;
+        }
     }
+    if (pick < 0) {
+        // every speculative proposal failed: continue one shrink at a time
+        const double shrink = a.k * (1.0 - a.c);
+        for (int k = kSpec;; ++k) {
+            const double mu = shrunk_mu(st->mu, shrink, k);
+            propose<CPT, SEL_STEP>(pd, 0, k, mu, S);
+            const CandMeta m = pd.meta[0];
+            bool accept = !m.changed;
+            if (!accept) {
+                const double den = omega_den_block<BITS>(pd, m.dcount, S.red);
+                const double omega = den > 0.0 ? m.dx2 / den : INFINITY;
+                accept = mu <= (1.0 - a.c) * omega;
+                if (!accept && k >= a.max_backtracks) capped = accept = true;
+            }
+            if (accept) {
+                pick = 0;
+                break;
+            }
+            __syncthreads();
+        }
+    }
+    commit_proposal<kSelectThreads>(pd, pick, a, capped);
+    for (int b = threadIdx.x; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
 }
 
 template <int CPT>
 __global__ __launch_bounds__(kSelectThreads) void k_hard_threshold(const float* a, int n, int s,
                                                                    int32_t* out, int* err) {
     __shared__ SelShared S;
-    propose_core<CPT, SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, nullptr, out, nullptr, nullptr,
-                               nullptr, nullptr, 0, 0.0, S, err);
+    for (int w = threadIdx.x; w < (n + 31) / 32; w += kSelectThreads) S.bm_new[w] = 0u;
+    if (threadIdx.x == 0) S.changed = 0;
+    __syncthreads();
+    select_full<CPT, SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, S, err);
+    emit_support<SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, nullptr, out, nullptr, S);
 }
 
 }  // namespace
@@ -358,24 +560,24 @@ void launch_propose(int cpt, const ProbDev* P, int count, const SolveArgs& a, in
 }
 
 template <int BITS>
-void launch_fallback_b(int cpt, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
-#define QIHT_FALLBACK(C)                                                                        \
-    case C:                                                                                     \
-        hipLaunchKernelGGL((k_fallback<BITS, C>), dim3(count), dim3(kSelectThreads), 0, st, P, \
-                           a);                                                                  \
+void launch_decide_b(int cpt, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
+#define QIHT_DECIDE(C)                                                                        \
+    case C:                                                                                   \
+        hipLaunchKernelGGL((k_decide<BITS, C>), dim3(count), dim3(kSelectThreads), 0, st, P, \
+                           a);                                                                \
         break;
-    QIHT_CPT_SWITCH(cpt, QIHT_FALLBACK)
-#undef QIHT_FALLBACK
+    QIHT_CPT_SWITCH(cpt, QIHT_DECIDE)
+#undef QIHT_DECIDE
 }
 
-void launch_fallback(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
-                     hipStream_t st) {
+void launch_decide(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
+                   hipStream_t st) {
     switch (bits) {
-        case 1: launch_fallback_b<1>(cpt, P, count, a, st); break;
-        case 2: launch_fallback_b<2>(cpt, P, count, a, st); break;
-        case 4: launch_fallback_b<4>(cpt, P, count, a, st); break;
-        case 8: launch_fallback_b<8>(cpt, P, count, a, st); break;
-        default: launch_fallback_b<32>(cpt, P, count, a, st); break;
+        case 1: launch_decide_b<1>(cpt, P, count, a, st); break;
+        case 2: launch_decide_b<2>(cpt, P, count, a, st); break;
+        case 4: launch_decide_b<4>(cpt, P, count, a, st); break;
+        case 8: launch_decide_b<8>(cpt, P, count, a, st); break;
+        default: launch_decide_b<32>(cpt, P, count, a, st); break;
     }
 }
 

@@ -14,7 +14,7 @@ constexpr int kGatherThreads = 256;   // column gathers
 constexpr int kPassThreads = 256;     // full pass
 constexpr int kSpec = 4;              // step sizes proposed at once
 constexpr int kMaxSelectN = kSelectThreads * 64;
-constexpr int kGatherCpg = 64;        // listed columns per gather workgroup
+constexpr int kCandCap = 4096;        // candidate keys a fast proposal holds in LDS
 
 // Per-problem control state (device memory).
 struct SolveState {
@@ -26,6 +26,8 @@ struct SolveState {
     int32_t capped;
     int32_t err;        // NaN met in a selection
     int32_t base_k;     // first shrink index still to be examined
+    int32_t full_selects;  // proposals that needed the full n-key rank
+    int32_t pad;
     double mu;          // step of this iteration before any shrink
     double mu_last;     // accepted step of the last iteration
 };
@@ -49,9 +51,9 @@ struct ProbDev {
     int32_t rows;
     int32_t n;
     int32_t s;
-    int32_t nrb;        // 256-byte row blocks per column
+    int32_t nwg;        // 16-byte row groups per column (gather workgroups)
     int32_t nslab;      // full-pass row slabs
-    int32_t gmax;       // column groups reserved per gather set
+    int32_t pad;
     double alpha;       // dequantized value = alpha * code + beta
     double beta;
     float alpha_f;
@@ -60,19 +62,16 @@ struct ProbDev {
     float* r32;         // residual, rows_pad (zero beyond rows)
     float* g;           // gradient, n
     float* gpart;       // nslab * n slab partials (nslab > 1)
-    float* x;           // current iterate, dense n
+    uint32_t* hist;     // 2048-bin histogram of the top 11 bits of |g|
+    float* x;           // current iterate, dense n (zero off the support)
     int32_t* sup;       // current support, s ascending
     int32_t* csup;      // kSpec * s proposal supports
     float* cval;        // kSpec * s proposal values on their supports
     int32_t* dlist;     // kSpec * 2s indices where a proposal differs from x
     double* dw;         // kSpec * 2s the differences
     CandMeta* meta;     // kSpec
-    double* part1;      // gather partials [set][group][row] (x2 for two matrices)
-    double* wsum1;      // [set][group]
-    double* part2;      // [set][row block] (x2)
-    unsigned* cnt1;     // [set][row block] arrivals of column groups
-    unsigned* cnt2;     // [set] arrivals of row blocks
-    unsigned* cnt3;     // arrivals of sets
+    double* part_mu;    // 2 * nwg partial (Q1_G g_G).(Q2_G g_G), |Q1_G g_G|^2
+    double* part_om;    // kSpec * nwg partial |Q1 (x'_t - x)|^2
     SolveState* st;
 };
 
@@ -150,15 +149,17 @@ __device__ __forceinline__ uint32_t code_at(uint32_t w, int q) {
 }
 
 // Launchers (defined in the kernel files).
-void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxrb, int gmax,
+void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, hipStream_t st);
+// ev0/ev1 (optional): events recorded by the dispatch itself around the
+// kernel (timing of the bandwidth-bound pass).
 void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,
-                 hipStream_t st);
+                 hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
 void launch_propose(int cpt, const ProbDev* P, int count, const SolveArgs& a, int mode,
                     hipStream_t st);
-void launch_fallback(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
-                     hipStream_t st);
+void launch_decide(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
+                   hipStream_t st);
 void launch_hard_threshold(int cpt, const float* a, int n, int s, int32_t* out, int* err,
                            hipStream_t st);
 
@@ -194,25 +195,6 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
         }
     }
     __syncthreads();
-}
-
-// The acceptance rule of the step-size test applied to proposals
-// base .. base + kSpec - 1 (meta[t] holds shrink count base + t).  Returns
-// the slot to accept, or -1 if every examined proposal is rejected and more
-// shrinks remain; *capped tells that the accepted slot hit max_backtracks.
-__device__ __forceinline__ int choose_proposal(const ProbDev& pd, const SolveArgs& a,
-                                               bool* capped) {
-    *capped = false;
-    for (int t = 0; t < kSpec; ++t) {
-        const CandMeta& m = pd.meta[t];
-        if (!m.changed) return t;
-        if (m.mu <= (1.0 - a.c) * m.omega) return t;
-        if (m.k >= a.max_backtracks) {
-            *capped = true;
-            return t;
-        }
-    }
-    return -1;
 }
 
 }  // namespace qiht

@@ -16,7 +16,7 @@ namespace {
 constexpr int kChunk = 16;  // iterations enqueued between stop-flag reads
 
 struct InfoDev {
-    int32_t iterations, reason, backtracks, capped, err, pad;
+    int32_t iterations, reason, backtracks, capped, err, full_selects;
     double mu_last;
 };
 
@@ -41,7 +41,7 @@ __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
         inf.backtracks = st->total_bt;
         inf.capped = st->capped;
         inf.err = st->err;
-        inf.pad = 0;
+        inf.full_selects = st->full_selects;
         inf.mu_last = st->mu_last;
         infos[blockIdx.y] = inf;
     }
@@ -75,15 +75,14 @@ struct Carver {
 };
 
 struct Layout {
-    size_t r32, g, gpart, x, sup, csup, cval, dlist, dw, meta, part1, wsum1, part2, cnt1, cnt2,
-        cnt3, st;
+    size_t r32, g, gpart, hist, x, sup, csup, cval, dlist, dw, meta, part_mu, part_om, st;
 };
 
 struct Plan {
     std::vector<ProbDev> host;
     std::vector<Layout> lay;
     std::vector<Task> tasks;
-    int bits = 0, cpl = 1, cpt = 1, maxrb = 1, maxg = 1;
+    int bits = 0, cpl = 1, cpt = 1, maxwg = 1;
     bool any_slab = false;
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0;
@@ -108,15 +107,14 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         const int64_t s = in[i].s;
         const int64_t chunks = q->col_bytes / 16;
         const int nslab = static_cast<int>((chunks + slab_chunks - 1) / slab_chunks);
-        const int nrb = static_cast<int>(q->col_bytes / 256);
-        const int gmax = static_cast<int>((2 * s + kGatherCpg - 1) / kGatherCpg);
-        pl.maxrb = std::max(pl.maxrb, nrb);
-        pl.maxg = std::max(pl.maxg, gmax);
+        const int nwg = static_cast<int>(q->col_bytes / 16);
+        pl.maxwg = std::max(pl.maxwg, nwg);
         pl.any_slab = pl.any_slab || nslab > 1;
         Layout& L = pl.lay[i];
         L.r32 = cv.take<float>(q->rows_pad);
         L.g = cv.take<float>(q->n);
         L.gpart = cv.take<float>(nslab > 1 ? static_cast<size_t>(nslab) * q->n : 1);
+        L.hist = cv.take<uint32_t>(2048);
         L.x = cv.take<float>(q->n);
         L.sup = cv.take<int32_t>(s);
         L.csup = cv.take<int32_t>(kSpec * s);
@@ -124,12 +122,8 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         L.dlist = cv.take<int32_t>(kSpec * 2 * s);
         L.dw = cv.take<double>(kSpec * 2 * s);
         L.meta = cv.take<CandMeta>(kSpec);
-        L.part1 = cv.take<double>(static_cast<size_t>(kSpec) * gmax * q->rows_pad);
-        L.wsum1 = cv.take<double>(static_cast<size_t>(kSpec) * gmax);
-        L.part2 = cv.take<double>(static_cast<size_t>(kSpec) * nrb * 2);
-        L.cnt1 = cv.take<unsigned>(static_cast<size_t>(kSpec) * nrb);
-        L.cnt2 = cv.take<unsigned>(kSpec);
-        L.cnt3 = cv.take<unsigned>(1);
+        L.part_mu = cv.take<double>(2 * static_cast<size_t>(nwg));
+        L.part_om = cv.take<double>(static_cast<size_t>(kSpec) * nwg);
         L.st = cv.take<SolveState>(1);
         ProbDev& p = pl.host[i];
         std::memset(&p, 0, sizeof(p));
@@ -139,9 +133,8 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.rows = static_cast<int32_t>(q->rows);
         p.n = static_cast<int32_t>(q->n);
         p.s = static_cast<int32_t>(s);
-        p.nrb = nrb;
+        p.nwg = nwg;
         p.nslab = nslab;
-        p.gmax = gmax;
         p.alpha = q->alpha;
         p.beta = q->beta;
         p.alpha_f = static_cast<float>(q->alpha);
@@ -173,6 +166,7 @@ void bind(Plan& pl, uint8_t* base) {
         p.r32 = reinterpret_cast<float*>(base + L.r32);
         p.g = reinterpret_cast<float*>(base + L.g);
         p.gpart = reinterpret_cast<float*>(base + L.gpart);
+        p.hist = reinterpret_cast<uint32_t*>(base + L.hist);
         p.x = reinterpret_cast<float*>(base + L.x);
         p.sup = reinterpret_cast<int32_t*>(base + L.sup);
         p.csup = reinterpret_cast<int32_t*>(base + L.csup);
@@ -180,29 +174,33 @@ void bind(Plan& pl, uint8_t* base) {
         p.dlist = reinterpret_cast<int32_t*>(base + L.dlist);
         p.dw = reinterpret_cast<double*>(base + L.dw);
         p.meta = reinterpret_cast<CandMeta*>(base + L.meta);
-        p.part1 = reinterpret_cast<double*>(base + L.part1);
-        p.wsum1 = reinterpret_cast<double*>(base + L.wsum1);
-        p.part2 = reinterpret_cast<double*>(base + L.part2);
-        p.cnt1 = reinterpret_cast<unsigned*>(base + L.cnt1);
-        p.cnt2 = reinterpret_cast<unsigned*>(base + L.cnt2);
-        p.cnt3 = reinterpret_cast<unsigned*>(base + L.cnt3);
+        p.part_mu = reinterpret_cast<double*>(base + L.part_mu);
+        p.part_om = reinterpret_cast<double*>(base + L.part_om);
         p.st = reinterpret_cast<SolveState*>(base + L.st);
     }
 }
 
-// HIP events around every full-pass launch (profile mode).
+// Events recorded by every full-pass dispatch (profile mode): the start and
+// end of the kernel itself, on its launch stream.
 struct PassTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;
     ~PassTimer() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
-    void mark(hipStream_t st) {
-        if (!on) return;
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        ev.push_back(e);
-        (void)hipEventRecord(e, st);
+    // Returns false (no events) when profiling is off or creation fails.
+    bool pair(hipEvent_t* a, hipEvent_t* b) {
+        *a = *b = nullptr;
+        if (!on) return false;
+        if (hipEventCreate(a) != hipSuccess) return false;
+        if (hipEventCreate(b) != hipSuccess) {
+            (void)hipEventDestroy(*a);
+            *a = nullptr;
+            return false;
+        }
+        ev.push_back(*a);
+        ev.push_back(*b);
+        return true;
     }
     double total_ms() const {
         double t = 0.0;
@@ -225,20 +223,20 @@ struct Workspace {
 
 void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                        const SolveArgs& a, int zero_x, hipStream_t st, PassTimer* tm) {
-    launch_gather(G_R, pl.bits, dP, count, pl.maxrb, pl.maxg, a, zero_x, st);
-    if (tm) tm->mark(st);
-    launch_pass(pl.bits, pl.cpl, dP, dT, static_cast<int>(pl.tasks.size()), st);
-    if (tm) tm->mark(st);
+    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, st);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) tm->pair(&e0, &e1);
+    launch_pass(pl.bits, pl.cpl, dP, dT, static_cast<int>(pl.tasks.size()), st, e0, e1);
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }
 
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                         const SolveArgs& a, bool reuse_gradient, hipStream_t st, PassTimer* tm) {
     if (!reuse_gradient) gradient_launches(pl, dP, dT, count, a, 0, st, tm);
-    launch_gather(G_MU, pl.bits, dP, count, pl.maxrb, pl.maxg, a, 0, st);
+    launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, st);
     launch_propose(pl.cpt, dP, count, a, SEL_STEP, st);
-    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxrb, pl.maxg, a, 0, st);
-    launch_fallback(pl.bits, pl.cpt, dP, count, a, st);
+    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, st);
+    launch_decide(pl.bits, pl.cpt, dP, count, a, st);
 }
 
 qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
@@ -339,7 +337,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
             infos[i].mu_last = hinf[i].mu_last;
             infos[i].pass_ms = timer.total_ms();
             infos[i].pass_launches = timer.launches();
-            infos[i].reserved = 0;
+            infos[i].full_selects = hinf[i].full_selects;
         }
     }
     if (nan) return fail(QIHT_ERR_NUMERIC, "NaN met in the iterate");
