@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libqiht.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QIHT_OFFLOAD_ARCH", "gfx950")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+COMMON = ["-I" + os.path.join(os.path.dirname(HERE), "include"), "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 PER_FILE = {"quantize.hip": ["-ffp-contract=off"]}

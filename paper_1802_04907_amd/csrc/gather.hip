@@ -36,7 +36,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const int32_t* cols;
     int ncols;
     const double* wlist = nullptr;  // per-list-position weights (G_OMEGA)
-    const float* wcol = nullptr;    // per-column weights (G_R: x, G_MU: g)
+    const float* wpos = nullptr;    // per-list-position weights (G_R: x on the support)
+    const float* wcol = nullptr;    // per-column weights (G_MU: g)
     if (MODE == G_OMEGA) {
         const CandMeta& m = pd.meta[set];
         if (!m.changed) return;  // no omega needed for this proposal
@@ -46,7 +47,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     } else {
         cols = pd.sup;
         ncols = (MODE == G_R && zero_x) ? 0 : pd.s;
-        wcol = (MODE == G_R) ? pd.x : pd.g;
+        if (MODE == G_R) wpos = pd.xs;
+        else wcol = pd.g;
     }
     const bool two = (MODE == G_MU) && (a.mu_mode == 0);
     const uint8_t* A = (MODE == G_R) ? pd.q2 : pd.q1;
@@ -80,7 +82,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             wa[u] = 0u;
             wb[u] = 0u;
             if (cidx[u] >= 0) {
-                wt[u] = (MODE == G_OMEGA) ? wlist[t] : static_cast<double>(wcol[cidx[u]]);
+                if (MODE == G_OMEGA) {
+                    wt[u] = wlist[t];
+                } else if (MODE == G_R) {
+                    wt[u] = static_cast<double>(wpos[t]);
+                } else {
+                    const float gv = wcol[cidx[u]];
+                    wt[u] = static_cast<double>(gv);
+                    if (wg == 0 && w == 0) pd.gs[t] = gv;  // g on the support, compact
+                }
                 const size_t off = static_cast<size_t>(cidx[u]) * pd.col_bytes + woff;
                 wa[u] = *reinterpret_cast<const uint32_t*>(A + off);
                 if (two) wb[u] = *reinterpret_cast<const uint32_t*>(B + off);

@@ -96,11 +96,16 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     const float bsum = static_cast<float>(pd.beta * wave_sum(sr));
     float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
     // Histogram of the top 11 bits of |g_j| (exponent and 3 mantissa bits)
-    // for the threshold search of the H_s proposals; built where g is final.
+    // over the entries off the current support, for the threshold search of
+    // the H_s proposals; built where g is final.
     const bool hist = pd.nslab == 1;
     __shared__ uint32_t lh[2048];
+    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];  // support bitmap of this task's columns
+    const int wbase = tk.c0 >> 5;
     if (hist) {
         for (int b = threadIdx.x; b < 2048; b += kPassThreads) lh[b] = 0u;
+        const int nwords = ((tk.c1 - 1) >> 5) - wbase + 1;
+        for (int w = threadIdx.x; w < nwords; w += kPassThreads) lbm[w] = pd.bmsup[wbase + w];
         __syncthreads();
     }
     const uint8_t* base = pd.q1 + static_cast<size_t>(chunk0) * 16;
@@ -132,11 +137,13 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
         if (lane == 0) {
             const float ga = (BITS == 32) ? sa : fmaf(pd.alpha_f, sa, bsum);
             out[j] = ga;
-            if (hist) atomicAdd(&lh[(__float_as_uint(ga) & 0x7FFFFFFFu) >> 20], 1u);
+            if (hist && !((lbm[(j >> 5) - wbase] >> (j & 31)) & 1u))
+                atomicAdd(&lh[(__float_as_uint(ga) & 0x7FFFFFFFu) >> 20], 1u);
             if (has2) {
                 const float gb = (BITS == 32) ? sb : fmaf(pd.alpha_f, sb, bsum);
                 out[j2] = gb;
-                if (hist) atomicAdd(&lh[(__float_as_uint(gb) & 0x7FFFFFFFu) >> 20], 1u);
+                if (hist && !((lbm[(j2 >> 5) - wbase] >> (j2 & 31)) & 1u))
+                    atomicAdd(&lh[(__float_as_uint(gb) & 0x7FFFFFFFu) >> 20], 1u);
             }
         }
     }
@@ -154,7 +161,8 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__
         float s = 0.f;
         for (int sl = 0; sl < pd.nslab; ++sl) s += pd.gpart[static_cast<size_t>(sl) * pd.n + j];
         pd.g[j] = s;
-        atomicAdd(&pd.hist[(__float_as_uint(s) & 0x7FFFFFFFu) >> 20], 1u);
+        if (!((pd.bmsup[j >> 5] >> (j & 31)) & 1u))
+            atomicAdd(&pd.hist[(__float_as_uint(s) & 0x7FFFFFFFu) >> 20], 1u);
     }
 }
 

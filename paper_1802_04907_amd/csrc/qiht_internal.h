@@ -8,7 +8,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/qiht.h"
+#include "qiht.h"
 
 // ---------------------------------------------------------------------------
 // Quantized matrix handle.

@@ -34,16 +34,26 @@ constexpr int kBmWords = kMaxSelectN / 32;
 
 struct SelShared {
     uint32_t hist[2048];
-    uint32_t cnt[kSelectThreads];
+    uint32_t hist2[1024];        // second and third radix digits
+    uint32_t hist3[1024];
     uint32_t bm_old[kBmWords];   // current support
     uint32_t bm_new[kBmWords];   // selected set
     uint32_t bm_tie[kBmWords];   // candidates equal to the threshold key
-    uint32_t ckey[kCandCap];
-    int32_t cidx[kCandCap];
+    uint32_t wpre[kBmWords];     // per-word prefix counts
+    union {
+        struct {                 // fast path: the candidate list
+            uint32_t ckey[kCandCap];
+            int32_t cidx[kCandCap];
+            float cval[kCandCap];  // a_j = x_j + mu g_j
+            float cxo[kCandCap];   // x_j (0 off the support)
+        } c;
+        uint32_t cnt[kSelectThreads];  // full path: per (round, wave) counts
+    } u;
     uint32_t scan[16];
-    uint32_t bin, krem, ncand;
-    int changed, overflow;
+    uint32_t bin, krem, ncand, total;
+    int changed;
     double red[16];
+    double red3[3][16];
 };
 
 __device__ __forceinline__ uint32_t abs_key(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
@@ -82,6 +92,45 @@ __device__ void find_bin(SelShared& S, int nb, uint32_t& prefix, uint32_t& krem,
     if (krem > 0) {
         prefix = (prefix << width) | S.bin;
         krem = S.krem;
+    }
+    __syncthreads();
+}
+
+// Bin of the krem-th largest key of a histogram of NB bins (scanned from
+// the top), found by wave 0 alone; every thread gets (S.bin, S.krem) after
+// the closing barrier.
+template <int NB>
+__device__ void find_bin_w0(const uint32_t* hist, uint32_t krem, SelShared& S) {
+    constexpr int PER = NB / 64;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int top = NB - 1 - lane * PER;  // this lane: bins top, top-1, ..., top-PER+1
+        uint32_t h[PER];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            h[i] = hist[top - i];
+            c += h[i];
+        }
+        uint32_t x = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t run = x - c;
+        if (krem > 0 && run < krem && krem <= x) {
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                if (!found && run < krem && krem <= run + h[i]) {
+                    S.bin = static_cast<uint32_t>(top - i);
+                    S.krem = krem - run;
+                    found = true;
+                }
+                run += h[i];
+            }
+        }
     }
     __syncthreads();
 }
@@ -166,14 +215,14 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
     for (int e = 0; e < CPT; ++e) {
         const int j = tid + kSelectThreads * e;
         const uint64_t b = __ballot(s > 0 && j < n && key[e] == T);
-        if (lane == 0) S.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
+        if (lane == 0) S.u.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
     }
     __syncthreads();
     {
         constexpr int NC = CPT * 16;
-        const uint32_t v = tid < NC ? S.cnt[tid] : 0u;
+        const uint32_t v = tid < NC ? S.u.cnt[tid] : 0u;
         const uint32_t before = block_excl_scan<kSelectThreads>(v, S.scan, nullptr);
-        if (tid < NC) S.cnt[tid] = before;
+        if (tid < NC) S.u.cnt[tid] = before;
         __syncthreads();
     }
 #pragma unroll
@@ -181,7 +230,7 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
         const int j = tid + kSelectThreads * e;
         const bool tie = s > 0 && j < n && key[e] == T;
         const uint64_t b = __ballot(tie);
-        const uint32_t rank = S.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
+        const uint32_t rank = S.u.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
         if (s > 0 && j < n && (key[e] > T || (tie && rank < need)))
             atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
     }
@@ -190,8 +239,9 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
 
 // Fast path over the support and the histogram candidates; returns false
 // (and selects nothing) when the candidate set does not fit in LDS.
-// Appends (key, index) to the LDS candidate list; one LDS atomic per wave.
-__device__ __forceinline__ void push_candidate(bool pred, uint32_t key, int j, SelShared& S) {
+// Appends a candidate to the LDS list; one LDS atomic per wave.
+__device__ __forceinline__ void push_candidate(bool pred, uint32_t key, int j, float a, float xo,
+                                               SelShared& S) {
     const uint64_t b = __ballot(pred);
     if (b == 0ull) return;
     const int lane = threadIdx.x & 63;
@@ -202,176 +252,402 @@ __device__ __forceinline__ void push_candidate(bool pred, uint32_t key, int j, S
     if (pred) {
         const uint32_t c = base + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
         if (c < static_cast<uint32_t>(kCandCap)) {
-            S.ckey[c] = key;
-            S.cidx[c] = j;
+            S.u.c.ckey[c] = key;
+            S.u.c.cidx[c] = j;
+            S.u.c.cval[c] = a;
+            S.u.c.cxo[c] = xo;
         }
     }
 }
 
-template <int CPT, int MODE>
-__device__ bool select_fast(int n, int s, const float* g, const float* x, float muf,
-                            const int32_t* old_sup, int nsup, const uint32_t* ghist,
-                            SelShared& S, int* err) {
-    const int tid = threadIdx.x;
-    // every |g_j| this thread owns, loaded up front (independent loads)
-    float gv[CPT];
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const int j = tid + kSelectThreads * e;
-        gv[e] = j < n ? g[j] : 0.0f;
-    }
-    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = ghist[b];
-    if (tid == 0) {
-        S.ncand = 0;
-        S.overflow = 0;
+// Sum of three values over the block, fixed order; every thread gets them.
+__device__ void block_sum3(double& a, double& b, double& c, SelShared& S) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+        S.red3[0][wv] = a;
+        S.red3[1][wv] = b;
+        S.red3[2][wv] = c;
     }
     __syncthreads();
-    for (int i = tid; i < nsup; i += kSelectThreads)
-        atomicSub(&S.hist[abs_key(g[old_sup[i]]) >> 20], 1u);
-    __syncthreads();
-    // bin of the s-th largest |g| off the support
-    const int off_count = n - nsup;
-    float thr = 0.0f;
-    if (off_count > s) {
-        uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
-        find_bin(S, 2048, prefix, krem, 11);
-        thr = __uint_as_float(prefix << 20) * (1.0f - 0x1p-20f);
-        if (!(thr >= 0x1p-100f)) return false;  // keep clear of subnormal products
-    }
-    // collect candidates: the support, and off-support entries above thr
-    int bad = 0;
-    for (int i0 = 0; i0 < nsup; i0 += kSelectThreads) {
-        const int i = i0 + tid;
-        const bool in = i < nsup;
-        const int j = in ? old_sup[i] : 0;
-        const uint32_t k = in ? abs_key(value_at<MODE>(nullptr, g, x, muf, j)) : 0u;
-        if (k > 0x7F800000u) bad = 1;
-        push_candidate(in, k, j, S);
-    }
+    a = b = c = 0.0;
 #pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const int j = tid + kSelectThreads * e;
-        const bool in = j < n && fabsf(gv[e]) >= thr && !((S.bm_old[j >> 5] >> (j & 31)) & 1u);
-        // off the support x_j = 0, so a_j = fma(mu, g_j, 0)
-        const uint32_t k = in ? abs_key((MODE == SEL_STEP) ? fmaf(muf, gv[e], 0.0f) : gv[e]) : 0u;
-        if (k > 0x7F800000u) bad = 1;
-        push_candidate(in, k, j, S);
+    for (int w = 0; w < kSelectThreads / 64; ++w) {
+        a += S.red3[0][w];
+        b += S.red3[1][w];
+        c += S.red3[2][w];
     }
-    if (bad) atomicOr(err, 1);
     __syncthreads();
-    const uint32_t nc = S.ncand;
-    if (nc > static_cast<uint32_t>(kCandCap)) return false;
-    // exact rank among the candidates
-    uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
+}
+
+// Bitmap words scanned by word_prefix.
+enum { BM_TIE = 0, BM_NEW = 1, BM_UNION = 2 };
+
+template <int WHICH>
+__device__ __forceinline__ uint32_t bm_word(const SelShared& S, int w) {
+    if (WHICH == BM_TIE) return S.bm_tie[w];
+    if (WHICH == BM_NEW) return S.bm_new[w];
+    return S.bm_old[w] | S.bm_new[w];
+}
+
+// Per-word exclusive prefix of popcount(bitmap word) into S.wpre (index
+// order), computed by wave 0 alone (no block-wide scan); returns the total.
+template <int WHICH>
+__device__ uint32_t word_prefix(int words, SelShared& S) {
+    constexpr int MAXW = kBmWords / 64;  // words per lane at the largest n
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int wpl = (words + 63) / 64;
+        const int w0 = lane * wpl;
+        uint32_t c = 0;
 #pragma unroll
-    for (int pass = 0; pass < 3; ++pass) {
-        const int width = pass == 0 ? 11 : 10;
-        const int sh = pass == 0 ? 20 : (pass == 1 ? 10 : 0);
-        const int nb = 1 << width;
-        const int hsh = sh + width;
-        for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
-        __syncthreads();
-        if (krem > 0) {
-            for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-                const uint32_t k = S.ckey[c];
-                if (pass == 0 || (k >> hsh) == prefix) atomicAdd(&S.hist[(k >> sh) & (nb - 1)], 1u);
+        for (int i = 0; i < MAXW; ++i) {
+            const int w = w0 + i;
+            if (i < wpl && w < words) c += static_cast<uint32_t>(__popc(bm_word<WHICH>(S, w)));
+        }
+        uint32_t x = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t pos = x - c;
+#pragma unroll
+        for (int i = 0; i < MAXW; ++i) {
+            const int w = w0 + i;
+            if (i < wpl && w < words) {
+                S.wpre[w] = pos;
+                pos += static_cast<uint32_t>(__popc(bm_word<WHICH>(S, w)));
             }
         }
-        __syncthreads();
-        find_bin(S, nb, prefix, krem, width);
-    }
-    const uint32_t T = prefix;
-    const uint32_t need = krem;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const uint32_t k = S.ckey[c];
-        const int j = S.cidx[c];
-        if (s > 0 && k > T) atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
-        else if (s > 0 && k == T) atomicOr(&S.bm_tie[j >> 5], 1u << (j & 31));
+        if (lane == 63) S.total = x;
     }
     __syncthreads();
-    // the `need` lowest-index ties
+    return S.total;
+}
+
+__device__ __forceinline__ uint32_t rank_in_word(uint32_t bits, int b) {
+    return static_cast<uint32_t>(__popc(bits & ((1u << b) - 1u)));
+}
+
+// Exact top-s of the candidate list (keys desc, ties to lower index) into
+// S.bm_new: three radix digits (11, 10, 10 bits) over the candidate keys,
+// each a histogram built by all threads and scanned by wave 0; ties at the
+// threshold key resolved to the lowest indices by an ordered bitmap scan.
+// S.hist, S.hist2, S.hist3 must be zero on entry.
+__device__ void rank_candidates(int n, int s, SelShared& S) {
+    const int tid = threadIdx.x;
+    const uint32_t nc = S.ncand;
+    if (s <= 0) return;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) atomicAdd(&S.hist[S.u.c.ckey[c] >> 20], 1u);
+    __syncthreads();
+    find_bin_w0<2048>(S.hist, static_cast<uint32_t>(s), S);
+    const uint32_t b1 = S.bin, k1 = S.krem;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.u.c.ckey[c];
+        if ((k >> 20) == b1) atomicAdd(&S.hist2[(k >> 10) & 1023u], 1u);
+    }
+    __syncthreads();
+    find_bin_w0<1024>(S.hist2, k1, S);
+    const uint32_t p2 = (b1 << 10) | S.bin, k2 = S.krem;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.u.c.ckey[c];
+        if ((k >> 10) == p2) atomicAdd(&S.hist3[k & 1023u], 1u);
+    }
+    __syncthreads();
+    find_bin_w0<1024>(S.hist3, k2, S);
+    const uint32_t T = (p2 << 10) | S.bin;  // the s-th largest key
+    const uint32_t need = S.krem;           // keys equal to T that are taken
+    int ties = 0;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.u.c.ckey[c];
+        const int j = S.u.c.cidx[c];
+        if (k > T) atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
+        else if (k == T) {
+            atomicOr(&S.bm_tie[j >> 5], 1u << (j & 31));
+            ties = 1;
+        }
+    }
+    (void)ties;
+    __syncthreads();
+    const uint32_t nties = S.hist3[T & 1023u];
+    if (need >= nties) {
+        // every tie is taken (the usual case): no ordering needed
+        const int words = (n + 31) / 32;
+        for (int w = tid; w < words; w += kSelectThreads) S.bm_new[w] |= S.bm_tie[w];
+        __syncthreads();
+        return;
+    }
     const int words = (n + 31) / 32;
-    const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
-    const int w0 = tid * wpt;
-    uint32_t cnt = 0;
-    for (int w = w0; w < min(words, w0 + wpt); ++w) cnt += __popc(S.bm_tie[w]);
-    uint32_t rank = block_excl_scan<kSelectThreads>(cnt, S.scan, nullptr);
-    for (int w = w0; w < min(words, w0 + wpt); ++w) {
+    word_prefix<BM_TIE>(words, S);
+    for (int w = tid; w < words; w += kSelectThreads) {
         uint32_t u = S.bm_tie[w];
+        uint32_t rank = S.wpre[w];
         while (u) {
             const int b = __ffs(u) - 1;
             u &= u - 1;
-            if (rank < need) S.bm_new[w] |= 1u << b;
+            if (rank < need) atomicOr(&S.bm_new[w], 1u << b);
             ++rank;
         }
     }
     __syncthreads();
-    return true;
 }
 
-// One complete proposal into `slot` (SEL_STEP) or the initial support
-// (SEL_INIT, written to pd.sup).  Thread 0 writes the slot's CandMeta.
+// One complete proposal.  SEL_INIT writes the initial support (pd.sup, xs,
+// bmsup); SEL_STEP writes proposal `slot` (support, values, difference list,
+// metadata).  Every global input is loaded before the first barrier.
+// With from_partials the step is mu = mu0 / (k(1-c))^k with mu0 finished
+// here from the gather partials (written to *mu0_out); returns false when
+// the iteration is stationary.
 template <int CPT, int MODE>
-__device__ void propose(const ProbDev& pd, int slot, int k, double mu, SelShared& S) {
+__device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool from_partials,
+                        double shrink, double* mu0_out, SelShared& S) {
     const int tid = threadIdx.x;
     const int n = pd.n, s = pd.s;
     const int words = (n + 31) / 32;
-    const float muf = static_cast<float>(mu);
     const int nsup = (MODE == SEL_STEP) ? s : 0;
+    // ---- loads (all independent)
+    float gv[CPT];
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+        const int j = tid + kSelectThreads * e;
+        gv[e] = j < n ? pd.g[j] : 0.0f;
+    }
+    const bool sreg = tid < nsup;  // first 1024 support entries in registers
+    const int sj = sreg ? pd.sup[tid] : 0;
+    const float sx = sreg ? pd.xs[tid] : 0.0f;
+    const float sg = sreg ? pd.gs[tid] : 0.0f;
+    double gg = 0.0, uv = 0.0, uu = 0.0;
+    if (from_partials) {
+        gg = static_cast<double>(sg) * static_cast<double>(sg);
+        for (int i = tid + kSelectThreads; i < nsup; i += kSelectThreads) {
+            const double v = static_cast<double>(pd.gs[i]);
+            gg += v * v;
+        }
+        for (int b = tid; b < pd.nwg; b += kSelectThreads) {
+            uv += pd.part_mu[2 * b + 0];
+            uu += pd.part_mu[2 * b + 1];
+        }
+    }
+    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = pd.hist[b];
+    for (int b = tid; b < 1024; b += kSelectThreads) {
+        S.hist2[b] = 0u;
+        S.hist3[b] = 0u;
+    }
     for (int w = tid; w < words; w += kSelectThreads) {
-        S.bm_old[w] = 0u;
+        S.bm_old[w] = (MODE == SEL_STEP) ? pd.bmsup[w] : 0u;
         S.bm_new[w] = 0u;
         S.bm_tie[w] = 0u;
     }
-    if (tid == 0) S.changed = 0;
-    __syncthreads();
-    for (int i = tid; i < nsup; i += kSelectThreads) {
-        const int j = pd.sup[i];
-        atomicOr(&S.bm_old[j >> 5], 1u << (j & 31));
+    if (tid == 0) {
+        S.ncand = 0;
+        S.changed = 0;
     }
-    __syncthreads();
-    if (!select_fast<CPT, MODE>(n, s, pd.g, pd.x, muf, pd.sup, nsup, pd.hist, S, &pd.st->err)) {
-        if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
-        for (int w = tid; w < words; w += kSelectThreads) S.bm_new[w] = 0u;
+    // ---- the step
+    double mu = mu_in;
+    if (from_partials) {
+        block_sum3(gg, uv, uu, S);
+        double den = uv;
+        if (!(den > 0.0) || !isfinite(den)) den = uu;
+        if (!(gg > 0.0) || !(den > 0.0) || !isfinite(gg / den)) return false;
+        *mu0_out = gg / den;
+        mu = shrunk_mu(gg / den, shrink, k);
+    } else {
         __syncthreads();
-        select_full<CPT, MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
     }
+    const float muf = static_cast<float>(mu);
+    // ---- threshold from the off-support histogram
+    bool fast = true;
+    float thr = 0.0f;
+    if (n - nsup > s) {
+        find_bin_w0<2048>(S.hist, static_cast<uint32_t>(s), S);
+        thr = __uint_as_float(S.bin << 20) * (1.0f - 0x1p-20f);
+        fast = thr >= 0x1p-100f;  // keep clear of subnormal products
+    }
+    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
+    int bad = 0;
+    if (fast) {
+        {
+            const float a = fmaf(muf, sg, sx);
+            const uint32_t key = abs_key(a);
+            if (sreg && key > 0x7F800000u) bad = 1;
+            push_candidate(sreg, key, sj, a, sx, S);
+        }
+        for (int i0 = kSelectThreads; i0 < nsup; i0 += kSelectThreads) {
+            const int i = i0 + tid;
+            const bool in = i < nsup;
+            const int j = in ? pd.sup[i] : 0;
+            const float xo = in ? pd.xs[i] : 0.0f;
+            const float a = in ? fmaf(muf, pd.gs[i], xo) : 0.0f;
+            const uint32_t key = abs_key(a);
+            if (in && key > 0x7F800000u) bad = 1;
+            push_candidate(in, key, j, a, xo, S);
+        }
+        // off the support: which of this thread's entries pass the
+        // threshold (a bit mask), one LDS atomic per wave for the slots
+        uint64_t cm = 0;
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            const int j = tid + kSelectThreads * e;
+            const bool in = j < n && fabsf(gv[e]) >= thr && !((S.bm_old[j >> 5] >> (j & 31)) & 1u);
+            cm |= static_cast<uint64_t>(in) << e;
+        }
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(cm));
+        const int lane = tid & 63;
+        uint32_t x = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t base = 0;
+        if (lane == 63 && x > 0) base = atomicAdd(&S.ncand, x);
+        base = __shfl(base, 63, 64) + (x - cnt);
+#pragma unroll
+        for (int e = 0; e < CPT; ++e) {
+            if ((cm >> e) & 1ull) {
+                const int j = tid + kSelectThreads * e;
+                // off the support x_j = 0, so a_j = fma(mu, g_j, 0)
+                const float a = (MODE == SEL_STEP) ? fmaf(muf, gv[e], 0.0f) : gv[e];
+                const uint32_t key = abs_key(a);
+                if (key > 0x7F800000u) bad = 1;
+                if (base < static_cast<uint32_t>(kCandCap)) {
+                    S.u.c.ckey[base] = key;
+                    S.u.c.cidx[base] = j;
+                    S.u.c.cval[base] = a;
+                    S.u.c.cxo[base] = 0.0f;
+                }
+                ++base;
+            }
+        }
+    }
+    __syncthreads();
+    fast = fast && S.ncand <= static_cast<uint32_t>(kCandCap);
+    if (bad) atomicOr(&pd.st->err, 1);
+    if (!fast) {
+        // ---- full path: every key
+        if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
+        select_full<CPT, MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
+        if (MODE == SEL_INIT) {
+            emit_support<MODE>(n, s, nullptr, pd.g, nullptr, muf, nullptr, pd.sup, nullptr, S);
+            for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.bm_new[w];
+            for (int i = tid; i < s; i += kSelectThreads) pd.xs[i] = 0.0f;
+            for (int b = tid; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
+            __syncthreads();
+            return true;
+        }
+        int32_t* out_sup = pd.csup + static_cast<size_t>(slot) * s;
+        float* out_val = pd.cval + static_cast<size_t>(slot) * s;
+        emit_support<MODE>(n, s, nullptr, pd.g, pd.x, muf, pd.sup, out_sup, out_val, S);
+        // difference list from global values (rare path)
+        const uint32_t total = word_prefix<BM_UNION>(words, S);
+        int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
+        double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
+        double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
+        for (int w = tid; w < words; w += kSelectThreads) {
+            uint32_t u = S.bm_old[w] | S.bm_new[w];
+            uint32_t pos = S.wpre[w];
+            while (u) {
+                const int b = __ffs(u) - 1;
+                u &= u - 1;
+                const int j = w * 32 + b;
+                const float xo = pd.x[j];
+                const float xn = ((S.bm_new[w] >> b) & 1u) ? fmaf(muf, pd.g[j], xo) : 0.0f;
+                const double d = static_cast<double>(xn) - static_cast<double>(xo);
+                if (pos < static_cast<uint32_t>(2 * s)) {
+                    dlist[pos] = j;
+                    dw[pos] = d;
+                }
+                ++pos;
+                dx2 += d * d;
+                xn2 += static_cast<double>(xn) * static_cast<double>(xn);
+            }
+        }
+        block_sum3(dx2, xn2, zero, S);
+        if (tid == 0) {
+            CandMeta m;
+            m.changed = S.changed;
+            m.dcount = static_cast<int32_t>(total);
+            m.k = k;
+            m.pad = 0;
+            m.mu = mu;
+            m.dx2 = dx2;
+            m.xn2 = xn2;
+            m.omega = 0.0;
+            pd.meta[slot] = m;
+        }
+        __syncthreads();
+        return true;
+    }
+    // ---- fast path: rank the candidates, then emit from LDS
+    rank_candidates(n, s, S);
+    const uint32_t nc = S.ncand;
     if (MODE == SEL_INIT) {
-        emit_support<MODE>(n, s, nullptr, pd.g, nullptr, muf, nullptr, pd.sup, nullptr, S);
-        return;
+        word_prefix<BM_NEW>(words, S);
+        for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+            const int j = S.u.c.cidx[c];
+            const int w = j >> 5, b = j & 31;
+            if ((S.bm_new[w] >> b) & 1u) {
+                const uint32_t pos = S.wpre[w] + rank_in_word(S.bm_new[w], b);
+                if (pos < static_cast<uint32_t>(s)) {
+                    pd.sup[pos] = j;
+                    pd.xs[pos] = 0.0f;
+                }
+            }
+        }
+        for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.bm_new[w];
+        // the next full pass rebuilds the histogram off the new support
+        for (int b = tid; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
+        __syncthreads();
+        return true;
     }
     int32_t* out_sup = pd.csup + static_cast<size_t>(slot) * s;
     float* out_val = pd.cval + static_cast<size_t>(slot) * s;
     int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
     double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
-    emit_support<MODE>(n, s, nullptr, pd.g, pd.x, muf, pd.sup, out_sup, out_val, S);
-    // difference list over the union of old and new supports, ascending
-    const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
-    const int w0 = tid * wpt;
-    uint32_t cnt = 0;
-    for (int w = w0; w < min(words, w0 + wpt); ++w) cnt += __popc(S.bm_old[w] | S.bm_new[w]);
-    uint32_t total = 0;
-    uint32_t pos = block_excl_scan<kSelectThreads>(cnt, S.scan, &total);
-    double dx2 = 0.0, xn2 = 0.0;
-    for (int w = w0; w < min(words, w0 + wpt); ++w) {
-        uint32_t u = S.bm_old[w] | S.bm_new[w];
-        const uint32_t nw = S.bm_new[w];
-        while (u) {
-            const int b = __ffs(u) - 1;
-            u &= u - 1;
-            const int j = w * 32 + b;
-            const float xo = pd.x[j];
-            const float xn = ((nw >> b) & 1u) ? value_at<MODE>(nullptr, pd.g, pd.x, muf, j) : 0.0f;
+    // changed: the selection bitmap differs from the support bitmap
+    {
+        int diff = 0;
+        for (int w = tid; w < words; w += kSelectThreads) diff |= (S.bm_new[w] != S.bm_old[w]);
+        if (diff) S.changed = 1;
+    }
+    word_prefix<BM_NEW>(words, S);
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const int j = S.u.c.cidx[c];
+        const int w = j >> 5, b = j & 31;
+        if ((S.bm_new[w] >> b) & 1u) {
+            const uint32_t pos = S.wpre[w] + rank_in_word(S.bm_new[w], b);
+            if (pos < static_cast<uint32_t>(s)) {
+                out_sup[pos] = j;
+                out_val[pos] = S.u.c.cval[c];
+            }
+        }
+    }
+    __syncthreads();
+    // difference list over the union of old and new supports, ascending;
+    // every member of the union is exactly one candidate
+    const uint32_t total = word_prefix<BM_UNION>(words, S);
+    double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
+    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
+        const int j = S.u.c.cidx[c];
+        const int w = j >> 5, b = j & 31;
+        const uint32_t uw = S.bm_old[w] | S.bm_new[w];
+        if ((uw >> b) & 1u) {
+            const uint32_t pos = S.wpre[w] + rank_in_word(uw, b);
+            const float xo = S.u.c.cxo[c];
+            const float xn = ((S.bm_new[w] >> b) & 1u) ? S.u.c.cval[c] : 0.0f;
             const double d = static_cast<double>(xn) - static_cast<double>(xo);
-            dlist[pos] = j;
-            dw[pos] = d;
-            ++pos;
+            if (pos < static_cast<uint32_t>(2 * s)) {
+                dlist[pos] = j;
+                dw[pos] = d;
+            }
             dx2 += d * d;
             xn2 += static_cast<double>(xn) * static_cast<double>(xn);
         }
     }
-    dx2 = block_sum<kSelectThreads>(dx2, S.red);
-    xn2 = block_sum<kSelectThreads>(xn2, S.red);
+    block_sum3(dx2, xn2, zero, S);
     if (tid == 0) {
         CandMeta m;
         m.changed = S.changed;
@@ -385,28 +661,7 @@ __device__ void propose(const ProbDev& pd, int slot, int k, double mu, SelShared
         pd.meta[slot] = m;
     }
     __syncthreads();
-}
-
-// mu = |g_G|^2 / ((Q1_G g_G).(Q2_G g_G)) from the gather partials (fixed
-// order); falls back to |Q1_G g_G|^2 when the cross term is not positive.
-// Returns a negative value when the iteration is stationary.
-__device__ double step_from_partials(const ProbDev& pd, SelShared& S) {
-    double gg = 0.0, uv = 0.0, uu = 0.0;
-    for (int i = threadIdx.x; i < pd.s; i += kSelectThreads) {
-        const double v = static_cast<double>(pd.g[pd.sup[i]]);
-        gg += v * v;
-    }
-    for (int b = threadIdx.x; b < pd.nwg; b += kSelectThreads) {
-        uv += pd.part_mu[2 * b + 0];
-        uu += pd.part_mu[2 * b + 1];
-    }
-    const double num = block_sum<kSelectThreads>(gg, S.red);
-    uv = block_sum<kSelectThreads>(uv, S.red);
-    uu = block_sum<kSelectThreads>(uu, S.red);
-    double den = uv;
-    if (!(den > 0.0) || !isfinite(den)) den = uu;
-    if (!(num > 0.0) || !(den > 0.0) || !isfinite(num / den)) return -1.0;
-    return num / den;
+    return true;
 }
 
 template <int CPT>
@@ -416,21 +671,21 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     SolveState* st = pd.st;
     __shared__ SelShared S;
     if (st->done) return;
+    double mu0 = 0.0;
     if (mode == SEL_INIT) {
-        propose<CPT, SEL_INIT>(pd, 0, 0, 1.0, S);
+        propose<CPT, SEL_INIT>(pd, 0, 0, 1.0, false, 1.0, &mu0, S);
         return;
     }
-    const double mu0 = step_from_partials(pd, S);
-    if (mu0 < 0.0) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int k = blockIdx.x;  // shrink count of this proposal
+    const bool ok = propose<CPT, SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok) {
+            st->mu = mu0;
+        } else {
             st->done = 1;
             st->reason = QIHT_REASON_STATIONARY;
         }
-        return;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->mu = mu0;
-    const int k = blockIdx.x;  // shrink count of this proposal
-    propose<CPT, SEL_STEP>(pd, k, k, shrunk_mu(mu0, a.k * (1.0 - a.c), k), S);
 }
 
 // |Q1 dx|^2 of slot 0's difference list, by one workgroup.
@@ -503,7 +758,8 @@ __global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __rest
         const double shrink = a.k * (1.0 - a.c);
         for (int k = kSpec;; ++k) {
             const double mu = shrunk_mu(st->mu, shrink, k);
-            propose<CPT, SEL_STEP>(pd, 0, k, mu, S);
+            double unused = 0.0;
+            propose<CPT, SEL_STEP>(pd, 0, k, mu, false, shrink, &unused, S);
             const CandMeta m = pd.meta[0];
             bool accept = !m.changed;
             if (!accept) {

@@ -12,9 +12,10 @@ namespace qiht {
 constexpr int kSelectThreads = 1024;  // one workgroup per H_s proposal
 constexpr int kGatherThreads = 256;   // column gathers
 constexpr int kPassThreads = 256;     // full pass
+constexpr int kPassMaxCols = 4096;    // columns of one full-pass task (at most)
 constexpr int kSpec = 4;              // step sizes proposed at once
 constexpr int kMaxSelectN = kSelectThreads * 64;
-constexpr int kCandCap = 4096;        // candidate keys a fast proposal holds in LDS
+constexpr int kCandCap = 3072;        // candidate keys a fast proposal holds in LDS
 
 // Per-problem control state (device memory).
 struct SolveState {
@@ -65,6 +66,9 @@ struct ProbDev {
     uint32_t* hist;     // 2048-bin histogram of the top 11 bits of |g|
     float* x;           // current iterate, dense n (zero off the support)
     int32_t* sup;       // current support, s ascending
+    float* xs;          // x on the support, in support order
+    float* gs;          // g on the support, in support order (written by G_MU)
+    uint32_t* bmsup;    // support bitmap, n bits
     int32_t* csup;      // kSpec * s proposal supports
     float* cval;        // kSpec * s proposal values on their supports
     int32_t* dlist;     // kSpec * 2s indices where a proposal differs from x
@@ -172,12 +176,17 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
     const CandMeta m = pd.meta[t];
     const int32_t* cs = pd.csup + static_cast<size_t>(t) * pd.s;
     const float* cv = pd.cval + static_cast<size_t>(t) * pd.s;
+    const int words = (pd.n + 31) / 32;
     for (int i = threadIdx.x; i < pd.s; i += NT) pd.x[pd.sup[i]] = 0.0f;
+    for (int w = threadIdx.x; w < words; w += NT) pd.bmsup[w] = 0u;
     __syncthreads();
     __threadfence_block();
     for (int i = threadIdx.x; i < pd.s; i += NT) {
-        pd.x[cs[i]] = cv[i];
-        pd.sup[i] = cs[i];
+        const int j = cs[i];
+        pd.x[j] = cv[i];
+        pd.xs[i] = cv[i];
+        pd.sup[i] = j;
+        atomicOr(&pd.bmsup[j >> 5], 1u << (j & 31));
     }
     if (threadIdx.x == 0) {
         st->iter += 1;

@@ -20,10 +20,18 @@ struct InfoDev {
     double mu_last;
 };
 
+// Warm start: x restricted to the given support, its compact copy and the
+// support bitmap.
 __global__ void k_warm_start(const ProbDev* __restrict__ P, const float* const* x0s) {
     const ProbDev& pd = P[blockIdx.x];
     const float* x0 = x0s[blockIdx.x];
-    for (int i = threadIdx.x; i < pd.s; i += blockDim.x) pd.x[pd.sup[i]] = x0[pd.sup[i]];
+    for (int i = threadIdx.x; i < pd.s; i += blockDim.x) {
+        const int j = pd.sup[i];
+        const float v = x0[j];
+        pd.x[j] = v;
+        pd.xs[i] = v;
+        atomicOr(&pd.bmsup[j >> 5], 1u << (j & 31));
+    }
 }
 
 __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
@@ -75,7 +83,8 @@ struct Carver {
 };
 
 struct Layout {
-    size_t r32, g, gpart, hist, x, sup, csup, cval, dlist, dw, meta, part_mu, part_om, st;
+    size_t r32, g, gpart, hist, x, sup, xs, gs, bmsup, csup, cval, dlist, dw, meta, part_mu,
+        part_om, st;
 };
 
 struct Plan {
@@ -117,6 +126,9 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         L.hist = cv.take<uint32_t>(2048);
         L.x = cv.take<float>(q->n);
         L.sup = cv.take<int32_t>(s);
+        L.xs = cv.take<float>(s);
+        L.gs = cv.take<float>(s);
+        L.bmsup = cv.take<uint32_t>((q->n + 31) / 32);
         L.csup = cv.take<int32_t>(kSpec * s);
         L.cval = cv.take<float>(kSpec * s);
         L.dlist = cv.take<int32_t>(kSpec * 2 * s);
@@ -143,7 +155,8 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         // ~256 workgroups per problem when the problem is small
         const int64_t slab_bytes = std::min<int64_t>(q->col_bytes, slab_chunks * 16);
         const int64_t tc_bw = std::max<int64_t>(8, (256 * 1024) / std::max<int64_t>(slab_bytes, 1));
-        const int64_t tc = std::max<int64_t>(8, std::min<int64_t>(tc_bw, (q->n + 255) / 256));
+        const int64_t tc = std::min<int64_t>(
+            kPassMaxCols, std::max<int64_t>(8, std::min<int64_t>(tc_bw, (q->n + 255) / 256)));
         for (int sl = 0; sl < nslab; ++sl)
             for (int64_t c0 = 0; c0 < q->n; c0 += tc)
                 pl.tasks.push_back(Task{i, sl, static_cast<int32_t>(c0),
@@ -169,6 +182,9 @@ void bind(Plan& pl, uint8_t* base) {
         p.hist = reinterpret_cast<uint32_t*>(base + L.hist);
         p.x = reinterpret_cast<float*>(base + L.x);
         p.sup = reinterpret_cast<int32_t*>(base + L.sup);
+        p.xs = reinterpret_cast<float*>(base + L.xs);
+        p.gs = reinterpret_cast<float*>(base + L.gs);
+        p.bmsup = reinterpret_cast<uint32_t*>(base + L.bmsup);
         p.csup = reinterpret_cast<int32_t*>(base + L.csup);
         p.cval = reinterpret_cast<float*>(base + L.cval);
         p.dlist = reinterpret_cast<int32_t*>(base + L.dlist);
@@ -231,8 +247,8 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
 }
 
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
-                        const SolveArgs& a, bool reuse_gradient, hipStream_t st, PassTimer* tm) {
-    if (!reuse_gradient) gradient_launches(pl, dP, dT, count, a, 0, st, tm);
+                        const SolveArgs& a, hipStream_t st, PassTimer* tm) {
+    gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, st);
     launch_propose(pl.cpt, dP, count, a, SEL_STEP, st);
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, st);
@@ -298,7 +314,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
         // x0 restricted to its support (x is zero elsewhere)
         hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
     } else {
-        // x0 = 0; G0 = supp H_s(Q1^T y_hat); iteration 1 reuses g0.
+        // x0 = 0; G0 = supp H_s(Q1^T y_hat).
         gradient_launches(pl, dP, dT, count, a, 1, st, &timer);
         launch_propose(pl.cpt, dP, count, a, SEL_INIT, st);
     }
@@ -307,7 +323,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
     std::vector<SolveState> hs(count);
     for (int it = 1; it <= a.max_iters;) {
         const int end = std::min(a.max_iters, it + kChunk - 1);
-        for (; it <= end; ++it) iteration_launches(pl, dP, dT, count, a, it == 1 && !warm, st, &timer);
+        for (; it <= end; ++it) iteration_launches(pl, dP, dT, count, a, st, &timer);
         QIHT_HIP(hipGetLastError());
         if (it > a.max_iters) break;
         for (int i = 0; i < count; ++i)

@@ -1,0 +1,101 @@
+"""Parity at the full size the benchmark times (8192 x 32768 Gaussian Phi,
+s = 512, 4-bit Phi / 8-bit y, 200 iterations), on sampled outputs the oracle
+can compute one column at a time.
+
+* codes: bit-exact on sampled columns of both realizations, and the scale;
+* y_hat: bit-exact;
+* g at x = 0 and g at the solve's final x (teacher-forced): sampled
+  entries within 1e-5 max(|g_S|, 1e-3 |g0_S|) of the FP64 oracle;
+* final solve: a valid s-sparse iterate on an ascending support that
+  recovers most of the true support (the 4-bit floor is about 80%).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1802_04907_amd as qiht  # noqa: E402
+import workloads  # noqa: E402
+from oracle import quantizer as qz  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+M, N, S, BITS = 8192, 32768, 512, 4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    say("generating the 8192 x 32768 workload")
+    p = workloads.config2(0)
+    phi = torch.from_numpy(p.phi).to(DEV)
+    y = torch.from_numpy(p.y).to(DEV)
+    q = qiht.quantize_matrix(phi, BITS, 2, p.seed)
+    yhat, _, _ = qiht.quantize_vector(y, 8, p.seed)
+    c = float(np.abs(p.phi).max())
+    rng = np.random.default_rng(123)
+    cols = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 30, replace=False)]))
+    yield p, q, yhat, c, cols
+    q.free()
+
+
+def _oracle_cols(p, c, cols, realization):
+    """Dequantized FP64 columns of one realization, computed column by column."""
+    out = np.empty((M, len(cols)))
+    for t, j in enumerate(cols):
+        codes, _ = qz.quantize(p.phi[:, j].astype(np.float64), BITS, p.seed,
+                               qz.STREAM_MATRIX, realization, e_offset=int(j) * M, scale=c)
+        out[:, t] = qz.dequantize(codes, c, BITS)
+    return out
+
+
+def test_fullsize_codes_sampled(big):
+    p, q, yhat, c, cols = big
+    assert q.scale == c
+    for r in range(2):
+        got = q.export_codes(r)[:, cols]
+        for t, j in enumerate(cols):
+            want, _ = qz.quantize(p.phi[:, j].astype(np.float64), BITS, p.seed,
+                                  qz.STREAM_MATRIX, r, e_offset=int(j) * M, scale=c)
+            np.testing.assert_array_equal(got[:, t], want.astype(np.uint8))
+
+
+def test_fullsize_yhat_exact(big):
+    p, q, yhat, c, cols = big
+    np.testing.assert_array_equal(yhat.cpu().numpy(), qz.dequantized_vector(p.y, 8, p.seed))
+
+
+def test_fullsize_gradient_and_solve(big):
+    p, q, yhat, c, cols = big
+    yh = yhat.cpu().numpy()
+    q1c = _oracle_cols(p, c, cols, 0)
+    g0_gpu, _ = qiht.gradient(q, yhat, None, None)
+    g0 = q1c.T @ yh
+    err = np.linalg.norm(g0_gpu.cpu().numpy()[cols] - g0)
+    assert err <= 1e-5 * np.linalg.norm(g0)
+
+    say("solve: 200 iterations as timed by the benchmark")
+    x, sup, info = qiht.niht_solve(q, yhat, S, max_iters=200, tol=-1.0)
+    assert info["iterations"] == 200
+    xs, ss = x.cpu().numpy(), sup.cpu().numpy()
+    assert ss.size == S and np.all(np.diff(ss) > 0) and ss[0] >= 0 and ss[-1] < N
+    assert np.count_nonzero(np.delete(xs, ss)) == 0
+    assert np.all(np.isfinite(xs))
+
+    # teacher-forced gradient at the final iterate, on the sampled columns
+    g_gpu, r_gpu = qiht.gradient(q, yhat, x, sup)
+    q2s = _oracle_cols(p, c, ss, 1)
+    r_or = yh - q2s @ xs[ss].astype(np.float64)
+    rg = r_gpu.cpu().numpy()
+    assert np.all(np.abs(rg - r_or) <= 2.0 ** -23 * np.abs(r_or) + 1e-30)
+    g_or = q1c.T @ r_or
+    err = np.linalg.norm(g_gpu.cpu().numpy()[cols] - g_or)
+    assert err <= 1e-5 * max(np.linalg.norm(g_or), 1e-3 * np.linalg.norm(g0))
+    # recovery on this workload: the 4-bit floor (about 80% of the support)
+    rec = len(np.intersect1d(ss, p.support)) / S
+    say(f"support recovery {rec:.3f}, info {info}")
+    assert rec > 0.6
