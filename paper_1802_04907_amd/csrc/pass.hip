@@ -57,11 +57,337 @@ __device__ __forceinline__ void dot_word(uint32_t w, const float* r, float& a0,
 }
 
 // ---------------------------------------------------------------------------
-// Full pass g = Q1^T r.  One wave per column: lane l owns the 16-byte chunks
-// l, l + 64, ..., l + 64 (CPL - 1) of its row slab and keeps the matching
-// residual rows in registers for every column it visits; each column is
-// reduced across the wave.  Affine dequantization is folded out of the loop:
-// g_j = alpha * sum_i code_ij r_i + beta * sum_i r_i.
+// Exact integer form of the packed-code pass.  The residual rows of a slab are
+// put on one fixed-point grid, r~_i = N_i 2^e with |N_i| <= 2^22 (e from the
+// slab's largest |r_i|), and N_i is split into signed digits: six base-16
+// digits in [-8, 7] for codes of 1, 2 or 4 bits, three base-256 digits in
+// [-128, 127] for 8-bit codes.  The digits are transposed so that each 32-bit
+// digit word lines up with the codes of one code word, and the codes enter
+// the integer dot instructions as they are stored (4- and 8-bit codes biased
+// to signed by an xor).  Every column then costs one dot instruction per
+// digit per code word and the sum over the rows is exact:
+//   sum_i k_ij N_i = sum_d base^d sum_i (k_ij - off) e_d(N_i) + off sum_i N_i,
+// and g_j = 2^e (alpha sum_i k_ij N_i + beta sum_i N_i) is rounded once, from
+// FP64, to FP32.  The only approximation is r -> r~ (relative 2^-22 of the
+// largest |r_i|).
+// ---------------------------------------------------------------------------
+template <int BITS>
+struct QDig {
+    static constexpr int DB = (BITS == 8) ? 8 : 4;         // digit width
+    static constexpr int ND = (BITS == 8) ? 3 : 6;         // digits per row
+    static constexpr int RPD = 32 / DB;                    // rows per digit word
+    static constexpr int H = (BITS == 8) ? 1 : 4 / BITS;   // digit words per code word
+    static constexpr int RPW = 32 / BITS;                  // rows per code word
+    static constexpr uint32_t OFF = (BITS == 8) ? 0x808080u : 0x888888u;
+    static constexpr int CODE_OFF = (BITS == 8) ? 128 : (BITS == 4 ? 8 : 0);
+    // digit word h of code word cw holds rows cw * RPW + u * H + h, u < RPD
+    // the signed operand of code word w for its h-th digit word
+    static __device__ __forceinline__ uint32_t split(uint32_t w, int h) {
+        if constexpr (BITS == 8) return w ^ 0x80808080u;
+        else if constexpr (BITS == 4) return w ^ 0x88888888u;
+        else if constexpr (BITS == 2) return (w >> (2 * h)) & 0x33333333u;
+        else return (w >> h) & 0x11111111u;
+    }
+    static __device__ __forceinline__ int dot(uint32_t a, uint32_t b, int c) {
+        if constexpr (BITS == 8) return __builtin_amdgcn_sdot4(static_cast<int>(a), static_cast<int>(b), c, false);
+        else return __builtin_amdgcn_sdot8(static_cast<int>(a), static_cast<int>(b), c, false);
+    }
+};
+
+// digits of RPD fixed-point values (offset form: field d of u[t] is digit d)
+// transposed in place: afterwards field t of u[d] is digit d of value t.
+template <int BITS>
+__device__ __forceinline__ void transpose_digits(uint32_t (&u)[QDig<BITS>::RPD]) {
+    if constexpr (QDig<BITS>::DB == 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t a = u[t], b = u[t + 4];
+            u[t] = (a & 0x0000FFFFu) | (b << 16);
+            u[t + 4] = (a >> 16) | (b & 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t += 4)
+#pragma unroll
+            for (int v = t; v < t + 2; ++v) {
+                const uint32_t a = u[v], b = u[v + 2];
+                u[v] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
+                u[v + 2] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
+            }
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            const uint32_t a = u[t], b = u[t + 1];
+            u[t] = (a & 0x0F0F0F0Fu) | ((b << 4) & 0xF0F0F0F0u);
+            u[t + 1] = ((a >> 4) & 0x0F0F0F0Fu) | (b & 0xF0F0F0F0u);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const uint32_t a = u[t], b = u[t + 2];
+            u[t] = (a & 0x0000FFFFu) | (b << 16);
+            u[t + 2] = (a >> 16) | (b & 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t += 2) {
+            const uint32_t a = u[t], b = u[t + 1];
+            u[t] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
+            u[t + 1] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
+        }
+    }
+}
+
+// Sum over the wave by DPP row shifts and row broadcasts; exact for integers.
+__device__ __forceinline__ int wave_total(int v) {
+    const int t = v;
+    v = t + __builtin_amdgcn_update_dpp(0, t, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v = v + __builtin_amdgcn_update_dpp(0, t, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v = v + __builtin_amdgcn_update_dpp(0, t, 0x113, 0xf, 0xf, false);  // row_shr:3
+    v = v + __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, false);  // row_shr:4
+    v = v + __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, false);  // row_shr:8
+    v = v + __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v = v + __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Codes of columns j, j + 4, ..., j + 4 (NCI - 1) at this lane's chunk
+// offsets.  Every load is issued unconditionally (so that the next step's
+// loads stay in flight while the current step is reduced): a column at or past
+// c1 reads column c1 - 1 and is never stored, and the chunk offsets are
+// clamped into the column, where rows past the column carry zero digits.
+template <int NCI, int CPL>
+__device__ __forceinline__ void load_step(const uint8_t* q, int64_t col_bytes, int j, int c1,
+                                          const uint32_t (&off)[CPL], uint4 (&v)[NCI][CPL]) {
+#pragma unroll
+    for (int k = 0; k < NCI; ++k) {
+        const int jk = min(j + 4 * k, c1 - 1);
+        const uint8_t* pc = q + static_cast<size_t>(jk) * col_bytes;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) v[k][c] = ldg_u4(pc + off[c]);
+    }
+}
+
+// Per-workgroup constants of the step epilogue.
+struct StepOut {
+    int e;            // fixed-point exponent of the slab
+    double corr;      // code offset times sum_i N_i
+    double bsum;      // beta times sum_i N_i
+    double alpha;
+    int c0, c1, wbase;
+    bool hist;
+};
+
+// One step: the dot products of NCI columns j, j + 4, ... against the digit
+// registers, the wave sums, and the results into LDS (g of the task's
+// columns after the 2048 histogram bins, and the histogram itself).
+template <int BITS, int CPL, int NCI>
+__device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
+                                            const uint32_t (&dg)[CPL][4 * QDig<BITS>::H][QDig<BITS>::ND],
+                                            int j, const StepOut& so, uint32_t* lx,
+                                            const uint32_t* lbm) {
+    using D = QDig<BITS>;
+    constexpr int ND = D::ND, H = D::H;
+    int acc[NCI][ND];
+#pragma unroll
+    for (int k = 0; k < NCI; ++k)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[k][d] = 0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int k = 0; k < NCI; ++k) {
+                    const uint32_t w = q == 0 ? v[k][c].x : q == 1 ? v[k][c].y : q == 2 ? v[k][c].z : v[k][c].w;
+                    const uint32_t x = D::split(w, h);
+#pragma unroll
+                    for (int d = 0; d < ND; ++d) acc[k][d] = D::dot(x, dg[c][q * H + h][d], acc[k][d]);
+                }
+#pragma unroll
+    for (int k = 0; k < NCI; ++k) {
+        const int jk = j + 4 * k;
+        double t;
+        if constexpr (BITS == 8)
+            t = static_cast<double>(wave_total(acc[k][0])) + 256.0 * wave_total(acc[k][1]) +
+                65536.0 * wave_total(acc[k][2]);
+        else
+            t = static_cast<double>(wave_total(acc[k][0] + 16 * acc[k][1] + 256 * acc[k][2])) +
+                4096.0 * wave_total(acc[k][3] + 16 * acc[k][4] + 256 * acc[k][5]);
+        if ((threadIdx.x & 63) == 0 && jk < so.c1) {
+            const float gv = static_cast<float>(ldexp(so.alpha * (t + so.corr) + so.bsum, so.e));
+            lx[2048 + jk - so.c0] = __float_as_uint(gv);
+            if (so.hist && !((lbm[(jk >> 5) - so.wbase] >> (jk & 31)) & 1u))
+                atomicAdd(&lx[(__float_as_uint(gv) & 0x7FFFFFFFu) >> 20], 1u);
+        }
+    }
+}
+
+template <int BITS, int CPL>
+__global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
+    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+    using D = QDig<BITS>;
+    constexpr int RPC = 128 / BITS;            // rows per 16-byte chunk
+    constexpr int SROWS = 64 * CPL * RPC;      // rows of a slab
+    constexpr int NDW = SROWS / D::RPD;        // digit words per digit
+    constexpr int ND = D::ND, H = D::H, RPW = D::RPW;
+    constexpr int F4T = SROWS / (4 * kPassThreads);      // residual float4s per thread
+    constexpr int CWT = SROWS / (RPW * kPassThreads);    // code words per thread
+    constexpr int NCI = (CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2;  // columns per step
+    constexpr int LX = (SROWS > 2048 + kPassMaxCols) ? SROWS : 2048 + kPassMaxCols;
+    static_assert(F4T >= 1 && CWT >= 1 && SROWS % (RPW * kPassThreads) == 0, "slab too small");
+    static_assert(ND * NDW <= LX, "digits exceed the staging area");
+    // One staging area, reused: the fixed-point residual, then its digits,
+    // then (once the digits sit in registers) the histogram and the task's g.
+    __shared__ uint32_t lx[LX];
+    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];
+    __shared__ float smax[kPassThreads / 64];
+    __shared__ long long ssum[kPassThreads / 64];
+    // lx[0, 2048): histogram bins; lx[2048, 2048 + c1 - c0): g of the task
+
+    const Task tk = tasks[blockIdx.x];
+    const ProbDev& pd = P[tk.p];
+    if (pd.st->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col_chunks = static_cast<int>(pd.col_bytes / 16);
+    const int slab_chunk0 = tk.slab * 64 * CPL;
+    const int rows_here = min(SROWS, (col_chunks - slab_chunk0) * RPC);  // a multiple of 16
+    const float* rs = pd.r32 + static_cast<size_t>(slab_chunk0) * RPC;
+    uint32_t off[CPL];  // byte offsets of this lane's chunks in a column
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        off[c] = static_cast<uint32_t>(min(slab_chunk0 + lane + 64 * c, col_chunks - 1)) * 16u;
+    // The codes of the first step do not depend on r: their loads go out
+    // first and stream while the residual is being prepared.
+    constexpr int STEP = 4 * NCI;
+    uint4 cur[NCI][CPL], nxt[NCI][CPL];
+    load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv, tk.c1, off, cur);
+    load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv + STEP, tk.c1, off, nxt);
+
+    // ---- the slab's residual, coalesced 16-byte loads; its max |r|
+    float4 rv[F4T];
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < F4T; ++i) {
+        const int r4 = tid + kPassThreads * i;
+        const uint4 w = ldg_u4(rs + 4 * min(r4, rows_here / 4 - 1));
+        const bool in = 4 * r4 < rows_here;
+        rv[i] = make_float4(in ? __uint_as_float(w.x) : 0.f, in ? __uint_as_float(w.y) : 0.f,
+                            in ? __uint_as_float(w.z) : 0.f, in ? __uint_as_float(w.w) : 0.f);
+        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(rv[i].x), fabsf(rv[i].y)), fmaxf(fabsf(rv[i].z), fabsf(rv[i].w))));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) smax[wv] = mx;
+    __syncthreads();
+    mx = smax[0];
+#pragma unroll
+    for (int w = 1; w < kPassThreads / 64; ++w) mx = fmaxf(mx, smax[w]);
+    int e = 0;
+    if (mx > 0.f) {
+        int ex;
+        frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+        e = ex - 22;      // mx 2^-e in [2^21, 2^22)
+    }
+    // ---- fixed point N_i = rint(r_i 2^-e), in row order
+    long long sn = 0;
+#pragma unroll
+    for (int i = 0; i < F4T; ++i) {
+        const int n0 = static_cast<int>(rintf(ldexpf(rv[i].x, -e)));
+        const int n1 = static_cast<int>(rintf(ldexpf(rv[i].y, -e)));
+        const int n2 = static_cast<int>(rintf(ldexpf(rv[i].z, -e)));
+        const int n3 = static_cast<int>(rintf(ldexpf(rv[i].w, -e)));
+        sn += static_cast<long long>(n0 + n1) + static_cast<long long>(n2 + n3);
+        *reinterpret_cast<uint4*>(lx + 4 * (tid + kPassThreads * i)) =
+            make_uint4(static_cast<uint32_t>(n0), static_cast<uint32_t>(n1),
+                       static_cast<uint32_t>(n2), static_cast<uint32_t>(n3));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o, 64);
+    if (lane == 0) ssum[wv] = sn;
+    __syncthreads();
+    // ---- digit words of this thread's code words (rows read back from LDS)
+    uint32_t dwv[CWT][H][ND];
+#pragma unroll
+    for (int i = 0; i < CWT; ++i) {
+        const int cw = tid + kPassThreads * i;
+        uint32_t nr[RPW];
+#pragma unroll
+        for (int v = 0; v < RPW / 4; ++v) {
+            const uint4 t = *reinterpret_cast<const uint4*>(lx + cw * RPW + 4 * v);
+            nr[4 * v] = t.x;
+            nr[4 * v + 1] = t.y;
+            nr[4 * v + 2] = t.z;
+            nr[4 * v + 3] = t.w;
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            uint32_t u[D::RPD];
+#pragma unroll
+            for (int t = 0; t < D::RPD; ++t) u[t] = (nr[t * H + h] + D::OFF) ^ D::OFF;
+            transpose_digits<BITS>(u);
+#pragma unroll
+            for (int d = 0; d < ND; ++d) dwv[i][h][d] = u[d];
+        }
+    }
+    long long sumn = 0;
+#pragma unroll
+    for (int w = 0; w < kPassThreads / 64; ++w) sumn += ssum[w];
+    const double sumn_d = static_cast<double>(sumn);
+    const double corr = static_cast<double>(D::CODE_OFF) * sumn_d;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CWT; ++i)
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) lx[d * NDW + (tid + kPassThreads * i) * H + h] = dwv[i][h][d];
+    __syncthreads();
+    // ---- this lane's digit words, in code-word order
+    uint32_t dg[CPL][4 * H][ND];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int v = 0; v < 4 * H; ++v)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) dg[c][v][d] = lx[d * NDW + (lane + 64 * c) * 4 * H + v];
+    __syncthreads();
+    const bool hist = pd.nslab == 1;
+    const int wbase = tk.c0 >> 5;
+    if (hist) {
+        for (int b = tid; b < 2048; b += kPassThreads) lx[b] = 0u;
+        const int nwords = ((tk.c1 - 1) >> 5) - wbase + 1;
+        for (int w = tid; w < nwords; w += kPassThreads) lbm[w] = pd.bmsup[wbase + w];
+    }
+    __syncthreads();
+    float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
+    const double alpha = pd.alpha, beta = pd.beta;
+
+    // Each wave takes NCI columns per step (j, j + 4, ...: the four waves of
+    // the workgroup read neighbouring columns together) and issues the loads
+    // of its next step before it reduces the current one.
+    // Steady state, two buffers in turn: while one step is reduced the other
+    // is in flight (a register copy between them would wait for both).
+    const StepOut so{e, corr, beta * sumn_d, alpha, tk.c0, tk.c1, wbase, hist};
+    for (int j = tk.c0 + wv; j < tk.c1; j += 2 * STEP) {
+        reduce_step<BITS, CPL, NCI>(cur, dg, j, so, lx, lbm);
+        load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 2 * STEP, tk.c1, off, cur);
+        reduce_step<BITS, CPL, NCI>(nxt, dg, j + STEP, so, lx, lbm);
+        load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 3 * STEP, tk.c1, off, nxt);
+    }
+    // no global store inside the loop: a store under a branch would make the
+    // compiler wait for the prefetched loads as well
+    __syncthreads();
+    for (int i = tid; i < tk.c1 - tk.c0; i += kPassThreads) out[tk.c0 + i] = __uint_as_float(lx[2048 + i]);
+    if (hist)
+        for (int b = tid; b < 2048; b += kPassThreads)
+            if (lx[b]) atomicAdd(&pd.hist[b], lx[b]);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 full pass g = Q1^T r (32-bit "codes" are the floats themselves).  One
+// wave per column: lane l owns the 16-byte chunks l, l + 64, ..., l + 64
+// (CPL - 1) of its row slab and keeps the matching residual rows in registers
+// for every column it visits; each column is reduced across the wave.
 // ---------------------------------------------------------------------------
 template <int BITS, int CPL>
 __global__ __launch_bounds__(kPassThreads) void k_fullpass(
@@ -166,6 +492,15 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__
     }
 }
 
+template <typename K>
+void launch_k(K kern, int ntasks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const ProbDev* P,
+              const Task* T) {
+    if (ev0)
+        hipExtLaunchKernelGGL(kern, dim3(ntasks), dim3(kPassThreads), 0, st, ev0, ev1, 0, P, T);
+    else
+        hipLaunchKernelGGL(kern, dim3(ntasks), dim3(kPassThreads), 0, st, P, T);
+}
+
 template <int BITS>
 void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
@@ -173,12 +508,10 @@ void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStre
 #define QIHT_PASS_CASE(C)                                                                   \
     case C:                                                                                 \
         if constexpr (C <= (BITS == 32 ? 16 : BITS)) {                                      \
-            if (ev0)                                                                        \
-                hipExtLaunchKernelGGL((k_fullpass<BITS, C>), dim3(ntasks), dim3(kPassThreads), \
-                                      0, st, ev0, ev1, 0, P, T);                            \
+            if constexpr (BITS == 32)                                                       \
+                launch_k(k_fullpass<BITS, C>, ntasks, st, ev0, ev1, P, T);                  \
             else                                                                            \
-                hipLaunchKernelGGL((k_fullpass<BITS, C>), dim3(ntasks), dim3(kPassThreads), \
-                                   0, st, P, T);                                            \
+                launch_k(k_fullpass_q<BITS, C>, ntasks, st, ev0, ev1, P, T);                \
         }                                                                                   \
         break;
         QIHT_PASS_CASE(1)
@@ -191,7 +524,49 @@ void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStre
     }
 }
 
+template <int BITS>
+int pass_blocks_b(int cpl) {
+    int nb = 0;
+    hipError_t err = hipSuccess;
+    switch (cpl) {
+#define QIHT_OCC_CASE(C)                                                                        \
+    case C:                                                                                     \
+        if constexpr (C <= (BITS == 32 ? 16 : BITS)) {                                          \
+            if constexpr (BITS == 32)                                                           \
+                err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fullpass<BITS, C>,    \
+                                                                   kPassThreads, 0);            \
+            else                                                                                \
+                err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fullpass_q<BITS, C>,  \
+                                                                   kPassThreads, 0);            \
+        }                                                                                       \
+        break;
+        QIHT_OCC_CASE(1)
+        QIHT_OCC_CASE(2)
+        QIHT_OCC_CASE(4)
+        QIHT_OCC_CASE(8)
+        QIHT_OCC_CASE(16)
+#undef QIHT_OCC_CASE
+        default: break;
+    }
+    return err == hipSuccess ? nb : 0;
+}
+
 }  // namespace
+
+int pass_slots(int bits, int cpl) {
+    int dev = 0, cus = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    switch (bits) {
+        case 1: nb = pass_blocks_b<1>(cpl); break;
+        case 2: nb = pass_blocks_b<2>(cpl); break;
+        case 4: nb = pass_blocks_b<4>(cpl); break;
+        case 8: nb = pass_blocks_b<8>(cpl); break;
+        default: nb = pass_blocks_b<32>(cpl); break;
+    }
+    return nb * cus;
+}
 
 void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1) {

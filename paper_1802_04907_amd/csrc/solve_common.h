@@ -89,6 +89,21 @@ enum { SEL_RAW = 0, SEL_INIT = 1, SEL_STEP = 2 };
 // ---------------------------------------------------------------------------
 // Block helpers (fixed reduction orders: results are bitwise reproducible).
 // ---------------------------------------------------------------------------
+// Load through a global-address-space pointer: pointers read out of ProbDev
+// are generic, and generic (flat) loads make the compiler wait for every
+// outstanding load before any use, which defeats prefetching.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ldg_u4(const void* p) {
+    const u32x4_t v = *(const __attribute__((address_space(1))) u32x4_t*)(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t ldg_u32(const void* p) {
+    return *(const __attribute__((address_space(1))) uint32_t*)(p);
+}
+__device__ __forceinline__ float ldg_f32(const void* p) {
+    return *(const __attribute__((address_space(1))) float*)(p);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -157,6 +172,8 @@ void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, hipStream_t st);
 // ev0/ev1 (optional): events recorded by the dispatch itself around the
 // kernel (timing of the bandwidth-bound pass).
+// Workgroups of the full pass that the device holds at once (0 if unknown).
+int pass_slots(int bits, int cpl);
 void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,
                  hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);

@@ -5,6 +5,7 @@
 // All control state lives on the device; the host only enqueues launches
 // and, every kChunk iterations, reads the stop flags back.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -151,13 +152,22 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.beta = q->beta;
         p.alpha_f = static_cast<float>(q->alpha);
         p.yhat = in[i].yhat;
-        // full-pass tasks: about 256 KB of codes per workgroup, at least
-        // ~256 workgroups per problem when the problem is small
+    }
+    // Full-pass tasks: column ranges of one row slab, sized so that the
+    // launch is one round of the workgroups the device holds at once (a
+    // second, partial round would leave most CUs idle at the end).
+    const int slots = std::max(1, pass_slots(pl.bits, pl.cpl));
+    double total = 0.0;
+    for (int i = 0; i < count; ++i)
+        total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
+    const double per_task = std::max(1.0, total / slots);
+    for (int i = 0; i < count; ++i) {
+        const qiht_qmatrix* q = in[i].q;
+        const ProbDev& p = pl.host[i];
         const int64_t slab_bytes = std::min<int64_t>(q->col_bytes, slab_chunks * 16);
-        const int64_t tc_bw = std::max<int64_t>(8, (256 * 1024) / std::max<int64_t>(slab_bytes, 1));
-        const int64_t tc = std::min<int64_t>(
-            kPassMaxCols, std::max<int64_t>(8, std::min<int64_t>(tc_bw, (q->n + 255) / 256)));
-        for (int sl = 0; sl < nslab; ++sl)
+        const int64_t want = static_cast<int64_t>(std::ceil(per_task / static_cast<double>(slab_bytes)));
+        const int64_t tc = std::min<int64_t>(kPassMaxCols, std::max<int64_t>(4, want));
+        for (int sl = 0; sl < p.nslab; ++sl)
             for (int64_t c0 = 0; c0 < q->n; c0 += tc)
                 pl.tasks.push_back(Task{i, sl, static_cast<int32_t>(c0),
                                         static_cast<int32_t>(std::min<int64_t>(q->n, c0 + tc))});
