@@ -17,6 +17,63 @@
 namespace qiht {
 namespace {
 
+// The residual rows of row chunk wg (held by threads < 4 RPW, one row each)
+// as fixed-point digits for the full pass: the chunk's exponent, the sum of
+// its N_i, and its digit words, in the layout the full pass reads.
+template <int BITS>
+__device__ void digitize_chunk(double r, int wg, const ProbDev& pd) {
+    using D = QDig<BITS>;
+    constexpr int NR = 4 * D::RPW;  // rows of the chunk, <= 128
+    constexpr int NWR = (NR + 63) / 64;
+    constexpr int H = D::H;
+    __shared__ double smx[NWR];
+    __shared__ int ssn[NWR];
+    __shared__ int snr[NR];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double m = tid < NR ? fabs(r) : 0.0;
+    if (wv < NWR) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) smx[wv] = m;
+    }
+    __syncthreads();
+    double mx = smx[0];
+#pragma unroll
+    for (int w = 1; w < NWR; ++w) mx = fmax(mx, smx[w]);
+    int e = 0;
+    if (mx > 0.0) {
+        int ex;
+        frexp(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+        e = ex - 22;     // mx 2^-e in [2^21, 2^22)
+    }
+    if (wv < NWR) {
+        const int nv = tid < NR ? static_cast<int>(rint(ldexp(r, -e))) : 0;
+        if (tid < NR) snr[tid] = nv;
+        int sn = nv;  // |sum| <= 64 * 2^22
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o, 64);
+        if (lane == 0) ssn[wv] = sn;
+    }
+    __syncthreads();
+    const size_t words = static_cast<size_t>(pd.nwg) * 4 * H;  // digit words per digit
+    if (tid < 4 * H) {  // digit word tid of the chunk: code word tid / H, rows offset tid % H
+        const int cw = tid / H, h = tid % H;
+        uint32_t u[D::RPD];
+#pragma unroll
+        for (int t = 0; t < D::RPD; ++t) u[t] = (static_cast<uint32_t>(snr[cw * D::RPW + t * H + h]) + D::OFF) ^ D::OFF;
+        transpose_digits<BITS>(u);
+#pragma unroll
+        for (int d = 0; d < D::ND; ++d) pd.rdig[d * words + static_cast<size_t>(wg) * 4 * H + tid] = u[d];
+    }
+    if (tid == 0) {
+        int sn = ssn[0];
+#pragma unroll
+        for (int w = 1; w < NWR; ++w) sn += ssn[w];
+        pd.rexp[wg] = e;
+        pd.rsum[wg] = sn;
+    }
+}
+
 template <int BITS, int MODE>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __restrict__ P,
                                                            SolveArgs a, int zero_x) {
@@ -137,7 +194,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     double wtot = 0.0;
 #pragma unroll
     for (int v = 0; v < NW; ++v) wtot += shw[v];
-    double l1 = 0.0, l2 = 0.0;
+    double l1 = 0.0, l2 = 0.0, rres = 0.0;
     if (threadIdx.x < 4 * RPW) {
         const int ww = threadIdx.x / RPW, q = threadIdx.x % RPW;
         const size_t row = (static_cast<size_t>(wg) * 4 + ww) * RPW + q;
@@ -151,7 +208,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
         const bool live = row < static_cast<size_t>(pd.rows);
         if (MODE == G_R) {
-            pd.r32[row] = live ? static_cast<float>(pd.yhat[row] - val[0]) : 0.0f;
+            rres = live ? pd.yhat[row] - val[0] : 0.0;
+            pd.r32[row] = static_cast<float>(rres);
         } else if (live) {
             if (MODE == G_MU) {
                 l1 = two ? val[0] * val[NM - 1] : val[0] * val[0];
@@ -161,7 +219,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             }
         }
     }
-    if (MODE == G_R) return;
+    if constexpr (MODE == G_R) {
+        if constexpr (BITS != 32) digitize_chunk<BITS>(rres, wg, pd);
+        return;
+    }
     // rows of this group: at most 4 * RPW <= 128 threads hold values
     const double s1 = block_sum<kGatherThreads>(l1, shr);
     if (MODE == G_MU) {

@@ -57,102 +57,46 @@ __device__ __forceinline__ void dot_word(uint32_t w, const float* r, float& a0,
 }
 
 // ---------------------------------------------------------------------------
-// Exact integer form of the packed-code pass.  The residual rows of a slab are
-// put on one fixed-point grid, r~_i = N_i 2^e with |N_i| <= 2^22 (e from the
-// slab's largest |r_i|), and N_i is split into signed digits: six base-16
-// digits in [-8, 7] for codes of 1, 2 or 4 bits, three base-256 digits in
-// [-128, 127] for 8-bit codes.  The digits are transposed so that each 32-bit
-// digit word lines up with the codes of one code word, and the codes enter
-// the integer dot instructions as they are stored (4- and 8-bit codes biased
-// to signed by an xor).  Every column then costs one dot instruction per
-// digit per code word and the sum over the rows is exact:
-//   sum_i k_ij N_i = sum_d base^d sum_i (k_ij - off) e_d(N_i) + off sum_i N_i,
-// and g_j = 2^e (alpha sum_i k_ij N_i + beta sum_i N_i) is rounded once, from
-// FP64, to FP32.  The only approximation is r -> r~ (relative 2^-22 of the
-// largest |r_i|).
+// Packed-code full pass on the integer dot instructions.  The residual comes
+// in as fixed-point digits, one scale per 16-byte row chunk (written by the
+// residual gather).  A lane holds the digit words of its chunks in registers
+// and, per column, accumulates one dot instruction per digit per code word;
+// a chunk's integer sums are exact, and the chunk's scale is applied in FP64:
+//   g_j = sum_chunks 2^e (alpha sum_i k_ij N_i + beta sum_i N_i),
+// with the column-independent part (the code offset and beta terms) summed
+// once per workgroup.  The only approximation is r -> N 2^e (a relative
+// 2^-22 of the chunk's largest |r_i|); g is rounded once, from FP64, to FP32.
 // ---------------------------------------------------------------------------
-template <int BITS>
-struct QDig {
-    static constexpr int DB = (BITS == 8) ? 8 : 4;         // digit width
-    static constexpr int ND = (BITS == 8) ? 3 : 6;         // digits per row
-    static constexpr int RPD = 32 / DB;                    // rows per digit word
-    static constexpr int H = (BITS == 8) ? 1 : 4 / BITS;   // digit words per code word
-    static constexpr int RPW = 32 / BITS;                  // rows per code word
-    static constexpr uint32_t OFF = (BITS == 8) ? 0x808080u : 0x888888u;
-    static constexpr int CODE_OFF = (BITS == 8) ? 128 : (BITS == 4 ? 8 : 0);
-    // digit word h of code word cw holds rows cw * RPW + u * H + h, u < RPD
-    // the signed operand of code word w for its h-th digit word
-    static __device__ __forceinline__ uint32_t split(uint32_t w, int h) {
-        if constexpr (BITS == 8) return w ^ 0x80808080u;
-        else if constexpr (BITS == 4) return w ^ 0x88888888u;
-        else if constexpr (BITS == 2) return (w >> (2 * h)) & 0x33333333u;
-        else return (w >> h) & 0x11111111u;
-    }
-    static __device__ __forceinline__ int dot(uint32_t a, uint32_t b, int c) {
-        if constexpr (BITS == 8) return __builtin_amdgcn_sdot4(static_cast<int>(a), static_cast<int>(b), c, false);
-        else return __builtin_amdgcn_sdot8(static_cast<int>(a), static_cast<int>(b), c, false);
-    }
-};
 
-// digits of RPD fixed-point values (offset form: field d of u[t] is digit d)
-// transposed in place: afterwards field t of u[d] is digit d of value t.
-template <int BITS>
-__device__ __forceinline__ void transpose_digits(uint32_t (&u)[QDig<BITS>::RPD]) {
-    if constexpr (QDig<BITS>::DB == 4) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint32_t a = u[t], b = u[t + 4];
-            u[t] = (a & 0x0000FFFFu) | (b << 16);
-            u[t + 4] = (a >> 16) | (b & 0xFFFF0000u);
-        }
-#pragma unroll
-        for (int t = 0; t < 8; t += 4)
-#pragma unroll
-            for (int v = t; v < t + 2; ++v) {
-                const uint32_t a = u[v], b = u[v + 2];
-                u[v] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
-                u[v + 2] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
-            }
-#pragma unroll
-        for (int t = 0; t < 8; t += 2) {
-            const uint32_t a = u[t], b = u[t + 1];
-            u[t] = (a & 0x0F0F0F0Fu) | ((b << 4) & 0xF0F0F0F0u);
-            u[t + 1] = ((a >> 4) & 0x0F0F0F0Fu) | (b & 0xF0F0F0F0u);
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const uint32_t a = u[t], b = u[t + 2];
-            u[t] = (a & 0x0000FFFFu) | (b << 16);
-            u[t + 2] = (a >> 16) | (b & 0xFFFF0000u);
-        }
-#pragma unroll
-        for (int t = 0; t < 4; t += 2) {
-            const uint32_t a = u[t], b = u[t + 1];
-            u[t] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
-            u[t + 1] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
-        }
-    }
+// DPP moves of the two halves of a double (lanes the pattern does not feed
+// read 0).
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, RM, BM, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, BM, false));
 }
 
-// Sum over the wave by DPP row shifts and row broadcasts; exact for integers.
-__device__ __forceinline__ int wave_total(int v) {
-    const int t = v;
-    v = t + __builtin_amdgcn_update_dpp(0, t, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v = v + __builtin_amdgcn_update_dpp(0, t, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v = v + __builtin_amdgcn_update_dpp(0, t, 0x113, 0xf, 0xf, false);  // row_shr:3
-    v = v + __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xe, false);  // row_shr:4
-    v = v + __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xc, false);  // row_shr:8
-    v = v + __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v = v + __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
+// Sum over the wave in a fixed order (row shifts, then row broadcasts), read
+// from lane 63.
+__device__ __forceinline__ double wave_total_f64(double v) {
+    const double t = v;
+    v = t + dpp_f64<0x111, 0xf, 0xf>(t);  // row_shr:1
+    v = v + dpp_f64<0x112, 0xf, 0xf>(t);  // row_shr:2
+    v = v + dpp_f64<0x113, 0xf, 0xf>(t);  // row_shr:3
+    v = v + dpp_f64<0x114, 0xf, 0xe>(v);  // row_shr:4
+    v = v + dpp_f64<0x118, 0xf, 0xc>(v);  // row_shr:8
+    v = v + dpp_f64<0x142, 0xa, 0xf>(v);  // row_bcast:15
+    v = v + dpp_f64<0x143, 0xc, 0xf>(v);  // row_bcast:31
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 // Codes of columns j, j + 4, ..., j + 4 (NCI - 1) at this lane's chunk
 // offsets.  Every load is issued unconditionally (so that the next step's
 // loads stay in flight while the current step is reduced): a column at or past
 // c1 reads column c1 - 1 and is never stored, and the chunk offsets are
-// clamped into the column, where rows past the column carry zero digits.
+// clamped into the column, where a chunk past the column has zero weight.
 template <int NCI, int CPL>
 __device__ __forceinline__ void load_step(const uint8_t* q, int64_t col_bytes, int j, int c1,
                                           const uint32_t (&off)[CPL], uint4 (&v)[NCI][CPL]) {
@@ -167,31 +111,31 @@ __device__ __forceinline__ void load_step(const uint8_t* q, int64_t col_bytes, i
 
 // Per-workgroup constants of the step epilogue.
 struct StepOut {
-    int e;            // fixed-point exponent of the slab
-    double corr;      // code offset times sum_i N_i
-    double bsum;      // beta times sum_i N_i
-    double alpha;
+    double bsum;  // column-independent part of g for this slab
     int c0, c1, wbase;
     bool hist;
 };
 
-// One step: the dot products of NCI columns j, j + 4, ... against the digit
-// registers, the wave sums, and the results into LDS (g of the task's
+// One step: NCI columns j, j + 4, ... against the digit registers, the
+// chunk scales, the wave sums, and the results into LDS (g of the task's
 // columns after the 2048 histogram bins, and the histogram itself).
 template <int BITS, int CPL, int NCI>
 __device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
                                             const uint32_t (&dg)[CPL][4 * QDig<BITS>::H][QDig<BITS>::ND],
-                                            int j, const StepOut& so, uint32_t* lx,
-                                            const uint32_t* lbm) {
+                                            const double (&ac)[CPL], int j, const StepOut& so,
+                                            uint32_t* lx, const uint32_t* lbm) {
     using D = QDig<BITS>;
     constexpr int ND = D::ND, H = D::H;
-    int acc[NCI][ND];
+    double col[NCI];
 #pragma unroll
-    for (int k = 0; k < NCI; ++k)
+    for (int k = 0; k < NCI; ++k) col[k] = 0.0;
 #pragma unroll
-        for (int d = 0; d < ND; ++d) acc[k][d] = 0;
+    for (int c = 0; c < CPL; ++c) {
+        int acc[NCI][ND];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c)
+        for (int k = 0; k < NCI; ++k)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) acc[k][d] = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -204,17 +148,22 @@ __device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
                     for (int d = 0; d < ND; ++d) acc[k][d] = D::dot(x, dg[c][q * H + h][d], acc[k][d]);
                 }
 #pragma unroll
+        for (int k = 0; k < NCI; ++k) {
+            double t;
+            if constexpr (BITS == 8)
+                t = static_cast<double>(acc[k][0] + 256 * acc[k][1]) + 65536.0 * acc[k][2];
+            else
+                t = static_cast<double>(acc[k][0] + 16 * acc[k][1] + 256 * acc[k][2]) +
+                    4096.0 * static_cast<double>(acc[k][3] + 16 * acc[k][4] + 256 * acc[k][5]);
+            col[k] = fma(ac[c], t, col[k]);
+        }
+    }
+#pragma unroll
     for (int k = 0; k < NCI; ++k) {
         const int jk = j + 4 * k;
-        double t;
-        if constexpr (BITS == 8)
-            t = static_cast<double>(wave_total(acc[k][0])) + 256.0 * wave_total(acc[k][1]) +
-                65536.0 * wave_total(acc[k][2]);
-        else
-            t = static_cast<double>(wave_total(acc[k][0] + 16 * acc[k][1] + 256 * acc[k][2])) +
-                4096.0 * wave_total(acc[k][3] + 16 * acc[k][4] + 256 * acc[k][5]);
+        const double t = wave_total_f64(col[k]);
         if ((threadIdx.x & 63) == 0 && jk < so.c1) {
-            const float gv = static_cast<float>(ldexp(so.alpha * (t + so.corr) + so.bsum, so.e));
+            const float gv = static_cast<float>(t + so.bsum);
             lx[2048 + jk - so.c0] = __float_as_uint(gv);
             if (so.hist && !((lbm[(jk >> 5) - so.wbase] >> (jk & 31)) & 1u))
                 atomicAdd(&lx[(__float_as_uint(gv) & 0x7FFFFFFFu) >> 20], 1u);
@@ -226,23 +175,14 @@ template <int BITS, int CPL>
 __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
     const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
     using D = QDig<BITS>;
-    constexpr int RPC = 128 / BITS;            // rows per 16-byte chunk
-    constexpr int SROWS = 64 * CPL * RPC;      // rows of a slab
-    constexpr int NDW = SROWS / D::RPD;        // digit words per digit
-    constexpr int ND = D::ND, H = D::H, RPW = D::RPW;
-    constexpr int F4T = SROWS / (4 * kPassThreads);      // residual float4s per thread
-    constexpr int CWT = SROWS / (RPW * kPassThreads);    // code words per thread
+    constexpr int RPC = 128 / BITS;  // rows per 16-byte chunk
+    constexpr int ND = D::ND, H = D::H;
     constexpr int NCI = (CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2;  // columns per step
-    constexpr int LX = (SROWS > 2048 + kPassMaxCols) ? SROWS : 2048 + kPassMaxCols;
-    static_assert(F4T >= 1 && CWT >= 1 && SROWS % (RPW * kPassThreads) == 0, "slab too small");
-    static_assert(ND * NDW <= LX, "digits exceed the staging area");
-    // One staging area, reused: the fixed-point residual, then its digits,
-    // then (once the digits sit in registers) the histogram and the task's g.
-    __shared__ uint32_t lx[LX];
-    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];
-    __shared__ float smax[kPassThreads / 64];
-    __shared__ long long ssum[kPassThreads / 64];
+    constexpr int STEP = 4 * NCI;
     // lx[0, 2048): histogram bins; lx[2048, 2048 + c1 - c0): g of the task
+    __shared__ uint32_t lx[2048 + kPassMaxCols];
+    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];
+    __shared__ double sb[kPassThreads / 64];
 
     const Task tk = tasks[blockIdx.x];
     const ProbDev& pd = P[tk.p];
@@ -250,107 +190,43 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int col_chunks = static_cast<int>(pd.col_bytes / 16);
     const int slab_chunk0 = tk.slab * 64 * CPL;
-    const int rows_here = min(SROWS, (col_chunks - slab_chunk0) * RPC);  // a multiple of 16
-    const float* rs = pd.r32 + static_cast<size_t>(slab_chunk0) * RPC;
+    (void)RPC;
+
+    // ---- this lane's chunks: digit words, scales; then the first two steps
+    int chk[CPL];
     uint32_t off[CPL];  // byte offsets of this lane's chunks in a column
 #pragma unroll
-    for (int c = 0; c < CPL; ++c)
-        off[c] = static_cast<uint32_t>(min(slab_chunk0 + lane + 64 * c, col_chunks - 1)) * 16u;
-    // The codes of the first step do not depend on r: their loads go out
-    // first and stream while the residual is being prepared.
-    constexpr int STEP = 4 * NCI;
+    for (int c = 0; c < CPL; ++c) {
+        chk[c] = slab_chunk0 + lane + 64 * c;
+        off[c] = static_cast<uint32_t>(min(chk[c], col_chunks - 1)) * 16u;
+    }
+    const size_t dwords = static_cast<size_t>(col_chunks) * 4 * H;  // digit words per digit
+    uint32_t dg[CPL][4 * H][ND];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const size_t w0 = static_cast<size_t>(min(chk[c], col_chunks - 1)) * 4 * H;
+#pragma unroll
+        for (int d = 0; d < ND; ++d)
+#pragma unroll
+            for (int v4 = 0; v4 < H; ++v4) {
+                const uint4 t = ldg_u4(pd.rdig + d * dwords + w0 + 4 * v4);
+                dg[c][4 * v4 + 0][d] = t.x;
+                dg[c][4 * v4 + 1][d] = t.y;
+                dg[c][4 * v4 + 2][d] = t.z;
+                dg[c][4 * v4 + 3][d] = t.w;
+            }
+    }
+    int ex[CPL], sn[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int cc = min(chk[c], col_chunks - 1);
+        ex[c] = static_cast<int>(ldg_u32(pd.rexp + cc));
+        sn[c] = static_cast<int>(ldg_u32(pd.rsum + cc));
+    }
     uint4 cur[NCI][CPL], nxt[NCI][CPL];
     load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv, tk.c1, off, cur);
     load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv + STEP, tk.c1, off, nxt);
 
-    // ---- the slab's residual, coalesced 16-byte loads; its max |r|
-    float4 rv[F4T];
-    float mx = 0.f;
-#pragma unroll
-    for (int i = 0; i < F4T; ++i) {
-        const int r4 = tid + kPassThreads * i;
-        const uint4 w = ldg_u4(rs + 4 * min(r4, rows_here / 4 - 1));
-        const bool in = 4 * r4 < rows_here;
-        rv[i] = make_float4(in ? __uint_as_float(w.x) : 0.f, in ? __uint_as_float(w.y) : 0.f,
-                            in ? __uint_as_float(w.z) : 0.f, in ? __uint_as_float(w.w) : 0.f);
-        mx = fmaxf(mx, fmaxf(fmaxf(fabsf(rv[i].x), fabsf(rv[i].y)), fmaxf(fabsf(rv[i].z), fabsf(rv[i].w))));
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    if (lane == 0) smax[wv] = mx;
-    __syncthreads();
-    mx = smax[0];
-#pragma unroll
-    for (int w = 1; w < kPassThreads / 64; ++w) mx = fmaxf(mx, smax[w]);
-    int e = 0;
-    if (mx > 0.f) {
-        int ex;
-        frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
-        e = ex - 22;      // mx 2^-e in [2^21, 2^22)
-    }
-    // ---- fixed point N_i = rint(r_i 2^-e), in row order
-    long long sn = 0;
-#pragma unroll
-    for (int i = 0; i < F4T; ++i) {
-        const int n0 = static_cast<int>(rintf(ldexpf(rv[i].x, -e)));
-        const int n1 = static_cast<int>(rintf(ldexpf(rv[i].y, -e)));
-        const int n2 = static_cast<int>(rintf(ldexpf(rv[i].z, -e)));
-        const int n3 = static_cast<int>(rintf(ldexpf(rv[i].w, -e)));
-        sn += static_cast<long long>(n0 + n1) + static_cast<long long>(n2 + n3);
-        *reinterpret_cast<uint4*>(lx + 4 * (tid + kPassThreads * i)) =
-            make_uint4(static_cast<uint32_t>(n0), static_cast<uint32_t>(n1),
-                       static_cast<uint32_t>(n2), static_cast<uint32_t>(n3));
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sn += __shfl_xor(sn, o, 64);
-    if (lane == 0) ssum[wv] = sn;
-    __syncthreads();
-    // ---- digit words of this thread's code words (rows read back from LDS)
-    uint32_t dwv[CWT][H][ND];
-#pragma unroll
-    for (int i = 0; i < CWT; ++i) {
-        const int cw = tid + kPassThreads * i;
-        uint32_t nr[RPW];
-#pragma unroll
-        for (int v = 0; v < RPW / 4; ++v) {
-            const uint4 t = *reinterpret_cast<const uint4*>(lx + cw * RPW + 4 * v);
-            nr[4 * v] = t.x;
-            nr[4 * v + 1] = t.y;
-            nr[4 * v + 2] = t.z;
-            nr[4 * v + 3] = t.w;
-        }
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            uint32_t u[D::RPD];
-#pragma unroll
-            for (int t = 0; t < D::RPD; ++t) u[t] = (nr[t * H + h] + D::OFF) ^ D::OFF;
-            transpose_digits<BITS>(u);
-#pragma unroll
-            for (int d = 0; d < ND; ++d) dwv[i][h][d] = u[d];
-        }
-    }
-    long long sumn = 0;
-#pragma unroll
-    for (int w = 0; w < kPassThreads / 64; ++w) sumn += ssum[w];
-    const double sumn_d = static_cast<double>(sumn);
-    const double corr = static_cast<double>(D::CODE_OFF) * sumn_d;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < CWT; ++i)
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-            for (int d = 0; d < ND; ++d) lx[d * NDW + (tid + kPassThreads * i) * H + h] = dwv[i][h][d];
-    __syncthreads();
-    // ---- this lane's digit words, in code-word order
-    uint32_t dg[CPL][4 * H][ND];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c)
-#pragma unroll
-        for (int v = 0; v < 4 * H; ++v)
-#pragma unroll
-            for (int d = 0; d < ND; ++d) dg[c][v][d] = lx[d * NDW + (lane + 64 * c) * 4 * H + v];
-    __syncthreads();
     const bool hist = pd.nslab == 1;
     const int wbase = tk.c0 >> 5;
     if (hist) {
@@ -358,25 +234,33 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
         const int nwords = ((tk.c1 - 1) >> 5) - wbase + 1;
         for (int w = tid; w < nwords; w += kPassThreads) lbm[w] = pd.bmsup[wbase + w];
     }
+    // chunk weights: alpha 2^e on the code sums, and the slab's
+    // column-independent part 2^e (alpha off + beta) sum_i N_i
+    double ac[CPL];
+    double bl = 0.0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const bool in = chk[c] < col_chunks;
+        ac[c] = in ? ldexp(pd.alpha, ex[c]) : 0.0;
+        bl += in ? ldexp((pd.alpha * D::CODE_OFF + pd.beta) * static_cast<double>(sn[c]), ex[c]) : 0.0;
+    }
+    const double bsum = wave_total_f64(bl);  // every wave holds all chunks of the slab
+    (void)sb;
     __syncthreads();
-    float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
-    const double alpha = pd.alpha, beta = pd.beta;
 
-    // Each wave takes NCI columns per step (j, j + 4, ...: the four waves of
-    // the workgroup read neighbouring columns together) and issues the loads
-    // of its next step before it reduces the current one.
     // Steady state, two buffers in turn: while one step is reduced the other
     // is in flight (a register copy between them would wait for both).
-    const StepOut so{e, corr, beta * sumn_d, alpha, tk.c0, tk.c1, wbase, hist};
+    const StepOut so{bsum, tk.c0, tk.c1, wbase, hist};
     for (int j = tk.c0 + wv; j < tk.c1; j += 2 * STEP) {
-        reduce_step<BITS, CPL, NCI>(cur, dg, j, so, lx, lbm);
+        reduce_step<BITS, CPL, NCI>(cur, dg, ac, j, so, lx, lbm);
         load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 2 * STEP, tk.c1, off, cur);
-        reduce_step<BITS, CPL, NCI>(nxt, dg, j + STEP, so, lx, lbm);
+        reduce_step<BITS, CPL, NCI>(nxt, dg, ac, j + STEP, so, lx, lbm);
         load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 3 * STEP, tk.c1, off, nxt);
     }
     // no global store inside the loop: a store under a branch would make the
     // compiler wait for the prefetched loads as well
     __syncthreads();
+    float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
     for (int i = tid; i < tk.c1 - tk.c0; i += kPassThreads) out[tk.c0 + i] = __uint_as_float(lx[2048 + i]);
     if (hist)
         for (int b = tid; b < 2048; b += kPassThreads)

@@ -61,6 +61,9 @@ struct ProbDev {
     float pad_f;
     const double* yhat;
     float* r32;         // residual, rows_pad (zero beyond rows)
+    uint32_t* rdig;     // residual digits, digit-major: ND x (nwg * 4H) words
+    int32_t* rexp;      // per row chunk: fixed-point exponent e
+    int32_t* rsum;      // per row chunk: sum_i N_i
     float* g;           // gradient, n
     float* gpart;       // nslab * n slab partials (nslab > 1)
     uint32_t* hist;     // 2048-bin histogram of the top 11 bits of |g|
@@ -82,6 +85,93 @@ struct ProbDev {
 struct Task {
     int32_t p, slab, c0, c1;
 };
+
+// ---------------------------------------------------------------------------
+// Fixed-point residual digits for the packed-code full pass.  The residual
+// rows of one 16-byte row chunk (the rows one gather workgroup owns) share a
+// scale: r~_i = N_i 2^e with |N_i| <= 2^22, e from the chunk's largest |r_i|.
+// N_i is split into signed digits (six base-16 digits in [-8, 7] for codes of
+// 1, 2 or 4 bits, three base-256 digits in [-128, 127] for 8-bit codes),
+// transposed so that one 32-bit digit word lines up with the codes of one
+// code word, and stored as rdig[d][chunk * 4H + v] (digit d, digit word v of
+// the chunk).  The integer dot instructions then take the codes as stored
+// (4- and 8-bit codes biased to signed by an xor):
+//   sum_i k_i N_i = sum_d base^d sum_i (k_i - off) e_d(N_i) + off sum_i N_i.
+// ---------------------------------------------------------------------------
+template <int BITS>
+struct QDig {
+    static constexpr int DB = (BITS == 8) ? 8 : 4;         // digit width
+    static constexpr int ND = (BITS == 8) ? 3 : 6;         // digits per row
+    static constexpr int RPD = 32 / DB;                    // rows per digit word
+    static constexpr int H = (BITS == 8) ? 1 : 4 / BITS;   // digit words per code word
+    static constexpr int RPW = 32 / BITS;                  // rows per code word
+    static constexpr uint32_t OFF = (BITS == 8) ? 0x808080u : 0x888888u;
+    static constexpr int CODE_OFF = (BITS == 8) ? 128 : (BITS == 4 ? 8 : 0);
+    // digit word h of code word cw holds rows cw * RPW + u * H + h, u < RPD
+    // the signed operand of code word w for its h-th digit word
+    static __device__ __forceinline__ uint32_t split(uint32_t w, int h) {
+        if constexpr (BITS == 8) return w ^ 0x80808080u;
+        else if constexpr (BITS == 4) return w ^ 0x88888888u;
+        else if constexpr (BITS == 2) return (w >> (2 * h)) & 0x33333333u;
+        else return (w >> h) & 0x11111111u;
+    }
+    static __device__ __forceinline__ int dot(uint32_t a, uint32_t b, int c) {
+        if constexpr (BITS == 8) return __builtin_amdgcn_sdot4(static_cast<int>(a), static_cast<int>(b), c, false);
+        else return __builtin_amdgcn_sdot8(static_cast<int>(a), static_cast<int>(b), c, false);
+    }
+};
+
+// digits of RPD fixed-point values (offset form: field d of u[t] is digit d)
+// transposed in place: afterwards field t of u[d] is digit d of value t.
+template <int BITS>
+__device__ __forceinline__ void transpose_digits(uint32_t (&u)[QDig<BITS>::RPD]) {
+    if constexpr (QDig<BITS>::DB == 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t a = u[t], b = u[t + 4];
+            u[t] = (a & 0x0000FFFFu) | (b << 16);
+            u[t + 4] = (a >> 16) | (b & 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t += 4)
+#pragma unroll
+            for (int v = t; v < t + 2; ++v) {
+                const uint32_t a = u[v], b = u[v + 2];
+                u[v] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
+                u[v + 2] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
+            }
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            const uint32_t a = u[t], b = u[t + 1];
+            u[t] = (a & 0x0F0F0F0Fu) | ((b << 4) & 0xF0F0F0F0u);
+            u[t + 1] = ((a >> 4) & 0x0F0F0F0Fu) | (b & 0xF0F0F0F0u);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const uint32_t a = u[t], b = u[t + 2];
+            u[t] = (a & 0x0000FFFFu) | (b << 16);
+            u[t + 2] = (a >> 16) | (b & 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t += 2) {
+            const uint32_t a = u[t], b = u[t + 1];
+            u[t] = (a & 0x00FF00FFu) | ((b << 8) & 0xFF00FF00u);
+            u[t + 1] = ((a >> 8) & 0x00FF00FFu) | (b & 0xFF00FF00u);
+        }
+    }
+}
+
+// 32-bit digit words per 16-byte row chunk (0 for FP32 codes).
+inline int digit_words_per_chunk(int bits) {
+    switch (bits) {
+        case 8: return 3 * 4;
+        case 4: return 6 * 4;
+        case 2: return 6 * 8;
+        case 1: return 6 * 16;
+        default: return 0;
+    }
+}
 
 enum { G_R = 0, G_MU = 1, G_OMEGA = 2 };
 enum { SEL_RAW = 0, SEL_INIT = 1, SEL_STEP = 2 };

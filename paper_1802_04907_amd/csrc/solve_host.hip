@@ -84,7 +84,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t r32, g, gpart, hist, x, sup, xs, gs, bmsup, csup, cval, dlist, dw, meta, part_mu,
+    size_t r32, rdig, rexp, rsum, g, gpart, hist, x, sup, xs, gs, bmsup, csup, cval, dlist, dw, meta, part_mu,
         part_om, st;
 };
 
@@ -122,6 +122,9 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         pl.any_slab = pl.any_slab || nslab > 1;
         Layout& L = pl.lay[i];
         L.r32 = cv.take<float>(q->rows_pad);
+        L.rdig = cv.take<uint32_t>(static_cast<size_t>(nwg) * digit_words_per_chunk(q->bits));
+        L.rexp = cv.take<int32_t>(nwg);
+        L.rsum = cv.take<int32_t>(nwg);
         L.g = cv.take<float>(q->n);
         L.gpart = cv.take<float>(nslab > 1 ? static_cast<size_t>(nslab) * q->n : 1);
         L.hist = cv.take<uint32_t>(2048);
@@ -187,6 +190,9 @@ void bind(Plan& pl, uint8_t* base) {
         ProbDev& p = pl.host[i];
         const Layout& L = pl.lay[i];
         p.r32 = reinterpret_cast<float*>(base + L.r32);
+        p.rdig = reinterpret_cast<uint32_t*>(base + L.rdig);
+        p.rexp = reinterpret_cast<int32_t*>(base + L.rexp);
+        p.rsum = reinterpret_cast<int32_t*>(base + L.rsum);
         p.g = reinterpret_cast<float*>(base + L.g);
         p.gpart = reinterpret_cast<float*>(base + L.gpart);
         p.hist = reinterpret_cast<uint32_t*>(base + L.hist);
