@@ -234,6 +234,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     } else if (threadIdx.x == 0) {
         pd.part_om[static_cast<size_t>(set) * pd.nwg + wg] = s1;
     }
+    // g is final here: the off-support candidates of this iteration's proposals
+    if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.nwg, true);
 }
 
 template <int MODE>

@@ -36,22 +36,24 @@ struct SelShared {
     uint32_t hist[2048];
     uint32_t hist2[1024];        // second and third radix digits
     uint32_t hist3[1024];
-    uint32_t bm_old[kBmWords];   // current support
-    uint32_t bm_new[kBmWords];   // selected set
-    uint32_t bm_tie[kBmWords];   // candidates equal to the threshold key
-    uint32_t wpre[kBmWords];     // per-word prefix counts
     union {
-        struct {                 // fast path: the candidate list
-            uint32_t ckey[kCandCap];
-            int32_t cidx[kCandCap];
-            float cval[kCandCap];  // a_j = x_j + mu g_j
-            float cxo[kCandCap];   // x_j (0 off the support)
-        } c;
-        uint32_t cnt[kSelectThreads];  // full path: per (round, wave) counts
+        struct {                 // fast path: the candidates in index order
+            uint32_t mkey[kCandCap];  //   |a_j| as FP32 bits
+            uint32_t midx[kCandCap];  //   j, bit 31 when on the support
+            float mval[kCandCap];     //   a_j
+            float mxo[kCandCap];      //   x_j
+        } f;
+        struct {                 // full path: bitmaps over all n
+            uint32_t bm_old[kBmWords];   // current support
+            uint32_t bm_new[kBmWords];   // selected set
+            uint32_t bm_tie[kBmWords];   // keys equal to the threshold key
+            uint32_t wpre[kBmWords];     // per-word prefix counts
+            uint32_t cnt[kSelectThreads];
+        } b;
     } u;
     uint32_t scan[16];
-    uint32_t bin, krem, ncand, total;
-    int changed;
+    uint32_t bin, krem, total, nc;
+    int changed, bad, full;
     double red[16];
     double red3[3][16];
 };
@@ -146,11 +148,11 @@ __device__ void emit_support(int n, int s, const float* a_in, const float* g, co
     const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
     const int w0 = tid * wpt;
     uint32_t c = 0;
-    for (int w = w0; w < min(words, w0 + wpt); ++w) c += __popc(S.bm_new[w]);
+    for (int w = w0; w < min(words, w0 + wpt); ++w) c += __popc(S.u.b.bm_new[w]);
     uint32_t pos = block_excl_scan<kSelectThreads>(c, S.scan, nullptr);
     int changed = 0;
     for (int w = w0; w < min(words, w0 + wpt); ++w) {
-        uint32_t u = S.bm_new[w];
+        uint32_t u = S.u.b.bm_new[w];
         while (u) {
             const int b = __ffs(u) - 1;
             u &= u - 1;
@@ -169,27 +171,19 @@ __device__ void emit_support(int n, int s, const float* a_in, const float* g, co
     __syncthreads();
 }
 
-// Rank over keys held in registers (thread t owns t, t + 1024, ...): the
-// full path.  Sets the selection bitmap S.bm_new.
-template <int CPT, int MODE>
+// Rank over all n keys: the full path (and plain H_s).  Thread t visits
+// t, t + 1024, ...; the keys are recomputed from the inputs on every radix
+// pass instead of being held in registers, which keeps this rarely taken path
+// from inflating the register budget of the fast path it shares a kernel
+// with.  Sets the selection bitmap S.u.b.bm_new.
+template <int MODE>
 __device__ void select_full(int n, int s, const float* a_in, const float* g, const float* x,
                             float muf, SelShared& S, int* err) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    uint32_t key[CPT];
+    const int rounds = (n + kSelectThreads - 1) / kSelectThreads;  // <= 64
     int bad = 0;
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const int j = tid + kSelectThreads * e;
-        key[e] = 0u;
-        if (j < n) {
-            key[e] = abs_key(value_at<MODE>(a_in, g, x, muf, j));
-            if (key[e] > 0x7F800000u) bad = 1;
-        }
-    }
-    if (bad) atomicOr(err, 1);
     uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
-#pragma unroll
     for (int pass = 0; pass < 3; ++pass) {
         const int width = pass == 0 ? 11 : 10;
         const int sh = pass == 0 ? 20 : (pass == 1 ? 10 : 0);
@@ -198,66 +192,47 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
         for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
         __syncthreads();
         if (krem > 0) {
-#pragma unroll
-            for (int e = 0; e < CPT; ++e) {
+            for (int e = 0; e < rounds; ++e) {
                 const int j = tid + kSelectThreads * e;
-                if (j < n && (pass == 0 || (key[e] >> hsh) == prefix))
-                    atomicAdd(&S.hist[(key[e] >> sh) & (nb - 1)], 1u);
+                if (j < n) {
+                    const uint32_t key = abs_key(value_at<MODE>(a_in, g, x, muf, j));
+                    if (pass == 0 && key > 0x7F800000u) bad = 1;
+                    if (pass == 0 || (key >> hsh) == prefix)
+                        atomicAdd(&S.hist[(key >> sh) & (nb - 1)], 1u);
+                }
             }
         }
         __syncthreads();
         find_bin(S, nb, prefix, krem, width);
     }
+    if (bad) atomicOr(err, 1);
     const uint32_t T = prefix;
     const uint32_t need = krem;
     // ties at T ranked in index order: (round, wave, lane) is index order
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
+    for (int e = 0; e < rounds; ++e) {
         const int j = tid + kSelectThreads * e;
-        const uint64_t b = __ballot(s > 0 && j < n && key[e] == T);
-        if (lane == 0) S.u.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
+        const bool tie = s > 0 && j < n && abs_key(value_at<MODE>(a_in, g, x, muf, j)) == T;
+        const uint64_t b = __ballot(tie);
+        if (lane == 0) S.u.b.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
     }
     __syncthreads();
     {
-        constexpr int NC = CPT * 16;
-        const uint32_t v = tid < NC ? S.u.cnt[tid] : 0u;
+        const int nc = rounds * 16;
+        const uint32_t v = tid < nc ? S.u.b.cnt[tid] : 0u;
         const uint32_t before = block_excl_scan<kSelectThreads>(v, S.scan, nullptr);
-        if (tid < NC) S.u.cnt[tid] = before;
+        if (tid < nc) S.u.b.cnt[tid] = before;
         __syncthreads();
     }
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
+    for (int e = 0; e < rounds; ++e) {
         const int j = tid + kSelectThreads * e;
-        const bool tie = s > 0 && j < n && key[e] == T;
+        const uint32_t key = j < n ? abs_key(value_at<MODE>(a_in, g, x, muf, j)) : 0u;
+        const bool tie = s > 0 && j < n && key == T;
         const uint64_t b = __ballot(tie);
-        const uint32_t rank = S.u.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
-        if (s > 0 && j < n && (key[e] > T || (tie && rank < need)))
-            atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
+        const uint32_t rank = S.u.b.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
+        if (s > 0 && j < n && (key > T || (tie && rank < need)))
+            atomicOr(&S.u.b.bm_new[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
-}
-
-// Fast path over the support and the histogram candidates; returns false
-// (and selects nothing) when the candidate set does not fit in LDS.
-// Appends a candidate to the LDS list; one LDS atomic per wave.
-__device__ __forceinline__ void push_candidate(bool pred, uint32_t key, int j, float a, float xo,
-                                               SelShared& S) {
-    const uint64_t b = __ballot(pred);
-    if (b == 0ull) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(static_cast<long long>(b)) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&S.ncand, static_cast<uint32_t>(__popcll(b)));
-    base = __shfl(base, leader, 64);
-    if (pred) {
-        const uint32_t c = base + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
-        if (c < static_cast<uint32_t>(kCandCap)) {
-            S.u.c.ckey[c] = key;
-            S.u.c.cidx[c] = j;
-            S.u.c.cval[c] = a;
-            S.u.c.cxo[c] = xo;
-        }
-    }
 }
 
 // Sum of three values over the block, fixed order; every thread gets them.
@@ -287,12 +262,12 @@ enum { BM_TIE = 0, BM_NEW = 1, BM_UNION = 2 };
 
 template <int WHICH>
 __device__ __forceinline__ uint32_t bm_word(const SelShared& S, int w) {
-    if (WHICH == BM_TIE) return S.bm_tie[w];
-    if (WHICH == BM_NEW) return S.bm_new[w];
-    return S.bm_old[w] | S.bm_new[w];
+    if (WHICH == BM_TIE) return S.u.b.bm_tie[w];
+    if (WHICH == BM_NEW) return S.u.b.bm_new[w];
+    return S.u.b.bm_old[w] | S.u.b.bm_new[w];
 }
 
-// Per-word exclusive prefix of popcount(bitmap word) into S.wpre (index
+// Per-word exclusive prefix of popcount(bitmap word) into S.u.b.wpre (index
 // order), computed by wave 0 alone (no block-wide scan); returns the total.
 template <int WHICH>
 __device__ uint32_t word_prefix(int words, SelShared& S) {
@@ -318,7 +293,7 @@ __device__ uint32_t word_prefix(int words, SelShared& S) {
         for (int i = 0; i < MAXW; ++i) {
             const int w = w0 + i;
             if (i < wpl && w < words) {
-                S.wpre[w] = pos;
+                S.u.b.wpre[w] = pos;
                 pos += static_cast<uint32_t>(__popc(bm_word<WHICH>(S, w)));
             }
         }
@@ -332,118 +307,109 @@ __device__ __forceinline__ uint32_t rank_in_word(uint32_t bits, int b) {
     return static_cast<uint32_t>(__popc(bits & ((1u << b) - 1u)));
 }
 
-// Exact top-s of the candidate list (keys desc, ties to lower index) into
-// S.bm_new: three radix digits (11, 10, 10 bits) over the candidate keys,
-// each a histogram built by all threads and scanned by wave 0; ties at the
-// threshold key resolved to the lowest indices by an ordered bitmap scan.
-// S.hist, S.hist2, S.hist3 must be zero on entry.
-__device__ void rank_candidates(int n, int s, SelShared& S) {
+// Rank step of the fast path: the s largest keys of the merged candidates
+// (ties to the lower index).  Radix digits of 11, 10 and 10 bits in LDS
+// histograms, stopping as soon as the bin holding the s-th largest key is
+// taken whole; the selection rule is then (key >> sh) > P, or == P within
+// the first `need` such entries in index order.  S.hist, hist2, hist3 must
+// be zero on entry.
+__device__ void rank_merged(int nc, int s, SelShared& S, int& sh, uint32_t& P, uint32_t& need,
+                            uint32_t& eq) {
     const int tid = threadIdx.x;
-    const uint32_t nc = S.ncand;
-    if (s <= 0) return;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) atomicAdd(&S.hist[S.u.c.ckey[c] >> 20], 1u);
+    for (int c = tid; c < nc; c += kSelectThreads) atomicAdd(&S.hist[S.u.f.mkey[c] >> 20], 1u);
     __syncthreads();
     find_bin_w0<2048>(S.hist, static_cast<uint32_t>(s), S);
-    const uint32_t b1 = S.bin, k1 = S.krem;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const uint32_t k = S.u.c.ckey[c];
-        if ((k >> 20) == b1) atomicAdd(&S.hist2[(k >> 10) & 1023u], 1u);
+    P = S.bin;
+    need = S.krem;
+    eq = S.hist[P];
+    sh = 20;
+    if (need == eq) return;
+    for (int c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.u.f.mkey[c];
+        if ((k >> 20) == P) atomicAdd(&S.hist2[(k >> 10) & 1023u], 1u);
     }
     __syncthreads();
-    find_bin_w0<1024>(S.hist2, k1, S);
-    const uint32_t p2 = (b1 << 10) | S.bin, k2 = S.krem;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const uint32_t k = S.u.c.ckey[c];
-        if ((k >> 10) == p2) atomicAdd(&S.hist3[k & 1023u], 1u);
+    find_bin_w0<1024>(S.hist2, need, S);
+    P = (P << 10) | S.bin;
+    need = S.krem;
+    eq = S.hist2[S.bin];
+    sh = 10;
+    if (need == eq) return;
+    for (int c = tid; c < nc; c += kSelectThreads) {
+        const uint32_t k = S.u.f.mkey[c];
+        if ((k >> 10) == P) atomicAdd(&S.hist3[k & 1023u], 1u);
     }
     __syncthreads();
-    find_bin_w0<1024>(S.hist3, k2, S);
-    const uint32_t T = (p2 << 10) | S.bin;  // the s-th largest key
-    const uint32_t need = S.krem;           // keys equal to T that are taken
-    int ties = 0;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const uint32_t k = S.u.c.ckey[c];
-        const int j = S.u.c.cidx[c];
-        if (k > T) atomicOr(&S.bm_new[j >> 5], 1u << (j & 31));
-        else if (k == T) {
-            atomicOr(&S.bm_tie[j >> 5], 1u << (j & 31));
-            ties = 1;
-        }
-    }
-    (void)ties;
-    __syncthreads();
-    const uint32_t nties = S.hist3[T & 1023u];
-    if (need >= nties) {
-        // every tie is taken (the usual case): no ordering needed
-        const int words = (n + 31) / 32;
-        for (int w = tid; w < words; w += kSelectThreads) S.bm_new[w] |= S.bm_tie[w];
-        __syncthreads();
-        return;
-    }
-    const int words = (n + 31) / 32;
-    word_prefix<BM_TIE>(words, S);
-    for (int w = tid; w < words; w += kSelectThreads) {
-        uint32_t u = S.bm_tie[w];
-        uint32_t rank = S.wpre[w];
-        while (u) {
-            const int b = __ffs(u) - 1;
-            u &= u - 1;
-            if (rank < need) atomicOr(&S.bm_new[w], 1u << b);
-            ++rank;
-        }
-    }
-    __syncthreads();
+    find_bin_w0<1024>(S.hist3, need, S);
+    P = (P << 10) | S.bin;
+    need = S.krem;
+    eq = S.hist3[S.bin];
+    sh = 0;
 }
 
 // One complete proposal.  SEL_INIT writes the initial support (pd.sup, xs,
 // bmsup); SEL_STEP writes proposal `slot` (support, values, difference list,
-// metadata).  Every global input is loaded before the first barrier.
-// With from_partials the step is mu = mu0 / (k(1-c))^k with mu0 finished
-// here from the gather partials (written to *mu0_out); returns false when
-// the iteration is stationary.
-template <int CPT, int MODE>
+// metadata).  With from_partials the step is mu = mu0 / (k(1-c))^k with mu0
+// finished here from the gather partials (written to *mu0_out); returns
+// false when the iteration is stationary.
+//
+// Fast path: the candidates are the support (ascending, with x and g on it)
+// and the off-support list of compact_candidates (ascending per index block);
+// both are merged into one list in index order, ranked, and the outputs
+// (support, values, difference list) are positions of a prefix sum over that
+// order.  Full path (too many candidates, or a threshold the fast path cannot
+// use): every key of the n in registers and bitmaps over all n.
+template <int MODE>
 __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool from_partials,
                         double shrink, double* mu0_out, SelShared& S) {
+    constexpr int MPT = kCandCap / kSelectThreads;  // merged positions per thread
+    constexpr int PRE = 4;                          // candidates loaded ahead per thread
     const int tid = threadIdx.x;
-    const int n = pd.n, s = pd.s;
+    const int n = pd.n, s = pd.s, nw = pd.nwg;
     const int words = (n + 31) / 32;
     const int nsup = (MODE == SEL_STEP) ? s : 0;
-    // ---- loads (all independent)
-    float gv[CPT];
-#pragma unroll
-    for (int e = 0; e < CPT; ++e) {
-        const int j = tid + kSelectThreads * e;
-        gv[e] = j < n ? pd.g[j] : 0.0f;
-    }
-    const bool sreg = tid < nsup;  // first 1024 support entries in registers
-    const int sj = sreg ? pd.sup[tid] : 0;
-    const float sx = sreg ? pd.xs[tid] : 0.0f;
-    const float sg = sreg ? pd.gs[tid] : 0.0f;
+    const int per = (n + nw - 1) / nw;
+    // ---- loads (one round trip): mu partials, the candidate counts of this
+    // thread's index blocks [t cpw, (t + 1) cpw), and the first PRE
+    // candidates of its first block
     double gg = 0.0, uv = 0.0, uu = 0.0;
     if (from_partials) {
-        gg = static_cast<double>(sg) * static_cast<double>(sg);
-        for (int i = tid + kSelectThreads; i < nsup; i += kSelectThreads) {
+        for (int i = tid; i < nsup; i += kSelectThreads) {
             const double v = static_cast<double>(pd.gs[i]);
             gg += v * v;
         }
-        for (int b = tid; b < pd.nwg; b += kSelectThreads) {
+        for (int b = tid; b < nw; b += kSelectThreads) {
             uv += pd.part_mu[2 * b + 0];
             uu += pd.part_mu[2 * b + 1];
         }
     }
-    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = pd.hist[b];
+    const int cpw = (nw + kSelectThreads - 1) / kSelectThreads;
+    const int w0 = tid * cpw, w1 = min(nw, w0 + cpw);
+    uint32_t pidx[PRE];
+    float2 pgx[PRE];
+    const int lo0 = w0 * per, len0 = w0 < w1 ? min(n, lo0 + per) - lo0 : 0;
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+        pidx[i] = i < len0 ? pd.cidx[lo0 + i] : 0u;
+        pgx[i] = i < len0 ? pd.cgx[lo0 + i] : make_float2(0.f, 0.f);
+    }
+    uint32_t mycnt = 0;
+    int c0 = 0, bad_cnt = 0;
+    for (int w = w0; w < w1; ++w) {
+        const int c = pd.ccnt[w];
+        if (w == w0) c0 = c;
+        if (c < 0) bad_cnt = 1;
+        else mycnt += static_cast<uint32_t>(c);
+    }
+    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
     for (int b = tid; b < 1024; b += kSelectThreads) {
         S.hist2[b] = 0u;
         S.hist3[b] = 0u;
     }
-    for (int w = tid; w < words; w += kSelectThreads) {
-        S.bm_old[w] = (MODE == SEL_STEP) ? pd.bmsup[w] : 0u;
-        S.bm_new[w] = 0u;
-        S.bm_tie[w] = 0u;
-    }
     if (tid == 0) {
-        S.ncand = 0;
         S.changed = 0;
+        S.bad = 0;
+        S.full = 0;
     }
     // ---- the step
     double mu = mu_in;
@@ -454,107 +420,50 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         if (!(gg > 0.0) || !(den > 0.0) || !isfinite(gg / den)) return false;
         *mu0_out = gg / den;
         mu = shrunk_mu(gg / den, shrink, k);
-    } else {
-        __syncthreads();
     }
     const float muf = static_cast<float>(mu);
-    // ---- threshold from the off-support histogram
-    bool fast = true;
-    float thr = 0.0f;
-    if (n - nsup > s) {
-        find_bin_w0<2048>(S.hist, static_cast<uint32_t>(s), S);
-        thr = __uint_as_float(S.bin << 20) * (1.0f - 0x1p-20f);
-        fast = thr >= 0x1p-100f;  // keep clear of subnormal products
-    }
-    for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
-    int bad = 0;
-    if (fast) {
-        {
-            const float a = fmaf(muf, sg, sx);
-            const uint32_t key = abs_key(a);
-            if (sreg && key > 0x7F800000u) bad = 1;
-            push_candidate(sreg, key, sj, a, sx, S);
-        }
-        for (int i0 = kSelectThreads; i0 < nsup; i0 += kSelectThreads) {
-            const int i = i0 + tid;
-            const bool in = i < nsup;
-            const int j = in ? pd.sup[i] : 0;
-            const float xo = in ? pd.xs[i] : 0.0f;
-            const float a = in ? fmaf(muf, pd.gs[i], xo) : 0.0f;
-            const uint32_t key = abs_key(a);
-            if (in && key > 0x7F800000u) bad = 1;
-            push_candidate(in, key, j, a, xo, S);
-        }
-        // off the support: which of this thread's entries pass the
-        // threshold (a bit mask), one LDS atomic per wave for the slots
-        uint64_t cm = 0;
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) {
-            const int j = tid + kSelectThreads * e;
-            const bool in = j < n && fabsf(gv[e]) >= thr && !((S.bm_old[j >> 5] >> (j & 31)) & 1u);
-            cm |= static_cast<uint64_t>(in) << e;
-        }
-        const uint32_t cnt = static_cast<uint32_t>(__popcll(cm));
-        const int lane = tid & 63;
-        uint32_t x = cnt;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        uint32_t base = 0;
-        if (lane == 63 && x > 0) base = atomicAdd(&S.ncand, x);
-        base = __shfl(base, 63, 64) + (x - cnt);
-#pragma unroll
-        for (int e = 0; e < CPT; ++e) {
-            if ((cm >> e) & 1ull) {
-                const int j = tid + kSelectThreads * e;
-                // off the support x_j = 0, so a_j = fma(mu, g_j, 0)
-                const float a = (MODE == SEL_STEP) ? fmaf(muf, gv[e], 0.0f) : gv[e];
-                const uint32_t key = abs_key(a);
-                if (key > 0x7F800000u) bad = 1;
-                if (base < static_cast<uint32_t>(kCandCap)) {
-                    S.u.c.ckey[base] = key;
-                    S.u.c.cidx[base] = j;
-                    S.u.c.cval[base] = a;
-                    S.u.c.cxo[base] = 0.0f;
-                }
-                ++base;
-            }
-        }
-    }
+    uint32_t total = 0;
+    const uint32_t obase = block_excl_scan<kSelectThreads>(mycnt, S.scan, &total);
+    if (bad_cnt) S.full = 1;
     __syncthreads();
-    fast = fast && S.ncand <= static_cast<uint32_t>(kCandCap);
-    if (bad) atomicOr(&pd.st->err, 1);
+    const int nc = static_cast<int>(total);
+    // (the list holds at least s entries unless the counts are inconsistent,
+    // which the full path then handles)
+    const bool fast = !S.full && nc <= kCandCap && nc >= s;
+    int32_t* out_sup = (MODE == SEL_INIT) ? pd.sup : pd.csup + static_cast<size_t>(slot) * s;
+    float* out_val = pd.cval + static_cast<size_t>(slot) * s;
+    int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
+    double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
     if (!fast) {
         // ---- full path: every key
+        for (int w = tid; w < words; w += kSelectThreads) {
+            S.u.b.bm_old[w] = (MODE == SEL_STEP) ? pd.bmsup[w] : 0u;
+            S.u.b.bm_new[w] = 0u;
+            S.u.b.bm_tie[w] = 0u;
+        }
+        __syncthreads();
         if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
-        select_full<CPT, MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
+        select_full<MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
         if (MODE == SEL_INIT) {
             emit_support<MODE>(n, s, nullptr, pd.g, nullptr, muf, nullptr, pd.sup, nullptr, S);
-            for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.bm_new[w];
+            for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.u.b.bm_new[w];
             for (int i = tid; i < s; i += kSelectThreads) pd.xs[i] = 0.0f;
             for (int b = tid; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
             __syncthreads();
             return true;
         }
-        int32_t* out_sup = pd.csup + static_cast<size_t>(slot) * s;
-        float* out_val = pd.cval + static_cast<size_t>(slot) * s;
         emit_support<MODE>(n, s, nullptr, pd.g, pd.x, muf, pd.sup, out_sup, out_val, S);
-        // difference list from global values (rare path)
         const uint32_t total = word_prefix<BM_UNION>(words, S);
-        int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
-        double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
         double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
         for (int w = tid; w < words; w += kSelectThreads) {
-            uint32_t u = S.bm_old[w] | S.bm_new[w];
-            uint32_t pos = S.wpre[w];
+            uint32_t u = S.u.b.bm_old[w] | S.u.b.bm_new[w];
+            uint32_t pos = S.u.b.wpre[w];
             while (u) {
                 const int b = __ffs(u) - 1;
                 u &= u - 1;
                 const int j = w * 32 + b;
                 const float xo = pd.x[j];
-                const float xn = ((S.bm_new[w] >> b) & 1u) ? fmaf(muf, pd.g[j], xo) : 0.0f;
+                const float xn = ((S.u.b.bm_new[w] >> b) & 1u) ? fmaf(muf, pd.g[j], xo) : 0.0f;
                 const double d = static_cast<double>(xn) - static_cast<double>(xo);
                 if (pos < static_cast<uint32_t>(2 * s)) {
                     dlist[pos] = j;
@@ -581,90 +490,152 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         __syncthreads();
         return true;
     }
-    // ---- fast path: rank the candidates, then emit from LDS
-    rank_candidates(n, s, S);
-    const uint32_t nc = S.ncand;
-    if (MODE == SEL_INIT) {
-        word_prefix<BM_NEW>(words, S);
-        for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-            const int j = S.u.c.cidx[c];
-            const int w = j >> 5, b = j & 31;
-            if ((S.bm_new[w] >> b) & 1u) {
-                const uint32_t pos = S.wpre[w] + rank_in_word(S.bm_new[w], b);
-                if (pos < static_cast<uint32_t>(s)) {
-                    pd.sup[pos] = j;
-                    pd.xs[pos] = 0.0f;
+
+    // ---- fast path: the candidates into LDS in index order, with their keys
+    int bad = 0;
+    {
+        // a_j = x_j + mu g_j (off the support x_j = 0; SEL_INIT: a_j = g_j)
+        auto put = [&](uint32_t pos, uint32_t mi, float2 gx) {
+            const float a = (MODE == SEL_STEP) ? fmaf(muf, gx.x, gx.y) : gx.x;
+            const uint32_t key = abs_key(a);
+            if (key > 0x7F800000u) bad = 1;
+            S.u.f.mkey[pos] = key;
+            S.u.f.midx[pos] = mi;
+            S.u.f.mval[pos] = a;
+            S.u.f.mxo[pos] = gx.y;
+        };
+        uint32_t pos = obase;
+        if (w0 < w1) {
+#pragma unroll
+            for (int q = 0; q < PRE; ++q)
+                if (q < c0) put(pos + q, pidx[q], pgx[q]);
+            for (int i = PRE; i < c0; ++i) put(pos + i, pd.cidx[lo0 + i], pd.cgx[lo0 + i]);
+            pos += static_cast<uint32_t>(max(c0, 0));
+        }
+        for (int w = w0 + 1; w < w1; ++w) {
+            const int c = pd.ccnt[w];
+            for (int i = 0; i < c; ++i) put(pos + i, pd.cidx[w * per + i], pd.cgx[w * per + i]);
+            pos += static_cast<uint32_t>(max(c, 0));
+        }
+    }
+    if (bad) atomicOr(&pd.st->err, 1);
+    __syncthreads();
+    // ---- rank
+    int sh = 0;
+    uint32_t P = 0, need = 0, eq = 0;
+    if (s > 0) rank_merged(nc, s, S, sh, P, need, eq);
+    // merged positions [MPT tid, MPT tid + MPT) belong to this thread
+    bool sel[MPT];
+    {
+        uint32_t tie_rank = 0;
+        if (need < eq) {  // some keys equal to the threshold are left out: index order decides
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < MPT; ++q) {
+                const int m = MPT * tid + q;
+                c += (m < nc && (S.u.f.mkey[m] >> sh) == P) ? 1u : 0u;
+            }
+            tie_rank = block_excl_scan<kSelectThreads>(c, S.scan, nullptr);
+        }
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int m = MPT * tid + q;
+            sel[q] = false;
+            if (m < nc && s > 0) {
+                const uint32_t kk = S.u.f.mkey[m] >> sh;
+                if (kk > P) sel[q] = true;
+                else if (kk == P) {
+                    sel[q] = need >= eq || tie_rank < need;  // tie_rank: rank among equal keys
+                    ++tie_rank;
                 }
             }
         }
-        for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.bm_new[w];
+    }
+    // ---- outputs: selection and union positions in index order (one scan,
+    // selected count in the low half, union count in the high half)
+    uint32_t v = 0;
+    int changed = 0;
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int m = MPT * tid + q;
+        if (m < nc) {
+            const bool on = (S.u.f.midx[m] >> 31) != 0u;
+            v += (sel[q] ? 1u : 0u) + ((sel[q] || on) ? 0x10000u : 0u);
+            if (on != sel[q]) changed = 1;
+        }
+    }
+    uint32_t tot = 0;
+    uint32_t pos = block_excl_scan<kSelectThreads>(v, S.scan, &tot);
+    if (changed) S.changed = 1;
+    double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
+#pragma unroll
+    for (int q = 0; q < MPT; ++q) {
+        const int m = MPT * tid + q;
+        if (m < nc) {
+            const uint32_t mi = S.u.f.midx[m];
+            const bool on = (mi >> 31) != 0u;
+            const int j = static_cast<int>(mi & 0x7FFFFFFFu);
+            const uint32_t ps = pos & 0xFFFFu, pu = pos >> 16;
+            if (sel[q] && ps < static_cast<uint32_t>(s)) {
+                out_sup[ps] = j;
+                if (MODE == SEL_STEP) out_val[ps] = S.u.f.mval[m];
+            }
+            if (MODE == SEL_STEP && (sel[q] || on)) {
+                const float xo = S.u.f.mxo[m];
+                const float xn = sel[q] ? S.u.f.mval[m] : 0.0f;
+                const double d = static_cast<double>(xn) - static_cast<double>(xo);
+                if (pu < static_cast<uint32_t>(2 * s)) {
+                    dlist[pu] = j;
+                    dw[pu] = d;
+                }
+                dx2 += d * d;
+                xn2 += static_cast<double>(xn) * static_cast<double>(xn);
+            }
+            pos += (sel[q] ? 1u : 0u) + ((sel[q] || on) ? 0x10000u : 0u);
+        }
+    }
+    if (MODE == SEL_INIT) {
+        // x stays 0; the support bitmap and x on the support follow the selection
+        for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = 0u;
+        for (int i = tid; i < s; i += kSelectThreads) pd.xs[i] = 0.0f;
+        __syncthreads();
         // the next full pass rebuilds the histogram off the new support
         for (int b = tid; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
+#pragma unroll
+        for (int q = 0; q < MPT; ++q) {
+            const int m = MPT * tid + q;
+            if (m < nc && sel[q]) {
+                const int j = static_cast<int>(S.u.f.midx[m] & 0x7FFFFFFFu);
+                atomicOr(&pd.bmsup[j >> 5], 1u << (j & 31));
+            }
+        }
         __syncthreads();
         return true;
     }
-    int32_t* out_sup = pd.csup + static_cast<size_t>(slot) * s;
-    float* out_val = pd.cval + static_cast<size_t>(slot) * s;
-    int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
-    double* dw = pd.dw + static_cast<size_t>(slot) * 2 * s;
-    // changed: the selection bitmap differs from the support bitmap
-    {
-        int diff = 0;
-        for (int w = tid; w < words; w += kSelectThreads) diff |= (S.bm_new[w] != S.bm_old[w]);
-        if (diff) S.changed = 1;
-    }
-    word_prefix<BM_NEW>(words, S);
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const int j = S.u.c.cidx[c];
-        const int w = j >> 5, b = j & 31;
-        if ((S.bm_new[w] >> b) & 1u) {
-            const uint32_t pos = S.wpre[w] + rank_in_word(S.bm_new[w], b);
-            if (pos < static_cast<uint32_t>(s)) {
-                out_sup[pos] = j;
-                out_val[pos] = S.u.c.cval[c];
-            }
-        }
-    }
-    __syncthreads();
-    // difference list over the union of old and new supports, ascending;
-    // every member of the union is exactly one candidate
-    const uint32_t total = word_prefix<BM_UNION>(words, S);
-    double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
-    for (uint32_t c = tid; c < nc; c += kSelectThreads) {
-        const int j = S.u.c.cidx[c];
-        const int w = j >> 5, b = j & 31;
-        const uint32_t uw = S.bm_old[w] | S.bm_new[w];
-        if ((uw >> b) & 1u) {
-            const uint32_t pos = S.wpre[w] + rank_in_word(uw, b);
-            const float xo = S.u.c.cxo[c];
-            const float xn = ((S.bm_new[w] >> b) & 1u) ? S.u.c.cval[c] : 0.0f;
-            const double d = static_cast<double>(xn) - static_cast<double>(xo);
-            if (pos < static_cast<uint32_t>(2 * s)) {
-                dlist[pos] = j;
-                dw[pos] = d;
-            }
-            dx2 += d * d;
-            xn2 += static_cast<double>(xn) * static_cast<double>(xn);
-        }
-    }
     block_sum3(dx2, xn2, zero, S);
     if (tid == 0) {
-        CandMeta m;
-        m.changed = S.changed;
-        m.dcount = static_cast<int32_t>(total);
-        m.k = k;
-        m.pad = 0;
-        m.mu = mu;
-        m.dx2 = dx2;
-        m.xn2 = xn2;
-        m.omega = 0.0;
-        pd.meta[slot] = m;
+        CandMeta mt;
+        mt.changed = S.changed;
+        mt.dcount = static_cast<int32_t>(tot >> 16);
+        mt.k = k;
+        mt.pad = 0;
+        mt.mu = mu;
+        mt.dx2 = dx2;
+        mt.xn2 = xn2;
+        mt.omega = 0.0;
+        pd.meta[slot] = mt;
     }
     __syncthreads();
     return true;
 }
 
-template <int CPT>
+// Off-support candidates for the first proposal (x = 0, empty support).
+__global__ __launch_bounds__(kGatherThreads) void k_candidates(const ProbDev* __restrict__ P) {
+    const ProbDev& pd = P[blockIdx.y];
+    if (pd.st->done || static_cast<int>(blockIdx.x) >= pd.nwg) return;
+    compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.nwg, false);
+}
+
 __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __restrict__ P,
                                                             SolveArgs a, int mode) {
     const ProbDev& pd = P[blockIdx.y];
@@ -673,11 +644,11 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     if (st->done) return;
     double mu0 = 0.0;
     if (mode == SEL_INIT) {
-        propose<CPT, SEL_INIT>(pd, 0, 0, 1.0, false, 1.0, &mu0, S);
+        propose<SEL_INIT>(pd, 0, 0, 1.0, false, 1.0, &mu0, S);
         return;
     }
     const int k = blockIdx.x;  // shrink count of this proposal
-    const bool ok = propose<CPT, SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S);
+    const bool ok = propose<SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (ok) {
             st->mu = mu0;
@@ -723,7 +694,7 @@ __device__ double omega_den_block(const ProbDev& pd, int dcount, double* red) {
     return block_sum<kSelectThreads>(tot, red);
 }
 
-template <int BITS, int CPT>
+template <int BITS>
 __global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __restrict__ P,
                                                            SolveArgs a) {
     const ProbDev& pd = P[blockIdx.x];
@@ -759,7 +730,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __rest
         for (int k = kSpec;; ++k) {
             const double mu = shrunk_mu(st->mu, shrink, k);
             double unused = 0.0;
-            propose<CPT, SEL_STEP>(pd, 0, k, mu, false, shrink, &unused, S);
+            propose<SEL_STEP>(pd, 0, k, mu, false, shrink, &unused, S);
             const CandMeta m = pd.meta[0];
             bool accept = !m.changed;
             if (!accept) {
@@ -779,73 +750,39 @@ __global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __rest
     for (int b = threadIdx.x; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
 }
 
-template <int CPT>
 __global__ __launch_bounds__(kSelectThreads) void k_hard_threshold(const float* a, int n, int s,
                                                                    int32_t* out, int* err) {
     __shared__ SelShared S;
-    for (int w = threadIdx.x; w < (n + 31) / 32; w += kSelectThreads) S.bm_new[w] = 0u;
+    for (int w = threadIdx.x; w < (n + 31) / 32; w += kSelectThreads) S.u.b.bm_new[w] = 0u;
     if (threadIdx.x == 0) S.changed = 0;
     __syncthreads();
-    select_full<CPT, SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, S, err);
+    select_full<SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, S, err);
     emit_support<SEL_RAW>(n, s, a, nullptr, nullptr, 0.f, nullptr, out, nullptr, S);
 }
 
 }  // namespace
 
-#define QIHT_CPT_SWITCH(CPT_VAR, MACRO) \
-    switch (CPT_VAR) {                  \
-        MACRO(1)                        \
-        MACRO(2)                        \
-        MACRO(4)                        \
-        MACRO(8)                        \
-        MACRO(16)                       \
-        MACRO(32)                       \
-        MACRO(64)                       \
-        default: break;                 \
-    }
+void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st) {
+    hipLaunchKernelGGL(k_candidates, dim3(maxwg, count), dim3(kGatherThreads), 0, st, P);
+}
 
-void launch_propose(int cpt, const ProbDev* P, int count, const SolveArgs& a, int mode,
-                    hipStream_t st) {
+void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st) {
     const dim3 grid(mode == SEL_INIT ? 1 : kSpec, count);
-#define QIHT_PROPOSE(C)                                                                     \
-    case C:                                                                                 \
-        hipLaunchKernelGGL((k_propose<C>), grid, dim3(kSelectThreads), 0, st, P, a, mode); \
-        break;
-    QIHT_CPT_SWITCH(cpt, QIHT_PROPOSE)
-#undef QIHT_PROPOSE
+    hipLaunchKernelGGL(k_propose, grid, dim3(kSelectThreads), 0, st, P, a, mode);
 }
 
-template <int BITS>
-void launch_decide_b(int cpt, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
-#define QIHT_DECIDE(C)                                                                        \
-    case C:                                                                                   \
-        hipLaunchKernelGGL((k_decide<BITS, C>), dim3(count), dim3(kSelectThreads), 0, st, P, \
-                           a);                                                                \
-        break;
-    QIHT_CPT_SWITCH(cpt, QIHT_DECIDE)
-#undef QIHT_DECIDE
-}
-
-void launch_decide(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
-                   hipStream_t st) {
+void launch_decide(int bits, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
     switch (bits) {
-        case 1: launch_decide_b<1>(cpt, P, count, a, st); break;
-        case 2: launch_decide_b<2>(cpt, P, count, a, st); break;
-        case 4: launch_decide_b<4>(cpt, P, count, a, st); break;
-        case 8: launch_decide_b<8>(cpt, P, count, a, st); break;
-        default: launch_decide_b<32>(cpt, P, count, a, st); break;
+        case 1: hipLaunchKernelGGL(k_decide<1>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        case 2: hipLaunchKernelGGL(k_decide<2>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        case 4: hipLaunchKernelGGL(k_decide<4>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        case 8: hipLaunchKernelGGL(k_decide<8>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        default: hipLaunchKernelGGL(k_decide<32>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
     }
 }
 
-void launch_hard_threshold(int cpt, const float* a, int n, int s, int32_t* out, int* err,
-                           hipStream_t st) {
-#define QIHT_HT(C)                                                                          \
-    case C:                                                                                 \
-        hipLaunchKernelGGL((k_hard_threshold<C>), dim3(1), dim3(kSelectThreads), 0, st, a, \
-                           n, s, out, err);                                                 \
-        break;
-    QIHT_CPT_SWITCH(cpt, QIHT_HT)
-#undef QIHT_HT
+void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st) {
+    hipLaunchKernelGGL(k_hard_threshold, dim3(1), dim3(kSelectThreads), 0, st, a, n, s, out, err);
 }
 
 }  // namespace qiht

@@ -79,6 +79,9 @@ struct ProbDev {
     CandMeta* meta;     // kSpec
     double* part_mu;    // 2 * nwg partial (Q1_G g_G).(Q2_G g_G), |Q1_G g_G|^2
     double* part_om;    // kSpec * nwg partial |Q1 (x'_t - x)|^2
+    uint32_t* cidx;     // n slots: candidates per index block (bit 31: on the support)
+    float2* cgx;        // n slots: (g_j, x_j) at those candidates
+    int32_t* ccnt;      // nwg: candidates of each index block (-1: use the full path)
     SolveState* st;
 };
 
@@ -242,6 +245,107 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
     return before + x - v;
 }
 
+// Candidates of the H_s proposals.  Off the support G the proposal value is
+// a_j = mu g_j, so the order of |a_j| there does not depend on mu: the full
+// pass counts |g_j| (j off G) in 2048 bins of the top 11 bits of its FP32
+// pattern, the bin B of the s-th largest gives t = lo(B)(1 - 2^-20), and an
+// entry off G with |g_j| < t has FP32 |a_j| strictly below at least s entries
+// off G for every mu > 0 (a rounded product moves by at most 2^-24
+// relative).  So the top s of all n lies in G plus {j off G : |g_j| >= t}.
+// Workgroup wg of nw takes the index block [wg per, min(n, (wg + 1) per)),
+// per = ceil(n / nw), and writes the candidates of that block (G's members,
+// flagged by bit 31, and the entries off G that pass t) in index order to
+// cidx / cgx from wg per on, and their count to ccnt[wg]; -1 when the fast
+// path cannot be used (t in the subnormal range, or a non-finite g in the
+// block: the full path flags those).
+template <int NT>
+__device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_support) {
+    constexpr int NW = NT / 64;
+    __shared__ float s_thr;
+    __shared__ int s_fast;
+    __shared__ uint32_t s_wc[NW];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = pd.n, s = pd.s;
+    const int nsup = with_support ? s : 0;
+    if (tid == 0) {
+        s_thr = 0.f;
+        s_fast = 1;
+        s_bad = 0;
+    }
+    __syncthreads();
+    if (wv == 0 && n - nsup > s) {
+        // bins from the top: lane l holds 2047 - 32 l - i, i < 32
+        uint32_t h[32];
+        uint32_t c = 0;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+            h[i] = ldg_u32(pd.hist + (2047 - 32 * lane - i));
+            c += h[i];
+        }
+        uint32_t x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        uint32_t run = x - c;
+        const uint32_t want = static_cast<uint32_t>(s);
+        const uint64_t hit = __ballot(run < want && want <= x);
+        if (hit == 0ull) {
+            if (lane == 0) s_fast = 0;  // counts inconsistent with n: full path
+        } else if (lane == __ffsll(static_cast<long long>(hit)) - 1) {
+            int bin = 0;
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < 32; ++i) {
+                if (!found && run + h[i] >= want) {
+                    bin = 2047 - 32 * lane - i;
+                    found = true;
+                }
+                run += h[i];
+            }
+            const float thr = __uint_as_float(static_cast<uint32_t>(bin) << 20) * (1.0f - 0x1p-20f);
+            s_thr = thr;
+            s_fast = thr >= 0x1p-100f;  // keep clear of subnormal products
+        }
+    }
+    __syncthreads();
+    const float thr = s_thr;
+    const int per = (n + nw - 1) / nw;
+    const int lo = wg * per, hi = min(n, lo + per);
+    uint32_t base = 0;
+    int bad = 0;
+    for (int r0 = lo; r0 < hi; r0 += NT) {
+        const int j = r0 + tid;
+        const bool in = j < hi;
+        const float gv = in ? ldg_f32(pd.g + j) : 0.f;
+        const bool on_sup = in && with_support && ((ldg_u32(pd.bmsup + (j >> 5)) >> (j & 31)) & 1u);
+        if (in && (__float_as_uint(gv) & 0x7FFFFFFFu) > 0x7F800000u) bad = 1;
+        const bool cand = on_sup || (in && fabsf(gv) >= thr);
+        const uint64_t b = __ballot(cand);
+        if (lane == 0) s_wc[wv] = static_cast<uint32_t>(__popcll(b));
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            before += w < wv ? s_wc[w] : 0u;
+            all += s_wc[w];
+        }
+        if (cand) {
+            const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+            const uint32_t pos = base + before + static_cast<uint32_t>(__popcll(b & lt));
+            pd.cidx[lo + pos] = static_cast<uint32_t>(j) | (on_sup ? 0x80000000u : 0u);
+            pd.cgx[lo + pos] = make_float2(gv, on_sup ? pd.x[j] : 0.0f);
+        }
+        base += all;
+        __syncthreads();
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == 0) pd.ccnt[wg] = (s_fast && !s_bad) ? static_cast<int32_t>(base) : -1;
+}
+
 // Step after k shrinks: k successive divisions, the same rounding sequence
 // as applying mu <- mu / (k(1-c)) k times.
 __device__ __forceinline__ double shrunk_mu(double mu, double shrink, int k) {
@@ -267,12 +371,10 @@ int pass_slots(int bits, int cpl);
 void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,
                  hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
-void launch_propose(int cpt, const ProbDev* P, int count, const SolveArgs& a, int mode,
-                    hipStream_t st);
-void launch_decide(int bits, int cpt, const ProbDev* P, int count, const SolveArgs& a,
-                   hipStream_t st);
-void launch_hard_threshold(int cpt, const float* a, int n, int s, int32_t* out, int* err,
-                           hipStream_t st);
+void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
+void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);
+void launch_decide(int bits, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st);
+void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st);
 
 // Device-side commit of proposal `t` (called by one whole workgroup of
 // `nt` threads): x and the support take the proposal's values, the state

@@ -56,12 +56,6 @@ __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
     }
 }
 
-int select_cpt(int64_t n) {
-    int cpt = 1;
-    while (static_cast<int64_t>(cpt) * kSelectThreads < n) cpt *= 2;
-    return cpt;
-}
-
 // Chunks per lane of a full-pass row slab: enough to cover the column, at
 // most 128 residual rows per lane (BITS chunks; 16 for FP32).
 int pass_cpl(int bits, int64_t col_bytes) {
@@ -84,7 +78,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t r32, rdig, rexp, rsum, g, gpart, hist, x, sup, xs, gs, bmsup, csup, cval, dlist, dw, meta, part_mu,
+    size_t cidx, cgx, ccnt, r32, rdig, rexp, rsum, g, gpart, hist, x, sup, xs, gs, bmsup, csup, cval, dlist, dw, meta, part_mu,
         part_om, st;
 };
 
@@ -92,7 +86,7 @@ struct Plan {
     std::vector<ProbDev> host;
     std::vector<Layout> lay;
     std::vector<Task> tasks;
-    int bits = 0, cpl = 1, cpt = 1, maxwg = 1;
+    int bits = 0, cpl = 1, maxwg = 1;
     bool any_slab = false;
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0;
@@ -107,7 +101,6 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     }
     if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
     pl.cpl = pass_cpl(pl.bits, max_cb);
-    pl.cpt = select_cpt(max_n);
     const int64_t slab_chunks = 64LL * pl.cpl;
     Carver cv;
     pl.lay.resize(count);
@@ -122,6 +115,9 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         pl.any_slab = pl.any_slab || nslab > 1;
         Layout& L = pl.lay[i];
         L.r32 = cv.take<float>(q->rows_pad);
+        L.cidx = cv.take<uint32_t>(q->n);
+        L.cgx = cv.take<float2>(q->n);
+        L.ccnt = cv.take<int32_t>(nwg);
         L.rdig = cv.take<uint32_t>(static_cast<size_t>(nwg) * digit_words_per_chunk(q->bits));
         L.rexp = cv.take<int32_t>(nwg);
         L.rsum = cv.take<int32_t>(nwg);
@@ -190,6 +186,9 @@ void bind(Plan& pl, uint8_t* base) {
         ProbDev& p = pl.host[i];
         const Layout& L = pl.lay[i];
         p.r32 = reinterpret_cast<float*>(base + L.r32);
+        p.cidx = reinterpret_cast<uint32_t*>(base + L.cidx);
+        p.cgx = reinterpret_cast<float2*>(base + L.cgx);
+        p.ccnt = reinterpret_cast<int32_t*>(base + L.ccnt);
         p.rdig = reinterpret_cast<uint32_t*>(base + L.rdig);
         p.rexp = reinterpret_cast<int32_t*>(base + L.rexp);
         p.rsum = reinterpret_cast<int32_t*>(base + L.rsum);
@@ -266,9 +265,9 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
                         const SolveArgs& a, hipStream_t st, PassTimer* tm) {
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, st);
-    launch_propose(pl.cpt, dP, count, a, SEL_STEP, st);
+    launch_propose(dP, count, a, SEL_STEP, st);
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, st);
-    launch_decide(pl.bits, pl.cpt, dP, count, a, st);
+    launch_decide(pl.bits, dP, count, a, st);
 }
 
 qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
@@ -332,7 +331,8 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
     } else {
         // x0 = 0; G0 = supp H_s(Q1^T y_hat).
         gradient_launches(pl, dP, dT, count, a, 1, st, &timer);
-        launch_propose(pl.cpt, dP, count, a, SEL_INIT, st);
+        launch_candidates(dP, count, pl.maxwg, st);
+        launch_propose(dP, count, a, SEL_INIT, st);
     }
     QIHT_HIP(hipGetLastError());
 
@@ -409,7 +409,7 @@ qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* su
     int* err = nullptr;
     QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&err), sizeof(int), st));
     QIHT_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
-    launch_hard_threshold(select_cpt(n), a, static_cast<int>(n), static_cast<int>(s), support_out,
+    launch_hard_threshold(a, static_cast<int>(n), static_cast<int>(s), support_out,
                           err, st);
     QIHT_HIP(hipGetLastError());
     int herr = 0;
