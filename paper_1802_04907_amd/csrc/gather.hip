@@ -108,6 +108,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         else wcol = pd.g;
     }
     const bool two = (MODE == G_MU) && (a.mu_mode == 0);
+    // the candidate compaction's inputs go out with the gather's loads
+    CandPre cpre;
+    if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.nwg, true);
     const uint8_t* A = (MODE == G_R) ? pd.q2 : pd.q1;
     const uint8_t* B = pd.q2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -123,35 +126,38 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     double wsum = 0.0;
 
     constexpr int U = 8;
+    // Every load of a batch is issued unconditionally (a list position past
+    // the end reads the last entry and gets weight 0), so that the batch's
+    // loads are in flight together.
     for (int t0 = slot; t0 < ncols; t0 += SLOTS * U) {
         int cidx[U];
+        bool valid[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + SLOTS * u;
-            cidx[u] = t < ncols ? cols[t] : -1;
+            valid[u] = t < ncols;
+            cidx[u] = static_cast<int>(ldg_u32(cols + min(t, ncols - 1)));
         }
         double wt[U];
         uint32_t wa[U], wb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int t = t0 + SLOTS * u;
-            wt[u] = 0.0;
-            wa[u] = 0u;
-            wb[u] = 0u;
-            if (cidx[u] >= 0) {
-                if (MODE == G_OMEGA) {
-                    wt[u] = wlist[t];
-                } else if (MODE == G_R) {
-                    wt[u] = static_cast<double>(wpos[t]);
-                } else {
-                    const float gv = wcol[cidx[u]];
-                    wt[u] = static_cast<double>(gv);
-                    if (wg == 0 && w == 0) pd.gs[t] = gv;  // g on the support, compact
-                }
-                const size_t off = static_cast<size_t>(cidx[u]) * pd.col_bytes + woff;
-                wa[u] = *reinterpret_cast<const uint32_t*>(A + off);
-                if (two) wb[u] = *reinterpret_cast<const uint32_t*>(B + off);
-            }
+            const int t = min(t0 + SLOTS * u, ncols - 1);
+            double wv;
+            if (MODE == G_OMEGA) wv = ldg_f64(wlist + t);
+            else if (MODE == G_R) wv = static_cast<double>(ldg_f32(wpos + t));
+            else wv = static_cast<double>(ldg_f32(wcol + cidx[u]));
+            wt[u] = valid[u] ? wv : 0.0;
+            const size_t off = static_cast<size_t>(cidx[u]) * pd.col_bytes + woff;
+            wa[u] = ldg_u32(A + off);
+            wb[u] = two ? ldg_u32(B + off) : 0u;
+        }
+        // g on the support, compact (stored once every load above has been
+        // issued: a store between them would serialize the loads)
+        if (MODE == G_MU && wg == 0 && w == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (valid[u]) pd.gs[t0 + SLOTS * u] = static_cast<float>(wt[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -170,15 +176,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
     }
 
-    // ---- butterfly over the 16 slots of the wave (lane bits 2..5)
+    // ---- sum over the 16 slots of the wave (lane bits 2..5); lanes 0..3 hold it
+    wsum = slot_sum(wsum);
 #pragma unroll
-    for (int off = 4; off < 64; off <<= 1) {
-        wsum += __shfl_xor(wsum, off, 64);
+    for (int mi = 0; mi < NM; ++mi)
 #pragma unroll
-        for (int mi = 0; mi < NM; ++mi)
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) acc[mi][q] += __shfl_xor(acc[mi][q], off, 64);
-    }
+        for (int q = 0; q < RPW; ++q) acc[mi][q] = slot_sum(acc[mi][q]);
     // ---- then the waves, in wave order
     __shared__ double sh[NW][4][NM][RPW];
     __shared__ double shw[NW];
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
         const bool live = row < static_cast<size_t>(pd.rows);
         if (MODE == G_R) {
-            rres = live ? pd.yhat[row] - val[0] : 0.0;
+            rres = live ? ldg_f64(pd.yhat + row) - val[0] : 0.0;
             pd.r32[row] = static_cast<float>(rres);
         } else if (live) {
             if (MODE == G_MU) {
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         pd.part_om[static_cast<size_t>(set) * pd.nwg + wg] = s1;
     }
     // g is final here: the off-support candidates of this iteration's proposals
-    if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.nwg, true);
+    if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.nwg, true, cpre);
 }
 
 template <int MODE>

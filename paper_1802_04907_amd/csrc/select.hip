@@ -633,7 +633,8 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
 __global__ __launch_bounds__(kGatherThreads) void k_candidates(const ProbDev* __restrict__ P) {
     const ProbDev& pd = P[blockIdx.y];
     if (pd.st->done || static_cast<int>(blockIdx.x) >= pd.nwg) return;
-    compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.nwg, false);
+    const CandPre pre = cand_preload<kGatherThreads>(pd, blockIdx.x, pd.nwg, false);
+    compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.nwg, false, pre);
 }
 
 __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __restrict__ P,

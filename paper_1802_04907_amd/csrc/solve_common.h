@@ -196,12 +196,71 @@ __device__ __forceinline__ uint32_t ldg_u32(const void* p) {
 __device__ __forceinline__ float ldg_f32(const void* p) {
     return *(const __attribute__((address_space(1))) float*)(p);
 }
+__device__ __forceinline__ double ldg_f64(const void* p) {
+    return *(const __attribute__((address_space(1))) double*)(p);
+}
 
+// Cross-lane moves without LDS: DPP within rows of 16 lanes and the gfx950
+// row / half-wave swaps.  dpp<CTRL>(v) reads lane CTRL(l) (0 where the
+// pattern feeds nothing); swap16_sum(v) = v + v of lane l ^ 16 and
+// swap32_sum(v) = v + v of lane l ^ 32, the two operands added in lane order
+// (so both lanes of a pair hold the same bits).
+template <int CTRL, int RM = 0xf, int BM = 0xf>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RM, BM, false));
+}
+template <int CTRL, int RM = 0xf, int BM = 0xf>
+__device__ __forceinline__ double dpp(double x) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, RM, BM, false),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, BM, false));
+}
+__device__ __forceinline__ float swap16_sum(float v) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap32_sum(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double swap16_sum(double v) {
+    const uint32_t lo = static_cast<uint32_t>(__double2loint(v)), hi = static_cast<uint32_t>(__double2hiint(v));
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(static_cast<int>(b[0]), static_cast<int>(a[0])) +
+           __hiloint2double(static_cast<int>(b[1]), static_cast<int>(a[1]));
+}
+__device__ __forceinline__ double swap32_sum(double v) {
+    const uint32_t lo = static_cast<uint32_t>(__double2loint(v)), hi = static_cast<uint32_t>(__double2hiint(v));
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(static_cast<int>(b[0]), static_cast<int>(a[0])) +
+           __hiloint2double(static_cast<int>(b[1]), static_cast<int>(a[1]));
+}
+__device__ __forceinline__ float lane0(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+}
+__device__ __forceinline__ double lane0(double v) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                            __builtin_amdgcn_readlane(__double2loint(v), 0));
+}
+
+// Sum over the 16 lanes of a row that share l mod 4, then over the four
+// rows: lanes 0..3 end with the totals of their residues mod 4.
+template <typename T>
+__device__ __forceinline__ T slot_sum(T v) {
+    v = v + dpp<0x124>(v);  // row_ror:4
+    v = v + dpp<0x128>(v);  // row_ror:8
+    v = swap16_sum(v);
+    return swap32_sum(v);
+}
+
+// Sum over the wave in a fixed order, lane 0's result in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v = v + dpp<0xB1>(v);  // quad_perm [1,0,3,2]
+    v = v + dpp<0x4E>(v);  // quad_perm [2,3,0,1]
+    return lane0(slot_sum(v));
 }
 
 template <int NT>
@@ -258,8 +317,32 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
 // cidx / cgx from wg per on, and their count to ccnt[wg]; -1 when the fast
 // path cannot be used (t in the subnormal range, or a non-finite g in the
 // block: the full path flags those).
+// Inputs of compact_candidates that do not depend on anything computed in
+// the calling kernel, loaded ahead: the histogram (wave 0, top-down, 32 bins
+// per lane) and this thread's first entry of the index block.
+struct CandPre {
+    uint32_t h[32];
+    float g0;
+    uint32_t bm0;
+};
+
 template <int NT>
-__device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_support) {
+__device__ __forceinline__ CandPre cand_preload(const ProbDev& pd, int wg, int nw, bool with_support) {
+    CandPre c;
+    const int tid = threadIdx.x, lane = tid & 63;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) c.h[i] = tid < 64 ? ldg_u32(pd.hist + (2047 - 32 * lane - i)) : 0u;
+    const int per = (pd.n + nw - 1) / nw;
+    const int lo = wg * per, hi = min(pd.n, lo + per);
+    const int j = min(lo + tid, hi - 1);  // clamped: a thread past the block ignores it
+    c.g0 = ldg_f32(pd.g + j);
+    c.bm0 = with_support ? ldg_u32(pd.bmsup + (j >> 5)) : 0u;
+    return c;
+}
+
+template <int NT>
+__device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_support,
+                                   const CandPre& pre) {
     constexpr int NW = NT / 64;
     __shared__ float s_thr;
     __shared__ int s_fast;
@@ -275,14 +358,9 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
     }
     __syncthreads();
     if (wv == 0 && n - nsup > s) {
-        // bins from the top: lane l holds 2047 - 32 l - i, i < 32
-        uint32_t h[32];
         uint32_t c = 0;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            h[i] = ldg_u32(pd.hist + (2047 - 32 * lane - i));
-            c += h[i];
-        }
+        for (int i = 0; i < 32; ++i) c += pre.h[i];
         uint32_t x = c;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -299,11 +377,11 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
             bool found = false;
 #pragma unroll
             for (int i = 0; i < 32; ++i) {
-                if (!found && run + h[i] >= want) {
+                if (!found && run + pre.h[i] >= want) {
                     bin = 2047 - 32 * lane - i;
                     found = true;
                 }
-                run += h[i];
+                run += pre.h[i];
             }
             const float thr = __uint_as_float(static_cast<uint32_t>(bin) << 20) * (1.0f - 0x1p-20f);
             s_thr = thr;
@@ -319,8 +397,10 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
     for (int r0 = lo; r0 < hi; r0 += NT) {
         const int j = r0 + tid;
         const bool in = j < hi;
-        const float gv = in ? ldg_f32(pd.g + j) : 0.f;
-        const bool on_sup = in && with_support && ((ldg_u32(pd.bmsup + (j >> 5)) >> (j & 31)) & 1u);
+        const int jc = min(j, hi - 1);
+        const float gv = r0 == lo ? pre.g0 : ldg_f32(pd.g + jc);
+        const uint32_t bw = r0 == lo ? pre.bm0 : (with_support ? ldg_u32(pd.bmsup + (jc >> 5)) : 0u);
+        const bool on_sup = in && ((bw >> (j & 31)) & 1u);
         if (in && (__float_as_uint(gv) & 0x7FFFFFFFu) > 0x7F800000u) bad = 1;
         const bool cand = on_sup || (in && fabsf(gv) >= thr);
         const uint64_t b = __ballot(cand);
