@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "solve_common.h"
@@ -212,36 +214,77 @@ void bind(Plan& pl, uint8_t* base) {
 }
 
 // Events recorded by every full-pass dispatch (profile mode): the start and
-// end of the kernel itself, on its launch stream.
+// end of the kernel itself, on its launch stream.  Creating events costs far
+// more host time than an iteration takes on the device, so they come from a
+// per-device pool: created on first use, handed to one solve at a time, and
+// kept until the process ends.
+class EventPool {
+  public:
+    // Moves `count` events of device `dev` into out (creating any missing).
+    bool take(int dev, size_t count, std::vector<hipEvent_t>& out) {
+        std::lock_guard<std::mutex> lk(m_);
+        std::vector<hipEvent_t>& f = free_[dev];
+        while (f.size() < count) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            f.push_back(e);
+        }
+        out.assign(f.end() - static_cast<std::ptrdiff_t>(count), f.end());
+        f.resize(f.size() - count);
+        return true;
+    }
+    void give(int dev, std::vector<hipEvent_t>& evs) {
+        std::lock_guard<std::mutex> lk(m_);
+        std::vector<hipEvent_t>& f = free_[dev];
+        f.insert(f.end(), evs.begin(), evs.end());
+        evs.clear();
+    }
+
+  private:
+    std::mutex m_;
+    std::map<int, std::vector<hipEvent_t>> free_;
+};
+
+EventPool& event_pool() {
+    static EventPool p;
+    return p;
+}
+
 struct PassTimer {
     bool on = false;
+    int dev = 0;
+    size_t used = 0;
     std::vector<hipEvent_t> ev;
     ~PassTimer() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (!ev.empty()) event_pool().give(dev, ev);
     }
-    // Returns false (no events) when profiling is off or creation fails.
+    // Events for up to `launches` profiled dispatches; profiling is off when
+    // they cannot be had.
+    void reserve(size_t launches) {
+        if (!on) return;
+        if (hipGetDevice(&dev) != hipSuccess || !event_pool().take(dev, 2 * launches, ev)) {
+            ev.clear();
+            on = false;
+        }
+    }
+    // Returns false (no events) when profiling is off or the reserve is used up.
     bool pair(hipEvent_t* a, hipEvent_t* b) {
         *a = *b = nullptr;
-        if (!on) return false;
-        if (hipEventCreate(a) != hipSuccess) return false;
-        if (hipEventCreate(b) != hipSuccess) {
-            (void)hipEventDestroy(*a);
-            *a = nullptr;
-            return false;
-        }
-        ev.push_back(*a);
-        ev.push_back(*b);
+        if (!on || used + 2 > ev.size()) return false;
+        *a = ev[used];
+        *b = ev[used + 1];
+        used += 2;
         return true;
     }
     double total_ms() const {
         double t = 0.0;
-        for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+        for (size_t i = 0; i + 1 < used; i += 2) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
         }
         return t;
     }
-    int launches() const { return static_cast<int>(ev.size() / 2); }
+    int launches() const { return static_cast<int>(used / 2); }
 };
 
 struct Workspace {
@@ -325,6 +368,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
 
     PassTimer timer;
     timer.on = a.profile != 0;
+    timer.reserve(static_cast<size_t>(a.max_iters) + 1);
     if (warm) {
         // x0 restricted to its support (x is zero elsewhere)
         hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
