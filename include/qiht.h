@@ -89,6 +89,10 @@ typedef struct {
                                 indices); required iff x0 != NULL           */
     int32_t profile;         /* 1: time every full-pass launch with HIP
                                 events on `stream` (qiht_info.pass_ms)      */
+    int32_t refit;           /* 1: after the last iteration, replace x on
+                                its support by the FP64 least-squares fit
+                                against Q1 and y_hat (qiht_refit); 0 keeps
+                                the last iterate (the paper's output)      */
 } qiht_params;
 
 typedef struct {
@@ -105,7 +109,7 @@ typedef struct {
 } qiht_info;
 
 /* Fill `p` (host) with the defaults: max_iters 300, tol 1e-8, k 2, c 0.01,
- * max_backtracks 32, mu_mode 0, no warm start, profile 0. */
+ * max_backtracks 32, mu_mode 0, no warm start, profile 0, refit 0. */
 void qiht_default_params(qiht_params* p);
 
 /*
@@ -239,6 +243,31 @@ qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat,
  */
 qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s,
                                 int32_t* support_out, void* stream);
+
+/*
+ * Least-squares refit on a support.  Not part of the paper's method (QIHT
+ * returns its last iterate, Algorithm 2); a post-processing step that takes
+ * the recovered support and solves, in FP64,
+ *     z = argmin |y - A_G z|_2,   A_G = the columns `support` of A,
+ * through the normal equations A_G^T A_G z = A_G^T y (blocked Cholesky on the
+ * device), then writes x_out = z on the support and 0 elsewhere.
+ *
+ *   A: the caller's dense matrix when phi != NULL (device, m x n row-major,
+ *      leading dimension ld >= n, dtype F32 or F64, or C64 / C128 taken as
+ *      the stacked real matrix [Re Phi; Im Phi] of 2m rows; q is ignored);
+ *      else the dequantized first realization Q1 of q (q's rows and n).
+ *   y: device, rows doubles (m, 2m for complex phi, or q's rows).
+ *   support: device, s int32 ascending, 1 <= s <= min(rows, n).
+ *   x_out: device, n floats.  xs_out: device, s doubles, optional (z).
+ *   Workspace: rows s + 10 s^2 doubles, allocated on `stream` and freed.
+ *   Errors: INVALID_ARG, UNSUPPORTED (dtype), NUMERIC (A_G rank-deficient:
+ *   the Gram matrix is not positive definite), OUT_OF_MEMORY, DEVICE.
+ *   Synchronizes stream.
+ */
+qiht_status qiht_refit(const qiht_qmatrix* q, const void* phi, int64_t m,
+                       int64_t n, int64_t ld, qiht_dtype dtype,
+                       const double* y, const int32_t* support, int64_t s,
+                       float* x_out, double* xs_out, void* stream);
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* qiht_last_error(void);

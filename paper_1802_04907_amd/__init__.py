@@ -142,12 +142,13 @@ def quantize_vector(y, bits, seed=0, stream=None, want_codes=False):
 
 
 def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=None,
-            profile=False):
+            profile=False, refit=False):
     p = _lib.QihtParams()
     _lib.load().qiht_default_params(C.byref(p))
     p.max_iters, p.tol, p.k, p.c = int(max_iters), float(tol), float(k), float(c)
     p.max_backtracks, p.mu_mode = int(max_backtracks), int(mu_mode)
     p.profile = 1 if profile else 0
+    p.refit = 1 if refit else 0
     p.x0 = None if x0 is None else x0.data_ptr()
     p.support0 = None if support0 is None else support0.data_ptr()
     return p
@@ -161,7 +162,7 @@ def _info_dict(inf):
 
 
 def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
-               mu_mode=0, x0=None, support0=None, stream=None, profile=False):
+               mu_mode=0, x0=None, support0=None, stream=None, profile=False, refit=False):
     """QIHT solve -> (x FP32 CUDA tensor, support int32 CUDA tensor, info dict)."""
     torch = _torch()
     x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
@@ -169,7 +170,7 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
     if x0 is not None:
         x0 = x0.to(dtype=torch.float32).contiguous()
         support0 = support0.to(dtype=torch.int32).contiguous()
-    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0, profile)
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0, profile, refit)
     inf = _lib.QihtInfo()
     _check(_lib.load().qiht_niht_solve(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
                                        _ptr(sup), C.byref(inf), _stream(stream)))
@@ -195,6 +196,35 @@ def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
     infos = (_lib.QihtInfo * cnt)()
     _check(_lib.load().qiht_niht_solve_batched(cnt, arr, C.byref(p), infos, _stream(stream)))
     return [(x, sup, _info_dict(infos[i])) for i, (x, sup) in enumerate(outs)]
+
+
+_DTYPES = {"float64": 0, "float32": 1, "complex64": 2, "complex128": 3}
+
+
+def refit(support, y, q=None, phi=None, n=None, stream=None):
+    """FP64 least-squares refit on a support (not part of the paper's method).
+
+    A is ``phi`` (a CUDA tensor, m x n row-major, real or complex) when given,
+    else the dequantized first realization of ``q``.  ``y`` holds the
+    rows measurements in FP64.  Returns (x FP32 n, z FP64 on the support)."""
+    torch = _torch()
+    sup = support.to(torch.int32).contiguous()
+    s = sup.numel()
+    yv = y.to(torch.float64).contiguous()
+    if phi is not None:
+        phi = phi.contiguous()
+        m, nn = phi.shape
+        ld = nn
+        dt = _DTYPES[str(phi.dtype).replace("torch.", "")]
+        handle = None
+    else:
+        nn, m, ld, dt, handle = q.n, 0, 0, 0, q.handle
+    x = torch.empty(nn, dtype=torch.float32, device=yv.device)
+    z = torch.empty(s, dtype=torch.float64, device=yv.device)
+    _check(_lib.load().qiht_refit(handle, _ptr(phi), int(m), int(nn), int(ld), int(dt),
+                                  _ptr(yv), _ptr(sup), int(s), _ptr(x), _ptr(z),
+                                  _stream(stream)))
+    return x, z
 
 
 def gradient(q, yhat, x, support, stream=None):

@@ -17,7 +17,7 @@ class QihtParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("tol", C.c_double), ("k", C.c_double),
                 ("c", C.c_double), ("max_backtracks", C.c_int32),
                 ("mu_mode", C.c_int32), ("x0", C.c_void_p), ("support0", C.c_void_p),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("refit", C.c_int32)]
 
 
 class QihtInfo(C.Structure):
@@ -57,6 +57,9 @@ SIGNATURES = {
                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     "qiht_hard_threshold": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64,
                                       C.c_void_p, C.c_void_p]),
+    "qiht_refit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                             C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                             C.c_void_p, C.c_void_p]),
     "qiht_last_error": (C.c_char_p, []),
     "qiht_version": (C.c_char_p, []),
 }

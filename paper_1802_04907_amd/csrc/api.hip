@@ -58,6 +58,7 @@ qiht_status check_params(const qiht_params* p) {
     if (std::isnan(p->tol)) return fail(QIHT_ERR_INVALID_ARG, "tol is NaN");
     if ((p->x0 == nullptr) != (p->support0 == nullptr))
         return fail(QIHT_ERR_INVALID_ARG, "x0 and support0 go together");
+    if (p->refit != 0 && p->refit != 1) return fail(QIHT_ERR_INVALID_ARG, "refit is 0 or 1");
     return QIHT_OK;
 }
 
@@ -71,6 +72,26 @@ SolveArgs to_args(const qiht_params* p) {
     a.mu_mode = p->mu_mode;
     a.profile = p->profile;
     return a;
+}
+
+// Refit of a solve's result on its support against the first realization.
+RefitIn codes_refit(const qiht_qmatrix* q, const double* y, const int32_t* sup, int64_t s,
+                    float* x_out) {
+    RefitIn r{};
+    r.codes = q->codes[0];
+    r.col_bytes = q->col_bytes;
+    r.bits = q->bits;
+    r.alpha = q->alpha;
+    r.beta = q->beta;
+    r.phi = nullptr;
+    r.rows = q->rows;
+    r.n = q->n;
+    r.s = s;
+    r.y = y;
+    r.sup = sup;
+    r.x_out = x_out;
+    r.xs_out = nullptr;
+    return r;
 }
 
 qiht_status check_problem(const qiht_qmatrix* q, const double* yhat, int64_t s, const void* x_out,
@@ -120,6 +141,7 @@ void qiht_default_params(qiht_params* p) {
     p->x0 = nullptr;
     p->support0 = nullptr;
     p->profile = 0;
+    p->refit = 0;
 }
 
 const char* qiht_last_error(void) { return last_error_cstr(); }
@@ -294,6 +316,10 @@ qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat, int64_t s
     qiht_info tmp;
     s0 = run_solve(&in, 1, to_args(p), &tmp, static_cast<hipStream_t>(stream));
     if (s0 != QIHT_OK) return s0;
+    if (p->refit) {
+        s0 = run_refit(codes_refit(q, yhat, support_out, s, x_out), static_cast<hipStream_t>(stream));
+        if (s0 != QIHT_OK) return s0;
+    }
     if (info) *info = tmp;
     return QIHT_OK;
 } catch (...) {
@@ -324,6 +350,14 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
     std::vector<qiht_info> tmp(count);
     s0 = run_solve(in.data(), count, to_args(p), tmp.data(), static_cast<hipStream_t>(stream));
     if (s0 != QIHT_OK) return s0;
+    if (p->refit) {
+        for (int i = 0; i < count; ++i) {
+            s0 = run_refit(codes_refit(probs[i].q, probs[i].yhat, probs[i].support_out, probs[i].s,
+                                       probs[i].x_out),
+                           static_cast<hipStream_t>(stream));
+            if (s0 != QIHT_OK) return fail(s0, "problem " + std::to_string(i) + ": " + last_error_cstr());
+        }
+    }
     if (infos) std::memcpy(infos, tmp.data(), sizeof(qiht_info) * count);
     return QIHT_OK;
 } catch (...) {
@@ -357,6 +391,43 @@ qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* s
     qiht_status s0 = need_device(&dev);
     if (s0 != QIHT_OK) return s0;
     return run_hard_threshold(a, n, s, support_out, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_refit(const qiht_qmatrix* q, const void* phi, int64_t m, int64_t n, int64_t ld,
+                       qiht_dtype dtype, const double* y, const int32_t* support, int64_t s,
+                       float* x_out, double* xs_out, void* stream) try {
+    set_error("");
+    if (!y || !support || !x_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    RefitIn r{};
+    if (phi) {
+        if (m < 1 || n < 1 || ld < n) return fail(QIHT_ERR_INVALID_ARG, "need m, n >= 1 and ld >= n");
+        if (dtype != QIHT_F32 && dtype != QIHT_F64 && dtype != QIHT_C64 && dtype != QIHT_C128)
+            return fail(QIHT_ERR_UNSUPPORTED, "dtype");
+        const bool cplx = dtype == QIHT_C64 || dtype == QIHT_C128;
+        r.phi = phi;
+        r.m = m;
+        r.ld = ld;
+        r.dtype = dtype;
+        r.rows = cplx ? 2 * m : m;
+        r.n = n;
+    } else {
+        if (!q) return fail(QIHT_ERR_INVALID_ARG, "need phi or a quantized matrix");
+        r = codes_refit(q, y, support, s, x_out);
+    }
+    if (s < 1 || s > std::min(r.rows, r.n)) return fail(QIHT_ERR_INVALID_ARG, "need 1 <= s <= min(rows, n)");
+    r.s = s;
+    r.y = y;
+    r.sup = support;
+    r.x_out = x_out;
+    r.xs_out = xs_out;
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    s0 = check_support(support, s, r.n, static_cast<hipStream_t>(stream));
+    if (s0 != QIHT_OK) return s0;
+    return run_refit(r, static_cast<hipStream_t>(stream));
 } catch (...) {
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }

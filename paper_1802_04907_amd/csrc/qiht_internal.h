@@ -86,6 +86,7 @@ struct SolveArgs {
     int32_t profile;
 };
 
+
 struct ProblemIn {
     const qiht_qmatrix* q;
     const double* yhat;
@@ -105,5 +106,24 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat,
 
 qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s,
                                int32_t* support_out, hipStream_t st);
+
+// Least-squares refit on a support (refit.hip).  A is the dense phi when
+// given (row-major m x n, leading dimension ld, real or complex stacked), else
+// the dequantized codes (bits, col_bytes, alpha, beta).
+struct RefitIn {
+    const uint8_t* codes;
+    int64_t col_bytes;
+    int bits;
+    double alpha, beta;
+    const void* phi;
+    int64_t m, ld;
+    qiht_dtype dtype;
+    int64_t rows, n, s;
+    const double* y;
+    const int32_t* sup;
+    float* x_out;
+    double* xs_out;
+};
+qiht_status run_refit(const RefitIn& in, hipStream_t st);
 
 }  // namespace qiht

@@ -446,6 +446,10 @@ void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, hipStream_t st);
 // ev0/ev1 (optional): events recorded by the dispatch itself around the
 // kernel (timing of the bandwidth-bound pass).
+size_t refit_workspace_bytes(int64_t rows, int64_t s);
+int* refit_flag(uint8_t* ws, int64_t rows, int64_t s);
+void launch_refit(const RefitIn& in, uint8_t* ws, hipStream_t st);
+
 // Workgroups of the full pass that the device holds at once (0 if unknown).
 int pass_slots(int bits, int cpl);
 void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "solve_common.h"
@@ -444,6 +445,23 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float*
     if (r_out)
         QIHT_HIP(hipMemcpyAsync(r_out, h.r32, sizeof(float) * h.rows, hipMemcpyDeviceToDevice, st));
     QIHT_HIP(hipStreamSynchronize(st));
+    return QIHT_OK;
+}
+
+qiht_status run_refit(const RefitIn& in, hipStream_t st) {
+    const size_t bytes = refit_workspace_bytes(in.rows, in.s);
+    uint8_t* ws = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&ws), bytes, st) != hipSuccess || !ws)
+        return fail(QIHT_ERR_OUT_OF_MEMORY, "refit workspace");
+    launch_refit(in, ws, st);
+    hipError_t e = hipGetLastError();
+    int herr = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&herr, refit_flag(ws, in.rows, in.s), sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipFreeAsync(ws, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(QIHT_ERR_DEVICE, std::string("refit: ") + hipGetErrorString(e));
+    if (herr) return fail(QIHT_ERR_NUMERIC, "refit: the support columns are not linearly independent");
     return QIHT_OK;
 }
 

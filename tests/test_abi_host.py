@@ -131,3 +131,28 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_refit_validation(lib):
+    ptr = C.c_void_p(64)
+    f = lib.qiht_refit
+    # q, phi, m, n, ld, dtype, y, support, s, x_out, xs_out, stream
+    assert f(None, None, 4, 4, 4, 0, ptr, ptr, 2, ptr, None, None) == 1   # no source
+    assert f(None, ptr, 4, 4, 4, 0, None, ptr, 2, ptr, None, None) == 1   # no y
+    assert f(None, ptr, 4, 4, 3, 0, ptr, ptr, 2, ptr, None, None) == 1    # ld < n
+    assert f(None, ptr, 4, 4, 4, 9, ptr, ptr, 2, ptr, None, None) == 2    # dtype
+    assert f(None, ptr, 4, 4, 4, 0, ptr, ptr, 5, ptr, None, None) == 1    # s > min(m, n)
+    assert f(None, ptr, 4, 4, 4, 0, ptr, ptr, 0, ptr, None, None) == 1    # s < 1
+    assert "s <=" in lib.qiht_last_error().decode()
+
+
+def test_default_params_refit_off(lib):
+    from paper_1802_04907_amd import _lib
+    p = _lib.QihtParams()
+    lib.qiht_default_params(C.byref(p))
+    assert p.refit == 0
+    p.refit = 2
+    ptr = C.c_void_p(64)
+    info = _lib.QihtInfo()
+    assert lib.qiht_niht_solve(ptr, ptr, 1, C.byref(p), ptr, ptr, C.byref(info), None) == 1
+    assert "refit" in lib.qiht_last_error().decode()
