@@ -14,10 +14,12 @@ quantizer  Stochastic quantizer Q(v, b) of Sec. III-A (max-abs scaled,
 niht       Hard threshold H_s, the normalized step size (Eq. step_size),
            the backtracking rule, Algorithm 1 (NIHT) and Algorithm 2 (QIHT),
            and the least-squares refit on the recovered support.
+lowprec    Deterministic BF16 / FP8-E4M3 storage of Phi with power-of-two
+           row scales (the shared-Phi variant; not in the paper).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against something
 other than itself (rocRAND's Philox, closed forms, brute force, invariants
 stated in the paper).
 """
 
-from . import philox, quantizer, niht  # noqa: F401
+from . import philox, quantizer, niht, lowprec  # noqa: F401
