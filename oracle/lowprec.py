@@ -41,17 +41,14 @@ def round_to(v, fmt):
     Returns FP64 values that the format represents exactly."""
     p, emin, vmax = _SPEC[fmt]
     v = np.asarray(v, dtype=np.float64)
-    out = np.empty_like(v)
-    flat_in, flat_out = v.ravel(), out.ravel()
-    for i, x in enumerate(flat_in):
-        if x == 0.0 or not math.isfinite(x):
-            flat_out[i] = x
-            continue
-        _, e2 = math.frexp(abs(x))      # |x| = f 2^e2, f in [0.5, 1)
-        e = max(e2 - 1, emin)           # exponent of the leading bit (clamped: subnormals)
-        quantum = 2.0 ** (e - (p - 1))  # spacing of representable values there
-        r = round(x / quantum) * quantum  # Python round(): ties to even; x / quantum exact
-        flat_out[i] = max(-vmax, min(vmax, r))
+    out = v.copy()
+    nz = np.isfinite(v) & (v != 0.0)
+    x = v[nz]
+    _, e2 = np.frexp(np.abs(x))           # |x| = f 2^e2, f in [0.5, 1)
+    e = np.maximum(e2 - 1, emin)          # exponent of the leading bit (clamped: subnormals)
+    quantum = np.ldexp(1.0, e - (p - 1))  # spacing of representable values there
+    # x / quantum is exact (a power of two); np.round rounds halves to even
+    out[nz] = np.clip(np.round(x / quantum) * quantum, -vmax, vmax)
     return out
 
 
@@ -83,19 +80,31 @@ def store_matrix(phi, fmt):
         st = phi.astype(np.float32).astype(np.float64)
         return st, np.zeros(phi.shape[0], dtype=np.int64), st
     e = row_exponents(phi, fmt)
-    scale = np.ldexp(1.0, e)[:, None]
-    st = round_to(phi.astype(np.float64) / scale, fmt)   # division by a power of two is exact
-    return st, e, st * scale
+    st = np.empty(phi.shape, dtype=np.float64)
+    for r0 in range(0, phi.shape[0], 1024):  # row blocks bound the temporaries
+        blk = phi[r0:r0 + 1024].astype(np.float64)
+        # division by a power of two is exact
+        st[r0:r0 + 1024] = round_to(blk / np.ldexp(1.0, e[r0:r0 + 1024])[:, None], fmt)
+    return st, e, st * np.ldexp(1.0, e)[:, None]
+
+
+def e4m3_byte_value(b):
+    """Value of one E4M3 bit pattern (sign, 4-bit exponent with bias 7, 3-bit
+    significand; exponent 0 is subnormal; S.1111.111 is NaN)."""
+    s, ex, m = (b >> 7) & 1, (b >> 3) & 15, b & 7
+    if ex == 15 and m == 7:
+        return math.nan
+    mag = (m / 8.0) * 2.0 ** -6 if ex == 0 else (1.0 + m / 8.0) * 2.0 ** (ex - 7)
+    return -mag if s else mag
+
+
+def e4m3_decode(codes):
+    """FP64 values of an array of E4M3 bytes."""
+    table = np.array([e4m3_byte_value(b) for b in range(256)])
+    return table[np.asarray(codes, dtype=np.uint8)]
 
 
 def e4m3_values():
-    """All finite E4M3 values from the bit patterns (sign, 4-bit exponent with
-    bias 7, 3-bit significand; exponent 0 is subnormal; S.1111.111 is NaN)."""
-    vals = []
-    for b in range(256):
-        s, ex, m = b >> 7, (b >> 3) & 15, b & 7
-        if ex == 15 and m == 7:
-            continue
-        mag = (m / 8.0) * 2.0 ** -6 if ex == 0 else (1.0 + m / 8.0) * 2.0 ** (ex - 7)
-        vals.append(-mag if s else mag)
-    return np.array(sorted(set(vals)))
+    """All finite E4M3 values, ascending."""
+    vals = [e4m3_byte_value(b) for b in range(256)]
+    return np.array(sorted(set(v for v in vals if not math.isnan(v))))

@@ -93,3 +93,12 @@ def test_store_matrix_error_within_half_a_unit(fmt):
     assert np.all(err <= rel * np.abs(phi) + floor)
     if fmt == "e4m3":
         np.testing.assert_array_equal(np.isin(st, lp.e4m3_values()), True)
+
+
+def test_e4m3_decode_matches_torch_bit_patterns():
+    b = np.arange(256, dtype=np.uint8)
+    want = torch.from_numpy(b).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = lp.e4m3_decode(b)
+    fin = ~np.isnan(want)
+    assert np.array_equal(np.isnan(got), ~fin)
+    np.testing.assert_array_equal(got[fin], want[fin])
