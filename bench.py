@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 
 M, N, S, SIGMA, SEED, ITERS = 8192, 32768, 512, 1e-3, 0, 200
 PEAK_HBM_GBPS = 8000.0
+# shared-matrix workload: one Phi, NRHS right-hand sides of sparsity S5
+NRHS, S5, ITERS5 = 256, 256, 30
+PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
 METRIC = "NIHT iterations/s + HBM GB/s, b=8/4/2-bit vs FP32 at equal recovery error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fullpass_traffic_config2.md")
 PASS_SOURCE = os.path.join(ROOT, "paper_1802_04907_amd", "csrc", "pass.hip")
@@ -138,6 +141,84 @@ def cpu_baseline(p, ncols=4096, iters=10):
     }
 
 
+def shared_bench(qiht, torch, dev, reps=2):
+    """The shared-matrix workload: one 8192 x 32768 Gaussian Phi held in
+    FP32 / BF16 / E4M3, 256 right-hand sides of sparsity 256, each batch one
+    GEMM per iteration.  Reports right-hand-side iterations/s, the GEMM's
+    average duration and its MFMA rate (algorithmic flops 2 m n nrhs; the BF16
+    formats issue twice that, the residual being split into two BF16 terms),
+    and support recovery; plus looped single solves on the FP32 handle for
+    comparison."""
+    import workloads
+    log("shared-matrix workload ...")
+    phi, Y, X, sups = workloads.shared_phi(M, N, NRHS, S5, SIGMA, SEED)
+    phi_d = torch.from_numpy(phi).to(dev)
+    ys = [torch.from_numpy(np.ascontiguousarray(Y[:, j])).to(dev) for j in range(NRHS)]
+    del phi
+    res = {"workload": (f"one Gaussian Phi {M}x{N} N(0,1/{M}), {NRHS} right-hand sides of "
+                        f"sparsity {S5}, sigma_e={SIGMA}; {ITERS5} NIHT iterations each"),
+           "formats": {}}
+    flops = 2.0 * M * N * NRHS
+    for fmt, code in (("f32", 32), ("bf16", qiht.BF16), ("e4m3", qiht.E4M3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        q = qiht.quantize_matrix(phi_d, code, 1, SEED)
+        torch.cuda.synchronize()
+        t_store = time.perf_counter() - t0
+        probs = [(q, ys[j], S5) for j in range(NRHS)]
+        qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gemm_ms, gemm_n = 0.0, 0
+        for _ in range(reps):
+            out = qiht.niht_solve_batched(probs, max_iters=ITERS5, tol=-1.0, profile=True)
+            gemm_ms += out[0][2]["pass_ms"]
+            gemm_n += out[0][2]["pass_launches"]
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        rec = [len(np.intersect1d(out[j][1].cpu().numpy(), sups[j])) / S5 for j in range(NRHS)]
+        err = [float(np.linalg.norm(out[j][0].cpu().numpy() - X[:, j]) / np.linalg.norm(X[:, j]))
+               for j in range(NRHS)]
+        # the same solves with the FP64 least-squares refit on each final support
+        t0 = time.perf_counter()
+        outr = qiht.niht_solve_batched(probs, max_iters=ITERS5, tol=-1.0, refit=True)
+        torch.cuda.synchronize()
+        el_r = time.perf_counter() - t0
+        err_r = [float(np.linalg.norm(outr[j][0].cpu().numpy() - X[:, j]) / np.linalg.norm(X[:, j]))
+                 for j in range(NRHS)]
+        avg = gemm_ms / max(gemm_n, 1) / 1e3
+        tf = flops / avg / 1e12
+        issued = tf * (1 if fmt == "f32" else 2)
+        res["formats"][fmt] = {
+            "rhs_iterations_per_s": round(NRHS * ITERS5 / el, 1),
+            "ms_per_batch_iteration": round(el / ITERS5 * 1e3, 4),
+            "store_ms": round(t_store * 1e3, 2),
+            "gemm_avg_us": round(avg * 1e6, 2), "gemm_launches_timed": gemm_n,
+            "gemm_tflops_algorithmic": round(tf, 2),
+            "gemm_tflops_issued": round(issued, 2),
+            "mfma_peak_tflops": PEAK_MFMA_TFLOPS[fmt],
+            "mfma_frac_issued": round(issued / PEAK_MFMA_TFLOPS[fmt], 4),
+            "min_support_recovery": round(min(rec), 4),
+            "median_rel_err": round(float(np.median(err)), 6),
+            "median_rel_err_after_refit": round(float(np.median(err_r)), 6),
+            "refit_ms_all_rhs": round((el_r - el) * 1e3, 2),
+        }
+        log(fmt, json.dumps(res["formats"][fmt]))
+        if fmt == "f32":
+            # the same problems one at a time on the per-problem FP32 path
+            k = 8
+            qiht.niht_solve(q, ys[0], S5, max_iters=2, tol=-1.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for j in range(k):
+                qiht.niht_solve(q, ys[j], S5, max_iters=ITERS5, tol=-1.0)
+            torch.cuda.synchronize()
+            res["looped_fp32_rhs_iterations_per_s"] = round(k * ITERS5 / (time.perf_counter() - t0), 1)
+        q.free()
+    del phi_d
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +227,8 @@ def main():
     ap.add_argument("--bits", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-shared", action="store_true",
+                    help="skip the shared-matrix (many right-hand sides) measurement")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
@@ -282,6 +365,11 @@ def main():
             for d in sweep.values():
                 d.pop("trajectory_every_5", None)
         out["sweep"] = sweep
+
+    if not args.no_shared:
+        del phi_d
+        torch.cuda.empty_cache()
+        out["shared_phi"] = shared_bench(qiht, torch, dev)
 
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")

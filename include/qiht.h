@@ -102,7 +102,10 @@ typedef struct {
     int32_t capped_iterations; /* iterations that hit max_backtracks         */
     double mu_last;            /* accepted step of the last iteration        */
     double pass_ms;            /* profile = 1: summed event time of the
-                                  g = Q1^T r launches (0 otherwise)          */
+                                  g = Q1^T r launches (0 otherwise); in a
+                                  batch every problem reports the batch's
+                                  launches (one GEMM per iteration when the
+                                  problems share one matrix)                 */
     int32_t pass_launches;     /* number of those launches                   */
     int32_t full_selects;      /* H_s proposals that ranked all n entries
                                   (the rest ranked the histogram candidates) */
@@ -111,6 +114,11 @@ typedef struct {
 /* Fill `p` (host) with the defaults: max_iters 300, tol 1e-8, k 2, c 0.01,
  * max_backtracks 32, mu_mode 0, no warm start, profile 0, refit 0. */
 void qiht_default_params(qiht_params* p);
+
+/* Dense storage formats accepted by qiht_quantize_matrix in place of a bit
+ * width (deterministic rounding, no randomness; not in the paper). */
+#define QIHT_FMT_BF16 116  /* bfloat16: 8 exponent, 7 stored significand bits */
+#define QIHT_FMT_E4M3 108  /* OCP FP8 E4M3: bias 7, 3 significand bits, max 448 */
 
 /*
  * Quantize the measurement matrix: Q(Phi, b) of Sec. III-A.
@@ -124,7 +132,14 @@ void qiht_default_params(qiht_params* p);
  *   fractional position (unbiased: E[Q(v)] = v).
  *
  *   bits: 1, 2, 4 or 8 (packed codes), or 32 (plain FP32 copy, no
- *   randomness; realizations is then forced to 1 and Q1 = Q2).
+ *   randomness; realizations is then forced to 1 and Q1 = Q2), or a dense
+ *   format QIHT_FMT_BF16 / QIHT_FMT_E4M3: row i is stored as
+ *   Phi_ij / 2^e_i rounded to nearest (ties to even significand), e_i the
+ *   smallest integer with max_j |Phi_ij| / 2^e_i <= 1 (BF16) or 448 (E4M3),
+ *   so the matrix the solver uses is diag(2^e) times the stored values; one
+ *   copy (Q1 = Q2), realizations and seed are ignored.  Solves on such a
+ *   handle run the shared-matrix path (one MFMA GEMM per iteration for all
+ *   right-hand sides of a batch; see qiht_niht_solve_batched).
  *   realizations: 1 (Q1 = Q2, single sampling) or 2 (independent Q1 for
  *   Phi^T and Q2 for Phi: double sampling, Sec. III-A).
  *   seed: 64-bit Philox4x32-10 key.  Element e (column-major index over
@@ -171,11 +186,18 @@ qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows,
 /*
  * Copy one realization's codes to host memory, unpacked: rows x n bytes,
  * column-major (byte j*rows + i is the code of element (i, j)).  For
- * bits = 32 the buffer receives rows x n floats instead.  For inspection
- * and tests; the device layout is private.
+ * bits = 32 and QIHT_FMT_BF16 the buffer receives rows x n floats instead
+ * (the stored values), for QIHT_FMT_E4M3 the rows x n E4M3 bytes.  For
+ * inspection and tests; the device layout is private.
  */
 qiht_status qiht_qmatrix_export_codes(const qiht_qmatrix* q, int realization,
                                       void* host_out);
+
+/*
+ * Row exponents e_i of a dense-format handle (host, rows int32): the matrix
+ * is diag(2^e) times the stored values.  INVALID_ARG for packed codes.
+ */
+qiht_status qiht_qmatrix_row_exponents(const qiht_qmatrix* q, int32_t* host_out);
 
 /* Release a handle (NULL is a no-op). */
 void qiht_qmatrix_free(qiht_qmatrix* q);

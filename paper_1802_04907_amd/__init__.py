@@ -71,6 +71,10 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+BF16 = _lib.QIHT_FMT_BF16  # dense storage formats for quantize_matrix(bits=...)
+E4M3 = _lib.QIHT_FMT_E4M3
+
+
 class QMatrix:
     """Handle on quantized measurement-matrix codes held in device memory."""
 
@@ -90,15 +94,23 @@ class QMatrix:
         return self._h
 
     def export_codes(self, realization=0):
-        """Codes of one realization as a (rows, n) numpy array (host)."""
+        """Codes of one realization as a (rows, n) numpy array (host): uint8
+        codes, or float32 values (bits 32 and BF16), or E4M3 bytes."""
         import numpy as np
-        if self.bits == 32:
+        if self.bits in (32, _lib.QIHT_FMT_BF16):
             out = np.empty((self.n, self.rows), dtype=np.float32)
         else:
             out = np.empty((self.n, self.rows), dtype=np.uint8)
         _check(_lib.load().qiht_qmatrix_export_codes(
             self._h, int(realization), out.ctypes.data_as(C.c_void_p)))
         return out.T
+
+    def row_exponents(self):
+        """Row exponents e_i of a dense-format matrix (host int32 array)."""
+        import numpy as np
+        out = np.empty(self.rows, dtype=np.int32)
+        _check(_lib.load().qiht_qmatrix_row_exponents(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def free(self):
         if self._h is not None and self._h.value:
@@ -178,7 +190,7 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
 
 
 def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
-                       max_backtracks=32, mu_mode=0, stream=None):
+                       max_backtracks=32, mu_mode=0, stream=None, profile=False, refit=False):
     """Batched solve; ``problems`` is a list of (QMatrix, yhat, s).
 
     Returns a list of (x, support, info)."""
@@ -192,7 +204,7 @@ def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
         outs.append((x, sup))
         arr[i] = _lib.QihtProblem(q.handle.value, yhat.data_ptr(), int(s),
                                   x.data_ptr(), sup.data_ptr())
-    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode)
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, profile=profile, refit=refit)
     infos = (_lib.QihtInfo * cnt)()
     _check(_lib.load().qiht_niht_solve_batched(cnt, arr, C.byref(p), infos, _stream(stream)))
     return [(x, sup, _info_dict(infos[i])) for i, (x, sup) in enumerate(outs)]

@@ -7,6 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqiht.so")
 
 QIHT_OK = 0
+QIHT_FMT_BF16 = 116  # dense formats (include/qiht.h)
+QIHT_FMT_E4M3 = 108
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
                 4: "DEVICE", 5: "NUMERIC"}
 DTYPE = {"f64": 0, "f32": 1, "c64": 2, "c128": 3}
@@ -46,6 +48,7 @@ SIGNATURES = {
                                     C.POINTER(C.c_int), C.POINTER(C.c_double),
                                     C.POINTER(C.c_int64)]),
     "qiht_qmatrix_export_codes": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    "qiht_qmatrix_row_exponents": (C.c_int, [C.c_void_p, C.c_void_p]),
     "qiht_qmatrix_free": (None, [C.c_void_p]),
     "qiht_niht_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
                                   C.POINTER(QihtParams), C.c_void_p, C.c_void_p,

@@ -31,7 +31,12 @@ qiht_status hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-bool bits_ok_matrix(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 32; }
+bool bits_ok_matrix(int b) {
+    return b == 1 || b == 2 || b == 4 || b == 8 || b == 32 || b == QIHT_FMT_BF16 || b == QIHT_FMT_E4M3;
+}
+// public bit width / format -> internal id, and back
+int internal_bits(int b) { return b == QIHT_FMT_BF16 ? kFmtBF16 : b == QIHT_FMT_E4M3 ? kFmtE4M3 : b; }
+int public_bits(int b) { return b == kFmtBF16 ? QIHT_FMT_BF16 : b == kFmtE4M3 ? QIHT_FMT_E4M3 : b; }
 bool bits_ok_vector(int b) { return (b >= 1 && b <= 8) || b == 32; }
 bool dtype_ok(int d) { return d >= QIHT_F64 && d <= QIHT_C128; }
 bool is_complex(qiht_dtype d) { return d == QIHT_C64 || d == QIHT_C128; }
@@ -83,6 +88,7 @@ RefitIn codes_refit(const qiht_qmatrix* q, const double* y, const int32_t* sup, 
     r.bits = q->bits;
     r.alpha = q->alpha;
     r.beta = q->beta;
+    r.rowexp = q->rexp;
     r.phi = nullptr;
     r.rows = q->rows;
     r.n = q->n;
@@ -128,6 +134,42 @@ const char* last_error_cstr() { return g_last_error.c_str(); }
 
 using namespace qiht;
 
+// Deterministic dense storage (QIHT_FMT_BF16 / QIHT_FMT_E4M3): one copy,
+// row exponents alongside.
+qiht_status store_dense(const void* phi, qiht_dtype dtype, int64_t m, int64_t n, int64_t ld,
+                        int bits, int64_t rows, int64_t cb, int dev, hipStream_t st,
+                        qiht_qmatrix** out) {
+    qiht_qmatrix* q = new qiht_qmatrix();
+    q->device = dev;
+    q->m = m;
+    q->n = n;
+    q->rows = rows;
+    q->bits = bits;
+    q->realizations = 1;
+    q->col_bytes = cb;
+    q->rows_pad = rows_in_bytes(cb, bits);
+    const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
+    const size_t rbytes = static_cast<size_t>(round_up(rows * 4, 256));
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&q->codes[0]), bytes + rbytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete q;
+        return fail(QIHT_ERR_OUT_OF_MEMORY, "storage allocation failed");
+    }
+    q->codes[1] = q->codes[0];
+    q->rexp = reinterpret_cast<int32_t*>(q->codes[0] + bytes);
+    e = hipMemsetAsync(q->codes[0], 0, bytes, st);  // padding rows stay 0
+    qiht_status s0 = (e == hipSuccess) ? launch_store_matrix(phi, dtype, m, n, ld, bits, q, st)
+                                       : hip_fail(e, "clear storage");
+    if (s0 != QIHT_OK) {
+        (void)hipFree(q->codes[0]);
+        delete q;
+        return s0;
+    }
+    *out = q;
+    return QIHT_OK;
+}
+
 extern "C" {
 
 void qiht_default_params(qiht_params* p) {
@@ -156,9 +198,11 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     if (m < 1 || n < 1) return fail(QIHT_ERR_INVALID_ARG, "need m >= 1 and n >= 1");
     if (ld < n) return fail(QIHT_ERR_INVALID_ARG, "need ld >= n");
     if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
-    if (!bits_ok_matrix(bits)) return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8 or 32");
+    if (!bits_ok_matrix(bits))
+        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8, 32, QIHT_FMT_BF16 or QIHT_FMT_E4M3");
     if (realizations != 1 && realizations != 2)
         return fail(QIHT_ERR_INVALID_ARG, "realizations must be 1 or 2");
+    bits = internal_bits(bits);
     const int64_t rows = is_complex(dtype) ? 2 * m : m;
     if (rows > (1LL << 31) - 1 || n > (1LL << 31) - 1)
         return fail(QIHT_ERR_UNSUPPORTED, "dimension above 2^31 - 1");
@@ -168,6 +212,7 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     qiht_status s0 = need_device(&dev);
     if (s0 != QIHT_OK) return s0;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (is_dense_format(bits)) return store_dense(phi, dtype, m, n, ld, bits, rows, cb, dev, st, out);
     double c = 0.0;
     s0 = device_absmax(phi, dtype, m, n, ld, st, &c);
     if (s0 != QIHT_OK) return s0;
@@ -254,7 +299,7 @@ qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows, int64_t* n, 
     if (!q) return fail(QIHT_ERR_INVALID_ARG, "handle is NULL");
     if (rows) *rows = q->rows;
     if (n) *n = q->n;
-    if (bits) *bits = q->bits;
+    if (bits) *bits = public_bits(q->bits);
     if (realizations) *realizations = q->realizations;
     if (scale) *scale = q->scale;
     if (col_bytes) *col_bytes = q->col_bytes;
@@ -276,6 +321,23 @@ qiht_status qiht_qmatrix_export_codes(const qiht_qmatrix* q, int realization,
             std::memcpy(o + j * rows, packed.data() + j * q->col_bytes, sizeof(float) * rows);
         return QIHT_OK;
     }
+    if (q->bits == kFmtBF16) {  // stored values as floats (exact)
+        float* o = static_cast<float*>(host_out);
+        for (int64_t j = 0; j < q->n; ++j)
+            for (int64_t i = 0; i < rows; ++i) {
+                uint16_t h;
+                std::memcpy(&h, packed.data() + j * q->col_bytes + 2 * i, 2);
+                const uint32_t u = static_cast<uint32_t>(h) << 16;
+                std::memcpy(o + j * rows + i, &u, 4);
+            }
+        return QIHT_OK;
+    }
+    if (q->bits == kFmtE4M3) {  // the raw E4M3 bytes
+        uint8_t* o = static_cast<uint8_t*>(host_out);
+        for (int64_t j = 0; j < q->n; ++j)
+            std::memcpy(o + j * rows, packed.data() + j * q->col_bytes, rows);
+        return QIHT_OK;
+    }
     uint8_t* o = static_cast<uint8_t*>(host_out);
     const int b = q->bits;
     const uint32_t mask = (1u << b) - 1u;
@@ -286,6 +348,16 @@ qiht_status qiht_qmatrix_export_codes(const qiht_qmatrix* q, int realization,
             o[j * rows + i] = static_cast<uint8_t>((col[bit >> 3] >> (bit & 7)) & mask);
         }
     }
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_qmatrix_row_exponents(const qiht_qmatrix* q, int32_t* host_out) try {
+    set_error("");
+    if (!q || !host_out) return fail(QIHT_ERR_INVALID_ARG, "handle or output is NULL");
+    if (!q->rexp) return fail(QIHT_ERR_INVALID_ARG, "not a dense-format matrix");
+    QIHT_HIP(hipMemcpy(host_out, q->rexp, sizeof(int32_t) * q->rows, hipMemcpyDeviceToHost));
     return QIHT_OK;
 } catch (...) {
     return fail(QIHT_ERR_DEVICE, "unexpected exception");

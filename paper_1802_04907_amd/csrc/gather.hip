@@ -77,7 +77,7 @@ __device__ void digitize_chunk(double r, int wg, const ProbDev& pd) {
 template <int BITS, int MODE>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __restrict__ P,
                                                            SolveArgs a, int zero_x) {
-    constexpr int RPW = (BITS == 32) ? 1 : 32 / BITS;  // rows per 32-bit word
+    constexpr int RPW = rows_per_word<BITS>();  // rows per 32-bit word
     constexpr int NSET = (MODE == G_OMEGA) ? kSpec : 1;
     constexpr int NM = (MODE == G_MU) ? 2 : 1;
     constexpr int NW = kGatherThreads / 64;
@@ -164,12 +164,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             wsum += wt[u];
 #pragma unroll
             for (int q = 0; q < RPW; ++q) {
-                const double va = (BITS == 32) ? static_cast<double>(__uint_as_float(wa[u]))
-                                               : static_cast<double>(code_at<BITS>(wa[u], q));
+                const double va = elem_at<BITS>(wa[u], q);
                 acc[0][q] = fma(wt[u], va, acc[0][q]);
                 if (NM == 2) {
-                    const double vb = (BITS == 32) ? static_cast<double>(__uint_as_float(wb[u]))
-                                                   : static_cast<double>(code_at<BITS>(wb[u], q));
+                    const double vb = elem_at<BITS>(wb[u], q);
                     acc[NM - 1][q] = fma(wt[u], vb, acc[NM - 1][q]);
                 }
             }
@@ -207,7 +205,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             double tot = 0.0;
 #pragma unroll
             for (int v = 0; v < NW; ++v) tot += sh[v][ww][mi][q];
-            val[mi] = (BITS == 32) ? tot : pd.alpha * tot + pd.beta * wtot;
+            if constexpr (BITS == 32) val[mi] = tot;
+            else if constexpr (BITS == 9 || BITS == 16)
+                val[mi] = row < static_cast<size_t>(pd.rows) ? ldexp(tot, pd.rowexp[row]) : 0.0;
+            else val[mi] = pd.alpha * tot + pd.beta * wtot;
         }
         const bool live = row < static_cast<size_t>(pd.rows);
         if (MODE == G_R) {
@@ -223,7 +224,21 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
     }
     if constexpr (MODE == G_R) {
-        if constexpr (BITS != 32) digitize_chunk<BITS>(rres, wg, pd);
+        if constexpr (BITS <= 8) {
+            digitize_chunk<BITS>(rres, wg, pd);
+        } else if constexpr (BITS == 9 || BITS == 16) {
+            // the GEMM's operand: 2^e r as a pair of BF16 (hi + lo), both
+            // rounded to nearest even from the exact FP64 value
+            if (threadIdx.x < 4 * RPW) {
+                const size_t row = (static_cast<size_t>(wg) * 4 + threadIdx.x / RPW) * RPW + threadIdx.x % RPW;
+                const double v = row < static_cast<size_t>(pd.rows) ? ldexp(rres, pd.rowexp[row]) : 0.0;
+                const uint32_t hi = bf16_rne(v);
+                const uint32_t lo = bf16_rne(v - static_cast<double>(bf16_value(hi)));
+                const size_t rp = static_cast<size_t>(pd.nwg) * 4 * RPW;  // rows_pad
+                pd.rb[row] = static_cast<uint16_t>(hi);
+                pd.rb[rp + row] = static_cast<uint16_t>(lo);
+            }
+        }
         return;
     }
     // rows of this group: at most 4 * RPW <= 128 threads hold values
@@ -251,6 +266,8 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
         case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
         case 4: hipLaunchKernelGGL((k_gather<4, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
         case 8: hipLaunchKernelGGL((k_gather<8, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+        case 9: hipLaunchKernelGGL((k_gather<9, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+        case 16: hipLaunchKernelGGL((k_gather<16, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
         default: hipLaunchKernelGGL((k_gather<32, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
     }
 }

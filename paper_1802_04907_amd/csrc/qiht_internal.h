@@ -24,7 +24,8 @@ struct qiht_qmatrix {
     int64_t m = 0;         // rows of the caller's Phi
     int64_t n = 0;         // columns
     int64_t rows = 0;      // m, or 2m for complex input ([Re; Im])
-    int bits = 0;          // 1, 2, 4, 8 or 32
+    int bits = 0;          // 1, 2, 4, 8 or 32 (codes / plain floats), or a dense
+                           // format: kFmtBF16 (16) or kFmtE4M3 (9)
     int realizations = 0;  // 1 or 2
     double scale = 0.0;    // c = max |Phi_ij| (0 for bits 32)
     double alpha = 0.0;    // dequantized value = alpha * code + beta
@@ -32,6 +33,7 @@ struct qiht_qmatrix {
     int64_t col_bytes = 0; // stride between columns
     int64_t rows_pad = 0;  // rows covered by col_bytes
     uint8_t* codes[2] = {nullptr, nullptr};  // codes[1] == codes[0] if R == 1
+    int32_t* rexp = nullptr;  // dense formats: row exponents e_i (device, rows)
 };
 
 namespace qiht {
@@ -49,15 +51,22 @@ qiht_status hip_fail(hipError_t e, const char* what);
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Internal ids of the dense formats (the public ones are QIHT_FMT_*).
+constexpr int kFmtBF16 = 16;
+constexpr int kFmtE4M3 = 9;
+inline bool is_dense_format(int bits) { return bits == kFmtBF16 || bits == kFmtE4M3; }
+// Stored bits per element.
+inline int storage_bits(int bits) { return bits == kFmtE4M3 ? 8 : bits; }
+
 // Bytes per column for a given row count and bit width (multiple of 256).
 inline int64_t column_bytes(int64_t rows, int bits) {
-    int64_t raw = (bits == 32) ? rows * 4 : (rows * bits + 7) / 8;
+    int64_t raw = (rows * storage_bits(bits) + 7) / 8;
     if (raw < 1) raw = 1;
     return round_up(raw, 256);
 }
 
 inline int64_t rows_in_bytes(int64_t col_bytes, int bits) {
-    return bits == 32 ? col_bytes / 4 : col_bytes * 8 / bits;
+    return col_bytes * 8 / storage_bits(bits);
 }
 
 // ---- quantization (quantize.hip) ----
@@ -69,6 +78,8 @@ qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
                                    int64_t n, int64_t ld, int bits, int R,
                                    uint64_t seed, double c, double K,
                                    qiht_qmatrix* q, hipStream_t st);
+qiht_status launch_store_matrix(const void* src, qiht_dtype dt, int64_t m, int64_t n,
+                                int64_t ld, int fmt, qiht_qmatrix* q, hipStream_t st);
 qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
                                    int bits, uint64_t seed, double c,
                                    double K, const double* levels_dev,
@@ -115,6 +126,7 @@ struct RefitIn {
     int64_t col_bytes;
     int bits;
     double alpha, beta;
+    const int32_t* rowexp;  // dense formats: row exponents
     const void* phi;
     int64_t m, ld;
     qiht_dtype dtype;

@@ -165,6 +165,128 @@ __global__ __launch_bounds__(256) void k_quantize_vec(
     if (codes) codes[i] = static_cast<uint8_t>(code);
 }
 
+// ---------------------------------------------------------------------------
+// Dense low-precision storage (no randomness): row i of the stacked matrix is
+// stored as Phi_ij / 2^e_i rounded to BF16 or FP8 E4M3 (OCP), to nearest,
+// ties to the even significand; e_i is the smallest integer with
+// max_j |Phi_ij| / 2^e_i <= F (F = 1 for BF16, 448 for E4M3), so the
+// division is exact and the rounding is the only error.
+// ---------------------------------------------------------------------------
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_rowexp(const T* __restrict__ src, int64_t m, int64_t n,
+                                                int64_t ld, double top, int32_t* __restrict__ rexp,
+                                                int* __restrict__ bad) {
+    __shared__ double smx[4];
+    __shared__ int sbad[4];
+    const int64_t i = blockIdx.x;  // stacked row
+    double mx = 0.0;
+    int nonfin = 0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double v = fabs(load_stacked<T, NC>(src, m, ld, i, j));
+        if (!isfinite(v)) nonfin = 1;
+        else mx = fmax(mx, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        nonfin |= __shfl_xor(nonfin, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        smx[threadIdx.x >> 6] = mx;
+        sbad[threadIdx.x >> 6] = nonfin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = fmax(fmax(smx[0], smx[1]), fmax(smx[2], smx[3]));
+        int e = 0;
+        if (mx > 0.0) {
+            e = ilogb(mx) - ilogb(top);
+            while (ldexp(mx, -e) > top) ++e;
+            while (ldexp(mx, -(e - 1)) <= top) --e;
+        }
+        rexp[i] = e;
+        if (sbad[0] | sbad[1] | sbad[2] | sbad[3]) atomicOr(bad, 1);
+    }
+}
+
+// Nearest value with P significand bits (the leading one included), smallest
+// normal exponent EMIN, saturating at +-VMAX.  Every step is exact except the
+// rint, which rounds ties to even.
+template <int P, int EMIN>
+__device__ __forceinline__ double round_format(double x, double vmax) {
+    if (x == 0.0) return 0.0;
+    const int e = max(ilogb(x), EMIN);
+    const int qe = e - (P - 1);
+    const double y = ldexp(rint(ldexp(x, -qe)), qe);
+    return fmin(fmax(y, -vmax), vmax);
+}
+
+__device__ __forceinline__ uint32_t encode_bf16(double x) {
+    return __float_as_uint(static_cast<float>(round_format<8, -126>(x, 0x1.fep127))) >> 16;
+}
+
+__device__ __forceinline__ uint32_t encode_e4m3(double x) {
+    const double y = round_format<4, -6>(x, 448.0);
+    const uint32_t sgn = y < 0.0 ? 0x80u : 0u;
+    const double a = fabs(y);
+    if (a == 0.0) return sgn;
+    if (a < 0x1p-6) return sgn | static_cast<uint32_t>(a * 512.0);  // subnormal: a = k 2^-9
+    const int E = ilogb(a);
+    return sgn | (static_cast<uint32_t>(E + 7) << 3) | (static_cast<uint32_t>(ldexp(a, 3 - E)) - 8u);
+}
+
+// One thread = one column j and one 16-byte chunk (8 BF16 or 16 E4M3 rows).
+template <int FMT, typename T, int NC>
+__global__ __launch_bounds__(256) void k_store(const T* __restrict__ src, int64_t m, int64_t n,
+                                               int64_t ld, int64_t rows, int64_t col_bytes,
+                                               int64_t nchunks, const int32_t* __restrict__ rexp,
+                                               uint8_t* __restrict__ out) {
+    constexpr int RPC = (FMT == 16) ? 8 : 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+    const int64_t chunk = static_cast<int64_t>(blockIdx.y) * 4 + wave;
+    if (j >= n || chunk >= nchunks) return;
+    const int64_t i0 = chunk * RPC;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < RPC; ++q) {
+        const int64_t i = i0 + q;
+        if (i >= rows) break;
+        const double x = ldexp(load_stacked<T, NC>(src, m, ld, i, j), -rexp[i]);
+        const int bit = q * (FMT == 16 ? 16 : 8);
+        w[bit >> 5] |= (FMT == 16 ? encode_bf16(x) : encode_e4m3(x)) << (bit & 31);
+    }
+    *reinterpret_cast<uint4*>(out + static_cast<size_t>(j) * col_bytes + chunk * 16) =
+        make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <typename T, int NC>
+qiht_status store_t(int fmt, const void* src, int64_t m, int64_t n, int64_t ld, qiht_qmatrix* q,
+                    hipStream_t st) {
+    int* d_bad = nullptr;
+    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_bad), sizeof(int), st));
+    QIHT_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), st));
+    hipLaunchKernelGGL((k_rowexp<T, NC>), dim3(static_cast<unsigned>(q->rows)), dim3(256), 0, st,
+                       static_cast<const T*>(src), m, n, ld, fmt == 16 ? 1.0 : 448.0, q->rexp, d_bad);
+    QIHT_HIP(hipGetLastError());
+    const int64_t nchunks = q->col_bytes / 16;
+    dim3 grid(static_cast<unsigned>((n + 63) / 64), static_cast<unsigned>((nchunks + 3) / 4));
+    if (fmt == 16)
+        hipLaunchKernelGGL((k_store<16, T, NC>), grid, dim3(256), 0, st, static_cast<const T*>(src),
+                           m, n, ld, q->rows, q->col_bytes, nchunks, q->rexp, q->codes[0]);
+    else
+        hipLaunchKernelGGL((k_store<9, T, NC>), grid, dim3(256), 0, st, static_cast<const T*>(src),
+                           m, n, ld, q->rows, q->col_bytes, nchunks, q->rexp, q->codes[0]);
+    QIHT_HIP(hipGetLastError());
+    int bad = 0;
+    QIHT_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    QIHT_HIP(hipFreeAsync(d_bad, st));
+    QIHT_HIP(hipStreamSynchronize(st));
+    if (bad) return fail(QIHT_ERR_NUMERIC, "input contains NaN or Inf");
+    return QIHT_OK;
+}
+
 template <typename T, int NC>
 qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
                      hipStream_t st, double* c_out) {
@@ -247,6 +369,17 @@ qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
         case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, q, st);
         case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
         case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
+    }
+    return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
+}
+
+qiht_status launch_store_matrix(const void* src, qiht_dtype dt, int64_t m, int64_t n,
+                                int64_t ld, int fmt, qiht_qmatrix* q, hipStream_t st) {
+    switch (dt) {
+        case QIHT_F32: return store_t<float, 1>(fmt, src, m, n, ld, q, st);
+        case QIHT_F64: return store_t<double, 1>(fmt, src, m, n, ld, q, st);
+        case QIHT_C64: return store_t<float, 2>(fmt, src, m, n, ld, q, st);
+        case QIHT_C128: return store_t<double, 2>(fmt, src, m, n, ld, q, st);
     }
     return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
 }

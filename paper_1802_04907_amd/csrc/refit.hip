@@ -18,25 +18,26 @@ constexpr int kNB = 32;       // Cholesky block
 constexpr int kTile = 64;     // Gram / update tile (16 x 16 threads, 4 x 4 each)
 constexpr int kKc = 16;       // rows per LDS step of the Gram product
 
-// Column t of A_G from packed codes: alpha code + beta (plain floats for 32).
+// Column t of A_G from the stored matrix: alpha code + beta (packed codes),
+// the float (32), or 2^e_i times the stored value (dense formats).
 template <int BITS>
 __global__ __launch_bounds__(256) void k_refit_codes(const uint8_t* __restrict__ codes,
                                                      int64_t col_bytes, int64_t rows,
                                                      double alpha, double beta,
+                                                     const int32_t* __restrict__ rowexp,
                                                      const int32_t* __restrict__ sup,
                                                      double* __restrict__ A) {
-    constexpr int RPW = (BITS == 32) ? 1 : 32 / BITS;
+    constexpr int RPW = rows_per_word<BITS>();
     const int t = blockIdx.y;
     const uint8_t* col = codes + static_cast<int64_t>(sup[t]) * col_bytes;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < rows;
          i += static_cast<int64_t>(gridDim.x) * 256) {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(col)[i / RPW];
+        const double e = elem_at<BITS>(w, static_cast<int>(i % RPW));
         double v;
-        if (BITS == 32) {
-            v = static_cast<double>(reinterpret_cast<const float*>(col)[i]);
-        } else {
-            const uint32_t w = reinterpret_cast<const uint32_t*>(col)[i / RPW];
-            v = alpha * static_cast<double>(code_at<BITS>(w, static_cast<int>(i % RPW))) + beta;
-        }
+        if constexpr (BITS == 32) v = e;
+        else if constexpr (BITS == 9 || BITS == 16) v = ldexp(e, rowexp[i]);
+        else v = alpha * e + beta;
         A[static_cast<int64_t>(t) * rows + i] = v;
     }
 }
@@ -404,11 +405,13 @@ void launch_refit(const RefitIn& in, uint8_t* ws, hipStream_t st) {
         }
     } else {
         switch (in.bits) {
-            case 1: hipLaunchKernelGGL((k_refit_codes<1>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.sup, w.A); break;
-            case 2: hipLaunchKernelGGL((k_refit_codes<2>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.sup, w.A); break;
-            case 4: hipLaunchKernelGGL((k_refit_codes<4>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.sup, w.A); break;
-            case 8: hipLaunchKernelGGL((k_refit_codes<8>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.sup, w.A); break;
-            default: hipLaunchKernelGGL((k_refit_codes<32>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.sup, w.A); break;
+            case 1: hipLaunchKernelGGL((k_refit_codes<1>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            case 2: hipLaunchKernelGGL((k_refit_codes<2>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            case 4: hipLaunchKernelGGL((k_refit_codes<4>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            case 8: hipLaunchKernelGGL((k_refit_codes<8>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            case 9: hipLaunchKernelGGL((k_refit_codes<9>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            case 16: hipLaunchKernelGGL((k_refit_codes<16>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+            default: hipLaunchKernelGGL((k_refit_codes<32>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
         }
     }
     const int T = (s + kTile - 1) / kTile;

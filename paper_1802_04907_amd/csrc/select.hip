@@ -663,7 +663,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
 // |Q1 dx|^2 of slot 0's difference list, by one workgroup.
 template <int BITS>
 __device__ double omega_den_block(const ProbDev& pd, int dcount, double* red) {
-    constexpr int RPW = (BITS == 32) ? 1 : 32 / BITS;
+    constexpr int RPW = rows_per_word<BITS>();
     const int words = static_cast<int>(pd.col_bytes / 4);
     double wsum = 0.0;
     for (int t = 0; t < dcount; ++t) wsum += pd.dw[t];
@@ -677,17 +677,16 @@ __device__ double omega_den_block(const ProbDev& pd, int dcount, double* red) {
                 pd.q1 + static_cast<size_t>(pd.dlist[t]) * pd.col_bytes + static_cast<size_t>(w) * 4);
             const double wt = pd.dw[t];
 #pragma unroll
-            for (int q = 0; q < RPW; ++q) {
-                const double v = (BITS == 32) ? static_cast<double>(__uint_as_float(word))
-                                              : static_cast<double>(code_at<BITS>(word, q));
-                acc[q] = fma(wt, v, acc[q]);
-            }
+            for (int q = 0; q < RPW; ++q) acc[q] = fma(wt, elem_at<BITS>(word, q), acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int64_t row = static_cast<int64_t>(w) * RPW + q;
             if (row < pd.rows) {
-                const double v = (BITS == 32) ? acc[q] : pd.alpha * acc[q] + pd.beta * wsum;
+                double v;
+                if constexpr (BITS == 32) v = acc[q];
+                else if constexpr (BITS == 9 || BITS == 16) v = ldexp(acc[q], pd.rowexp[row]);
+                else v = pd.alpha * acc[q] + pd.beta * wsum;
                 tot += v * v;
             }
         }
@@ -778,6 +777,8 @@ void launch_decide(int bits, const ProbDev* P, int count, const SolveArgs& a, hi
         case 2: hipLaunchKernelGGL(k_decide<2>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
         case 4: hipLaunchKernelGGL(k_decide<4>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
         case 8: hipLaunchKernelGGL(k_decide<8>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        case 9: hipLaunchKernelGGL(k_decide<9>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
+        case 16: hipLaunchKernelGGL(k_decide<16>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
         default: hipLaunchKernelGGL(k_decide<32>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
     }
 }

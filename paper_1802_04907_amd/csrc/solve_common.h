@@ -61,6 +61,8 @@ struct ProbDev {
     float pad_f;
     const double* yhat;
     float* r32;         // residual, rows_pad (zero beyond rows)
+    const int32_t* rowexp; // dense formats: row exponents (value = 2^e stored)
+    uint16_t* rb;       // dense formats: 2^e r as BF16 hi (rows_pad) then lo (rows_pad)
     uint32_t* rdig;     // residual digits, digit-major: ND x (nwg * 4H) words
     int32_t* rexp;      // per row chunk: fixed-point exponent e
     int32_t* rsum;      // per row chunk: sum_i N_i
@@ -441,6 +443,39 @@ __device__ __forceinline__ uint32_t code_at(uint32_t w, int q) {
     return (w >> (q * BITS)) & ((1u << BITS) - 1u);
 }
 
+// Dense formats: the stored value of an FP8 E4M3 byte / a BF16 half word.
+__device__ __forceinline__ float e4m3_value(uint32_t b) {
+    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+    const float mag = e == 0u ? static_cast<float>(m) * 0x1p-9f
+                              : __uint_as_float(((e + 120u) << 23) | (m << 20));
+    return (b & 0x80u) ? -mag : mag;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+// Nearest BF16 of an FP64 value (ties to even), as its 16-bit pattern: the
+// significand is cut at 8 bits directly from the FP64 value (one rounding).
+__device__ __forceinline__ uint32_t bf16_rne(double x) {
+    if (x == 0.0 || !isfinite(x)) return __float_as_uint(static_cast<float>(x)) >> 16;
+    const int qe = max(ilogb(x), -126) - 7;
+    const float y = static_cast<float>(ldexp(rint(ldexp(x, -qe)), qe));
+    return __float_as_uint(y) >> 16;
+}
+
+// Rows held by one 32-bit word of a column, and the value of row q of the
+// word before the row scaling: the integer code (packed formats), the float
+// (32), or the stored low-precision value (kFmtE4M3 = 9, kFmtBF16 = 16).
+template <int BITS>
+constexpr int rows_per_word() {
+    return BITS == 32 ? 1 : BITS == 16 ? 2 : BITS == 9 ? 4 : 32 / BITS;
+}
+template <int BITS>
+__device__ __forceinline__ double elem_at(uint32_t w, int q) {
+    if constexpr (BITS == 32) return static_cast<double>(__uint_as_float(w));
+    else if constexpr (BITS == 16) return static_cast<double>(bf16_value((w >> (16 * q)) & 0xFFFFu));
+    else if constexpr (BITS == 9) return static_cast<double>(e4m3_value((w >> (8 * q)) & 0xFFu));
+    else return static_cast<double>(code_at<BITS>(w, q));
+}
+
 // Launchers (defined in the kernel files).
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, hipStream_t st);
@@ -449,6 +484,23 @@ void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
 size_t refit_workspace_bytes(int64_t rows, int64_t s);
 int* refit_flag(uint8_t* ws, int64_t rows, int64_t s);
 void launch_refit(const RefitIn& in, uint8_t* ws, hipStream_t st);
+
+// Shared-matrix pass (gemm.hip): G = Phi~^T R' on the matrix cores for all
+// problems of a batch that share one dense-format or FP32 matrix.
+struct SharedGemm {
+    const uint8_t* a;   // stored columns
+    int64_t col_bytes;
+    int n;              // columns
+    int rows_pad;       // rows covered by col_bytes (a multiple of 32)
+    int bits;           // kFmtBF16, kFmtE4M3 or 32
+    const void* b;      // R' of problem 0; problem k at + k * ldb elements
+    int64_t ldb;        //   (BF16 hi/lo: 16-bit elements, lo at + lo_off; FP32: floats)
+    int64_t lo_off;
+    float* g;           // g of problem 0; problem k at + k * ldg
+    int64_t ldg;
+};
+void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipStream_t st,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Workgroups of the full pass that the device holds at once (0 if unknown).
 int pass_slots(int bits, int cpl);

@@ -93,10 +93,22 @@ struct Plan {
     bool any_slab = false;
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0;
+    // shared-matrix path: one GEMM per iteration instead of per-problem passes
+    bool shared = false;
+    SharedGemm sg{};
+    size_t gblk_off = 0, bblk_off = 0;
 };
 
 qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     pl.bits = in[0].q->bits;
+    // All problems on one matrix: the pass is a GEMM on the matrix cores.
+    // Dense formats have no per-problem pass; FP32 takes the GEMM from two
+    // problems on.
+    bool same = true;
+    for (int i = 1; i < count; ++i) same = same && in[i].q == in[0].q;
+    if (is_dense_format(pl.bits) && !same)
+        return fail(QIHT_ERR_UNSUPPORTED, "problems on a dense-format matrix must share one handle");
+    pl.shared = same && (is_dense_format(pl.bits) || (pl.bits == 32 && count > 1));
     int64_t max_cb = 0, max_n = 0;
     for (int i = 0; i < count; ++i) {
         max_cb = std::max(max_cb, in[i].q->col_bytes);
@@ -117,15 +129,16 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         pl.maxwg = std::max(pl.maxwg, nwg);
         pl.any_slab = pl.any_slab || nslab > 1;
         Layout& L = pl.lay[i];
-        L.r32 = cv.take<float>(q->rows_pad);
+        // (FP32 on a shared matrix: r lives in the GEMM's operand block)
+        L.r32 = (pl.shared && pl.bits == 32) ? 0 : cv.take<float>(q->rows_pad);
         L.cidx = cv.take<uint32_t>(q->n);
         L.cgx = cv.take<float2>(q->n);
         L.ccnt = cv.take<int32_t>(nwg);
         L.rdig = cv.take<uint32_t>(static_cast<size_t>(nwg) * digit_words_per_chunk(q->bits));
         L.rexp = cv.take<int32_t>(nwg);
         L.rsum = cv.take<int32_t>(nwg);
-        L.g = cv.take<float>(q->n);
-        L.gpart = cv.take<float>(nslab > 1 ? static_cast<size_t>(nslab) * q->n : 1);
+        L.g = pl.shared ? 0 : cv.take<float>(q->n);
+        L.gpart = cv.take<float>(nslab > 1 && !pl.shared ? static_cast<size_t>(nslab) * q->n : 1);
         L.hist = cv.take<uint32_t>(2048);
         L.x = cv.take<float>(q->n);
         L.sup = cv.take<int32_t>(s);
@@ -149,21 +162,43 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.n = static_cast<int32_t>(q->n);
         p.s = static_cast<int32_t>(s);
         p.nwg = nwg;
-        p.nslab = nslab;
+        p.nslab = pl.shared ? 1 : nslab;
+        p.rowexp = q->rexp;
         p.alpha = q->alpha;
         p.beta = q->beta;
         p.alpha_f = static_cast<float>(q->alpha);
         p.yhat = in[i].yhat;
     }
+    if (pl.shared) {
+        // G (problem k's g at k ldg) and R' (problem k's at k ldb), contiguous
+        const qiht_qmatrix* q = in[0].q;
+        pl.any_slab = false;
+        pl.sg.a = q->codes[0];
+        pl.sg.col_bytes = q->col_bytes;
+        pl.sg.n = static_cast<int>(q->n);
+        pl.sg.rows_pad = static_cast<int>(q->rows_pad);
+        pl.sg.bits = pl.bits;
+        pl.sg.ldg = round_up(q->n, 64);
+        pl.gblk_off = cv.take<float>(static_cast<size_t>(count) * pl.sg.ldg);
+        if (pl.bits == 32) {
+            pl.sg.ldb = q->rows_pad;
+            pl.sg.lo_off = 0;
+            pl.bblk_off = cv.take<float>(static_cast<size_t>(count) * q->rows_pad);
+        } else {
+            pl.sg.ldb = 2 * q->rows_pad;
+            pl.sg.lo_off = q->rows_pad;
+            pl.bblk_off = cv.take<uint16_t>(static_cast<size_t>(count) * 2 * q->rows_pad);
+        }
+    }
     // Full-pass tasks: column ranges of one row slab, sized so that the
     // launch is one round of the workgroups the device holds at once (a
     // second, partial round would leave most CUs idle at the end).
-    const int slots = std::max(1, pass_slots(pl.bits, pl.cpl));
+    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl));
     double total = 0.0;
     for (int i = 0; i < count; ++i)
         total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
     const double per_task = std::max(1.0, total / slots);
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0; i < count && !pl.shared; ++i) {
         const qiht_qmatrix* q = in[i].q;
         const ProbDev& p = pl.host[i];
         const int64_t slab_bytes = std::min<int64_t>(q->col_bytes, slab_chunks * 16);
@@ -185,17 +220,28 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
 }
 
 void bind(Plan& pl, uint8_t* base) {
+    if (pl.shared) {
+        pl.sg.g = reinterpret_cast<float*>(base + pl.gblk_off);
+        pl.sg.b = base + pl.bblk_off;
+    }
     for (size_t i = 0; i < pl.host.size(); ++i) {
         ProbDev& p = pl.host[i];
         const Layout& L = pl.lay[i];
-        p.r32 = reinterpret_cast<float*>(base + L.r32);
+        p.r32 = reinterpret_cast<float*>(base + L.r32);  // replaced below for FP32 shared
+        if (pl.shared) {
+            p.g = pl.sg.g + static_cast<int64_t>(i) * pl.sg.ldg;
+            if (pl.bits == 32)
+                p.r32 = static_cast<float*>(const_cast<void*>(pl.sg.b)) + static_cast<int64_t>(i) * pl.sg.ldb;
+            else
+                p.rb = static_cast<uint16_t*>(const_cast<void*>(pl.sg.b)) + static_cast<int64_t>(i) * pl.sg.ldb;
+        }
         p.cidx = reinterpret_cast<uint32_t*>(base + L.cidx);
         p.cgx = reinterpret_cast<float2*>(base + L.cgx);
         p.ccnt = reinterpret_cast<int32_t*>(base + L.ccnt);
         p.rdig = reinterpret_cast<uint32_t*>(base + L.rdig);
         p.rexp = reinterpret_cast<int32_t*>(base + L.rexp);
         p.rsum = reinterpret_cast<int32_t*>(base + L.rsum);
-        p.g = reinterpret_cast<float*>(base + L.g);
+        if (!pl.shared) p.g = reinterpret_cast<float*>(base + L.g);
         p.gpart = reinterpret_cast<float*>(base + L.gpart);
         p.hist = reinterpret_cast<uint32_t*>(base + L.hist);
         p.x = reinterpret_cast<float*>(base + L.x);
@@ -301,6 +347,10 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
     launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, st);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) tm->pair(&e0, &e1);
+    if (pl.shared) {
+        launch_shared_pass(pl.sg, dP, count, st, e0, e1);
+        return;
+    }
     launch_pass(pl.bits, pl.cpl, dP, dT, static_cast<int>(pl.tasks.size()), st, e0, e1);
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }

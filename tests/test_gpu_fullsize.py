@@ -99,3 +99,75 @@ def test_fullsize_gradient_and_solve(big):
     rec = len(np.intersect1d(ss, p.support)) / S
     say(f"support recovery {rec:.3f}, info {info}")
     assert rec > 0.6
+
+
+# ------------------------------------------------ shared matrix, full size
+# One 8192 x 32768 Gaussian Phi held in a dense format, 256 right-hand sides
+# of sparsity 256 solved together: the shared-matrix benchmark's shapes, with
+# equal-magnitude nonzeros so that the s-th and (s+1)-th entries H_s compares
+# are far apart (with N(0, 1) nonzeros some true entries sit among the noise
+# and the support boundary becomes a near-tie that any rounding can flip).
+NRHS, S5 = 256, 256
+SHARED_FMTS = {"f32": 32, "bf16": qiht.BF16, "e4m3": qiht.E4M3}
+
+
+@pytest.fixture(scope="module")
+def shared_big():
+    say("generating the shared-matrix workload (256 right-hand sides)")
+    phi, Y, X, sups = workloads.shared_phi(M, N, NRHS, S5, 1e-3, 0, equal=True)
+    yield phi, Y, X, sups
+
+
+@pytest.mark.parametrize("fmt", list(SHARED_FMTS))
+def test_fullsize_shared_first_iteration_and_solve(shared_big, fmt):
+    from oracle import lowprec as lp
+    from oracle import niht
+    phi, Y, X, sups = shared_big
+    say(f"shared {fmt}: storing")
+    q = qiht.quantize_matrix(torch.from_numpy(phi).to(DEV), SHARED_FMTS[fmt], 1, 0)
+    st, e, A = lp.store_matrix(phi, fmt)
+    del st
+    if fmt != "f32":
+        np.testing.assert_array_equal(q.row_exponents(), e)
+        rng = np.random.default_rng(5)
+        cols = np.unique(np.concatenate([[0, N - 1], rng.choice(N, 30, replace=False)]))
+        codes = q.export_codes(0)[:, cols]
+        got = lp.e4m3_decode(codes) if fmt == "e4m3" else codes.astype(np.float64)
+        np.testing.assert_array_equal(got * np.ldexp(1.0, e)[:, None], A[:, cols])
+        del codes
+    ys = [torch.from_numpy(np.ascontiguousarray(Y[:, j])).to(DEV) for j in range(NRHS)]
+    probs = [(q, ys[j], S5) for j in range(NRHS)]
+
+    say(f"shared {fmt}: one iteration of every problem against the oracle on samples")
+    res = qiht.niht_solve_batched(probs, max_iters=1, tol=-1.0)
+    for j in (0, 97, 200, NRHS - 1):
+        ref = niht.qiht_solve(A, A, Y[:, j], S5, max_iters=1, tol=-1.0)
+        x, sup, info = res[j]
+        np.testing.assert_array_equal(sup.cpu().numpy(), ref.support, err_msg=f"rhs {j}")
+        err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        say(f"  rhs {j}: rel err {err:.2e}, backtracks {info['backtracks']}/{ref.backtracks}")
+        assert err <= 1e-4, j
+
+    say(f"shared {fmt}: 30 iterations")
+    res = qiht.niht_solve_batched(probs, max_iters=30, tol=-1.0)
+    rec = []
+    for j, (x, sup, info) in enumerate(res):
+        xs, ss = x.cpu().numpy(), sup.cpu().numpy()
+        assert ss.size == S5 and np.all(np.diff(ss) > 0) and ss[0] >= 0 and ss[-1] < N
+        assert np.count_nonzero(np.delete(xs, ss)) == 0 and np.all(np.isfinite(xs))
+        rec.append(len(np.intersect1d(ss, sups[j])) / S5)
+    say(f"  support recovery: min {min(rec):.3f}, mean {np.mean(rec):.3f}")
+    assert min(rec) >= 0.95
+    # teacher-forced gradient at one final iterate, sampled columns
+    j = 7
+    x, sup, _ = res[j]
+    g, r = qiht.gradient(q, ys[j], x, sup)
+    ss = sup.cpu().numpy()
+    r_or = Y[:, j] - A[:, ss] @ x.cpu().numpy()[ss].astype(np.float64)
+    assert np.all(np.abs(r.cpu().numpy() - r_or) <= 2.0 ** -23 * np.abs(r_or) + 1e-30)
+    g_or = A.T @ r_or
+    g0n = np.linalg.norm(A.T @ Y[:, j])
+    err = np.linalg.norm(g.cpu().numpy() - g_or)
+    say(f"  gradient at the final iterate: |dg| {err:.2e}, |g| {np.linalg.norm(g_or):.2e}")
+    assert err <= 1e-5 * max(np.linalg.norm(g_or), 1e-3 * g0n)
+    q.free()

@@ -133,10 +133,13 @@ def batch_uneven(count=96, m_lo=1024, m_hi=8192, seed=0, sigma_e=1e-3,
 
 
 def shared_phi(m=8192, n=32768, nrhs=256, s=256, sigma_e=1e-3, seed=0,
-               dtype=np.float32):
+               dtype=np.float32, equal=False):
     """Config 5 recipe: one Gaussian Phi, nrhs sparse right-hand sides.
 
+    ``s`` is the sparsity of every signal, or a sequence of nrhs sparsities;
+    ``equal`` sets every nonzero to 1 (no draw) instead of N(0, 1).
     Returns (phi, Y (m, nrhs), X (n, nrhs), supports list)."""
+    s_list = [int(s)] * nrhs if np.isscalar(s) else [int(v) for v in s]
     rng = np.random.default_rng(seed)
     if np.dtype(dtype) == np.float32:
         phi = rng.standard_normal((m, n), dtype=np.float32)
@@ -146,8 +149,8 @@ def shared_phi(m=8192, n=32768, nrhs=256, s=256, sigma_e=1e-3, seed=0,
     X = np.zeros((n, nrhs))
     sups = []
     for j in range(nrhs):
-        sup = np.sort(rng.choice(n, s, replace=False))
-        X[sup, j] = rng.standard_normal(s)
+        sup = np.sort(rng.choice(n, s_list[j], replace=False))
+        X[sup, j] = 1.0 if equal else rng.standard_normal(s_list[j])
         sups.append(sup)
     E = sigma_e * rng.standard_normal((m, nrhs))
     Y = np.zeros((m, nrhs))
