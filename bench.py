@@ -141,7 +141,7 @@ def cpu_baseline(p, ncols=4096, iters=10):
     }
 
 
-def shared_bench(qiht, torch, dev, reps=2):
+def shared_bench(qiht, torch, dev, reps=2, only=None):
     """The shared-matrix workload: one 8192 x 32768 Gaussian Phi held in
     FP32 / BF16 / E4M3, 256 right-hand sides of sparsity 256, each batch one
     GEMM per iteration.  Reports right-hand-side iterations/s, the GEMM's
@@ -160,6 +160,8 @@ def shared_bench(qiht, torch, dev, reps=2):
            "formats": {}}
     flops = 2.0 * M * N * NRHS
     for fmt, code in (("f32", 32), ("bf16", qiht.BF16), ("e4m3", qiht.E4M3)):
+        if only is not None and fmt != only:
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         q = qiht.quantize_matrix(phi_d, code, 1, SEED)
@@ -204,7 +206,7 @@ def shared_bench(qiht, torch, dev, reps=2):
             "refit_ms_all_rhs": round((el_r - el) * 1e3, 2),
         }
         log(fmt, json.dumps(res["formats"][fmt]))
-        if fmt == "f32":
+        if fmt == "f32" and only is None:
             # the same problems one at a time on the per-problem FP32 path
             k = 8
             qiht.niht_solve(q, ys[0], S5, max_iters=2, tol=-1.0)
@@ -229,6 +231,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-shared", action="store_true",
                     help="skip the shared-matrix (many right-hand sides) measurement")
+    ap.add_argument("--shared-only", default=None, choices=["f32", "bf16", "e4m3"],
+                    help="only the shared-matrix workload in one format (short run for "
+                         "rocprofv3 traces of its kernels)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
@@ -255,6 +260,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 4 << 28, "bytes_written": 4 << 28,
                           "launches": 3}))
+        return
+    if args.shared_only:
+        print(json.dumps(shared_bench(qiht, torch, dev, reps=1, only=args.shared_only)))
         return
     log("generating workload ...")
     p = workloads.config2(SEED)

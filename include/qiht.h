@@ -239,6 +239,15 @@ typedef struct {
  * infos: host array of `count` (optional).  Same semantics per problem as
  * qiht_niht_solve; the warm start in p is not supported here (must be
  * NULL).  Synchronizes stream.
+ *
+ * Shared matrix: when every problem uses the same handle and that handle
+ * is a dense format (QIHT_FMT_BF16 / QIHT_FMT_E4M3), or bits = 32 with
+ * count > 1, the per-iteration products g_k = A^T r_k of all problems are
+ * one GEMM G = A^T R on the matrix cores (FP32 accumulation; BF16 and E4M3
+ * storage multiply in BF16 with each r_k carried as two BF16 terms, about
+ * 16 significant bits; FP32 storage in FP32), and the column gathers read
+ * 256-byte row segments.  Problems on dense-format handles must all share
+ * one handle (UNSUPPORTED otherwise).
  */
 qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
                                     const qiht_params* p, qiht_info* infos,

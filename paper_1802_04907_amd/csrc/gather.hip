@@ -107,10 +107,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         if (MODE == G_R) wpos = pd.xs;
         else wcol = pd.g;
     }
-    const bool two = (MODE == G_MU) && (a.mu_mode == 0);
+    // (one copy of the matrix: Q2_G g_G = Q1_G g_G, read once)
+    const bool two = (MODE == G_MU) && (a.mu_mode == 0) && (pd.q1 != pd.q2);
     // the candidate compaction's inputs go out with the gather's loads
     CandPre cpre;
-    if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.nwg, true);
+    if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
     const uint8_t* A = (MODE == G_R) ? pd.q2 : pd.q1;
     const uint8_t* B = pd.q2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -253,13 +254,149 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         pd.part_om[static_cast<size_t>(set) * pd.nwg + wg] = s1;
     }
     // g is final here: the off-support candidates of this iteration's proposals
-    if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.nwg, true, cpre);
+    if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.npart, true, cpre);
+}
+
+
+// ---------------------------------------------------------------------------
+// Wide gathers for a batch on one shared dense-format or FP32 matrix (one
+// copy: Q1 = Q2).  Hundreds of problems each list hundreds of columns, so
+// the gathers move gigabytes per iteration and must run at bandwidth rather
+// than latency: a workgroup owns a 256-byte row segment of every listed
+// column (one coalesced 256-byte read per wave and column), its four waves
+// take the listed columns w, w + 4, ..., and the list itself (indices and
+// weights) is staged through LDS first, so every batch of loads is one HBM
+// round trip.  Rows are summed per lane in FP64, then over the waves in wave
+// order (fixed order, bitwise reproducible).  Partials and candidate lists
+// are per 256-byte segment (npart of them).
+// ---------------------------------------------------------------------------
+constexpr int kWideBytes = 256;
+constexpr int kWideList = 1024;  // list entries staged at once
+
+template <int BITS, int MODE>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* __restrict__ P,
+                                                                SolveArgs a, int zero_x) {
+    constexpr int RPW = rows_per_word<BITS>();
+    constexpr int NSET = (MODE == G_OMEGA) ? kSpec : 1;
+    constexpr int NW = kGatherThreads / 64;
+    constexpr int NR = 64 * RPW;  // rows of the segment
+    static_assert(NR <= kGatherThreads, "one thread per row of the segment");
+    constexpr int U = 8;
+    const int p = blockIdx.y / NSET;
+    const int set = blockIdx.y % NSET;
+    const ProbDev& pd = P[p];
+    if (pd.st->done) return;
+    const int wg = blockIdx.x;  // 256-byte row segment
+    if (wg >= pd.npart) return;
+
+    const int32_t* cols;
+    int ncols;
+    if (MODE == G_OMEGA) {
+        const CandMeta& m = pd.meta[set];
+        if (!m.changed) return;
+        ncols = m.dcount;
+        cols = pd.dlist + static_cast<size_t>(set) * 2 * pd.s;
+    } else {
+        cols = pd.sup;
+        ncols = (MODE == G_R && zero_x) ? 0 : pd.s;
+    }
+    CandPre cpre;
+    if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
+    const uint8_t* A = pd.q1;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t woff = static_cast<size_t>(wg) * kWideBytes + static_cast<size_t>(lane) * 4;
+
+    __shared__ int32_t lidx[kWideList];
+    __shared__ double lw[kWideList];
+    double acc[RPW];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) acc[q] = 0.0;
+    for (int base = 0; base < ncols; base += kWideList) {
+        const int cnt = min(kWideList, ncols - base);
+        for (int i = tid; i < cnt; i += kGatherThreads) {
+            const int c = static_cast<int>(ldg_u32(cols + base + i));
+            double w;
+            if (MODE == G_OMEGA) w = ldg_f64(pd.dw + static_cast<size_t>(set) * 2 * pd.s + base + i);
+            else if (MODE == G_R) w = static_cast<double>(ldg_f32(pd.xs + base + i));
+            else w = static_cast<double>(ldg_f32(pd.g + c));
+            lidx[i] = c;
+            lw[i] = w;
+        }
+        __syncthreads();
+        for (int t0 = wv; t0 < cnt; t0 += NW * U) {
+            uint32_t wa[U];
+            double wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + NW * u;
+                const int tc = min(t, cnt - 1);
+                wt[u] = t < cnt ? lw[tc] : 0.0;
+                wa[u] = ldg_u32(A + static_cast<size_t>(lidx[tc]) * pd.col_bytes + woff);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < RPW; ++q) acc[q] = fma(wt[u], elem_at<BITS>(wa[u], q), acc[q]);
+        }
+        __syncthreads();
+    }
+    // ---- waves in wave order; thread t < NR then holds row wg NR + t
+    __shared__ double sh[NW][64][RPW];
+    __shared__ double shr[NW];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) sh[wv][lane][q] = acc[q];
+    __syncthreads();
+    double val = 0.0;
+    const size_t row = static_cast<size_t>(wg) * NR + tid;
+    const bool live = tid < NR && row < static_cast<size_t>(pd.rows);
+    if (tid < NR) {
+        double tot = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) tot += sh[v][tid / RPW][tid % RPW];
+        if constexpr (BITS == 32) val = tot;
+        else val = live ? ldexp(tot, pd.rowexp[row]) : 0.0;
+    }
+    if constexpr (MODE == G_R) {
+        if (tid < NR) {
+            const double rres = live ? ldg_f64(pd.yhat + row) - val : 0.0;
+            pd.r32[row] = static_cast<float>(rres);
+            if constexpr (BITS == 9 || BITS == 16) {
+                // the GEMM's operand: 2^e r as a pair of BF16 (hi + lo)
+                const double v = live ? ldexp(rres, pd.rowexp[row]) : 0.0;
+                const uint32_t hi = bf16_rne(v);
+                const uint32_t lo = bf16_rne(v - static_cast<double>(bf16_value(hi)));
+                const size_t rp = static_cast<size_t>(pd.nwg) * 4 * RPW;  // rows_pad
+                pd.rb[row] = static_cast<uint16_t>(hi);
+                pd.rb[rp + row] = static_cast<uint16_t>(lo);
+            }
+        }
+        return;
+    }
+    const double s1 = block_sum<kGatherThreads>(live ? val * val : 0.0, shr);
+    if (MODE == G_MU) {
+        if (tid == 0) {
+            pd.part_mu[2 * wg + 0] = s1;  // u.v with v = u (one copy of the matrix)
+            pd.part_mu[2 * wg + 1] = s1;
+        }
+        compact_candidates<kGatherThreads>(pd, wg, pd.npart, true, cpre);
+    } else if (tid == 0) {
+        pd.part_om[static_cast<size_t>(set) * pd.nwg + wg] = s1;
+    }
 }
 
 template <int MODE>
 void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveArgs& a,
-                 int zero_x, hipStream_t st) {
+                 int zero_x, bool wide, hipStream_t st) {
     const int nset = (MODE == G_OMEGA) ? kSpec : 1;
+    if (wide) {
+        dim3 gw((maxwg * 16 + kWideBytes - 1) / kWideBytes, count * nset);
+        switch (bits) {
+            case 9: hipLaunchKernelGGL((k_gather_wide<9, MODE>), gw, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+            case 16: hipLaunchKernelGGL((k_gather_wide<16, MODE>), gw, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+            default: hipLaunchKernelGGL((k_gather_wide<32, MODE>), gw, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+        }
+        return;
+    }
     dim3 grid(maxwg, count * nset);
     switch (bits) {
         case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
@@ -275,11 +412,11 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
 }  // namespace
 
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg, const SolveArgs& a,
-                   int zero_x, hipStream_t st) {
+                   int zero_x, bool wide, hipStream_t st) {
     switch (mode) {
-        case G_R: launch_mode<G_R>(bits, P, count, maxwg, a, zero_x, st); break;
-        case G_MU: launch_mode<G_MU>(bits, P, count, maxwg, a, 0, st); break;
-        default: launch_mode<G_OMEGA>(bits, P, count, maxwg, a, 0, st); break;
+        case G_R: launch_mode<G_R>(bits, P, count, maxwg, a, zero_x, wide, st); break;
+        case G_MU: launch_mode<G_MU>(bits, P, count, maxwg, a, 0, wide, st); break;
+        default: launch_mode<G_OMEGA>(bits, P, count, maxwg, a, 0, wide, st); break;
     }
 }
 

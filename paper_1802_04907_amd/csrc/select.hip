@@ -365,7 +365,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     constexpr int MPT = kCandCap / kSelectThreads;  // merged positions per thread
     constexpr int PRE = 4;                          // candidates loaded ahead per thread
     const int tid = threadIdx.x;
-    const int n = pd.n, s = pd.s, nw = pd.nwg;
+    const int n = pd.n, s = pd.s, nw = pd.npart;
     const int words = (n + 31) / 32;
     const int nsup = (MODE == SEL_STEP) ? s : 0;
     const int per = (n + nw - 1) / nw;
@@ -632,9 +632,9 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
 // Off-support candidates for the first proposal (x = 0, empty support).
 __global__ __launch_bounds__(kGatherThreads) void k_candidates(const ProbDev* __restrict__ P) {
     const ProbDev& pd = P[blockIdx.y];
-    if (pd.st->done || static_cast<int>(blockIdx.x) >= pd.nwg) return;
-    const CandPre pre = cand_preload<kGatherThreads>(pd, blockIdx.x, pd.nwg, false);
-    compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.nwg, false, pre);
+    if (pd.st->done || static_cast<int>(blockIdx.x) >= pd.npart) return;
+    const CandPre pre = cand_preload<kGatherThreads>(pd, blockIdx.x, pd.npart, false);
+    compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.npart, false, pre);
 }
 
 __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __restrict__ P,
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __rest
             break;
         }
         double den = 0.0;
-        for (int b = threadIdx.x; b < pd.nwg; b += kSelectThreads)
+        for (int b = threadIdx.x; b < pd.npart; b += kSelectThreads)
             den += pd.part_om[static_cast<size_t>(t) * pd.nwg + b];
         den = block_sum<kSelectThreads>(den, S.red);
         const double omega = den > 0.0 ? m.dx2 / den : INFINITY;

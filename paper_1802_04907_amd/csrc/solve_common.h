@@ -53,6 +53,8 @@ struct ProbDev {
     int32_t n;
     int32_t s;
     int32_t nwg;        // 16-byte row groups per column (gather workgroups)
+    int32_t npart;      // gather row segments: nwg, or 256-byte segments for the
+                        // wide gathers of a shared matrix (partials, candidate blocks)
     int32_t nslab;      // full-pass row slabs
     int32_t pad;
     double alpha;       // dequantized value = alpha * code + beta
@@ -79,11 +81,11 @@ struct ProbDev {
     int32_t* dlist;     // kSpec * 2s indices where a proposal differs from x
     double* dw;         // kSpec * 2s the differences
     CandMeta* meta;     // kSpec
-    double* part_mu;    // 2 * nwg partial (Q1_G g_G).(Q2_G g_G), |Q1_G g_G|^2
-    double* part_om;    // kSpec * nwg partial |Q1 (x'_t - x)|^2
+    double* part_mu;    // 2 * npart partial (Q1_G g_G).(Q2_G g_G), |Q1_G g_G|^2
+    double* part_om;    // kSpec x npart (stride nwg) partial |Q1 (x'_t - x)|^2
     uint32_t* cidx;     // n slots: candidates per index block (bit 31: on the support)
     float2* cgx;        // n slots: (g_j, x_j) at those candidates
-    int32_t* ccnt;      // nwg: candidates of each index block (-1: use the full path)
+    int32_t* ccnt;      // npart: candidates of each index block (-1: use the full path)
     SolveState* st;
 };
 
@@ -478,7 +480,7 @@ __device__ __forceinline__ double elem_at(uint32_t w, int q) {
 
 // Launchers (defined in the kernel files).
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
-                   const SolveArgs& a, int zero_x, hipStream_t st);
+                   const SolveArgs& a, int zero_x, bool wide, hipStream_t st);
 // ev0/ev1 (optional): events recorded by the dispatch itself around the
 // kernel (timing of the bandwidth-bound pass).
 size_t refit_workspace_bytes(int64_t rows, int64_t s);

@@ -162,6 +162,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.n = static_cast<int32_t>(q->n);
         p.s = static_cast<int32_t>(s);
         p.nwg = nwg;
+        p.npart = pl.shared ? static_cast<int>(q->col_bytes / 256) : nwg;
         p.nslab = pl.shared ? 1 : nslab;
         p.rowexp = q->rexp;
         p.alpha = q->alpha;
@@ -344,7 +345,7 @@ struct Workspace {
 
 void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                        const SolveArgs& a, int zero_x, hipStream_t st, PassTimer* tm) {
-    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, st);
+    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, pl.shared, st);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) tm->pair(&e0, &e1);
     if (pl.shared) {
@@ -358,9 +359,9 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                         const SolveArgs& a, hipStream_t st, PassTimer* tm) {
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
-    launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, st);
+    launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
     launch_propose(dP, count, a, SEL_STEP, st);
-    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, st);
+    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
     launch_decide(pl.bits, dP, count, a, st);
 }
 
