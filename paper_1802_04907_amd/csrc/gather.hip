@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
             else w = static_cast<double>(ldg_f32(pd.g + c));
             lidx[i] = c;
             lw[i] = w;
+            if (MODE == G_MU && wg == 0) pd.gs[base + i] = static_cast<float>(w);  // g on the support
         }
         __syncthreads();
         for (int t0 = wv; t0 < cnt; t0 += NW * U) {
