@@ -29,6 +29,9 @@
  *    qiht_last_error() (thread-local).  No C++ exception crosses the ABI.
  *  - Not thread-safe on one qiht_qmatrix; distinct handles may be used
  *    from distinct threads.
+ *  - Per-call workspaces are allocated stream-ordered from a memory pool the
+ *    library creates per device; the pool keeps freed memory for reuse (it
+ *    grows to the largest workspace in use at once) until the process ends.
  */
 #ifndef QIHT_H_
 #define QIHT_H_

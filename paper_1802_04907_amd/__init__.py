@@ -197,12 +197,21 @@ def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
     torch = _torch()
     cnt = len(problems)
     arr = (_lib.QihtProblem * cnt)()
+    # one allocation each for all x and all supports; the outputs are views
+    dev = problems[0][1].device
+    nx = [q.n for q, _, _ in problems]
+    ns = [int(s) for _, _, s in problems]
+    xall = torch.empty(sum(nx), dtype=torch.float32, device=dev)
+    sall = torch.empty(max(1, sum(ns)), dtype=torch.int32, device=dev)
     outs = []
+    ox = osp = 0
     for i, (q, yhat, s) in enumerate(problems):
-        x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
-        sup = torch.empty(int(s), dtype=torch.int32, device=yhat.device)
+        x = xall[ox:ox + nx[i]]
+        sup = sall[osp:osp + ns[i]]
+        ox += nx[i]
+        osp += ns[i]
         outs.append((x, sup))
-        arr[i] = _lib.QihtProblem(q.handle.value, yhat.data_ptr(), int(s),
+        arr[i] = _lib.QihtProblem(q.handle.value, yhat.data_ptr(), ns[i],
                                   x.data_ptr(), sup.data_ptr())
     p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, profile=profile, refit=refit)
     infos = (_lib.QihtInfo * cnt)()

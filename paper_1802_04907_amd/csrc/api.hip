@@ -4,6 +4,7 @@
 // status codes plus a thread-local message; no exception crosses the ABI.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -130,6 +131,38 @@ qiht_status check_support(const int32_t* dev_sup, int64_t s, int64_t n, hipStrea
 }  // namespace
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
+
+hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::vector<hipMemPool_t> pools;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (pools.size() <= static_cast<size_t>(dev)) pools.resize(dev + 1, nullptr);
+        if (!pools[dev]) {
+            hipMemPoolProps props{};
+            props.allocType = hipMemAllocationTypePinned;
+            props.handleTypes = hipMemHandleTypeNone;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            hipMemPool_t np = nullptr;
+            e = hipMemPoolCreate(&np, &props);
+            if (e != hipSuccess) return e;
+            uint64_t keep = UINT64_MAX;
+            e = hipMemPoolSetAttribute(np, hipMemPoolAttrReleaseThreshold, &keep);
+            if (e != hipSuccess) {
+                (void)hipMemPoolDestroy(np);
+                return e;
+            }
+            pools[dev] = np;
+        }
+        pool = pools[dev];
+    }
+    return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
 }  // namespace qiht
 
 using namespace qiht;
@@ -280,7 +313,7 @@ qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype, int
         std::vector<double> h(L);
         for (int k = 0; k < L; ++k) h[k] = c * (2.0 * k / static_cast<double>(L - 1) - 1.0);
         K = c > 0.0 ? (L - 1) / (2.0 * c) : 0.0;
-        QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&lev), sizeof(double) * L, st));
+        QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&lev), sizeof(double) * L, st));
         QIHT_HIP(hipMemcpyAsync(lev, h.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
     }
     s0 = launch_quantize_vector(y, dtype, m, bits, seed, c, K, lev, yhat_out, codes_out, st);

@@ -138,4 +138,12 @@ struct RefitIn {
 };
 qiht_status run_refit(const RefitIn& in, hipStream_t st);
 
+// Stream-ordered device allocation from the library's own memory pool (one per
+// device, created on first use).  The pool keeps freed memory for the next
+// call instead of handing it back to the driver at every synchronization
+// (re-mapping a workspace of hundreds of MB cost milliseconds per solve); it
+// grows to the largest workspace in use at once and is held until the
+// process ends.  Free with hipFreeAsync.
+hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st);
+
 }  // namespace qiht

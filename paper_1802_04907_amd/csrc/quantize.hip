@@ -265,7 +265,7 @@ template <typename T, int NC>
 qiht_status store_t(int fmt, const void* src, int64_t m, int64_t n, int64_t ld, qiht_qmatrix* q,
                     hipStream_t st) {
     int* d_bad = nullptr;
-    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_bad), sizeof(int), st));
+    QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&d_bad), sizeof(int), st));
     QIHT_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), st));
     hipLaunchKernelGGL((k_rowexp<T, NC>), dim3(static_cast<unsigned>(q->rows)), dim3(256), 0, st,
                        static_cast<const T*>(src), m, n, ld, fmt == 16 ? 1.0 : 448.0, q->rexp, d_bad);
@@ -292,7 +292,7 @@ qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
                      hipStream_t st, double* c_out) {
     unsigned long long* d_max = nullptr;
     int* d_bad = nullptr;
-    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&d_max), 16, st));
+    QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&d_max), 16, st));
     d_bad = reinterpret_cast<int*>(d_max + 1);
     QIHT_HIP(hipMemsetAsync(d_max, 0, 16, st));
     const int64_t row_len = n * NC;

@@ -38,6 +38,12 @@ __global__ void k_warm_start(const ProbDev* __restrict__ P, const float* const* 
     }
 }
 
+// Stop flags of every problem, gathered for one read-back.
+__global__ void k_done_flags(const ProbDev* __restrict__ P, int count, int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = P[i].st->done;
+}
+
 __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
                            int32_t* const* souts, InfoDev* infos) {
     const ProbDev& pd = P[blockIdx.y];
@@ -92,7 +98,7 @@ struct Plan {
     int bits = 0, cpl = 1, maxwg = 1;
     bool any_slab = false;
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
-    size_t x0ptr_off = 0;
+    size_t x0ptr_off = 0, done_off = 0;
     // shared-matrix path: one GEMM per iteration instead of per-problem passes
     bool shared = false;
     SharedGemm sg{};
@@ -216,6 +222,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     pl.sptr_off = cv.take<int32_t*>(count);
     pl.x0ptr_off = cv.take<const float*>(count);
     pl.info_off = cv.take<InfoDev>(count);
+    pl.done_off = cv.take<int32_t>(count);
     pl.bytes = cv.off;
     return QIHT_OK;
 }
@@ -370,7 +377,7 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
     qiht_status s0 = make_plan(in, count, pl);
     if (s0 != QIHT_OK) return s0;
     ws.st = st;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&ws.base), pl.bytes, st);
+    hipError_t e = pool_malloc(reinterpret_cast<void**>(&ws.base), pl.bytes, st);
     if (e != hipSuccess || ws.base == nullptr) {
         ws.base = nullptr;
         (void)hipGetLastError();
@@ -432,20 +439,21 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
     }
     QIHT_HIP(hipGetLastError());
 
-    std::vector<SolveState> hs(count);
+    std::vector<int32_t> hdone(count);
+    int32_t* ddone = reinterpret_cast<int32_t*>(ws.base + pl.done_off);
     for (int it = 1; it <= a.max_iters;) {
         const int end = std::min(a.max_iters, it + kChunk - 1);
         for (; it <= end; ++it) iteration_launches(pl, dP, dT, count, a, st, &timer);
-        QIHT_HIP(hipGetLastError());
         if (it > a.max_iters) break;
-        for (int i = 0; i < count; ++i)
-            QIHT_HIP(hipMemcpyAsync(&hs[i], pl.host[i].st, sizeof(SolveState),
-                                    hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
+        QIHT_HIP(hipGetLastError());
+        QIHT_HIP(hipMemcpyAsync(hdone.data(), ddone, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
         QIHT_HIP(hipStreamSynchronize(st));
         bool all_done = true;
-        for (int i = 0; i < count; ++i) all_done = all_done && hs[i].done;
+        for (int i = 0; i < count; ++i) all_done = all_done && hdone[i] != 0;
         if (all_done) break;
     }
+    QIHT_HIP(hipGetLastError());
 
     InfoDev* dinf = reinterpret_cast<InfoDev*>(ws.base + pl.info_off);
     hipLaunchKernelGGL(k_finalize, dim3(32, count), dim3(256), 0, st, dP, dxo, dso, dinf);
@@ -502,7 +510,7 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float*
 qiht_status run_refit(const RefitIn& in, hipStream_t st) {
     const size_t bytes = refit_workspace_bytes(in.rows, in.s);
     uint8_t* ws = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void**>(&ws), bytes, st) != hipSuccess || !ws)
+    if (pool_malloc(reinterpret_cast<void**>(&ws), bytes, st) != hipSuccess || !ws)
         return fail(QIHT_ERR_OUT_OF_MEMORY, "refit workspace");
     launch_refit(in, ws, st);
     hipError_t e = hipGetLastError();
@@ -520,7 +528,7 @@ qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* su
                                hipStream_t st) {
     if (n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
     int* err = nullptr;
-    QIHT_HIP(hipMallocAsync(reinterpret_cast<void**>(&err), sizeof(int), st));
+    QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&err), sizeof(int), st));
     QIHT_HIP(hipMemsetAsync(err, 0, sizeof(int), st));
     launch_hard_threshold(a, static_cast<int>(n), static_cast<int>(s), support_out,
                           err, st);
