@@ -24,53 +24,57 @@
 namespace qiht {
 namespace {
 
-constexpr int kBM = 128;  // columns of Phi per workgroup
+constexpr int kBM = 128;  // FP32 kernel: columns of Phi per workgroup
 constexpr int kBN = 256;  // right-hand sides per workgroup (at most)
 constexpr int kBK = 32;   // rows per step
 constexpr int kPadH = 8;  // LDS row padding in 16-bit elements
+constexpr int kBM2 = 256; // BF16 kernel: columns of Phi per workgroup
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ bf16x8_t as_bf16x8(uint4 v) {
     return __builtin_bit_cast(bf16x8_t, v);
 }
 
-// Exact E4M3 -> BF16 (bit patterns): normals rebias the exponent (+120),
-// subnormals k 2^-9 are normal in BF16.
-__device__ __forceinline__ uint32_t e4m3_to_bf16(uint32_t b) {
-    const uint32_t s = (b & 0x80u) << 8, e = (b >> 3) & 15u, m = b & 7u;
-    if (e != 0u) return s | ((e + 120u) << 7) | (m << 4);
-    if (m == 0u) return s;
-    const uint32_t f = __float_as_uint(static_cast<float>(m) * 0x1p-9f);
-    return s | (f >> 16);
+// Four E4M3 bytes -> four BF16 (two words), exactly: the hardware converts
+// to FP32 (every E4M3 value is exact there and in BF16), the upper halves are
+// the BF16 patterns.
+__device__ __forceinline__ uint2 e4m3x4_to_bf16(uint32_t w) {
+    const f32x2_t lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), false);
+    const f32x2_t hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), true);
+    return make_uint2((__float_as_uint(lo.x) >> 16) | (__float_as_uint(lo.y) & 0xFFFF0000u),
+                      (__float_as_uint(hi.x) >> 16) | (__float_as_uint(hi.y) & 0xFFFF0000u));
 }
 
 struct GemmArgs {
     const uint8_t* a;    // stored columns, col_bytes apart
     int64_t col_bytes;
     int n;               // columns (M)
-    int rows;            // K
+    int rows;            // K (a multiple of 32 ksplit)
     int nrhs;            // N
     const void* b;       // R': BF16 hi/lo (ldb 16-bit elements apart per RHS; lo at +lo_off)
     int64_t ldb;         //     or FP32 r (ldb floats apart)
     int64_t lo_off;
     float* g;            // G, g_k at g + k * ldg
     int64_t ldg;
+    int ksplit;          // row splits (blockIdx.z); > 1: partial G at gp + split * count * ldg
+    float* gp;
 };
 
 // C tile (mt, nt) of a wave: lane holds rows 4 (lane / 16) + t (columns of
 // Phi) of right-hand side 16 nt + lane % 16; four consecutive g_j per store.
-__device__ __forceinline__ void store_tiles(const GemmArgs& p, const f32x4_t (&acc)[4][8], int jw,
-                                            int kw, int lane) {
+template <int MT, int NT>
+__device__ __forceinline__ void store_tiles(const GemmArgs& p, float* out, const f32x4_t (&acc)[MT][NT],
+                                            int jw, int kw, int lane) {
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
+    for (int nt = 0; nt < NT; ++nt) {
         const int k = kw + 16 * nt + (lane & 15);
         if (k >= p.nrhs) continue;
-        float* gk = p.g + static_cast<int64_t>(k) * p.ldg;
+        float* gk = out + static_cast<int64_t>(k) * p.ldg;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
+        for (int mt = 0; mt < MT; ++mt) {
             const int j = jw + 16 * mt + 4 * (lane >> 4);
             if (j + 3 < p.n) {
                 *reinterpret_cast<float4*>(gk + j) =
@@ -84,32 +88,39 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& p, const f32x4_t (&a
     }
 }
 
+// BF16 and E4M3 storage.  A workgroup of 4 waves computes 256 columns of Phi
+// x 256 right-hand sides over its row split, each wave a 128 x 128 block (8 x 8
+// tiles of 16 x 16, two MFMAs per tile and step: hi and lo), so every LDS
+// fragment read feeds 8 or 16 MFMAs.  Per step of 32 rows the workgroup
+// stages 256 columns (thread t: column t) and the 256 right-hand sides
+// (thread t: right-hand side t, both terms) with the next step's global loads
+// in flight.
 template <int FMT>  // 16: BF16 storage, 9: E4M3 storage
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs p) {
-    __shared__ uint16_t la[kBM][kBK + kPadH];
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
+    __shared__ uint16_t la[kBM2][kBK + kPadH];
     __shared__ uint16_t lb[2][kBN][kBK + kPadH];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int j0 = blockIdx.x * kBM;
-    const int wm = (wv & 1) * 64, wn = (wv >> 1) * 128;
+    const int j0 = blockIdx.x * kBM2;
+    const int n0 = blockIdx.y * kBN;
+    const int kper = p.rows / p.ksplit;
+    const int kbeg = blockIdx.z * kper;
+    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 128;
 
-    // global -> register assignment: A: column tid / 2, rows 16 (tid % 2) .. + 16
-    const int acol = min(j0 + tid / 2, p.n - 1);
+    const int acol = min(j0 + tid, p.n - 1);
     const uint8_t* ap = p.a + static_cast<int64_t>(acol) * p.col_bytes;
-    const int ahalf = tid & 1;
-    // B: right-hand side tid (clamped), both terms, 32 rows
-    const int n0 = blockIdx.y * kBN;  // first right-hand side of this workgroup
     const int brhs = min(n0 + tid, p.nrhs - 1);
     const uint16_t* bh = static_cast<const uint16_t*>(p.b) + static_cast<int64_t>(brhs) * p.ldb;
     const uint16_t* bl = bh + p.lo_off;
 
-    uint4 ra[2], rbh[4], rbl[4];
+    uint4 ra[4], rbh[4], rbl[4];
     auto load = [&](int k0) {
         if constexpr (FMT == 16) {
-            const uint16_t* src = reinterpret_cast<const uint16_t*>(ap) + k0 + 16 * ahalf;
-            ra[0] = ldg_u4(src);
-            ra[1] = ldg_u4(src + 8);
+            const uint16_t* src = reinterpret_cast<const uint16_t*>(ap) + k0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ra[q] = ldg_u4(src + 8 * q);
         } else {
-            ra[0] = ldg_u4(ap + k0 + 16 * ahalf);
+            ra[0] = ldg_u4(ap + k0);
+            ra[1] = ldg_u4(ap + k0 + 16);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -118,20 +129,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs p) {
         }
     };
     auto stash = [&]() {
-        uint16_t* dst = &la[tid / 2][16 * ahalf];
+        uint4* dst = reinterpret_cast<uint4*>(&la[tid][0]);
         if constexpr (FMT == 16) {
-            *reinterpret_cast<uint4*>(dst) = ra[0];
-            *reinterpret_cast<uint4*>(dst + 8) = ra[1];
-        } else {
-            const uint32_t w[4] = {ra[0].x, ra[0].y, ra[0].z, ra[0].w};
-            uint32_t o[8];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                o[2 * q] = e4m3_to_bf16(w[q] & 0xFFu) | (e4m3_to_bf16((w[q] >> 8) & 0xFFu) << 16);
-                o[2 * q + 1] = e4m3_to_bf16((w[q] >> 16) & 0xFFu) | (e4m3_to_bf16(w[q] >> 24) << 16);
+            for (int q = 0; q < 4; ++q) dst[q] = ra[q];
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint2 a0 = e4m3x4_to_bf16(ra[h].x), a1 = e4m3x4_to_bf16(ra[h].y);
+                const uint2 a2 = e4m3x4_to_bf16(ra[h].z), a3 = e4m3x4_to_bf16(ra[h].w);
+                dst[2 * h] = make_uint4(a0.x, a0.y, a1.x, a1.y);
+                dst[2 * h + 1] = make_uint4(a2.x, a2.y, a3.x, a3.y);
             }
-            *reinterpret_cast<uint4*>(dst) = make_uint4(o[0], o[1], o[2], o[3]);
-            *reinterpret_cast<uint4*>(dst + 8) = make_uint4(o[4], o[5], o[6], o[7]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -140,23 +149,23 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs p) {
         }
     };
 
-    f32x4_t acc[4][8];
+    f32x4_t acc[8][8];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
+    for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    const int ksteps = p.rows / kBK;  // rows is a multiple of 32 (columns are padded)
-    load(0);
+    const int ksteps = kper / kBK;
+    load(kbeg);
     for (int ks = 0; ks < ksteps; ++ks) {
         __syncthreads();
         stash();
         __syncthreads();
-        if (ks + 1 < ksteps) load((ks + 1) * kBK);
+        if (ks + 1 < ksteps) load(kbeg + (ks + 1) * kBK);
         const int kq = (lane >> 4) * 8;  // this lane's 8 rows of the step
-        bf16x8_t af[4];
+        bf16x8_t af[8];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int mt = 0; mt < 8; ++mt)
             af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[wm + 16 * mt + (lane & 15)][kq]));
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
@@ -164,13 +173,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs p) {
             const bf16x8_t bh8 = as_bf16x8(*reinterpret_cast<const uint4*>(&lb[0][col][kq]));
             const bf16x8_t bl8 = as_bf16x8(*reinterpret_cast<const uint4*>(&lb[1][col][kq]));
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
+            for (int mt = 0; mt < 8; ++mt) {
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
             }
         }
     }
-    store_tiles(p, acc, j0 + wm, n0 + wn, lane);
+    float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
+    store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
 }
 
 // FP32 storage: FP32 MFMA (16 x 16 x 4), r in FP32.
@@ -226,13 +236,17 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
             }
         }
     }
-    store_tiles(p, acc, j0 + wm, n0 + wn, lane);
+    store_tiles<4, 8>(p, p.g, acc, j0 + wm, n0 + wn, lane);
 }
 
-// Histogram of the top 11 bits of |g_j| off the support, per problem (what
-// the per-problem pass builds in its epilogue): blockIdx.y = problem.
-__global__ __launch_bounds__(256) void k_hist_g(const ProbDev* __restrict__ P) {
-    const ProbDev& pd = P[blockIdx.y];
+// Per problem (blockIdx.y): with row splits, g = the sum of the split
+// partials in split order; then the histogram of the top 11 bits of |g_j| off
+// the support (what the per-problem pass builds in its epilogue).
+__global__ __launch_bounds__(256) void k_hist_g(const ProbDev* __restrict__ P, int ksplit,
+                                                const float* __restrict__ gp, int64_t part_stride,
+                                                int64_t ldg) {
+    const int prob = blockIdx.y;
+    const ProbDev& pd = P[prob];
     if (pd.st->done) return;
     __shared__ uint32_t lh[2048];
     for (int b = threadIdx.x; b < 2048; b += 256) lh[b] = 0u;
@@ -240,8 +254,17 @@ __global__ __launch_bounds__(256) void k_hist_g(const ProbDev* __restrict__ P) {
     const int per = (pd.n + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * per, hi = min(pd.n, lo + per);
     for (int j = lo + threadIdx.x; j < hi; j += 256) {
+        float gj;
+        if (ksplit > 1) {
+            const float* src = gp + static_cast<int64_t>(prob) * ldg + j;
+            gj = src[0];
+            for (int k = 1; k < ksplit; ++k) gj += src[k * part_stride];
+            pd.g[j] = gj;
+        } else {
+            gj = pd.g[j];
+        }
         if ((pd.bmsup[j >> 5] >> (j & 31)) & 1u) continue;
-        atomicAdd(&lh[(__float_as_uint(pd.g[j]) & 0x7FFFFFFFu) >> 20], 1u);
+        atomicAdd(&lh[(__float_as_uint(gj) & 0x7FFFFFFFu) >> 20], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < 2048; b += 256)
@@ -265,7 +288,16 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
     a.lo_off = sg.lo_off;
     a.g = sg.g;
     a.ldg = sg.ldg;
-    const dim3 grid((sg.n + kBM - 1) / kBM, (count + kBN - 1) / kBN);
+    a.ksplit = 1;
+    a.gp = sg.gp;
+    const bool bf = sg.bits == kFmtBF16 || sg.bits == kFmtE4M3;
+    dim3 grid;
+    if (bf) {
+        a.ksplit = sg.ksplit;
+        grid = dim3((sg.n + kBM2 - 1) / kBM2, (count + kBN - 1) / kBN, a.ksplit);
+    } else {
+        grid = dim3((sg.n + kBM - 1) / kBM, (count + kBN - 1) / kBN);
+    }
     auto go = [&](auto kern) {
         if (ev0) hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, st, ev0, ev1, 0, a);
         else hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
@@ -273,7 +305,19 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
     if (sg.bits == kFmtBF16) go(k_gemm_bf16<16>);
     else if (sg.bits == kFmtE4M3) go(k_gemm_bf16<9>);
     else go(k_gemm_f32);
-    hipLaunchKernelGGL(k_hist_g, dim3(std::max(1, std::min(64, (sg.n + 2047) / 2048)), count), dim3(256), 0, st, P);
+    hipLaunchKernelGGL(k_hist_g, dim3(std::max(1, std::min(64, (sg.n + 2047) / 2048)), count), dim3(256), 0, st,
+                       P, a.ksplit, static_cast<const float*>(sg.gp), static_cast<int64_t>(count) * sg.ldg, sg.ldg);
+}
+
+// Row splits of the BF16 GEMM: enough workgroups for the device (about one
+// per CU) while each split keeps at least 8 steps of 32 rows.
+int shared_ksplit(int bits, int n, int count, int rows_pad) {
+    if (bits != kFmtBF16 && bits != kFmtE4M3) return 1;
+    const int tiles = ((n + kBM2 - 1) / kBM2) * ((count + kBN - 1) / kBN);
+    int ks = 1;
+    while (ks < 4 && tiles * ks < 256 && rows_pad % (2 * ks * kBK) == 0 && rows_pad / (2 * ks) >= 8 * kBK)
+        ks *= 2;
+    return ks;
 }
 
 }  // namespace qiht

@@ -500,7 +500,10 @@ struct SharedGemm {
     int64_t lo_off;
     float* g;           // g of problem 0; problem k at + k * ldg
     int64_t ldg;
+    int ksplit;         // row splits of the GEMM (BF16 kernel), partial G in gp
+    float* gp;          //   ksplit x count x ldg floats (unused when ksplit = 1)
 };
+int shared_ksplit(int bits, int n, int count, int rows_pad);
 void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipStream_t st,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 

@@ -102,7 +102,7 @@ struct Plan {
     // shared-matrix path: one GEMM per iteration instead of per-problem passes
     bool shared = false;
     SharedGemm sg{};
-    size_t gblk_off = 0, bblk_off = 0;
+    size_t gblk_off = 0, bblk_off = 0, gpart_off = 0;
 };
 
 qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
@@ -187,6 +187,10 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         pl.sg.bits = pl.bits;
         pl.sg.ldg = round_up(q->n, 64);
         pl.gblk_off = cv.take<float>(static_cast<size_t>(count) * pl.sg.ldg);
+        pl.sg.ksplit = shared_ksplit(pl.bits, pl.sg.n, count, pl.sg.rows_pad);
+        pl.gpart_off = pl.sg.ksplit > 1
+                           ? cv.take<float>(static_cast<size_t>(pl.sg.ksplit) * count * pl.sg.ldg)
+                           : 0;
         if (pl.bits == 32) {
             pl.sg.ldb = q->rows_pad;
             pl.sg.lo_off = 0;
@@ -231,6 +235,7 @@ void bind(Plan& pl, uint8_t* base) {
     if (pl.shared) {
         pl.sg.g = reinterpret_cast<float*>(base + pl.gblk_off);
         pl.sg.b = base + pl.bblk_off;
+        pl.sg.gp = pl.sg.ksplit > 1 ? reinterpret_cast<float*>(base + pl.gpart_off) : nullptr;
     }
     for (size_t i = 0; i < pl.host.size(); ++i) {
         ProbDev& p = pl.host[i];
