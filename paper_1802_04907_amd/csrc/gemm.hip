@@ -91,14 +91,19 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& p, float* out, const
 // BF16 and E4M3 storage.  A workgroup of 4 waves computes 256 columns of Phi
 // x 256 right-hand sides over its row split, each wave a 128 x 128 block (8 x 8
 // tiles of 16 x 16, two MFMAs per tile and step: hi and lo), so every LDS
-// fragment read feeds 8 or 16 MFMAs.  Per step of 32 rows the workgroup
-// stages 256 columns (thread t: column t) and the 256 right-hand sides
-// (thread t: right-hand side t, both terms) with the next step's global loads
-// in flight.
+// fragment read feeds 8 or 16 MFMAs.  Steps of 32 rows.  The next step's global loads
+// are in flight during the MFMAs; LDS is double-buffered, so one barrier per
+// step both publishes a buffer and retires the other.
+template <int FMT>
+struct Stage {
+    uint4 a[FMT == 16 ? 4 : 2];  // A: 16 bytes of each of this thread's columns
+    uint4 bh[4], bl[4];          // R': 16 bytes of each of its 4 right-hand sides, both terms
+};
+
 template <int FMT>  // 16: BF16 storage, 9: E4M3 storage
 __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
-    __shared__ uint16_t la[kBM2][kBK + kPadH];
-    __shared__ uint16_t lb[2][kBN][kBK + kPadH];
+    __shared__ uint16_t la[2][kBM2][kBK + kPadH];
+    __shared__ uint16_t lb[2][2][kBN][kBK + kPadH];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int j0 = blockIdx.x * kBM2;
     const int n0 = blockIdx.y * kBN;
@@ -106,46 +111,57 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
     const int kbeg = blockIdx.z * kper;
     const int wm = (wv & 1) * 128, wn = (wv >> 1) * 128;
 
-    const int acol = min(j0 + tid, p.n - 1);
-    const uint8_t* ap = p.a + static_cast<int64_t>(acol) * p.col_bytes;
-    const int brhs = min(n0 + tid, p.nrhs - 1);
-    const uint16_t* bh = static_cast<const uint16_t*>(p.b) + static_cast<int64_t>(brhs) * p.ldb;
-    const uint16_t* bl = bh + p.lo_off;
+    // Global -> LDS mapping: consecutive lanes share a column (so a wave's
+    // load touches a few long contiguous pieces, not 64 scattered ones).
+    // BF16 A and both R' terms: 4 lanes x 16 bytes = the 32 rows of one
+    // column, lanes tid / 4 + 64 i, i < 4.  E4M3 A: 2 lanes x 16 bytes, columns
+    // tid / 2 + 128 i, i < 2.
+    constexpr int AL = FMT == 16 ? 4 : 2;       // lanes per column of A
+    constexpr int AI = 256 * AL / 256;          // columns of A per thread (= AL)
+    const int akc = tid % AL;                   // 16-byte piece of the column
+    const uint8_t* ap[AI];
+#pragma unroll
+    for (int i = 0; i < AI; ++i) {
+        const int col = min(j0 + tid / AL + (256 / AL) * i, p.n - 1);
+        ap[i] = p.a + static_cast<int64_t>(col) * p.col_bytes + 16 * akc;
+    }
+    const int bkc = tid % 4;
+    const uint16_t* bp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rhs = min(n0 + tid / 4 + 64 * i, p.nrhs - 1);
+        bp[i] = static_cast<const uint16_t*>(p.b) + static_cast<int64_t>(rhs) * p.ldb + 8 * bkc;
+    }
 
-    uint4 ra[4], rbh[4], rbl[4];
-    auto load = [&](int k0) {
-        if constexpr (FMT == 16) {
-            const uint16_t* src = reinterpret_cast<const uint16_t*>(ap) + k0;
+    // k0 in rows; a 16-bit element is 2 bytes, an E4M3 one 1
+    auto load = [&](Stage<FMT>& r, int k0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ra[q] = ldg_u4(src + 8 * q);
-        } else {
-            ra[0] = ldg_u4(ap + k0);
-            ra[1] = ldg_u4(ap + k0 + 16);
-        }
+        for (int i = 0; i < AI; ++i) r.a[i] = ldg_u4(ap[i] + (FMT == 16 ? 2 : 1) * k0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            rbh[q] = ldg_u4(bh + k0 + 8 * q);
-            rbl[q] = ldg_u4(bl + k0 + 8 * q);
+        for (int i = 0; i < 4; ++i) {
+            r.bh[i] = ldg_u4(bp[i] + k0);
+            r.bl[i] = ldg_u4(bp[i] + p.lo_off + k0);
         }
     };
-    auto stash = [&]() {
-        uint4* dst = reinterpret_cast<uint4*>(&la[tid][0]);
+    auto stash = [&](const Stage<FMT>& r, int buf) {
         if constexpr (FMT == 16) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) dst[q] = ra[q];
+            for (int i = 0; i < 4; ++i)
+                *reinterpret_cast<uint4*>(&la[buf][tid / 4 + 64 * i][8 * akc]) = r.a[i];
         } else {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint2 a0 = e4m3x4_to_bf16(ra[h].x), a1 = e4m3x4_to_bf16(ra[h].y);
-                const uint2 a2 = e4m3x4_to_bf16(ra[h].z), a3 = e4m3x4_to_bf16(ra[h].w);
-                dst[2 * h] = make_uint4(a0.x, a0.y, a1.x, a1.y);
-                dst[2 * h + 1] = make_uint4(a2.x, a2.y, a3.x, a3.y);
+            for (int i = 0; i < 2; ++i) {
+                const uint2 a0 = e4m3x4_to_bf16(r.a[i].x), a1 = e4m3x4_to_bf16(r.a[i].y);
+                const uint2 a2 = e4m3x4_to_bf16(r.a[i].z), a3 = e4m3x4_to_bf16(r.a[i].w);
+                uint4* dst = reinterpret_cast<uint4*>(&la[buf][tid / 2 + 128 * i][16 * akc]);
+                dst[0] = make_uint4(a0.x, a0.y, a1.x, a1.y);
+                dst[1] = make_uint4(a2.x, a2.y, a3.x, a3.y);
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            *reinterpret_cast<uint4*>(&lb[0][tid][8 * q]) = rbh[q];
-            *reinterpret_cast<uint4*>(&lb[1][tid][8 * q]) = rbl[q];
+        for (int i = 0; i < 4; ++i) {
+            *reinterpret_cast<uint4*>(&lb[buf][0][tid / 4 + 64 * i][8 * bkc]) = r.bh[i];
+            *reinterpret_cast<uint4*>(&lb[buf][1][tid / 4 + 64 * i][8 * bkc]) = r.bl[i];
         }
     };
 
@@ -155,29 +171,55 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    const int ksteps = kper / kBK;
-    load(kbeg);
-    for (int ks = 0; ks < ksteps; ++ks) {
-        __syncthreads();
-        stash();
-        __syncthreads();
-        if (ks + 1 < ksteps) load(kbeg + (ks + 1) * kBK);
+    auto compute = [&](int buf) {
         const int kq = (lane >> 4) * 8;  // this lane's 8 rows of the step
         bf16x8_t af[8];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
-            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[wm + 16 * mt + (lane & 15)][kq]));
+            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[buf][wm + 16 * mt + (lane & 15)][kq]));
+        // B fragments one tile column ahead of the MFMAs that use them
+        auto bfrag = [&](int term, int nt) {
+            return as_bf16x8(*reinterpret_cast<const uint4*>(&lb[buf][term][wn + 16 * nt + (lane & 15)][kq]));
+        };
+        bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) {
-            const int col = wn + 16 * nt + (lane & 15);
-            const bf16x8_t bh8 = as_bf16x8(*reinterpret_cast<const uint4*>(&lb[0][col][kq]));
-            const bf16x8_t bl8 = as_bf16x8(*reinterpret_cast<const uint4*>(&lb[1][col][kq]));
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
+            const bf16x8_t bh8 = bhn, bl8 = bln;
+            if (nt + 1 < 8) {
+                bhn = bfrag(0, nt + 1);
+                bln = bfrag(1, nt + 1);
             }
+            // hi terms of the 8 tiles, then the lo terms: consecutive MFMAs
+            // never wait on each other's accumulator
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
         }
+        // instruction order of the step: the A fragments and the first B pair,
+        // then per tile column the next B pair ahead of its 16 MFMAs (so an
+        // LDS read's latency hides behind MFMAs already issued)
+        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            if (nt + 1 < 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+        }
+    };
+
+    // step t's data: registers (loaded one step ahead), then LDS buffer t % 2
+    const int ksteps = kper / kBK;  // >= 8, see shared_ksplit
+    Stage<FMT> r;
+    load(r, kbeg);
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int buf = ks & 1;
+        stash(r, buf);
+        if (ks + 1 < ksteps) load(r, kbeg + (ks + 1) * kBK);
+        // the stash is visible, and buffer buf ^ 1 (step ks - 1) is no longer read
+        __syncthreads();
+        compute(buf);
     }
     float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
     store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
