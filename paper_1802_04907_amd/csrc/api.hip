@@ -456,12 +456,12 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
     s0 = run_solve(in.data(), count, to_args(p), tmp.data(), static_cast<hipStream_t>(stream));
     if (s0 != QIHT_OK) return s0;
     if (p->refit) {
-        for (int i = 0; i < count; ++i) {
-            s0 = run_refit(codes_refit(probs[i].q, probs[i].yhat, probs[i].support_out, probs[i].s,
-                                       probs[i].x_out),
-                           static_cast<hipStream_t>(stream));
-            if (s0 != QIHT_OK) return fail(s0, "problem " + std::to_string(i) + ": " + last_error_cstr());
-        }
+        std::vector<RefitIn> rin(count);
+        for (int i = 0; i < count; ++i)
+            rin[i] = codes_refit(probs[i].q, probs[i].yhat, probs[i].support_out, probs[i].s,
+                                 probs[i].x_out);
+        s0 = run_refit_batch(rin.data(), count, static_cast<hipStream_t>(stream));
+        if (s0 != QIHT_OK) return s0;
     }
     if (infos) std::memcpy(infos, tmp.data(), sizeof(qiht_info) * count);
     return QIHT_OK;

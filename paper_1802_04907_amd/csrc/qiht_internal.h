@@ -137,6 +137,9 @@ struct RefitIn {
     double* xs_out;
 };
 qiht_status run_refit(const RefitIn& in, hipStream_t st);
+// The refits of `count` problems (same source kind: packed codes of one bit
+// width or format, or one dense dtype) as one sequence of launches.
+qiht_status run_refit_batch(const RefitIn* in, int count, hipStream_t st);
 
 // Stream-ordered device allocation from the library's own memory pool (one per
 // device, created on first use).  The pool keeps freed memory for the next

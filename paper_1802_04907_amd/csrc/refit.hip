@@ -4,152 +4,191 @@
 // step-size and quantization bias of x on the recovered support.  A is the
 // caller's dense Phi, or the dequantized first realization of the codes.
 //
-// Layout: A_G is rows x s, column-major (column t = column sup[t] of A, lda =
-// rows); G = A_G^T A_G is s x s, row-major, lower triangle used (the
-// Cholesky factor L overwrites it); b = A_G^T y.
+// Batched: every kernel serves a group of problems (blockIdx.z = problem, its
+// parameters and workspace in a RefitDev), so the refits of a batched solve
+// are one sequence of launches.
+//
+// Layout per problem: A_G is lda x s, column-major (column t = column sup[t]
+// of A, lda = rows rounded up to 16, padding rows 0); G = A_G^T A_G is s x s,
+// row-major, lower triangle used (the Cholesky factor L overwrites it);
+// b = A_G^T y.
 #include <algorithm>
+#include <vector>
 
 #include "solve_common.h"
 
 namespace qiht {
 namespace {
 
-constexpr int kNB = 32;       // Cholesky block
-constexpr int kTile = 64;     // Gram / update tile (16 x 16 threads, 4 x 4 each)
-constexpr int kKc = 16;       // rows per LDS step of the Gram product
+constexpr int kNB = 32;    // Cholesky block
+constexpr int kTile = 64;  // trailing-update tile (16 x 16 threads, 4 x 4 each)
+constexpr int kGT = 64;    // Gram tile of one wave (4 x 4 MFMA tiles of 16 x 16)
+constexpr int kGK = 16;    // rows per Gram chunk (4 MFMA steps of 4 rows)
+
+struct RefitDev {
+    const uint8_t* codes;  // stored matrix (codes path)
+    int64_t col_bytes;
+    double alpha, beta;
+    const int32_t* rowexp;
+    const void* phi;       // dense Phi (phi path)
+    int64_t m, ld;
+    int64_t rows, lda, n;
+    int s;
+    int64_t split;         // Gram rows per split (a multiple of kGK)
+    const double* y;
+    const int32_t* sup;
+    float* x_out;
+    double* xs_out;
+    double *A, *Gp, *G, *b, *diag;
+    int* flag;
+};
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
 
 // Column t of A_G from the stored matrix: alpha code + beta (packed codes),
 // the float (32), or 2^e_i times the stored value (dense formats).
 template <int BITS>
-__global__ __launch_bounds__(256) void k_refit_codes(const uint8_t* __restrict__ codes,
-                                                     int64_t col_bytes, int64_t rows,
-                                                     double alpha, double beta,
-                                                     const int32_t* __restrict__ rowexp,
-                                                     const int32_t* __restrict__ sup,
-                                                     double* __restrict__ A) {
+__global__ __launch_bounds__(256) void k_refit_codes(const RefitDev* __restrict__ R) {
     constexpr int RPW = rows_per_word<BITS>();
+    const RefitDev& r = R[blockIdx.z];
     const int t = blockIdx.y;
-    const uint8_t* col = codes + static_cast<int64_t>(sup[t]) * col_bytes;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < rows;
+    if (t >= r.s) return;
+    const uint8_t* col = r.codes + static_cast<int64_t>(r.sup[t]) * r.col_bytes;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < r.lda;
          i += static_cast<int64_t>(gridDim.x) * 256) {
-        const uint32_t w = reinterpret_cast<const uint32_t*>(col)[i / RPW];
-        const double e = elem_at<BITS>(w, static_cast<int>(i % RPW));
-        double v;
-        if constexpr (BITS == 32) v = e;
-        else if constexpr (BITS == 9 || BITS == 16) v = ldexp(e, rowexp[i]);
-        else v = alpha * e + beta;
-        A[static_cast<int64_t>(t) * rows + i] = v;
+        double v = 0.0;
+        if (i < r.rows) {
+            const uint32_t w = reinterpret_cast<const uint32_t*>(col)[i / RPW];
+            const double e = elem_at<BITS>(w, static_cast<int>(i % RPW));
+            if constexpr (BITS == 32) v = e;
+            else if constexpr (BITS == 9 || BITS == 16) v = ldexp(e, r.rowexp[i]);
+            else v = r.alpha * e + r.beta;
+        }
+        r.A[static_cast<int64_t>(t) * r.lda + i] = v;
     }
 }
 
 // Column t of A_G from a dense row-major Phi (real, or complex interleaved:
 // the stacked real matrix [Re Phi; Im Phi] of 2m rows).
 template <typename T, bool CPLX>
-__global__ __launch_bounds__(256) void k_refit_phi(const T* __restrict__ phi, int64_t m,
-                                                   int64_t ld, const int32_t* __restrict__ sup,
-                                                   double* __restrict__ A) {
+__global__ __launch_bounds__(256) void k_refit_phi(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
     const int t = blockIdx.y;
-    const int64_t j = sup[t];
-    const int64_t rows = CPLX ? 2 * m : m;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < rows;
+    if (t >= r.s) return;
+    const T* phi = static_cast<const T*>(r.phi);
+    const int64_t j = r.sup[t];
+    const int64_t m = r.m;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < r.lda;
          i += static_cast<int64_t>(gridDim.x) * 256) {
-        double v;
-        if (CPLX) {
-            const int64_t r = i < m ? i : i - m;
-            v = static_cast<double>(phi[2 * (r * ld + j) + (i < m ? 0 : 1)]);
-        } else {
-            v = static_cast<double>(phi[i * ld + j]);
+        double v = 0.0;
+        if (i < r.rows) {
+            if (CPLX) {
+                const int64_t q = i < m ? i : i - m;
+                v = static_cast<double>(phi[2 * (q * r.ld + j) + (i < m ? 0 : 1)]);
+            } else {
+                v = static_cast<double>(phi[i * r.ld + j]);
+            }
         }
-        A[static_cast<int64_t>(t) * rows + i] = v;
+        r.A[static_cast<int64_t>(t) * r.lda + i] = v;
     }
 }
 
-// Tile (I, J), I >= J, of the partial G_ks = A[rows of split ks]^T A[...]:
-// 64 x 64, each thread 4 x 4 entries; blockIdx.y = ks of KS row splits.
-__global__ __launch_bounds__(256) void k_refit_gram(const double* __restrict__ A, int64_t rows,
-                                                    int s, int64_t split, double* __restrict__ Gp) {
+// Tile (I, J), I >= J, of the partial Gram product of row split blockIdx.y,
+// on the FP64 matrix cores: one wave, 64 x 64 entries as 4 x 4 tiles of
+// v_mfma_f64_16x16x4 (A operand: lane l holds row l % 16, step row l / 16;
+// B operand: step row l / 16, column l % 16; result element t of lane l:
+// row l / 16 + 4 t, column l % 16).  Per chunk of 16 rows lane l reads rows 4 (l / 16) .. + 3
+// of its columns (one 32-byte piece; the four lanes of a column read 128
+// contiguous bytes) and feeds them to the four MFMA steps in turn.  Columns
+// past s read column s - 1 and are not stored.
+__global__ __launch_bounds__(64) void k_refit_gram(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
+    const int s = r.s;
+    const int T = (s + kGT - 1) / kGT;
+    if (static_cast<int>(blockIdx.x) >= T * (T + 1) / 2) return;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * r.split;
+    if (r0 >= r.lda) return;
+    const int64_t r1 = min(r.lda, r0 + r.split);
     int I = 0, rem = blockIdx.x;
     while (rem > I) {
         rem -= I + 1;
         ++I;
     }
     const int J = rem;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.y) * split;
-    const int64_t r1 = min(rows, r0 + split);
-    double* G = Gp + static_cast<int64_t>(blockIdx.y) * s * s;
-    __shared__ double sa[kKc][kTile + 1];
-    __shared__ double sb[kKc][kTile + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4];
+    const int lane = threadIdx.x, c = lane & 15, kq = lane >> 4;
+    const double* pa[4];
+    const double* pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        pa[q] = r.A + static_cast<int64_t>(min(I * kGT + 16 * q + c, s - 1)) * r.lda + 4 * kq;
+        pb[q] = r.A + static_cast<int64_t>(min(J * kGT + 16 * q + c, s - 1)) * r.lda + 4 * kq;
+    }
+    f64x4_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int64_t k0 = r0; k0 < r1; k0 += kKc) {
-        // 16 rows x 64 columns of each operand: thread (r = tid % 16, c4 = tid / 16)
-        const int r = threadIdx.x & 15, c4 = threadIdx.x >> 4;
+        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    for (int64_t k0 = r0; k0 < r1; k0 += kGK) {
+        double4 va[4], vb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int c = c4 * 4 + q;
-            const int64_t kr = k0 + r;
-            const int ci = I * kTile + c, cj = J * kTile + c;
-            sa[r][c] = (kr < r1 && ci < s) ? A[static_cast<int64_t>(ci) * rows + kr] : 0.0;
-            sb[r][c] = (kr < r1 && cj < s) ? A[static_cast<int64_t>(cj) * rows + kr] : 0.0;
+            va[q] = *reinterpret_cast<const double4*>(pa[q] + k0);
+            vb[q] = *reinterpret_cast<const double4*>(pb[q] + k0);
         }
-        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kKc; ++k) {
-            double va[4], vb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) va[a] = sa[k][ty * 4 + a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vb[b] = sb[k][tx * 4 + b];
+        for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(va[a], vb[b], acc[a][b]);
-        }
-        __syncthreads();
+                for (int b = 0; b < 4; ++b) {
+                    const double xa = t == 0 ? va[a].x : t == 1 ? va[a].y : t == 2 ? va[a].z : va[a].w;
+                    const double xb = t == 0 ? vb[b].x : t == 1 ? vb[b].y : t == 2 ? vb[b].z : vb[b].w;
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, xb, acc[a][b], 0, 0, 0);
+                }
     }
+    double* G = r.Gp + static_cast<int64_t>(blockIdx.y) * s * s;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int i = I * kTile + ty * 4 + a, j = J * kTile + tx * 4 + b;
-            if (i < s && j < s) G[static_cast<int64_t>(i) * s + j] = acc[a][b];
-        }
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = I * kGT + 16 * a + kq + 4 * t, j = J * kGT + 16 * b + c;
+                if (i < s && j <= i) G[static_cast<int64_t>(i) * s + j] = acc[a][b][t];
+            }
 }
 
-// G = sum of the KS partials, in split order (lower triangle).
-// (The diagonal is also kept aside: the factorization judges its pivots
-// against it.)
-__global__ __launch_bounds__(256) void k_refit_gram_sum(const double* __restrict__ Gp, int s, int ks,
-                                                        double* __restrict__ G, double* __restrict__ diag) {
+// G = sum of the row-split partials, in split order (lower triangle).  The
+// diagonal is also kept aside: the factorization judges its pivots against it.
+__global__ __launch_bounds__(256) void k_refit_gram_sum(const RefitDev* __restrict__ R, int ks) {
+    const RefitDev& r = R[blockIdx.z];
+    const int s = r.s;
     const int64_t total = static_cast<int64_t>(s) * s;
+    const int nsplit = static_cast<int>(min<int64_t>(ks, (r.lda + r.split - 1) / r.split));
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * 256) {
         if (e % s > e / s) continue;
         double v = 0.0;
-        for (int q = 0; q < ks; ++q) v += Gp[q * total + e];
-        G[e] = v;
-        if (e % s == e / s) diag[e / s] = v;
+        for (int q = 0; q < nsplit; ++q) v += r.Gp[q * total + e];
+        r.G[e] = v;
+        if (e % s == e / s) r.diag[e / s] = v;
     }
 }
 
-__global__ void k_fill_i32(int* p, int count, int v) {
-    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = v;
-}
-
-// b = A^T y, one workgroup per column, fixed summation order.
-__global__ __launch_bounds__(256) void k_refit_rhs(const double* __restrict__ A, int64_t rows,
-                                                   const double* __restrict__ y,
-                                                   double* __restrict__ b) {
-    __shared__ double red[4];
+// b = A^T y, one workgroup per column, fixed summation order; the flag is
+// cleared here.
+__global__ __launch_bounds__(256) void k_refit_rhs(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
     const int t = blockIdx.x;
+    if (t >= r.s) return;
+    __shared__ double red[4];
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < rows; i += 256) acc = fma(A[static_cast<int64_t>(t) * rows + i], y[i], acc);
+    for (int64_t i = threadIdx.x; i < r.rows; i += 256) acc = fma(r.A[static_cast<int64_t>(t) * r.lda + i], r.y[i], acc);
     acc = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) b[t] = acc;
+    if (threadIdx.x == 0) {
+        r.b[t] = acc;
+        if (t == 0) *r.flag = 0;
+    }
 }
 
 // Cholesky of the nb x nb diagonal block at (k0, k0), in LDS.  A pivot at or
@@ -157,9 +196,11 @@ __global__ __launch_bounds__(256) void k_refit_rhs(const double* __restrict__ A,
 // columns are (numerically) linearly dependent.
 constexpr double kPivotRel = 1e-12;
 
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int s, int k0,
-                                                    const double* __restrict__ diag, int* flag) {
-    if (*flag) return;
+__global__ __launch_bounds__(256) void k_potrf_diag(const RefitDev* __restrict__ R, int k0) {
+    const RefitDev& r = R[blockIdx.z];
+    const int s = r.s;
+    if (k0 >= s || *r.flag) return;
+    double* G = r.G;
     __shared__ double L[kNB][kNB + 1];
     const int nb = min(kNB, s - k0);
     for (int e = threadIdx.x; e < nb * nb; e += 256) {
@@ -169,14 +210,14 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int 
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
         const double d = L[k][k];
-        if (!(d > kPivotRel * diag[k0 + k]) || !isfinite(d)) {
-            if (threadIdx.x == 0) atomicOr(flag, 1);
+        if (!(d > kPivotRel * r.diag[k0 + k]) || !isfinite(d)) {
+            if (threadIdx.x == 0) atomicOr(r.flag, 1);
             return;  // uniform: every thread read the same d
         }
-        const double r = sqrt(d);
+        const double rt = sqrt(d);
         __syncthreads();
-        if (threadIdx.x == 0) L[k][k] = r;
-        for (int i = k + 1 + threadIdx.x; i < nb; i += 256) L[i][k] /= r;
+        if (threadIdx.x == 0) L[k][k] = rt;
+        for (int i = k + 1 + threadIdx.x; i < nb; i += 256) L[i][k] /= rt;
         __syncthreads();
         for (int e = threadIdx.x; e < nb * nb; e += 256) {
             const int i = e / nb, j = e % nb;
@@ -191,8 +232,11 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ G, int 
 }
 
 // Panel below the diagonal block: rows i >= k0 + nb solve x L11^T = a.
-__global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ G, int s, int k0, const int* flag) {
-    if (*flag) return;
+__global__ __launch_bounds__(256) void k_trsm_panel(const RefitDev* __restrict__ R, int k0) {
+    const RefitDev& r = R[blockIdx.z];
+    const int s = r.s;
+    if (k0 >= s || *r.flag) return;
+    double* G = r.G;
     __shared__ double L[kNB][kNB + 1];
     const int nb = min(kNB, s - k0);
     for (int e = threadIdx.x; e < nb * nb; e += 256) {
@@ -222,10 +266,15 @@ __global__ __launch_bounds__(256) void k_trsm_panel(double* __restrict__ G, int 
 }
 
 // Trailing update: A22 -= L21 L21^T on the lower triangle, 64 x 64 tiles.
-__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ G, int s, int k0, const int* flag) {
-    if (*flag) return;
+__global__ __launch_bounds__(256) void k_syrk_update(const RefitDev* __restrict__ R, int k0) {
+    const RefitDev& r = R[blockIdx.z];
+    const int s = r.s;
+    if (k0 >= s || *r.flag) return;
     const int nb = min(kNB, s - k0);
     const int base = k0 + nb;  // first trailing row / column
+    const int Tr = (s - base + kTile - 1) / kTile;
+    if (static_cast<int>(blockIdx.x) >= Tr * (Tr + 1) / 2) return;
+    double* G = r.G;
     int I = 0, rem = blockIdx.x;
     while (rem > I) {
         rem -= I + 1;
@@ -271,9 +320,12 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-__global__ __launch_bounds__(1024) void k_refit_solve(const double* __restrict__ G, int s,
-                                                      double* __restrict__ b, const int* flag) {
-    if (*flag) return;
+__global__ __launch_bounds__(1024) void k_refit_solve(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
+    if (*r.flag) return;
+    const int s = r.s;
+    const double* G = r.G;
+    double* b = r.b;
     __shared__ double D[kNB][kNB + 1];
     __shared__ double z[kNB];
     const int tid = threadIdx.x;
@@ -330,109 +382,176 @@ __global__ __launch_bounds__(1024) void k_refit_solve(const double* __restrict__
     }
 }
 
-// x_out: zero off the support, x_out[sup[t]] = x_t (FP32); xs_out
-// (optional) = x (FP64).  The support is ascending, so one pass over n with
-// a binary search would do; two launches keep it simple.
-__global__ __launch_bounds__(256) void k_refit_zero(int64_t n, float* __restrict__ x_out, const int* flag) {
-    if (*flag) return;
-    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < n;
+// x_out: zero off the support, then x_out[sup[t]] = x_t (FP32); xs_out
+// (optional) = x (FP64).
+__global__ __launch_bounds__(256) void k_refit_zero(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
+    if (*r.flag) return;
+    for (int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; j < r.n;
          j += static_cast<int64_t>(gridDim.x) * 256)
-        x_out[j] = 0.0f;
+        r.x_out[j] = 0.0f;
 }
 
-__global__ __launch_bounds__(256) void k_refit_scatter(const double* __restrict__ xz,
-                                                       const int32_t* __restrict__ sup, int s,
-                                                       float* __restrict__ x_out,
-                                                       double* __restrict__ xs_out, const int* flag) {
-    if (*flag) return;
-    for (int t = blockIdx.x * 256 + threadIdx.x; t < s; t += gridDim.x * 256) {
-        x_out[sup[t]] = static_cast<float>(xz[t]);
-        if (xs_out) xs_out[t] = xz[t];
+__global__ __launch_bounds__(256) void k_refit_scatter(const RefitDev* __restrict__ R) {
+    const RefitDev& r = R[blockIdx.z];
+    if (*r.flag) return;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < r.s; t += gridDim.x * 256) {
+        r.x_out[r.sup[t]] = static_cast<float>(r.b[t]);
+        if (r.xs_out) r.xs_out[t] = r.b[t];
     }
 }
-
-}  // namespace
-
-namespace {
-constexpr int kSplitK = 8;  // row splits of the Gram product
 
 size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
-struct RefitWs {
-    double *A, *Gp, *G, *b, *diag;
-    int* flag;
-    size_t bytes;
-};
-
-RefitWs refit_layout(uint8_t* base, int64_t rows, int64_t s) {
-    RefitWs w{};
-    size_t off = 0;
+// Workspace of one problem with `ks` Gram row splits.
+size_t refit_bytes(int64_t lda, int64_t s, int ks) {
     const size_t ss = static_cast<size_t>(s) * static_cast<size_t>(s) * sizeof(double);
-    w.A = reinterpret_cast<double*>(base + off);
-    off += up256(static_cast<size_t>(rows) * static_cast<size_t>(s) * sizeof(double));
-    w.Gp = reinterpret_cast<double*>(base + off);
-    off += up256(kSplitK * ss);
-    w.G = reinterpret_cast<double*>(base + off);
-    off += up256(ss);
-    w.b = reinterpret_cast<double*>(base + off);
-    off += up256(static_cast<size_t>(s) * sizeof(double));
-    w.diag = reinterpret_cast<double*>(base + off);
-    off += up256(static_cast<size_t>(s) * sizeof(double));
-    w.flag = reinterpret_cast<int*>(base + off);
-    off += 256;
-    w.bytes = off;
-    return w;
-}
-}  // namespace
-
-size_t refit_workspace_bytes(int64_t rows, int64_t s) {
-    return refit_layout(nullptr, rows, s).bytes;
+    return up256(static_cast<size_t>(lda) * static_cast<size_t>(s) * sizeof(double)) +
+           up256(static_cast<size_t>(ks) * ss) + up256(ss) + 2 * up256(static_cast<size_t>(s) * sizeof(double)) + 256;
 }
 
-int* refit_flag(uint8_t* ws, int64_t rows, int64_t s) { return refit_layout(ws, rows, s).flag; }
+int64_t lda_of(int64_t rows) { return (rows + kGK - 1) / kGK * kGK; }
 
-void launch_refit(const RefitIn& in, uint8_t* ws, hipStream_t st) {
-    const int64_t rows = in.rows;
-    const int s = static_cast<int>(in.s);
-    const RefitWs w = refit_layout(ws, rows, s);
-    const dim3 gcol(static_cast<unsigned>(std::min<int64_t>((rows + 255) / 256, 64)), s);
-    if (in.phi) {
-        switch (in.dtype) {
-            case QIHT_F64: hipLaunchKernelGGL((k_refit_phi<double, false>), gcol, dim3(256), 0, st, static_cast<const double*>(in.phi), in.m, in.ld, in.sup, w.A); break;
-            case QIHT_F32: hipLaunchKernelGGL((k_refit_phi<float, false>), gcol, dim3(256), 0, st, static_cast<const float*>(in.phi), in.m, in.ld, in.sup, w.A); break;
-            case QIHT_C128: hipLaunchKernelGGL((k_refit_phi<double, true>), gcol, dim3(256), 0, st, static_cast<const double*>(in.phi), in.m, in.ld, in.sup, w.A); break;
-            default: hipLaunchKernelGGL((k_refit_phi<float, true>), gcol, dim3(256), 0, st, static_cast<const float*>(in.phi), in.m, in.ld, in.sup, w.A); break;
+// Launch the refit of problems [0, cnt) whose RefitDev array is at dR (device).
+void launch_group(const RefitIn& k, const RefitDev* dR, int cnt, int ks, int64_t max_lda, int max_s,
+                  int64_t max_n, hipStream_t st) {
+    const dim3 gcol(static_cast<unsigned>(std::min<int64_t>((max_lda + 255) / 256, 64)), max_s, cnt);
+    if (k.phi) {
+        switch (k.dtype) {
+            case QIHT_F64: hipLaunchKernelGGL((k_refit_phi<double, false>), gcol, dim3(256), 0, st, dR); break;
+            case QIHT_F32: hipLaunchKernelGGL((k_refit_phi<float, false>), gcol, dim3(256), 0, st, dR); break;
+            case QIHT_C128: hipLaunchKernelGGL((k_refit_phi<double, true>), gcol, dim3(256), 0, st, dR); break;
+            default: hipLaunchKernelGGL((k_refit_phi<float, true>), gcol, dim3(256), 0, st, dR); break;
         }
     } else {
-        switch (in.bits) {
-            case 1: hipLaunchKernelGGL((k_refit_codes<1>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            case 2: hipLaunchKernelGGL((k_refit_codes<2>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            case 4: hipLaunchKernelGGL((k_refit_codes<4>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            case 8: hipLaunchKernelGGL((k_refit_codes<8>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            case 9: hipLaunchKernelGGL((k_refit_codes<9>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            case 16: hipLaunchKernelGGL((k_refit_codes<16>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
-            default: hipLaunchKernelGGL((k_refit_codes<32>), gcol, dim3(256), 0, st, in.codes, in.col_bytes, rows, in.alpha, in.beta, in.rowexp, in.sup, w.A); break;
+        switch (k.bits) {
+            case 1: hipLaunchKernelGGL((k_refit_codes<1>), gcol, dim3(256), 0, st, dR); break;
+            case 2: hipLaunchKernelGGL((k_refit_codes<2>), gcol, dim3(256), 0, st, dR); break;
+            case 4: hipLaunchKernelGGL((k_refit_codes<4>), gcol, dim3(256), 0, st, dR); break;
+            case 8: hipLaunchKernelGGL((k_refit_codes<8>), gcol, dim3(256), 0, st, dR); break;
+            case 9: hipLaunchKernelGGL((k_refit_codes<9>), gcol, dim3(256), 0, st, dR); break;
+            case 16: hipLaunchKernelGGL((k_refit_codes<16>), gcol, dim3(256), 0, st, dR); break;
+            default: hipLaunchKernelGGL((k_refit_codes<32>), gcol, dim3(256), 0, st, dR); break;
         }
     }
-    const int T = (s + kTile - 1) / kTile;
-    const int64_t split = ((rows + kSplitK - 1) / kSplitK + kKc - 1) / kKc * kKc;
-    hipLaunchKernelGGL(k_refit_gram, dim3(T * (T + 1) / 2, kSplitK), dim3(256), 0, st, w.A, rows, s, split, w.Gp);
-    hipLaunchKernelGGL(k_refit_gram_sum, dim3(static_cast<unsigned>(std::min<int64_t>((static_cast<int64_t>(s) * s + 255) / 256, 4096))), dim3(256), 0, st, w.Gp, s, kSplitK, w.G, w.diag);
-    hipLaunchKernelGGL(k_refit_rhs, dim3(s), dim3(256), 0, st, w.A, rows, in.y, w.b);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, w.flag, 1, 0);
-    for (int k0 = 0; k0 < s; k0 += kNB) {
-        const int nb = std::min(kNB, s - k0);
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, w.G, s, k0, w.diag, w.flag);
-        const int rest = s - k0 - nb;
+    const int T = (max_s + kGT - 1) / kGT;
+    hipLaunchKernelGGL(k_refit_gram, dim3(T * (T + 1) / 2, ks, cnt), dim3(64), 0, st, dR);
+    hipLaunchKernelGGL(k_refit_gram_sum,
+                       dim3(static_cast<unsigned>(std::min<int64_t>((static_cast<int64_t>(max_s) * max_s + 255) / 256, 1024)), 1, cnt),
+                       dim3(256), 0, st, dR, ks);
+    hipLaunchKernelGGL(k_refit_rhs, dim3(max_s, 1, cnt), dim3(256), 0, st, dR);
+    for (int k0 = 0; k0 < max_s; k0 += kNB) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1, 1, cnt), dim3(256), 0, st, dR, k0);
+        const int rest = max_s - k0 - std::min(kNB, max_s - k0);
         if (rest > 0) {
-            hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 255) / 256), dim3(256), 0, st, w.G, s, k0, w.flag);
+            hipLaunchKernelGGL(k_trsm_panel, dim3((rest + 255) / 256, 1, cnt), dim3(256), 0, st, dR, k0);
             const int Tr = (rest + kTile - 1) / kTile;
-            hipLaunchKernelGGL(k_syrk_update, dim3(Tr * (Tr + 1) / 2), dim3(256), 0, st, w.G, s, k0, w.flag);
+            hipLaunchKernelGGL(k_syrk_update, dim3(Tr * (Tr + 1) / 2, 1, cnt), dim3(256), 0, st, dR, k0);
         }
     }
-    hipLaunchKernelGGL(k_refit_solve, dim3(1), dim3(1024), 0, st, w.G, s, w.b, w.flag);
-    hipLaunchKernelGGL(k_refit_zero, dim3(static_cast<unsigned>(std::min<int64_t>((in.n + 255) / 256, 1024))), dim3(256), 0, st, in.n, in.x_out, w.flag);
-    hipLaunchKernelGGL(k_refit_scatter, dim3((s + 255) / 256), dim3(256), 0, st, w.b, in.sup, s, in.x_out, in.xs_out, w.flag);
+    hipLaunchKernelGGL(k_refit_solve, dim3(1, 1, cnt), dim3(1024), 0, st, dR);
+    hipLaunchKernelGGL(k_refit_zero, dim3(static_cast<unsigned>(std::min<int64_t>((max_n + 255) / 256, 1024)), 1, cnt),
+                       dim3(256), 0, st, dR);
+    hipLaunchKernelGGL(k_refit_scatter, dim3((max_s + 255) / 256, 1, cnt), dim3(256), 0, st, dR);
 }
+
+}  // namespace
+
+qiht_status run_refit_batch(const RefitIn* in, int count, hipStream_t st) {
+    // groups whose workspaces together stay under the cap
+    constexpr size_t kCap = size_t(2) << 30;
+    int first = 0;
+    while (first < count) {
+        // row splits: enough Gram waves for the device, each split >= 64 rows
+        int last = first;
+        size_t bytes = 0;
+        int64_t tiles = 0, min_lda = INT64_MAX;
+        while (last < count) {
+            const int64_t lda = lda_of(in[last].rows);
+            const size_t b1 = refit_bytes(lda, in[last].s, 1);
+            if (last > first && bytes + b1 > kCap / 2) break;
+            bytes += b1;
+            const int64_t T = (in[last].s + kGT - 1) / kGT;
+            tiles += T * (T + 1) / 2;
+            min_lda = std::min(min_lda, lda);
+            ++last;
+        }
+        const int cnt = last - first;
+        int ks = 1;
+        while (ks < 256 && tiles * ks < 2048 && min_lda / (2 * ks) >= 64) ks *= 2;
+        std::vector<RefitDev> h(cnt);
+        std::vector<size_t> off(cnt);
+        size_t total = up256(sizeof(RefitDev) * cnt) + up256(sizeof(int) * cnt);
+        int64_t max_lda = 0, max_n = 0;
+        int max_s = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const RefitIn& q = in[first + i];
+            off[i] = total;
+            total += refit_bytes(lda_of(q.rows), q.s, ks);
+            max_lda = std::max(max_lda, lda_of(q.rows));
+            max_s = std::max(max_s, static_cast<int>(q.s));
+            max_n = std::max(max_n, q.n);
+        }
+        uint8_t* ws = nullptr;
+        if (pool_malloc(reinterpret_cast<void**>(&ws), total, st) != hipSuccess || !ws) {
+            (void)hipGetLastError();
+            return fail(QIHT_ERR_OUT_OF_MEMORY, "refit workspace");
+        }
+        int* flags = reinterpret_cast<int*>(ws + up256(sizeof(RefitDev) * cnt));
+        for (int i = 0; i < cnt; ++i) {
+            const RefitIn& q = in[first + i];
+            RefitDev& d = h[i];
+            d = RefitDev{};
+            d.codes = q.codes;
+            d.col_bytes = q.col_bytes;
+            d.alpha = q.alpha;
+            d.beta = q.beta;
+            d.rowexp = q.rowexp;
+            d.phi = q.phi;
+            d.m = q.m;
+            d.ld = q.ld;
+            d.rows = q.rows;
+            d.lda = lda_of(q.rows);
+            d.n = q.n;
+            d.s = static_cast<int>(q.s);
+            d.split = ((d.lda + ks - 1) / ks + kGK - 1) / kGK * kGK;
+            d.y = q.y;
+            d.sup = q.sup;
+            d.x_out = q.x_out;
+            d.xs_out = q.xs_out;
+            uint8_t* p = ws + off[i];
+            const size_t ss = static_cast<size_t>(q.s) * static_cast<size_t>(q.s) * sizeof(double);
+            d.A = reinterpret_cast<double*>(p);
+            p += up256(static_cast<size_t>(d.lda) * static_cast<size_t>(q.s) * sizeof(double));
+            d.Gp = reinterpret_cast<double*>(p);
+            p += up256(static_cast<size_t>(ks) * ss);
+            d.G = reinterpret_cast<double*>(p);
+            p += up256(ss);
+            d.b = reinterpret_cast<double*>(p);
+            p += up256(static_cast<size_t>(q.s) * sizeof(double));
+            d.diag = reinterpret_cast<double*>(p);
+            d.flag = flags + i;
+        }
+        RefitDev* dR = reinterpret_cast<RefitDev*>(ws);
+        hipError_t e = hipMemcpyAsync(dR, h.data(), sizeof(RefitDev) * cnt, hipMemcpyHostToDevice, st);
+        std::vector<int> hf(cnt, 0);
+        if (e == hipSuccess) {
+            launch_group(in[first], dR, cnt, ks, max_lda, max_s, max_n, st);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), flags, sizeof(int) * cnt, hipMemcpyDeviceToHost, st);
+        (void)hipFreeAsync(ws, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(QIHT_ERR_DEVICE, std::string("refit: ") + hipGetErrorString(e));
+        for (int i = 0; i < cnt; ++i)
+            if (hf[i])
+                return fail(QIHT_ERR_NUMERIC, "refit of problem " + std::to_string(first + i) +
+                                                  ": the support columns are not linearly independent");
+        first = last;
+    }
+    return QIHT_OK;
+}
+
+qiht_status run_refit(const RefitIn& in, hipStream_t st) { return run_refit_batch(&in, 1, st); }
 
 }  // namespace qiht

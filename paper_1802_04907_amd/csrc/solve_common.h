@@ -483,9 +483,6 @@ void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, bool wide, hipStream_t st);
 // ev0/ev1 (optional): events recorded by the dispatch itself around the
 // kernel (timing of the bandwidth-bound pass).
-size_t refit_workspace_bytes(int64_t rows, int64_t s);
-int* refit_flag(uint8_t* ws, int64_t rows, int64_t s);
-void launch_refit(const RefitIn& in, uint8_t* ws, hipStream_t st);
 
 // Shared-matrix pass (gemm.hip): G = Phi~^T R' on the matrix cores for all
 // problems of a batch that share one dense-format or FP32 matrix.

@@ -512,23 +512,6 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float*
     return QIHT_OK;
 }
 
-qiht_status run_refit(const RefitIn& in, hipStream_t st) {
-    const size_t bytes = refit_workspace_bytes(in.rows, in.s);
-    uint8_t* ws = nullptr;
-    if (pool_malloc(reinterpret_cast<void**>(&ws), bytes, st) != hipSuccess || !ws)
-        return fail(QIHT_ERR_OUT_OF_MEMORY, "refit workspace");
-    launch_refit(in, ws, st);
-    hipError_t e = hipGetLastError();
-    int herr = 0;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&herr, refit_flag(ws, in.rows, in.s), sizeof(int), hipMemcpyDeviceToHost, st);
-    (void)hipFreeAsync(ws, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(QIHT_ERR_DEVICE, std::string("refit: ") + hipGetErrorString(e));
-    if (herr) return fail(QIHT_ERR_NUMERIC, "refit: the support columns are not linearly independent");
-    return QIHT_OK;
-}
-
 qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* support_out,
                                hipStream_t st) {
     if (n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
