@@ -262,31 +262,32 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
 // Wide gathers for a batch on one shared dense-format or FP32 matrix (one
 // copy: Q1 = Q2).  Hundreds of problems each list hundreds of columns, so
 // the gathers move gigabytes per iteration and must run at bandwidth rather
-// than latency: a workgroup owns a 256-byte row segment of every listed
-// column (one coalesced 256-byte read per wave and column), its four waves
-// take the listed columns w, w + 4, ..., and the list itself (indices and
-// weights) is staged through LDS first, so every batch of loads is one HBM
-// round trip.  Rows are summed per lane in FP64, then over the waves in wave
-// order (fixed order, bitwise reproducible).  Partials and candidate lists
-// are per 256-byte segment (npart of them).
+// than latency: a workgroup owns a 1 KB row segment of every listed column
+// (each lane one 16-byte piece: one coalesced 1 KB read per wave and
+// column), its four waves take the listed columns w, w + 4, ..., and the
+// list itself (indices and weights) is staged through LDS first.  Rows are
+// summed per lane in FP64, then over the waves in wave order (fixed order,
+// bitwise reproducible).  Partials and candidate lists are per segment
+// (npart of them; the last segment of a column may be partial).
 // ---------------------------------------------------------------------------
-constexpr int kWideBytes = 256;
+constexpr int kWideBytes = 1024;
 constexpr int kWideList = 1024;  // list entries staged at once
 
 template <int BITS, int MODE>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* __restrict__ P,
                                                                 SolveArgs a, int zero_x) {
     constexpr int RPW = rows_per_word<BITS>();
+    constexpr int NV = 4;               // words per lane
+    constexpr int NA = NV * RPW;        // rows per lane
     constexpr int NSET = (MODE == G_OMEGA) ? kSpec : 1;
     constexpr int NW = kGatherThreads / 64;
-    constexpr int NR = 64 * RPW;  // rows of the segment
-    static_assert(NR <= kGatherThreads, "one thread per row of the segment");
-    constexpr int U = 8;
+    constexpr int NR = 64 * NA;         // rows of the segment
+    constexpr int U = 8;  // column loads in flight per lane
     const int p = blockIdx.y / NSET;
     const int set = blockIdx.y % NSET;
     const ProbDev& pd = P[p];
     if (pd.st->done) return;
-    const int wg = blockIdx.x;  // 256-byte row segment
+    const int wg = blockIdx.x;  // 1 KB row segment
     if (wg >= pd.npart) return;
 
     const int32_t* cols;
@@ -304,13 +305,20 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
     const uint8_t* A = pd.q1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const size_t woff = static_cast<size_t>(wg) * kWideBytes + static_cast<size_t>(lane) * 4;
+    // a lane past the end of the column reads its last piece (those rows are not used)
+    const size_t woff = min(static_cast<size_t>(wg) * kWideBytes + static_cast<size_t>(lane) * 16,
+                            static_cast<size_t>(pd.col_bytes) - 16);
+    const size_t rows_pad = static_cast<size_t>(pd.nwg) * 4 * RPW;
 
-    __shared__ int32_t lidx[kWideList];
-    __shared__ double lw[kWideList];
-    double acc[RPW];
+    // LDS: the staged list during the loads, then the per-wave row sums
+    constexpr size_t kListBytes = kWideList * (sizeof(int32_t) + sizeof(double));
+    constexpr size_t kSumBytes = sizeof(double) * NW * 64 * (NA + 1);
+    __shared__ __align__(16) uint8_t lds_raw[kListBytes > kSumBytes ? kListBytes : kSumBytes];
+    double* lw = reinterpret_cast<double*>(lds_raw);
+    int32_t* lidx = reinterpret_cast<int32_t*>(lds_raw + kWideList * sizeof(double));
+    double acc[NA];
 #pragma unroll
-    for (int q = 0; q < RPW; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (int base = 0; base < ncols; base += kWideList) {
         const int cnt = min(kWideList, ncols - base);
         for (int i = tid; i < cnt; i += kGatherThreads) {
@@ -325,40 +333,44 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
         }
         __syncthreads();
         for (int t0 = wv; t0 < cnt; t0 += NW * U) {
-            uint32_t wa[U];
-            double wt[U];
+            uint4 wa[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int tc = min(t0 + NW * u, cnt - 1);
+                wa[u] = ldg_u4(A + static_cast<size_t>(lidx[tc]) * pd.col_bytes + woff);
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int t = t0 + NW * u;
-                const int tc = min(t, cnt - 1);
-                wt[u] = t < cnt ? lw[tc] : 0.0;
-                wa[u] = ldg_u32(A + static_cast<size_t>(lidx[tc]) * pd.col_bytes + woff);
+                const double wt = t < cnt ? lw[min(t, cnt - 1)] : 0.0;
+                const uint32_t w4[NV] = {wa[u].x, wa[u].y, wa[u].z, wa[u].w};
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int q = 0; q < RPW; ++q) acc[v * RPW + q] = fma(wt, elem_at<BITS>(w4[v], q), acc[v * RPW + q]);
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int q = 0; q < RPW; ++q) acc[q] = fma(wt[u], elem_at<BITS>(wa[u], q), acc[q]);
         }
         __syncthreads();
     }
-    // ---- waves in wave order; thread t < NR then holds row wg NR + t
-    __shared__ double sh[NW][64][RPW];
+    // ---- waves in wave order; thread t then holds rows t, t + 256, ... of the segment
+    // (the last __syncthreads of the loop retired the list)
+    double (*sh)[64][NA + 1] = reinterpret_cast<double (*)[64][NA + 1]>(lds_raw);
     __shared__ double shr[NW];
 #pragma unroll
-    for (int q = 0; q < RPW; ++q) sh[wv][lane][q] = acc[q];
+    for (int q = 0; q < NA; ++q) sh[wv][lane][q] = acc[q];
     __syncthreads();
-    double val = 0.0;
-    const size_t row = static_cast<size_t>(wg) * NR + tid;
-    const bool live = tid < NR && row < static_cast<size_t>(pd.rows);
-    if (tid < NR) {
+    double l1 = 0.0;
+    for (int rr = tid; rr < NR; rr += kGatherThreads) {
+        const size_t row = static_cast<size_t>(wg) * NR + rr;
+        if (row >= rows_pad) break;
+        const bool live = row < static_cast<size_t>(pd.rows);
         double tot = 0.0;
 #pragma unroll
-        for (int v = 0; v < NW; ++v) tot += sh[v][tid / RPW][tid % RPW];
+        for (int v = 0; v < NW; ++v) tot += sh[v][rr / NA][rr % NA];
+        double val;
         if constexpr (BITS == 32) val = tot;
         else val = live ? ldexp(tot, pd.rowexp[row]) : 0.0;
-    }
-    if constexpr (MODE == G_R) {
-        if (tid < NR) {
+        if constexpr (MODE == G_R) {
             const double rres = live ? ldg_f64(pd.yhat + row) - val : 0.0;
             pd.r32[row] = static_cast<float>(rres);
             if constexpr (BITS == 9 || BITS == 16) {
@@ -366,14 +378,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
                 const double v = live ? ldexp(rres, pd.rowexp[row]) : 0.0;
                 const uint32_t hi = bf16_rne(v);
                 const uint32_t lo = bf16_rne(v - static_cast<double>(bf16_value(hi)));
-                const size_t rp = static_cast<size_t>(pd.nwg) * 4 * RPW;  // rows_pad
                 pd.rb[row] = static_cast<uint16_t>(hi);
-                pd.rb[rp + row] = static_cast<uint16_t>(lo);
+                pd.rb[rows_pad + row] = static_cast<uint16_t>(lo);
             }
+        } else if (live) {
+            l1 += val * val;
         }
-        return;
     }
-    const double s1 = block_sum<kGatherThreads>(live ? val * val : 0.0, shr);
+    if constexpr (MODE == G_R) return;
+    const double s1 = block_sum<kGatherThreads>(l1, shr);
     if (MODE == G_MU) {
         if (tid == 0) {
             pd.part_mu[2 * wg + 0] = s1;  // u.v with v = u (one copy of the matrix)

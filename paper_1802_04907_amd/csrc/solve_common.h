@@ -53,8 +53,8 @@ struct ProbDev {
     int32_t n;
     int32_t s;
     int32_t nwg;        // 16-byte row groups per column (gather workgroups)
-    int32_t npart;      // gather row segments: nwg, or 256-byte segments for the
-                        // wide gathers of a shared matrix (partials, candidate blocks)
+    int32_t npart;      // gather row segments: nwg, or 1 KB segments for the wide
+                        // gathers of a shared matrix (partials, candidate blocks)
     int32_t nslab;      // full-pass row slabs
     int32_t pad;
     double alpha;       // dequantized value = alpha * code + beta
@@ -474,7 +474,13 @@ template <int BITS>
 __device__ __forceinline__ double elem_at(uint32_t w, int q) {
     if constexpr (BITS == 32) return static_cast<double>(__uint_as_float(w));
     else if constexpr (BITS == 16) return static_cast<double>(bf16_value((w >> (16 * q)) & 0xFFFFu));
-    else if constexpr (BITS == 9) return static_cast<double>(e4m3_value((w >> (8 * q)) & 0xFFu));
+    else if constexpr (BITS == 9) {
+        // hardware FP8 (OCP E4M3) conversion, two bytes per instruction; exact
+        typedef float f32x2_v __attribute__((ext_vector_type(2)));
+        const f32x2_v pr = q >= 2 ? __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), true)
+                                  : __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w), false);
+        return static_cast<double>((q & 1) ? pr.y : pr.x);
+    }
     else return static_cast<double>(code_at<BITS>(w, q));
 }
 

@@ -168,7 +168,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.n = static_cast<int32_t>(q->n);
         p.s = static_cast<int32_t>(s);
         p.nwg = nwg;
-        p.npart = pl.shared ? static_cast<int>(q->col_bytes / 256) : nwg;
+        p.npart = pl.shared ? static_cast<int>((q->col_bytes + 1023) / 1024) : nwg;
         p.nslab = pl.shared ? 1 : nslab;
         p.rowexp = q->rexp;
         p.alpha = q->alpha;
