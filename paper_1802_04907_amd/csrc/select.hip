@@ -361,7 +361,7 @@ __device__ void rank_merged(int nc, int s, SelShared& S, int& sh, uint32_t& P, u
 // use): every key of the n in registers and bitmaps over all n.
 template <int MODE>
 __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool from_partials,
-                        double shrink, double* mu0_out, SelShared& S) {
+                        double shrink, double* mu0_out, SelShared& S, bool* skipped = nullptr) {
     constexpr int MPT = kCandCap / kSelectThreads;  // merged positions per thread
     constexpr int PRE = 4;                          // candidates loaded ahead per thread
     const int tid = threadIdx.x;
@@ -372,6 +372,9 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     // ---- loads (one round trip): mu partials, the candidate counts of this
     // thread's index blocks [t cpw, (t + 1) cpw), and the first PRE
     // candidates of its first block
+    // (with `skipped`, the solve's stop flag is read alongside these loads
+    // and an already finished problem returns before touching anything)
+    const int done_now = skipped ? pd.st->done : 0;
     double gg = 0.0, uv = 0.0, uu = 0.0;
     if (from_partials) {
         for (int i = tid; i < nsup; i += kSelectThreads) {
@@ -400,6 +403,10 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         if (w == w0) c0 = c;
         if (c < 0) bad_cnt = 1;
         else mycnt += static_cast<uint32_t>(c);
+    }
+    if (done_now) {  // uniform: every thread read the same flag
+        *skipped = true;
+        return false;
     }
     for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
     for (int b = tid; b < 1024; b += kSelectThreads) {
@@ -504,17 +511,35 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             S.u.f.mval[pos] = a;
             S.u.f.mxo[pos] = gx.y;
         };
+        // a block's entries [i0, c) in batches whose loads are issued
+        // together (clamped into the block, the extra ones not stored)
+        auto put_block = [&](uint32_t at, int lo, int i0, int c) {
+            constexpr int B = 4;
+            for (int ib = i0; ib < c; ib += B) {
+                uint32_t ti[B];
+                float2 tg[B];
+#pragma unroll
+                for (int q = 0; q < B; ++q) {
+                    const int i = min(ib + q, c - 1);
+                    ti[q] = pd.cidx[lo + i];
+                    tg[q] = pd.cgx[lo + i];
+                }
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+                    if (ib + q < c) put(at + ib + q, ti[q], tg[q]);
+            }
+        };
         uint32_t pos = obase;
         if (w0 < w1) {
 #pragma unroll
             for (int q = 0; q < PRE; ++q)
                 if (q < c0) put(pos + q, pidx[q], pgx[q]);
-            for (int i = PRE; i < c0; ++i) put(pos + i, pd.cidx[lo0 + i], pd.cgx[lo0 + i]);
+            put_block(pos, lo0, PRE, c0);
             pos += static_cast<uint32_t>(max(c0, 0));
         }
         for (int w = w0 + 1; w < w1; ++w) {
             const int c = pd.ccnt[w];
-            for (int i = 0; i < c; ++i) put(pos + i, pd.cidx[w * per + i], pd.cgx[w * per + i]);
+            put_block(pos, w * per, 0, c);
             pos += static_cast<uint32_t>(max(c, 0));
         }
     }
@@ -642,14 +667,16 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     const ProbDev& pd = P[blockIdx.y];
     SolveState* st = pd.st;
     __shared__ SelShared S;
-    if (st->done) return;
     double mu0 = 0.0;
     if (mode == SEL_INIT) {
+        if (st->done) return;
         propose<SEL_INIT>(pd, 0, 0, 1.0, false, 1.0, &mu0, S);
         return;
     }
     const int k = blockIdx.x;  // shrink count of this proposal
-    const bool ok = propose<SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S);
+    bool skipped = false;
+    const bool ok = propose<SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S, &skipped);
+    if (skipped) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (ok) {
             st->mu = mu0;

@@ -115,3 +115,45 @@ def test_refit_fullsize_support():
     want[sup] = niht.refit(cols, p.y.astype(np.float64), np.arange(len(sup)))
     x, z = qiht.refit(_t(sup), _t(p.y.astype(np.float64)), phi=_t(p.phi))
     _check(x, z, want, sup, p.phi.shape[1])
+
+
+def test_batched_solve_refit_matches_per_problem_lstsq():
+    """Refit of a batch (one launch sequence over all problems) against the
+    oracle's lstsq of every problem on its own support and Q1."""
+    probs = workloads.batch_uneven(count=6, m_lo=150, m_hi=600, seed=5)
+    gpu = []
+    for p in probs:
+        q = qiht.quantize_matrix(_t(p.phi), 4, 2, p.seed)
+        yh, _, _ = qiht.quantize_vector(_t(p.y), 8, p.seed)
+        gpu.append((q, yh, p.s))
+    plain = qiht.niht_solve_batched(gpu, max_iters=100, tol=-1.0)
+    res = qiht.niht_solve_batched(gpu, max_iters=100, tol=-1.0, refit=True)
+    for p, (q, yh, s), (x0, sup0, _), (x, sup, _) in zip(probs, gpu, plain, res):
+        assert torch.equal(sup0, sup)
+        c1, s1 = qz.quantize_matrix(p.phi, 4, p.seed, 0)
+        want = niht.refit(qz.dequantize(c1, s1, 4), yh.cpu().numpy(), sup.cpu().numpy())
+        got = x.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(got - want) <= 1e-6 * np.linalg.norm(want)
+        q.free()
+
+
+def test_batched_refit_names_the_rank_deficient_problem():
+    """A shared FP32 matrix with two equal columns: a problem whose solve
+    selects both cannot be refit, and the error names it."""
+    rng = np.random.default_rng(11)
+    m, n = 96, 200
+    phi = (rng.standard_normal((m, n)) / np.sqrt(m)).astype(np.float32)
+    phi[:, 11] = phi[:, 5]
+    x_ok = np.zeros(n)
+    x_ok[[20, 40, 60]] = [1.0, -1.0, 2.0]
+    x_bad = np.zeros(n)
+    x_bad[[5, 11, 90]] = [1.0, 1.0, 1.5]
+    q = qiht.quantize_matrix(_t(phi), 32, 1, 0)
+    ys = [_t(phi.astype(np.float64) @ x) for x in (x_ok, x_bad)]
+    probs = [(q, ys[0], 3), (q, ys[1], 3)]
+    res = qiht.niht_solve_batched(probs, max_iters=50, tol=-1.0)
+    if not {5, 11} <= set(res[1][1].cpu().numpy().tolist()):
+        pytest.skip("the solve did not select both equal columns")
+    with pytest.raises(RuntimeError, match="problem 1"):
+        qiht.niht_solve_batched(probs, max_iters=50, tol=-1.0, refit=True)
+    q.free()
