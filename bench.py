@@ -222,6 +222,120 @@ def shared_bench(qiht, torch, dev, reps=2, only=None):
     return res
 
 
+def interferometry_bench(qiht, torch, dev, iters=ITERS, reps=3):
+    """Fourier-sampled complex instance at full size: 32640 visibilities (u, v
+    uniform in a disk of radius 0.5), a 128 x 128 sky (n = 16384), 200 point
+    sources of log-uniform flux in [0.1, 10], 30 dB SNR; 4-bit Phi (real and
+    imaginary parts, stacked: 65280 rows) / 8-bit y.  The recipe of
+    workloads.interferometry with the same random draws, Phi and y computed on
+    the device (Phi_jk = exp(-2 pi i (u_j l_k + v_j m_k)), FP64 phases, complex64)."""
+    n_vis, side, s, snr_db = 32640, 128, 200, 30.0
+    rng = np.random.default_rng(SEED)
+    rad = 0.5 * np.sqrt(rng.random(n_vis))
+    th = 2.0 * np.pi * rng.random(n_vis)
+    u = torch.from_numpy(rad * np.cos(th)).to(dev)
+    v = torch.from_numpy(rad * np.sin(th)).to(dev)
+    n = side * side
+    k = torch.arange(n, device=dev, dtype=torch.float64)
+    lk = torch.remainder(k, side) - side // 2
+    mk = torch.div(k, side, rounding_mode="floor") - side // 2
+    phi = torch.empty((n_vis, n), dtype=torch.complex64, device=dev)
+    for r0 in range(0, n_vis, 2048):
+        ph = torch.outer(u[r0:r0 + 2048], lk) + torch.outer(v[r0:r0 + 2048], mk)
+        phi[r0:r0 + 2048] = torch.polar(torch.ones_like(ph), -2.0 * math.pi * ph).to(torch.complex64)
+        del ph
+    sup = np.sort(rng.choice(n, s, replace=False))
+    xv = 10.0 ** rng.uniform(-1.0, 1.0, s)
+    x_true = np.zeros(n)
+    x_true[sup] = xv
+    cols = phi[:, torch.from_numpy(sup).to(dev)].to(torch.complex128)
+    clean = cols @ torch.from_numpy(xv).to(dev).to(torch.complex128)
+    sig2 = float((clean.abs() ** 2).sum()) / (n_vis * 10.0 ** (snr_db / 10.0))
+    e = math.sqrt(sig2 / 2.0) * (rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis))
+    y = (clean + torch.from_numpy(e).to(dev)).to(torch.complex64).contiguous()
+    del cols, clean
+    q = qiht.quantize_matrix(phi, 4, 2, SEED)
+    yhat, _, _ = qiht.quantize_vector(y, 8, SEED)
+    del phi
+    qiht.niht_solve(q, yhat, s, max_iters=5, tol=-1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_ms, tot_l = 0.0, 0
+    for _ in range(reps):
+        x, sp, inf = qiht.niht_solve(q, yhat, s, max_iters=iters, tol=-1.0, profile=True)
+        tot_ms += inf["pass_ms"]
+        tot_l += inf["pass_launches"]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    avg = tot_ms / tot_l / 1e3
+    rows = 2 * n_vis
+    xs, ss = x.cpu().numpy().astype(np.float64), sp.cpu().numpy()
+    q.free()
+    return {
+        "workload": (f"complex Fourier-sampled Phi {n_vis} x {n} (stacked {rows} real rows), s={s}, "
+                     f"{snr_db:.0f} dB SNR, 4-bit Phi (2 realizations) / 8-bit y, {iters} iterations"),
+        "iterations_per_s": round(iters / el, 1),
+        "pass_avg_us": round(avg * 1e6, 2),
+        "pass_GBps": round(pass_bytes(rows, n, 4) / avg / 1e9, 1),
+        "support_recovery": round(len(np.intersect1d(ss, sup)) / s, 4),
+        "rel_err": round(float(np.linalg.norm(xs - x_true) / np.linalg.norm(x_true)), 5),
+    }
+
+
+def batched_bench(qiht, torch, dev, count=96, iters=100):
+    """Uneven independent problems: m uniform in [1024, 8192] (the master draw
+    of workloads.batch_uneven), n = 4m, s = m/16, Gaussian Phi N(0, 1/m) in
+    FP32 drawn on the device with a per-problem seeded generator, 4-bit Phi /
+    8-bit y.  One batched solve against the same problems solved one by one."""
+    master = np.random.default_rng(SEED)
+    ms = master.integers(1024, 8192 + 1, size=count)
+    probs, qs = [], []
+    for i, m in enumerate(ms):
+        m = int(m)
+        n, s = 4 * m, max(1, m // 16)
+        g = torch.Generator(device=dev)
+        g.manual_seed(1000 + i)
+        phi = torch.randn((m, n), generator=g, device=dev, dtype=torch.float32) * (1.0 / math.sqrt(m))
+        rng = np.random.default_rng([SEED, i])
+        sup = np.sort(rng.choice(n, s, replace=False))
+        xv = rng.standard_normal(s)
+        y = phi[:, torch.from_numpy(sup).to(dev)].double() @ torch.from_numpy(xv).to(dev)
+        y = y + SIGMA * torch.from_numpy(rng.standard_normal(m)).to(dev)
+        q = qiht.quantize_matrix(phi, 4, 2, i)
+        yhat, _, _ = qiht.quantize_vector(y.contiguous(), 8, i)
+        del phi
+        qs.append(q)
+        probs.append((q, yhat, s))
+    qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)
+    qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qiht.niht_solve_batched(probs, max_iters=iters, tol=-1.0)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for q, yhat, s in probs[:2]:
+        qiht.niht_solve(q, yhat, s, max_iters=2, tol=-1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, yhat, s in probs:
+        qiht.niht_solve(q, yhat, s, max_iters=iters, tol=-1.0)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    code_bytes = sum(2.0 * int(m) * int(m) for m in ms)  # 4-bit Q1 of every problem: m x 4m / 2 bytes
+    for q in qs:
+        q.free()
+    return {
+        "workload": (f"{count} independent Gaussian problems, m uniform in [1024, 8192], n = 4m, "
+                     f"s = m/16, 4-bit Phi / 8-bit y, {iters} iterations"),
+        "batched_ms": round(t_batch * 1e3, 2),
+        "sequential_ms": round(t_seq * 1e3, 2),
+        "speedup_vs_sequential": round(t_seq / t_batch, 2),
+        "problem_iterations_per_s": round(count * iters / t_batch, 1),
+        "q1_bytes_per_iteration": code_bytes,
+        "effective_q1_GBps": round(code_bytes * iters / t_batch / 1e9, 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +346,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-shared", action="store_true",
                     help="skip the shared-matrix (many right-hand sides) measurement")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the interferometry and batched-uneven measurements")
     ap.add_argument("--shared-only", default=None, choices=["f32", "bf16", "e4m3"],
                     help="only the shared-matrix workload in one format (short run for "
                          "rocprofv3 traces of its kernels)")
@@ -375,10 +491,20 @@ def main():
                 d.pop("trajectory_every_5", None)
         out["sweep"] = sweep
 
-    if not args.no_shared:
+    if not args.no_shared or not args.no_extra:
         del phi_d
         torch.cuda.empty_cache()
+    if not args.no_shared:
         out["shared_phi"] = shared_bench(qiht, torch, dev)
+    if not args.no_extra:
+        log("interferometry workload ...")
+        out["interferometry"] = interferometry_bench(qiht, torch, dev)
+        log(json.dumps(out["interferometry"]))
+        torch.cuda.empty_cache()
+        log("batched uneven workload ...")
+        out["batched_uneven"] = batched_bench(qiht, torch, dev)
+        log(json.dumps(out["batched_uneven"]))
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")
