@@ -171,22 +171,22 @@ __device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
     }
 }
 
+// LDS of a pass workgroup: lx[0, 2048) histogram bins, lx[2048, 2048 + c1 -
+// c0) g of the task; lbm the support bitmap of the task's columns.
+struct PassLds {
+    uint32_t lx[2048 + kPassMaxCols];
+    uint32_t lbm[kPassMaxCols / 32 + 2];
+};
+
 template <int BITS, int CPL>
-__global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
-    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+__device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, PassLds& L) {
     using D = QDig<BITS>;
     constexpr int RPC = 128 / BITS;  // rows per 16-byte chunk
     constexpr int ND = D::ND, H = D::H;
     constexpr int NCI = (CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2;  // columns per step
     constexpr int STEP = 4 * NCI;
-    // lx[0, 2048): histogram bins; lx[2048, 2048 + c1 - c0): g of the task
-    __shared__ uint32_t lx[2048 + kPassMaxCols];
-    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];
-    __shared__ double sb[kPassThreads / 64];
-
-    const Task tk = tasks[blockIdx.x];
-    const ProbDev& pd = P[tk.p];
-    if (pd.st->done) return;
+    uint32_t* lx = L.lx;
+    uint32_t* lbm = L.lbm;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int col_chunks = static_cast<int>(pd.col_bytes / 16);
     const int slab_chunk0 = tk.slab * 64 * CPL;
@@ -245,7 +245,6 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
         bl += in ? ldexp((pd.alpha * D::CODE_OFF + pd.beta) * static_cast<double>(sn[c]), ex[c]) : 0.0;
     }
     const double bsum = wave_total_f64(bl);  // every wave holds all chunks of the slab
-    (void)sb;
     __syncthreads();
 
     // Steady state, two buffers in turn: while one step is reduced the other
@@ -267,6 +266,29 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
             if (lx[b]) atomicAdd(&pd.hist[b], lx[b]);
 }
 
+// One launch over the spans of a batch: workgroup w runs span w, then the
+// spans its `next` links name; each span carries the chunks per lane of its
+// problem (small columns would leave most lanes idle at the batch's largest
+// CPL), the body is picked per span.
+template <int BITS, int CMAX>
+__global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
+    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+    __shared__ PassLds L;
+    for (int t = blockIdx.x; t >= 0;) {
+    const Task tk = tasks[t];
+    if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
+    t = tk.next;
+    const ProbDev& pd = P[tk.p];
+    if (pd.st->done) continue;  // uniform over the workgroup
+    switch (tk.cpl) {
+        case 1: pass_q_body<BITS, 1>(pd, tk, L); break;
+        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2>(pd, tk, L); break;
+        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4>(pd, tk, L); break;
+        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8>(pd, tk, L); break;
+    }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // FP32 full pass g = Q1^T r (32-bit "codes" are the floats themselves).  One
 // wave per column: lane l owns the 16-byte chunks l, l + 64, ..., l + 64
@@ -274,12 +296,8 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
 // for every column it visits; each column is reduced across the wave.
 // ---------------------------------------------------------------------------
 template <int BITS, int CPL>
-__global__ __launch_bounds__(kPassThreads) void k_fullpass(
-    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+__device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, PassLds& L) {
     constexpr int RPC = (BITS == 32) ? 4 : 128 / BITS;  // rows per chunk
-    const Task tk = tasks[blockIdx.x];
-    const ProbDev& pd = P[tk.p];
-    if (pd.st->done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col_chunks = static_cast<int>(pd.col_bytes / 16);
     const int chunk0 = tk.slab * 64 * CPL + lane;
@@ -309,8 +327,8 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     // over the entries off the current support, for the threshold search of
     // the H_s proposals; built where g is final.
     const bool hist = pd.nslab == 1;
-    __shared__ uint32_t lh[2048];
-    __shared__ uint32_t lbm[kPassMaxCols / 32 + 2];  // support bitmap of this task's columns
+    uint32_t* lh = L.lx;    // histogram bins
+    uint32_t* lbm = L.lbm;  // support bitmap of this task's columns
     const int wbase = tk.c0 >> 5;
     if (hist) {
         for (int b = threadIdx.x; b < 2048; b += kPassThreads) lh[b] = 0u;
@@ -364,6 +382,26 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     }
 }
 
+template <int BITS, int CMAX>
+__global__ __launch_bounds__(kPassThreads) void k_fullpass(
+    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+    __shared__ PassLds L;
+    for (int t = blockIdx.x; t >= 0;) {
+    const Task tk = tasks[t];
+    if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
+    t = tk.next;
+    const ProbDev& pd = P[tk.p];
+    if (pd.st->done) continue;  // uniform over the workgroup
+    switch (tk.cpl) {
+        case 1: pass_f_body<BITS, 1>(pd, tk, L); break;
+        case 2: if constexpr (CMAX >= 2) pass_f_body<BITS, 2>(pd, tk, L); break;
+        case 4: if constexpr (CMAX >= 4) pass_f_body<BITS, 4>(pd, tk, L); break;
+        case 8: if constexpr (CMAX >= 8) pass_f_body<BITS, 8>(pd, tk, L); break;
+        default: if constexpr (CMAX >= 16) pass_f_body<BITS, 16>(pd, tk, L); break;
+    }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__ P) {
     const ProbDev& pd = P[blockIdx.y];
     if (pd.st->done || pd.nslab <= 1) return;
@@ -377,25 +415,25 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__
 }
 
 template <typename K>
-void launch_k(K kern, int ntasks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const ProbDev* P,
+void launch_k(K kern, int nwg, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const ProbDev* P,
               const Task* T) {
     if (ev0)
-        hipExtLaunchKernelGGL(kern, dim3(ntasks), dim3(kPassThreads), 0, st, ev0, ev1, 0, P, T);
+        hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, ev0, ev1, 0, P, T);
     else
-        hipLaunchKernelGGL(kern, dim3(ntasks), dim3(kPassThreads), 0, st, P, T);
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, P, T);
 }
 
 template <int BITS>
-void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
+void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
     switch (cpl) {
 #define QIHT_PASS_CASE(C)                                                                   \
     case C:                                                                                 \
         if constexpr (C <= (BITS == 32 ? 16 : BITS)) {                                      \
             if constexpr (BITS == 32)                                                       \
-                launch_k(k_fullpass<BITS, C>, ntasks, st, ev0, ev1, P, T);                  \
+                launch_k(k_fullpass<BITS, C>, nwg, st, ev0, ev1, P, T);                     \
             else                                                                            \
-                launch_k(k_fullpass_q<BITS, C>, ntasks, st, ev0, ev1, P, T);                \
+                launch_k(k_fullpass_q<BITS, C>, nwg, st, ev0, ev1, P, T);                   \
         }                                                                                   \
         break;
         QIHT_PASS_CASE(1)
@@ -452,14 +490,14 @@ int pass_slots(int bits, int cpl) {
     return nb * cus;
 }
 
-void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks, hipStream_t st,
+void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1) {
     switch (bits) {
-        case 1: launch_pass_b<1>(cpl, P, T, ntasks, st, ev0, ev1); break;
-        case 2: launch_pass_b<2>(cpl, P, T, ntasks, st, ev0, ev1); break;
-        case 4: launch_pass_b<4>(cpl, P, T, ntasks, st, ev0, ev1); break;
-        case 8: launch_pass_b<8>(cpl, P, T, ntasks, st, ev0, ev1); break;
-        default: launch_pass_b<32>(cpl, P, T, ntasks, st, ev0, ev1); break;
+        case 1: launch_pass_b<1>(cpl, P, T, nwg, st, ev0, ev1); break;
+        case 2: launch_pass_b<2>(cpl, P, T, nwg, st, ev0, ev1); break;
+        case 4: launch_pass_b<4>(cpl, P, T, nwg, st, ev0, ev1); break;
+        case 8: launch_pass_b<8>(cpl, P, T, nwg, st, ev0, ev1); break;
+        default: launch_pass_b<32>(cpl, P, T, nwg, st, ev0, ev1); break;
     }
 }
 

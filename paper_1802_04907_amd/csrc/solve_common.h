@@ -91,6 +91,8 @@ struct ProbDev {
 
 struct Task {
     int32_t p, slab, c0, c1;
+    int32_t cpl;   // 16-byte chunks per lane of the problem's row slabs
+    int32_t next;  // the workgroup's next span, or -1
 };
 
 // ---------------------------------------------------------------------------
@@ -512,8 +514,8 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
 
 // Workgroups of the full pass that the device holds at once (0 if unknown).
 int pass_slots(int bits, int cpl);
-void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int ntasks,
-                 hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
+                 hipEvent_t ev0, hipEvent_t ev1);
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);

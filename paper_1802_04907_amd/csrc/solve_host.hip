@@ -99,6 +99,7 @@ struct Plan {
     bool any_slab = false;
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0, done_off = 0;
+    int npass = 0;  // full-pass workgroups
     // shared-matrix path: one GEMM per iteration instead of per-problem passes
     bool shared = false;
     SharedGemm sg{};
@@ -121,8 +122,9 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         max_n = std::max(max_n, in[i].q->n);
     }
     if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    // the kernel is built for the largest column; each problem's row slabs use
+    // its own chunks per lane (a task carries them)
     pl.cpl = pass_cpl(pl.bits, max_cb);
-    const int64_t slab_chunks = 64LL * pl.cpl;
     Carver cv;
     pl.lay.resize(count);
     pl.host.resize(count);
@@ -130,6 +132,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         const qiht_qmatrix* q = in[i].q;
         const int64_t s = in[i].s;
         const int64_t chunks = q->col_bytes / 16;
+        const int64_t slab_chunks = 64LL * pass_cpl(pl.bits, q->col_bytes);
         const int nslab = static_cast<int>((chunks + slab_chunks - 1) / slab_chunks);
         const int nwg = static_cast<int>(q->col_bytes / 16);
         pl.maxwg = std::max(pl.maxwg, nwg);
@@ -201,24 +204,52 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
             pl.bblk_off = cv.take<uint16_t>(static_cast<size_t>(count) * 2 * q->rows_pad);
         }
     }
-    // Full-pass tasks: column ranges of one row slab, sized so that the
-    // launch is one round of the workgroups the device holds at once (a
-    // second, partial round would leave most CUs idle at the end).
+    // Full-pass work: one round of the workgroups the device holds at once
+    // (a second, partial round would leave most CUs idle at the end).  The
+    // columns of every problem's row slabs are cut into spans so that each
+    // workgroup gets the same number of code bytes, a workgroup's spans
+    // running on across problem boundaries.  Workgroup w starts at span w;
+    // its further spans follow the `next` links (after the first spans).
     const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl));
     double total = 0.0;
     for (int i = 0; i < count; ++i)
         total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
-    const double per_task = std::max(1.0, total / slots);
+    const double budget = std::max(1.0, std::ceil(total / slots));
+    std::vector<std::vector<Task>> wgs(1);
+    double cur = 0.0;
     for (int i = 0; i < count && !pl.shared; ++i) {
         const qiht_qmatrix* q = in[i].q;
         const ProbDev& p = pl.host[i];
-        const int64_t slab_bytes = std::min<int64_t>(q->col_bytes, slab_chunks * 16);
-        const int64_t want = static_cast<int64_t>(std::ceil(per_task / static_cast<double>(slab_bytes)));
-        const int64_t tc = std::min<int64_t>(kPassMaxCols, std::max<int64_t>(4, want));
-        for (int sl = 0; sl < p.nslab; ++sl)
-            for (int64_t c0 = 0; c0 < q->n; c0 += tc)
-                pl.tasks.push_back(Task{i, sl, static_cast<int32_t>(c0),
-                                        static_cast<int32_t>(std::min<int64_t>(q->n, c0 + tc))});
+        const int cpl = pass_cpl(pl.bits, q->col_bytes);
+        const int64_t slab_max = 64LL * cpl * 16;
+        for (int sl = 0; sl < p.nslab; ++sl) {
+            const double sb = static_cast<double>(std::min<int64_t>(q->col_bytes - sl * slab_max, slab_max));
+            int64_t c0 = 0;
+            while (c0 < q->n) {
+                const int64_t fit = std::max<int64_t>(1, static_cast<int64_t>(std::ceil((budget - cur) / sb)));
+                const int64_t take = std::min<int64_t>({q->n - c0, fit, static_cast<int64_t>(kPassMaxCols)});
+                wgs.back().push_back(Task{i, sl, static_cast<int32_t>(c0), static_cast<int32_t>(c0 + take), cpl, -1});
+                c0 += take;
+                cur += static_cast<double>(take) * sb;
+                if (cur >= budget) {
+                    wgs.emplace_back();
+                    cur = 0.0;
+                }
+            }
+        }
+    }
+    if (wgs.back().empty()) wgs.pop_back();
+    pl.npass = static_cast<int>(wgs.size());
+    pl.tasks.resize(wgs.size());
+    for (size_t w = 0; w < wgs.size(); ++w) {
+        int32_t prev = -1;  // index of the workgroup's previous span
+        for (size_t k = 0; k < wgs[w].size(); ++k) {
+            const int32_t at = k == 0 ? static_cast<int32_t>(w) : static_cast<int32_t>(pl.tasks.size());
+            if (k == 0) pl.tasks[w] = wgs[w][0];
+            else pl.tasks.push_back(wgs[w][k]);
+            if (prev >= 0) pl.tasks[prev].next = at;
+            prev = at;
+        }
     }
     pl.probs_off = cv.take<ProbDev>(count);
     pl.tasks_off = cv.take<Task>(pl.tasks.size());
@@ -364,7 +395,7 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
         launch_shared_pass(pl.sg, dP, count, st, e0, e1);
         return;
     }
-    launch_pass(pl.bits, pl.cpl, dP, dT, static_cast<int>(pl.tasks.size()), st, e0, e1);
+    launch_pass(pl.bits, pl.cpl, dP, dT, pl.npass, st, e0, e1);
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }
 
@@ -396,6 +427,7 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
                             st));
     QIHT_HIP(hipMemcpyAsync(*dT, pl.tasks.data(), sizeof(Task) * pl.tasks.size(),
                             hipMemcpyHostToDevice, st));
+
     return QIHT_OK;
 }
 
