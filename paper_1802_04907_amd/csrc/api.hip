@@ -229,6 +229,7 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     set_error("");
     if (!phi || !out) return fail(QIHT_ERR_INVALID_ARG, "phi or out is NULL");
     if (m < 1 || n < 1) return fail(QIHT_ERR_INVALID_ARG, "need m >= 1 and n >= 1");
+    if (n > int64_t(65535) * 64) return fail(QIHT_ERR_UNSUPPORTED, "n above 4194240 columns");
     if (ld < n) return fail(QIHT_ERR_INVALID_ARG, "need ld >= n");
     if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
     if (!bits_ok_matrix(bits))

@@ -21,10 +21,11 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
             k0 += kWeylA;
             k1 += kWeylB;
         }
-        const uint32_t pa_hi = __umulhi(kMulA, c.x);
-        const uint32_t pa_lo = kMulA * c.x;
-        const uint32_t pb_hi = __umulhi(kMulB, c.z);
-        const uint32_t pb_lo = kMulB * c.z;
+        // full 32 x 32 -> 64 products (one v_mad_u64_u32 each)
+        const uint64_t pa = static_cast<uint64_t>(kMulA) * c.x;
+        const uint64_t pb = static_cast<uint64_t>(kMulB) * c.z;
+        const uint32_t pa_hi = static_cast<uint32_t>(pa >> 32), pa_lo = static_cast<uint32_t>(pa);
+        const uint32_t pb_hi = static_cast<uint32_t>(pb >> 32), pb_lo = static_cast<uint32_t>(pb);
         c = make_uint4(pb_hi ^ c.y ^ k0, pb_lo, pa_hi ^ c.w ^ k1, pa_lo);
     }
     return c;

@@ -10,6 +10,7 @@
 // bit for bit by any other IEEE implementation of the same rule.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "philox_dev.h"
 #include "qiht_internal.h"
@@ -95,10 +96,56 @@ __global__ __launch_bounds__(256) void k_absmax(const T* __restrict__ src,
     }
 }
 
+// FP32 rows whose length and stride are multiples of 4: 16-byte loads, four
+// in flight per thread (the max of |float| values is exact in FP32).
+__global__ __launch_bounds__(256) void k_absmax_f4(const float4* __restrict__ src, int64_t m,
+                                                   int64_t row4, int64_t ld4,
+                                                   unsigned long long* out, int* bad) {
+    float mx = 0.0f;
+    int nonfinite = 0;
+    const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y) {
+        const float4* row = src + i * ld4;
+        for (int64_t t0 = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t0 < row4;
+             t0 += 4 * step) {
+            float4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t t = t0 + u * step;
+                v[u] = t < row4 ? row[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float a[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (!isfinite(a[k])) nonfinite = 1;
+                    mx = fmaxf(mx, fabsf(a[k]));
+                }
+            }
+        }
+    }
+    __shared__ float sh[256];
+    __shared__ int shbad;
+    if (threadIdx.x == 0) shbad = 0;
+    __syncthreads();
+    if (nonfinite) shbad = 1;
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(static_cast<double>(sh[0]))));
+        if (shbad) atomicOr(bad, 1);
+    }
+}
+
 // One thread = one column j and one 16-byte chunk of that column (the codes
 // of RPC consecutive rows), for every realization.  Lanes of a wave take 64
 // consecutive columns, so the row-major source is read in coalesced rows.
-template <int BITS, typename T, int NC>
+template <int BITS, typename T, int NC, bool ALIGNED>
 __global__ __launch_bounds__(256) void k_quantize(
     const T* __restrict__ src, int64_t m, int64_t n, int64_t ld, int64_t rows,
     int64_t col_bytes, int64_t nchunks, double c, double K, uint32_t k0,
@@ -107,8 +154,11 @@ __global__ __launch_bounds__(256) void k_quantize(
     constexpr int RPC = (BITS == 32) ? 4 : 128 / BITS;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + lane;
-    const int64_t chunk = static_cast<int64_t>(blockIdx.y) * 4 + wave;
+    // blockIdx.x runs over chunk groups: neighbouring workgroups fill the
+    // neighbouring 64 bytes of the same 64 columns, so a cache line of codes
+    // is completed while it is still in L2
+    const int64_t j = static_cast<int64_t>(blockIdx.y) * 64 + lane;
+    const int64_t chunk = static_cast<int64_t>(blockIdx.x) * 4 + wave;
     if (j >= n || chunk >= nchunks) return;
     const int64_t i0 = chunk * RPC;
     const size_t off = static_cast<size_t>(j) * col_bytes + chunk * 16;
@@ -123,6 +173,35 @@ __global__ __launch_bounds__(256) void k_quantize(
         }
         *reinterpret_cast<float4*>(out0 + off) =
             make_float4(vals[0], vals[1], vals[2], vals[3]);
+    } else if (ALIGNED) {
+        // rows % 4 == 0: element j rows + i0 + q is word q % 4 of block
+        // (j rows + i0) / 4 + q / 4.  Every row of the chunk is loaded first
+        // (clamped; padding rows get code 0), then the Philox blocks.
+        constexpr int L = 1 << BITS;
+        T v[RPC];  // the input type: every value converts to FP64 exactly
+#pragma unroll
+        for (int q = 0; q < RPC; ++q)
+            v[q] = static_cast<T>(load_stacked<T, NC>(src, m, ld, min(i0 + q, rows - 1), j));
+        const uint64_t b0 = (static_cast<uint64_t>(j) * rows + i0) >> 2;
+        const int nlive = static_cast<int>(min<int64_t>(RPC, rows - i0));
+        for (int r = 0; r < R; ++r) {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int b = 0; b < RPC / 4; ++b) {
+                const uint64_t blk = b0 + b;
+                const uint4 u = philox10(make_uint4(static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
+                                                    0u, static_cast<uint32_t>(r)),
+                                         k0, k1);
+                const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int q = 4 * b + t;
+                    const uint32_t code = q < nlive ? quantize_one(static_cast<double>(v[q]), c, K, L, uu[t]) : 0u;
+                    w[(q * BITS) >> 5] |= code << ((q * BITS) & 31);
+                }
+            }
+            *reinterpret_cast<uint4*>((r == 0 ? out0 : out1) + off) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
     } else {
         constexpr int L = 1 << BITS;
         PhiloxStream s0{k0, k1, 0u, 0u};
@@ -296,11 +375,22 @@ qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
     d_bad = reinterpret_cast<int*>(d_max + 1);
     QIHT_HIP(hipMemsetAsync(d_max, 0, 16, st));
     const int64_t row_len = n * NC;
-    const int64_t gx = std::min<int64_t>((row_len + 1023) / 1024, 16);
-    const int64_t gy = std::min<int64_t>(m, std::max<int64_t>(1, 4096 / gx));
-    dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(gy));
-    hipLaunchKernelGGL((k_absmax<T, NC>), grid, dim3(256), 0, st,
-                       static_cast<const T*>(src), m, n, ld, d_max, d_bad);
+    bool vec = false;
+    if constexpr (std::is_same<T, float>::value)
+        vec = row_len % 4 == 0 && (ld * NC) % 4 == 0 && reinterpret_cast<uintptr_t>(src) % 16 == 0;
+    if (vec) {
+        const int64_t row4 = row_len / 4;
+        const int64_t gx = std::min<int64_t>((row4 + 1023) / 1024, 16);
+        const int64_t gy = std::min<int64_t>(m, std::max<int64_t>(1, 4096 / gx));
+        hipLaunchKernelGGL(k_absmax_f4, dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)), dim3(256), 0, st,
+                           static_cast<const float4*>(src), m, row4, ld * NC / 4, d_max, d_bad);
+    } else {
+        const int64_t gx = std::min<int64_t>((row_len + 1023) / 1024, 16);
+        const int64_t gy = std::min<int64_t>(m, std::max<int64_t>(1, 4096 / gx));
+        dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(gy));
+        hipLaunchKernelGGL((k_absmax<T, NC>), grid, dim3(256), 0, st,
+                           static_cast<const T*>(src), m, n, ld, d_max, d_bad);
+    }
     QIHT_HIP(hipGetLastError());
     unsigned long long h[2] = {0, 0};
     QIHT_HIP(hipMemcpyAsync(h, d_max, 16, hipMemcpyDeviceToHost, st));
@@ -320,14 +410,22 @@ void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
               uint64_t seed, double c, double K, qiht_qmatrix* q,
               hipStream_t st) {
     const int64_t nchunks = q->col_bytes / 16;
-    dim3 grid(static_cast<unsigned>((n + 63) / 64),
-              static_cast<unsigned>((nchunks + 3) / 4));
-    hipLaunchKernelGGL((k_quantize<BITS, T, NC>), grid, dim3(256), 0, st,
-                       static_cast<const T*>(src), m, n, ld, q->rows,
-                       q->col_bytes, nchunks, c, K,
-                       static_cast<uint32_t>(seed),
-                       static_cast<uint32_t>(seed >> 32), R, q->codes[0],
-                       q->codes[1]);
+    dim3 grid(static_cast<unsigned>((nchunks + 3) / 4),
+              static_cast<unsigned>((n + 63) / 64));  // n <= 65535 * 64 (checked by the caller)
+    if (q->rows % 4 == 0)
+        hipLaunchKernelGGL((k_quantize<BITS, T, NC, true>), grid, dim3(256), 0, st,
+                           static_cast<const T*>(src), m, n, ld, q->rows,
+                           q->col_bytes, nchunks, c, K,
+                           static_cast<uint32_t>(seed),
+                           static_cast<uint32_t>(seed >> 32), R, q->codes[0],
+                           q->codes[1]);
+    else
+        hipLaunchKernelGGL((k_quantize<BITS, T, NC, false>), grid, dim3(256), 0, st,
+                           static_cast<const T*>(src), m, n, ld, q->rows,
+                           q->col_bytes, nchunks, c, K,
+                           static_cast<uint32_t>(seed),
+                           static_cast<uint32_t>(seed >> 32), R, q->codes[0],
+                           q->codes[1]);
 }
 
 template <typename T, int NC>
