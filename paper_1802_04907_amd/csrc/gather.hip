@@ -85,10 +85,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const int p = blockIdx.y / NSET;
     const int set = blockIdx.y % NSET;
     const ProbDev& pd = P[p];
-    SolveState* st = pd.st;
-    if (st->done) return;
     const int wg = blockIdx.x;  // 16-byte row group
     if (wg >= pd.nwg) return;
+    // the stop flag is read alongside the first loads and checked once they
+    // are issued (every address stays valid after the solve has stopped)
+    const int done_now = pd.st->done;
 
     const int32_t* cols;
     int ncols;
@@ -139,6 +140,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             valid[u] = t < ncols;
             cidx[u] = static_cast<int>(ldg_u32(cols + min(t, ncols - 1)));
         }
+        if (done_now) return;  // uniform over the workgroup
         double wt[U];
         uint32_t wa[U], wb[U];
 #pragma unroll
@@ -175,6 +177,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
     }
 
+    if (done_now) return;  // (a workgroup whose lanes had no list entries)
     // ---- sum over the 16 slots of the wave (lane bits 2..5); lanes 0..3 hold it
     wsum = slot_sum(wsum);
 #pragma unroll

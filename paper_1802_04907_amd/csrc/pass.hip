@@ -179,7 +179,7 @@ struct PassLds {
 };
 
 template <int BITS, int CPL>
-__device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, PassLds& L) {
+__device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, PassLds& L, int done_now) {
     using D = QDig<BITS>;
     constexpr int RPC = 128 / BITS;  // rows per 16-byte chunk
     constexpr int ND = D::ND, H = D::H;
@@ -226,6 +226,9 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
     uint4 cur[NCI][CPL], nxt[NCI][CPL];
     load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv, tk.c1, off, cur);
     load_step<NCI, CPL>(pd.q1, pd.col_bytes, tk.c0 + wv + STEP, tk.c1, off, nxt);
+    // the stop flag was read alongside these loads (every address stays valid
+    // after the solve has stopped); uniform over the workgroup
+    if (done_now) return;
 
     const bool hist = pd.nslab == 1;
     const int wbase = tk.c0 >> 5;
@@ -279,12 +282,12 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
     if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
     t = tk.next;
     const ProbDev& pd = P[tk.p];
-    if (pd.st->done) continue;  // uniform over the workgroup
+    const int dn = pd.st->done;  // checked inside, once the first loads are issued
     switch (tk.cpl) {
-        case 1: pass_q_body<BITS, 1>(pd, tk, L); break;
-        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2>(pd, tk, L); break;
-        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4>(pd, tk, L); break;
-        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8>(pd, tk, L); break;
+        case 1: pass_q_body<BITS, 1>(pd, tk, L, dn); break;
+        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2>(pd, tk, L, dn); break;
+        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4>(pd, tk, L, dn); break;
+        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8>(pd, tk, L, dn); break;
     }
     }
 }
