@@ -178,12 +178,16 @@ struct PassLds {
     uint32_t lbm[kPassMaxCols / 32 + 2];
 };
 
-template <int BITS, int CPL>
+template <int BITS, int CPL, bool LONG>
 __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, PassLds& L, int done_now) {
     using D = QDig<BITS>;
     constexpr int RPC = 128 / BITS;  // rows per 16-byte chunk
     constexpr int ND = D::ND, H = D::H;
-    constexpr int NCI = (CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2;  // columns per step
+    // columns per step and wave: two when the codes stream from the Infinity
+    // Cache (more bytes in flight per wave, two waves per SIMD); one for long
+    // streams from HBM (fewer registers: three waves per SIMD hide more of
+    // the memory latency)
+    constexpr int NCI = LONG ? 1 : ((CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2);
     constexpr int STEP = 4 * NCI;
     uint32_t* lx = L.lx;
     uint32_t* lbm = L.lbm;
@@ -273,8 +277,11 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
 // spans its `next` links name; each span carries the chunks per lane of its
 // problem (small columns would leave most lanes idle at the batch's largest
 // CPL), the body is picked per span.
-template <int BITS, int CMAX>
-__global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
+// LONG: three workgroups per CU (except where the registers of 8-bit codes
+// at 8 chunks per lane would spill), for code streams larger than the
+// Infinity Cache.
+template <int BITS, int CMAX, bool LONG>
+__global__ __launch_bounds__(kPassThreads, (LONG && !(BITS == 8 && CMAX == 8)) ? 3 : 2) void k_fullpass_q(
     const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
     __shared__ PassLds L;
     for (int t = blockIdx.x; t >= 0;) {
@@ -284,10 +291,10 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass_q(
     const ProbDev& pd = P[tk.p];
     const int dn = pd.st->done;  // checked inside, once the first loads are issued
     switch (tk.cpl) {
-        case 1: pass_q_body<BITS, 1>(pd, tk, L, dn); break;
-        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2>(pd, tk, L, dn); break;
-        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4>(pd, tk, L, dn); break;
-        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8>(pd, tk, L, dn); break;
+        case 1: pass_q_body<BITS, 1, LONG>(pd, tk, L, dn); break;
+        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2, LONG>(pd, tk, L, dn); break;
+        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4, LONG>(pd, tk, L, dn); break;
+        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8, LONG>(pd, tk, L, dn); break;
     }
     }
 }
@@ -426,7 +433,7 @@ void launch_k(K kern, int nwg, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, c
         hipLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, P, T);
 }
 
-template <int BITS>
+template <int BITS, bool LONG>
 void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
     switch (cpl) {
@@ -436,7 +443,7 @@ void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_
             if constexpr (BITS == 32)                                                       \
                 launch_k(k_fullpass<BITS, C>, nwg, st, ev0, ev1, P, T);                     \
             else                                                                            \
-                launch_k(k_fullpass_q<BITS, C>, nwg, st, ev0, ev1, P, T);                   \
+                launch_k(k_fullpass_q<BITS, C, LONG>, nwg, st, ev0, ev1, P, T);                \
         }                                                                                   \
         break;
         QIHT_PASS_CASE(1)
@@ -449,7 +456,7 @@ void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_
     }
 }
 
-template <int BITS>
+template <int BITS, bool LONG>
 int pass_blocks_b(int cpl) {
     int nb = 0;
     hipError_t err = hipSuccess;
@@ -461,7 +468,7 @@ int pass_blocks_b(int cpl) {
                 err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fullpass<BITS, C>,    \
                                                                    kPassThreads, 0);            \
             else                                                                                \
-                err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fullpass_q<BITS, C>,  \
+                err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fullpass_q<BITS, C, LONG>, \
                                                                    kPassThreads, 0);            \
         }                                                                                       \
         break;
@@ -478,30 +485,34 @@ int pass_blocks_b(int cpl) {
 
 }  // namespace
 
-int pass_slots(int bits, int cpl) {
+int pass_slots(int bits, int cpl, bool long_stream) {
     int dev = 0, cus = 0, nb = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     switch (bits) {
-        case 1: nb = pass_blocks_b<1>(cpl); break;
-        case 2: nb = pass_blocks_b<2>(cpl); break;
-        case 4: nb = pass_blocks_b<4>(cpl); break;
-        case 8: nb = pass_blocks_b<8>(cpl); break;
-        default: nb = pass_blocks_b<32>(cpl); break;
+        case 1: nb = long_stream ? pass_blocks_b<1, true>(cpl) : pass_blocks_b<1, false>(cpl); break;
+        case 2: nb = long_stream ? pass_blocks_b<2, true>(cpl) : pass_blocks_b<2, false>(cpl); break;
+        case 4: nb = long_stream ? pass_blocks_b<4, true>(cpl) : pass_blocks_b<4, false>(cpl); break;
+        case 8: nb = long_stream ? pass_blocks_b<8, true>(cpl) : pass_blocks_b<8, false>(cpl); break;
+        default: nb = pass_blocks_b<32, false>(cpl); break;
     }
     return nb * cus;
 }
 
-void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
-                 hipEvent_t ev0, hipEvent_t ev1) {
+void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg,
+                 hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+#define QIHT_LP(B)                                                                   \
+    (long_stream ? launch_pass_b<B, true>(cpl, P, T, nwg, st, ev0, ev1)              \
+                 : launch_pass_b<B, false>(cpl, P, T, nwg, st, ev0, ev1))
     switch (bits) {
-        case 1: launch_pass_b<1>(cpl, P, T, nwg, st, ev0, ev1); break;
-        case 2: launch_pass_b<2>(cpl, P, T, nwg, st, ev0, ev1); break;
-        case 4: launch_pass_b<4>(cpl, P, T, nwg, st, ev0, ev1); break;
-        case 8: launch_pass_b<8>(cpl, P, T, nwg, st, ev0, ev1); break;
-        default: launch_pass_b<32>(cpl, P, T, nwg, st, ev0, ev1); break;
+        case 1: QIHT_LP(1); break;
+        case 2: QIHT_LP(2); break;
+        case 4: QIHT_LP(4); break;
+        case 8: QIHT_LP(8); break;
+        default: launch_pass_b<32, false>(cpl, P, T, nwg, st, ev0, ev1); break;
     }
+#undef QIHT_LP
 }
 
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st) {

@@ -512,9 +512,12 @@ int shared_ksplit(int bits, int n, int count, int rows_pad);
 void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipStream_t st,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// Bytes of the last-level Infinity Cache (MALL) that code streams up to
+// this size are assumed to stay in from one pass to the next.
+constexpr double kInfinityCacheBytes = 200.0 * 1024 * 1024;
 // Workgroups of the full pass that the device holds at once (0 if unknown).
-int pass_slots(int bits, int cpl);
-void launch_pass(int bits, int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
+int pass_slots(int bits, int cpl, bool long_stream);
+void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1);
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);

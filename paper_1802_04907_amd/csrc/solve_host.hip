@@ -97,6 +97,7 @@ struct Plan {
     std::vector<Task> tasks;
     int bits = 0, cpl = 1, maxwg = 1;
     bool any_slab = false;
+    bool long_stream = false;  // codes of one pass larger than the Infinity Cache
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0, done_off = 0;
     int npass = 0;  // full-pass workgroups
@@ -210,10 +211,15 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     // workgroup gets the same number of code bytes, a workgroup's spans
     // running on across problem boundaries.  Workgroup w starts at span w;
     // its further spans follow the `next` links (after the first spans).
-    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl));
     double total = 0.0;
     for (int i = 0; i < count; ++i)
         total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
+    // Codes that stay in the 256 MiB Infinity Cache between passes are read
+    // at cache latency: two waves per SIMD with two columns in flight each
+    // do best there.  Longer streams come from HBM, where three waves per
+    // SIMD with one column each hide more of the latency.
+    pl.long_stream = total > kInfinityCacheBytes;
+    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream));
     const double budget = std::max(1.0, std::ceil(total / slots));
     std::vector<std::vector<Task>> wgs(1);
     double cur = 0.0;
@@ -395,7 +401,7 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
         launch_shared_pass(pl.sg, dP, count, st, e0, e1);
         return;
     }
-    launch_pass(pl.bits, pl.cpl, dP, dT, pl.npass, st, e0, e1);
+    launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, st, e0, e1);
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }
 
