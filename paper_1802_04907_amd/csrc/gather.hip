@@ -74,6 +74,17 @@ __device__ void digitize_chunk(double r, int wg, const ProbDev& pd) {
     }
 }
 
+// Row group of workgroup x in grid row y.  Workgroups are handed to the
+// eight XCDs in turn (linear id mod 8; the grid's width is a multiple of
+// 64), and each XCD has its own L2: the eight 16-byte row groups of one
+// 128-byte line are given to workgroups on the same XCD, so the line is
+// fetched into one L2 only, and the lines rotate over the XCDs with the
+// line index and the grid row.
+__device__ __forceinline__ int xcd_row_group(int x, int y) {
+    const int c = x & 7, i = (x >> 3) & 7;
+    return (x & ~63) + 8 * ((c - y) & 7) + i;
+}
+
 template <int BITS, int MODE>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __restrict__ P,
                                                            SolveArgs a, int zero_x) {
@@ -85,7 +96,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const int p = blockIdx.y / NSET;
     const int set = blockIdx.y % NSET;
     const ProbDev& pd = P[p];
-    const int wg = blockIdx.x;  // 16-byte row group
+    const int wg = xcd_row_group(blockIdx.x, blockIdx.y);  // 16-byte row group
     if (wg >= pd.nwg) return;
     // the stop flag is read alongside the first loads and checked once they
     // are issued (every address stays valid after the solve has stopped)
@@ -414,7 +425,7 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
         }
         return;
     }
-    dim3 grid(maxwg, count * nset);
+    dim3 grid((maxwg + 63) / 64 * 64, count * nset);
     switch (bits) {
         case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
         case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;

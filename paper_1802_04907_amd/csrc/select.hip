@@ -52,6 +52,7 @@ struct SelShared {
         } b;
     } u;
     uint32_t scan[16];
+    uint32_t flg[16];
     uint32_t bin, krem, total, nc;
     int changed, bad, full;
     double red[16];
@@ -114,12 +115,7 @@ __device__ void find_bin_w0(const uint32_t* hist, uint32_t krem, SelShared& S) {
             h[i] = hist[top - i];
             c += h[i];
         }
-        uint32_t x = c;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
+        const uint32_t x = wave_incl_scan(c);
         uint32_t run = x - c;
         if (krem > 0 && run < krem && krem <= x) {
             bool found = false;
@@ -257,6 +253,46 @@ __device__ void block_sum3(double& a, double& b, double& c, SelShared& S) {
     __syncthreads();
 }
 
+// Three block sums (per wave, then over the waves in wave order, as
+// block_sum3), the exclusive prefix of v in thread order with its total,
+// and the number of threads with f set, over one barrier.  Every thread
+// gets the results; S.red3, S.scan and S.flg must not be read again before
+// a later barrier (their next writer follows at least one more barrier).
+struct BlockAgg {
+    double a, b, c;
+    uint32_t before, total, nf;
+};
+
+__device__ BlockAgg block_sums_scan(double a, double b, double c, uint32_t v, bool f, SelShared& S) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const uint32_t x = wave_incl_scan(v);
+    const uint32_t nf = static_cast<uint32_t>(__popcll(__ballot(f)));
+    if (lane == 63) {
+        S.red3[0][wv] = a;
+        S.red3[1][wv] = b;
+        S.red3[2][wv] = c;
+        S.scan[wv] = x;
+        S.flg[wv] = nf;
+    }
+    __syncthreads();
+    BlockAgg r{0.0, 0.0, 0.0, 0u, 0u, 0u};
+#pragma unroll
+    for (int w = 0; w < kSelectThreads / 64; ++w) {
+        r.a += S.red3[0][w];
+        r.b += S.red3[1][w];
+        r.c += S.red3[2][w];
+        const uint32_t t = S.scan[w];
+        r.before += w < wv ? t : 0u;
+        r.total += t;
+        r.nf += S.flg[w];
+    }
+    r.before += x - v;
+    return r;
+}
+
 // Bitmap words scanned by word_prefix.
 enum { BM_TIE = 0, BM_NEW = 1, BM_UNION = 2 };
 
@@ -282,12 +318,7 @@ __device__ uint32_t word_prefix(int words, SelShared& S) {
             const int w = w0 + i;
             if (i < wpl && w < words) c += static_cast<uint32_t>(__popc(bm_word<WHICH>(S, w)));
         }
-        uint32_t x = c;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
+        const uint32_t x = wave_incl_scan(c);
         uint32_t pos = x - c;
 #pragma unroll
         for (int i = 0; i < MAXW; ++i) {
@@ -416,27 +447,23 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     if (tid == 0) {
         S.changed = 0;
         S.bad = 0;
-        S.full = 0;
     }
-    // ---- the step
+    // ---- the step, and this thread's place in the candidate list
+    const BlockAgg ag = block_sums_scan(gg, uv, uu, mycnt, bad_cnt != 0, S);
     double mu = mu_in;
     if (from_partials) {
-        block_sum3(gg, uv, uu, S);
-        double den = uv;
-        if (!(den > 0.0) || !isfinite(den)) den = uu;
-        if (!(gg > 0.0) || !(den > 0.0) || !isfinite(gg / den)) return false;
-        *mu0_out = gg / den;
-        mu = shrunk_mu(gg / den, shrink, k);
+        double den = ag.b;
+        if (!(den > 0.0) || !isfinite(den)) den = ag.c;
+        if (!(ag.a > 0.0) || !(den > 0.0) || !isfinite(ag.a / den)) return false;
+        *mu0_out = ag.a / den;
+        mu = shrunk_mu(ag.a / den, shrink, k);
     }
     const float muf = static_cast<float>(mu);
-    uint32_t total = 0;
-    const uint32_t obase = block_excl_scan<kSelectThreads>(mycnt, S.scan, &total);
-    if (bad_cnt) S.full = 1;
-    __syncthreads();
-    const int nc = static_cast<int>(total);
+    const uint32_t obase = ag.before;
+    const int nc = static_cast<int>(ag.total);
     // (the list holds at least s entries unless the counts are inconsistent,
     // which the full path then handles)
-    const bool fast = !S.full && nc <= kCandCap && nc >= s;
+    const bool fast = ag.nf == 0 && nc <= kCandCap && nc >= s;
     int32_t* out_sup = (MODE == SEL_INIT) ? pd.sup : pd.csup + static_cast<size_t>(slot) * s;
     float* out_val = pd.cval + static_cast<size_t>(slot) * s;
     int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
@@ -577,9 +604,11 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         }
     }
     // ---- outputs: selection and union positions in index order (one scan,
-    // selected count in the low half, union count in the high half)
+    // selected count in the low half, union count in the high half), taken
+    // together with |x' - x|^2, |x'|^2 and the support-change flag
     uint32_t v = 0;
     int changed = 0;
+    double dx2 = 0.0, xn2 = 0.0;
 #pragma unroll
     for (int q = 0; q < MPT; ++q) {
         const int m = MPT * tid + q;
@@ -587,12 +616,16 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             const bool on = (S.u.f.midx[m] >> 31) != 0u;
             v += (sel[q] ? 1u : 0u) + ((sel[q] || on) ? 0x10000u : 0u);
             if (on != sel[q]) changed = 1;
+            if (MODE == SEL_STEP && (sel[q] || on)) {
+                const double xo = static_cast<double>(S.u.f.mxo[m]);
+                const double xn = sel[q] ? static_cast<double>(S.u.f.mval[m]) : 0.0;
+                dx2 += (xn - xo) * (xn - xo);
+                xn2 += xn * xn;
+            }
         }
     }
-    uint32_t tot = 0;
-    uint32_t pos = block_excl_scan<kSelectThreads>(v, S.scan, &tot);
-    if (changed) S.changed = 1;
-    double dx2 = 0.0, xn2 = 0.0, zero = 0.0;
+    const BlockAgg out = block_sums_scan(dx2, xn2, 0.0, v, changed != 0, S);
+    uint32_t pos = out.before;
 #pragma unroll
     for (int q = 0; q < MPT; ++q) {
         const int m = MPT * tid + q;
@@ -605,16 +638,11 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
                 out_sup[ps] = j;
                 if (MODE == SEL_STEP) out_val[ps] = S.u.f.mval[m];
             }
-            if (MODE == SEL_STEP && (sel[q] || on)) {
+            if (MODE == SEL_STEP && (sel[q] || on) && pu < static_cast<uint32_t>(2 * s)) {
                 const float xo = S.u.f.mxo[m];
                 const float xn = sel[q] ? S.u.f.mval[m] : 0.0f;
-                const double d = static_cast<double>(xn) - static_cast<double>(xo);
-                if (pu < static_cast<uint32_t>(2 * s)) {
-                    dlist[pu] = j;
-                    dw[pu] = d;
-                }
-                dx2 += d * d;
-                xn2 += static_cast<double>(xn) * static_cast<double>(xn);
+                dlist[pu] = j;
+                dw[pu] = static_cast<double>(xn) - static_cast<double>(xo);
             }
             pos += (sel[q] ? 1u : 0u) + ((sel[q] || on) ? 0x10000u : 0u);
         }
@@ -637,16 +665,15 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         __syncthreads();
         return true;
     }
-    block_sum3(dx2, xn2, zero, S);
     if (tid == 0) {
         CandMeta mt;
-        mt.changed = S.changed;
-        mt.dcount = static_cast<int32_t>(tot >> 16);
+        mt.changed = out.nf > 0 ? 1 : 0;
+        mt.dcount = static_cast<int32_t>(out.total >> 16);
         mt.k = k;
         mt.pad = 0;
         mt.mu = mu;
-        mt.dx2 = dx2;
-        mt.xn2 = xn2;
+        mt.dx2 = out.a;
+        mt.xn2 = out.b;
         mt.omega = 0.0;
         pd.meta[slot] = mt;
     }

@@ -251,6 +251,20 @@ __device__ __forceinline__ double lane0(double v) {
                             __builtin_amdgcn_readlane(__double2loint(v), 0));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, in DPP moves only:
+// shifts by 1, 2, 4, 8 lanes within each row of 16 (lanes shifted in from
+// outside the row add 0), then lane 15's total added to rows 1 and 3 and
+// lane 31's to rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x111, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x112, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x114, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x118, 0xf, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x142, 0xa, 0xf, false));
+    x += static_cast<uint32_t>(__builtin_amdgcn_update_dpp(0, static_cast<int>(x), 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // Sum over the 16 lanes of a row that share l mod 4, then over the four
 // rows: lanes 0..3 end with the totals of their residues mod 4.
 template <typename T>
@@ -289,12 +303,7 @@ template <int NT>
 __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t x = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
+    const uint32_t x = wave_incl_scan(v);
     __syncthreads();
     if (lane == 63) sh[wv] = x;
     __syncthreads();
@@ -367,12 +376,7 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
         uint32_t c = 0;
 #pragma unroll
         for (int i = 0; i < 32; ++i) c += pre.h[i];
-        uint32_t x = c;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
+        const uint32_t x = wave_incl_scan(c);
         uint32_t run = x - c;
         const uint32_t want = static_cast<uint32_t>(s);
         const uint64_t hit = __ballot(run < want && want <= x);
