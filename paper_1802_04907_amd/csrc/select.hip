@@ -417,23 +417,29 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             uu += pd.part_mu[2 * b + 1];
         }
     }
-    const int cpw = (nw + kSelectThreads - 1) / kSelectThreads;
-    const int w0 = tid * cpw, w1 = min(nw, w0 + cpw);
+    // Few index blocks: G = 2 or 4 threads share one, thread gq of the group
+    // taking its entries gq, gq + G, ... (so PRE G of them arrive with the
+    // first loads); many: each thread takes cpw whole blocks.
+    const int G = 4 * nw <= kSelectThreads ? 4 : (2 * nw <= kSelectThreads ? 2 : 1);
+    const int cpw = G > 1 ? 1 : (nw + kSelectThreads - 1) / kSelectThreads;
+    const int gq = tid % G;
+    const int w0 = (tid / G) * cpw, w1 = min(nw, w0 + cpw);
     uint32_t pidx[PRE];
     float2 pgx[PRE];
     const int lo0 = w0 * per, len0 = w0 < w1 ? min(n, lo0 + per) - lo0 : 0;
 #pragma unroll
     for (int i = 0; i < PRE; ++i) {
-        pidx[i] = i < len0 ? pd.cidx[lo0 + i] : 0u;
-        pgx[i] = i < len0 ? pd.cgx[lo0 + i] : make_float2(0.f, 0.f);
+        const int e = gq + G * i;
+        pidx[i] = e < len0 ? pd.cidx[lo0 + e] : 0u;
+        pgx[i] = e < len0 ? pd.cgx[lo0 + e] : make_float2(0.f, 0.f);
     }
-    uint32_t mycnt = 0;
+    uint32_t mycnt = 0;  // (counted by the group's first thread)
     int c0 = 0, bad_cnt = 0;
     for (int w = w0; w < w1; ++w) {
         const int c = pd.ccnt[w];
         if (w == w0) c0 = c;
         if (c < 0) bad_cnt = 1;
-        else mycnt += static_cast<uint32_t>(c);
+        else if (gq == 0) mycnt += static_cast<uint32_t>(c);
     }
     if (done_now) {  // uniform: every thread read the same flag
         *skipped = true;
@@ -459,7 +465,8 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         mu = shrunk_mu(ag.a / den, shrink, k);
     }
     const float muf = static_cast<float>(mu);
-    const uint32_t obase = ag.before;
+    // the group's first thread counted the block: it starts c0 before the others
+    const uint32_t obase = ag.before - (gq > 0 ? static_cast<uint32_t>(max(c0, 0)) : 0u);
     const int nc = static_cast<int>(ag.total);
     // (the list holds at least s entries unless the counts are inconsistent,
     // which the full path then handles)
@@ -538,35 +545,36 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             S.u.f.mval[pos] = a;
             S.u.f.mxo[pos] = gx.y;
         };
-        // a block's entries [i0, c) in batches whose loads are issued
-        // together (clamped into the block, the extra ones not stored)
-        auto put_block = [&](uint32_t at, int lo, int i0, int c) {
+        // a block's entries i0, i0 + step, ... below c in batches whose
+        // loads are issued together (clamped into the block, the extra ones
+        // not stored)
+        auto put_block = [&](uint32_t at, int lo, int i0, int c, int step) {
             constexpr int B = 4;
-            for (int ib = i0; ib < c; ib += B) {
+            for (int ib = i0; ib < c; ib += B * step) {
                 uint32_t ti[B];
                 float2 tg[B];
 #pragma unroll
                 for (int q = 0; q < B; ++q) {
-                    const int i = min(ib + q, c - 1);
+                    const int i = min(ib + q * step, c - 1);
                     ti[q] = pd.cidx[lo + i];
                     tg[q] = pd.cgx[lo + i];
                 }
 #pragma unroll
                 for (int q = 0; q < B; ++q)
-                    if (ib + q < c) put(at + ib + q, ti[q], tg[q]);
+                    if (ib + q * step < c) put(at + ib + q * step, ti[q], tg[q]);
             }
         };
         uint32_t pos = obase;
         if (w0 < w1) {
 #pragma unroll
-            for (int q = 0; q < PRE; ++q)
-                if (q < c0) put(pos + q, pidx[q], pgx[q]);
-            put_block(pos, lo0, PRE, c0);
+            for (int i = 0; i < PRE; ++i)
+                if (gq + G * i < c0) put(pos + gq + G * i, pidx[i], pgx[i]);
+            put_block(pos, lo0, gq + G * PRE, c0, G);
             pos += static_cast<uint32_t>(max(c0, 0));
         }
-        for (int w = w0 + 1; w < w1; ++w) {
+        for (int w = w0 + 1; w < w1; ++w) {  // (G = 1 only)
             const int c = pd.ccnt[w];
-            put_block(pos, w * per, 0, c);
+            put_block(pos, w * per, 0, c, 1);
             pos += static_cast<uint32_t>(max(c, 0));
         }
     }
