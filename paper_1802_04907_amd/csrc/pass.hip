@@ -184,10 +184,11 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
     constexpr int RPC = 128 / BITS;  // rows per 16-byte chunk
     constexpr int ND = D::ND, H = D::H;
     // columns per step and wave: two when the codes stream from the Infinity
-    // Cache (more bytes in flight per wave, two waves per SIMD); one for long
-    // streams from HBM (fewer registers: three waves per SIMD hide more of
-    // the memory latency)
-    constexpr int NCI = LONG ? 1 : ((CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2);
+    // Cache (more bytes in flight per wave, two waves per SIMD); for long
+    // streams from HBM (three waves per SIMD) four, two or one, so that every
+    // wave keeps about 4 KB of a step in flight whatever the column height
+    constexpr int NCI = LONG ? (CPL == 1 ? 4 : (CPL == 2 ? 2 : 1))
+                             : ((CPL * 4 * H * ND >= 96 && BITS == 8) ? 1 : 2);
     constexpr int STEP = 4 * NCI;
     uint32_t* lx = L.lx;
     uint32_t* lbm = L.lbm;
@@ -293,6 +294,7 @@ __global__ __launch_bounds__(kPassThreads, (LONG && !(BITS == 8 && CMAX == 8)) ?
     switch (tk.cpl) {
         case 1: pass_q_body<BITS, 1, LONG>(pd, tk, L, dn); break;
         case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2, LONG>(pd, tk, L, dn); break;
+        case 3: if constexpr (CMAX >= 4) pass_q_body<BITS, 3, LONG>(pd, tk, L, dn); break;
         case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4, LONG>(pd, tk, L, dn); break;
         default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8, LONG>(pd, tk, L, dn); break;
     }

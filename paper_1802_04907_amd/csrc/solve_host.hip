@@ -66,14 +66,22 @@ __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
 }
 
 // Chunks per lane of a full-pass row slab: enough to cover the column, at
-// most 128 residual rows per lane (BITS chunks; 16 for FP32).
+// most 128 residual rows per lane (BITS chunks; 16 for FP32).  A power of
+// two, or 3 for packed codes whose columns hold 129 .. 192 chunks (a lane
+// past the column's end idles through every column: 3 per lane leaves a
+// quarter of them idle where 4 would leave up to half).
 int pass_cpl(int bits, int64_t col_bytes) {
     const int64_t chunks = col_bytes / 16;
     const int maxc = bits == 32 ? 16 : bits;
     int c = 1;
     while (c < maxc && static_cast<int64_t>(c) * 64 < chunks) c *= 2;
+    if (c == 4 && bits <= 8 && chunks <= 3 * 64) c = 3;
     return c;
 }
+
+// The kernel instance a batch's largest chunks per lane runs in (a power
+// of two: its spans switch down to their own count).
+int pass_cmax(int cpl) { return cpl == 3 ? 4 : cpl; }
 
 struct Carver {
     size_t off = 0;
@@ -125,7 +133,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
     // the kernel is built for the largest column; each problem's row slabs use
     // its own chunks per lane (a task carries them)
-    pl.cpl = pass_cpl(pl.bits, max_cb);
+    pl.cpl = pass_cmax(pass_cpl(pl.bits, max_cb));
     Carver cv;
     pl.lay.resize(count);
     pl.host.resize(count);

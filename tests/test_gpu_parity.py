@@ -163,6 +163,8 @@ GRAD_CASES = [
     (777, 901, 12, 1, False),
     (5000, 1200, 20, 32, False),    # two FP32 slabs
     (4500, 1300, 25, 4, True),      # complex: 9000 stacked rows, two slabs
+    (5000, 1100, 30, 4, False),     # 157 chunks a column: three per lane, ragged
+    (2500, 900, 20, 8, False),      # 157 chunks a column: three per lane, ragged
 ]
 
 
@@ -286,6 +288,24 @@ def test_batched_uneven_matches_oracle():
     for p, (x, sup, info) in zip(probs, res):
         q1, q2, yh = _oracle_mats(p, 4)
         ref = niht.qiht_solve(q1, q2, yh, p.s, max_iters=300, tol=1e-7)
+        np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
+        err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        say(f"  batch m={p.m} err {err:.1e} {info}")
+        assert err <= 1e-4
+
+
+def test_batched_mixed_chunks_per_lane_matches_oracle():
+    # columns of 22, 79, 157 and 219 chunks: the batch's spans run with one,
+    # two, three and four chunks per lane in one launch
+    probs = [workloads.gaussian(m, 640, 12, 1e-3, seed=m) for m in (700, 2500, 5000, 7000)]
+    gpu = []
+    for p in probs:
+        q, yhat = _gpu_problem(p, 4)
+        gpu.append((q, yhat, p.s))
+    res = qiht.niht_solve_batched(gpu, max_iters=100, tol=1e-7)
+    for p, (x, sup, info) in zip(probs, res):
+        q1, q2, yh = _oracle_mats(p, 4)
+        ref = niht.qiht_solve(q1, q2, yh, p.s, max_iters=100, tol=1e-7)
         np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
         err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
         say(f"  batch m={p.m} err {err:.1e} {info}")
