@@ -34,7 +34,7 @@ PEAK_HBM_GBPS = 8000.0
 NRHS, S5, ITERS5 = 256, 256, 30
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
 METRIC = "NIHT iterations/s + HBM GB/s, b=8/4/2-bit vs FP32 at equal recovery error"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fullpass_traffic_config2.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fullpass_traffic_gaussian_8192x32768_4bit.md")
 PASS_SOURCE = os.path.join(ROOT, "paper_1802_04907_amd", "csrc", "pass.hip")
 
 
@@ -382,7 +382,7 @@ def main():
         print(json.dumps(shared_bench(qiht, torch, dev, reps=1, only=args.shared_only)))
         return
     log("generating workload ...")
-    p = workloads.config2(SEED)
+    p = workloads.gaussian_8192x32768(SEED)
     phi_d = torch.from_numpy(p.phi).to(dev)
     y_d = torch.from_numpy(p.y).to(dev)
     torch.cuda.synchronize()

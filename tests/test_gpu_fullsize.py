@@ -31,7 +31,7 @@ def say(*a):
 @pytest.fixture(scope="module")
 def big():
     say("generating the 8192 x 32768 workload")
-    p = workloads.config2(0)
+    p = workloads.gaussian_8192x32768(0)
     phi = torch.from_numpy(p.phi).to(DEV)
     y = torch.from_numpy(p.y).to(DEV)
     q = qiht.quantize_matrix(phi, BITS, 2, p.seed)

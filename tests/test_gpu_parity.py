@@ -217,9 +217,9 @@ def _compare_solve(p, bits, max_iters=300, tol=1e-8, mu_mode=0, realizations=2,
     return x, sup, info, ref
 
 
-def test_solve_config1():
-    say("solve config1")
-    p = workloads.config1(0)
+def test_solve_gaussian_256x1024():
+    say("solve 256 x 1024")
+    p = workloads.gaussian_256x1024(0)
     _compare_solve(p, 8, 300, 1e-8)
 
 
@@ -242,10 +242,10 @@ def test_solve_complex_interferometry():
     _compare_solve(p, 4, 300, 1e-7)
 
 
-def test_teacher_forced_iterations_config1():
+def test_teacher_forced_iterations_256x1024():
     """One GPU iteration at a time (warm start), each checked against the
     oracle's iteration from the very same state."""
-    p = workloads.config1(0)
+    p = workloads.gaussian_256x1024(0)
     q, yhat = _gpu_problem(p, 8)
     q1, q2, yh = _oracle_mats(p, 8)
     x = np.zeros(p.n)

@@ -67,7 +67,7 @@ def test_refit_complex_is_stacked_real():
 
 @pytest.mark.parametrize("bits", [1, 2, 4, 8, 32])
 def test_refit_codes_match_lstsq_on_q1(bits):
-    p = workloads.config1(0)
+    p = workloads.gaussian_256x1024(0)
     q = qiht.quantize_matrix(_t(p.phi), bits, 2, p.seed)
     c1, s1 = qz.quantize_matrix(p.phi, bits, p.seed, 0)
     q1 = c1 if bits == 32 else qz.dequantize(c1, s1, bits)
@@ -80,7 +80,7 @@ def test_refit_codes_match_lstsq_on_q1(bits):
 
 
 def test_solve_with_refit():
-    p = workloads.config1(0)
+    p = workloads.gaussian_256x1024(0)
     q = qiht.quantize_matrix(_t(p.phi), 8, 2, p.seed)
     yh, _, _ = qiht.quantize_vector(_t(p.y), 8, p.seed)
     x0, sup0, _ = qiht.niht_solve(q, yh, p.s, max_iters=300, tol=1e-8)
@@ -108,7 +108,7 @@ def test_refit_rank_deficient_is_numeric_error():
 
 def test_refit_fullsize_support():
     """8192 x 32768 FP32 Gaussian, s = 512: the shape the benchmark solves."""
-    p = workloads.config2(0)
+    p = workloads.gaussian_8192x32768(0)
     sup = p.support.astype(np.int32)
     cols = p.phi[:, sup].astype(np.float64)  # the oracle on the support columns only
     want = np.zeros(p.phi.shape[1])

@@ -279,11 +279,11 @@ def test_refit_noiseless_exact():
     np.testing.assert_allclose(z, x, atol=1e-12)
 
 
-def test_qiht_config1_quality():
+def test_qiht_256x1024_quality():
     # Config-1 recipe: the quantized solve recovers the true support; the
     # 8-bit error floor is small (Sec. IV-A: >= 5 bits is close to NIHT).
     import workloads
-    p = workloads.config1(0)
+    p = workloads.gaussian_256x1024(0)
     q1 = qz.dequantized_matrix(p.phi, 8, p.seed, 0)
     q2 = qz.dequantized_matrix(p.phi, 8, p.seed, 1)
     yh = qz.dequantized_vector(p.y, 8, p.seed)

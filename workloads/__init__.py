@@ -49,7 +49,7 @@ class Problem:
 
 def gaussian(m, n, s, sigma_e=1e-3, seed=0, dtype=np.float64, equal=False,
              qseed=None):
-    """Real Gaussian instance (configs 1, 2 and the synthetic sweep)."""
+    """Real Gaussian instance: Phi m x n N(0, 1/m), an s-sparse signal, noise sigma_e."""
     rng = np.random.default_rng(seed)
     if np.dtype(dtype) == np.float32:
         phi = rng.standard_normal((m, n), dtype=np.float32)
@@ -77,19 +77,20 @@ def _matvec(phi, x):
     return out
 
 
-def config1(seed=0):
+def gaussian_256x1024(seed=0):
     """Phi 256 x 1024 FP64 N(0, 1/256), s = 16, sigma_e = 1e-3."""
     return gaussian(256, 1024, 16, 1e-3, seed, np.float64)
 
 
-def config2(seed=0, m=8192, n=32768, s=512):
+def gaussian_8192x32768(seed=0, m=8192, n=32768, s=512):
     """Phi 8192 x 32768 FP32 N(0, 1/8192), s = 512, sigma_e = 1e-3."""
     return gaussian(m, n, s, 1e-3, seed, np.float32)
 
 
 def interferometry(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0,
                    dtype=np.complex64):
-    """Fourier-sampled complex instance (config 3 at full size)."""
+    """Fourier-sampled complex instance: n_vis visibilities of a side x side
+    sky image (32640 x 16384 at the defaults), s point sources."""
     rng = np.random.default_rng(seed)
     rad = 0.5 * np.sqrt(rng.random(n_vis))
     th = 2.0 * np.pi * rng.random(n_vis)
@@ -120,7 +121,8 @@ def interferometry(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0,
 
 def batch_uneven(count=96, m_lo=1024, m_hi=8192, seed=0, sigma_e=1e-3,
                  dtype=np.float32):
-    """Config 4 recipe: uneven independent Gaussian problems."""
+    """Uneven independent Gaussian problems: m uniform in [m_lo, m_hi],
+    n = 4m, s = m/16."""
     master = np.random.default_rng(seed)
     ms = master.integers(m_lo, m_hi + 1, size=count)
     probs = []
@@ -134,7 +136,7 @@ def batch_uneven(count=96, m_lo=1024, m_hi=8192, seed=0, sigma_e=1e-3,
 
 def shared_phi(m=8192, n=32768, nrhs=256, s=256, sigma_e=1e-3, seed=0,
                dtype=np.float32, equal=False):
-    """Config 5 recipe: one Gaussian Phi, nrhs sparse right-hand sides.
+    """One Gaussian Phi shared by nrhs sparse right-hand sides.
 
     ``s`` is the sparsity of every signal, or a sequence of nrhs sparsities;
     ``equal`` sets every nonzero to 1 (no draw) instead of N(0, 1).
