@@ -12,6 +12,10 @@
 // row's sum has one fixed order and results are bitwise reproducible.  No
 // workgroup waits on another: the per-workgroup partial dot products of
 // G_MU and G_OMEGA are finished, in workgroup order, by the next kernel.
+// G_R after the first round also takes the step-size test of the previous
+// round's proposals: every workgroup computes the same pick from the omega
+// partials and gathers the picked proposal's support and values, and one
+// extra workgroup per problem commits it (decide_pick, commit_round).
 #include "solve_common.h"
 
 namespace qiht {
@@ -97,10 +101,19 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const int set = blockIdx.y % NSET;
     const ProbDev& pd = P[p];
     const int wg = xcd_row_group(blockIdx.x, blockIdx.y);  // 16-byte row group
+    // G_R after the first round: the last round's step-size test is taken
+    // here, by every workgroup alike; one extra workgroup commits it
+    __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
+    __shared__ int s_done;
+    const bool decide = MODE == G_R && !zero_x && pd.st->phase == 1;
+    if (MODE == G_R && wg == pd.nwg) {
+        if (decide && !pd.st->done) commit_round<kGatherThreads>(pd, a, s_dec);
+        return;
+    }
     if (wg >= pd.nwg) return;
     // the stop flag is read alongside the first loads and checked once they
     // are issued (every address stays valid after the solve has stopped)
-    const int done_now = pd.st->done;
+    int done_now = pd.st->done;
 
     const int32_t* cols;
     int ncols;
@@ -118,6 +131,22 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         ncols = (MODE == G_R && zero_x) ? 0 : pd.s;
         if (MODE == G_R) wpos = pd.xs;
         else wcol = pd.g;
+    }
+    if (MODE == G_R && decide) {
+        // The commit workgroup of this launch may stop the problem while the
+        // others run: thread 0's reading of the flag, passed on through LDS
+        // across the test's barrier, is the one every wave acts on.
+        if (threadIdx.x == 0) s_done = done_now;
+        // the picked proposal's support and values (after a failed test the
+        // current ones: the next round proposes further shrinks from this x)
+        bool capped;
+        const int pick = decide_pick<kGatherThreads>(pd, a, &capped, s_dec);
+        done_now = s_done;
+        if (done_now) return;  // uniform over the workgroup
+        if (pick >= 0) {
+            cols = pd.csup + static_cast<size_t>(pick) * pd.s;
+            wpos = pd.cval + static_cast<size_t>(pick) * pd.s;
+        }
     }
     // (one copy of the matrix: Q2_G g_G = Q1_G g_G, read once)
     const bool two = (MODE == G_MU) && (a.mu_mode == 0) && (pd.q1 != pd.q2);
@@ -300,11 +329,25 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     const int p = blockIdx.y / NSET;
     const int set = blockIdx.y % NSET;
     const ProbDev& pd = P[p];
-    if (pd.st->done) return;
     const int wg = blockIdx.x;  // 1 KB row segment
+    // G_R after the first round: the last round's step-size test (as in
+    // k_gather).  Its commit workgroup may stop the problem while the others
+    // run, so those act on thread 0's reading of the flag, passed on through
+    // LDS across the test's barrier; without a test nothing changes the flag
+    // during the launch.
+    __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
+    __shared__ int s_done;
+    const bool decide = MODE == G_R && !zero_x && pd.st->phase == 1;
+    const int done_now = pd.st->done;
+    if (MODE == G_R && wg == pd.npart) {
+        if (decide && !done_now) commit_round<kGatherThreads>(pd, a, s_dec);
+        return;
+    }
     if (wg >= pd.npart) return;
+    if (!decide && done_now) return;
 
     const int32_t* cols;
+    const float* xw = pd.xs;  // G_R: x on the listed columns
     int ncols;
     if (MODE == G_OMEGA) {
         const CandMeta& m = pd.meta[set];
@@ -314,6 +357,16 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     } else {
         cols = pd.sup;
         ncols = (MODE == G_R && zero_x) ? 0 : pd.s;
+    }
+    if (MODE == G_R && decide) {
+        if (threadIdx.x == 0) s_done = done_now;
+        bool capped;
+        const int pick = decide_pick<kGatherThreads>(pd, a, &capped, s_dec);
+        if (s_done) return;  // uniform over the workgroup
+        if (pick >= 0) {
+            cols = pd.csup + static_cast<size_t>(pick) * pd.s;
+            xw = pd.cval + static_cast<size_t>(pick) * pd.s;
+        }
     }
     CandPre cpre;
     if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
@@ -339,7 +392,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
             const int c = static_cast<int>(ldg_u32(cols + base + i));
             double w;
             if (MODE == G_OMEGA) w = ldg_f64(pd.dw + static_cast<size_t>(set) * 2 * pd.s + base + i);
-            else if (MODE == G_R) w = static_cast<double>(ldg_f32(pd.xs + base + i));
+            else if (MODE == G_R) w = static_cast<double>(ldg_f32(xw + base + i));
             else w = static_cast<double>(ldg_f32(pd.g + c));
             lidx[i] = c;
             lw[i] = w;
@@ -416,8 +469,10 @@ template <int MODE>
 void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveArgs& a,
                  int zero_x, bool wide, hipStream_t st) {
     const int nset = (MODE == G_OMEGA) ? kSpec : 1;
+    // G_R: one more workgroup per problem, the commit of the last round's step
+    const int extra = MODE == G_R ? 1 : 0;
     if (wide) {
-        dim3 gw((maxwg * 16 + kWideBytes - 1) / kWideBytes, count * nset);
+        dim3 gw((maxwg * 16 + kWideBytes - 1) / kWideBytes + extra, count * nset);
         switch (bits) {
             case 9: hipLaunchKernelGGL((k_gather_wide<9, MODE>), gw, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
             case 16: hipLaunchKernelGGL((k_gather_wide<16, MODE>), gw, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
@@ -425,7 +480,7 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
         }
         return;
     }
-    dim3 grid((maxwg + 63) / 64 * 64, count * nset);
+    dim3 grid((maxwg + extra + 63) / 64 * 64, count * nset);
     switch (bits) {
         case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
         case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;

@@ -3,8 +3,8 @@
 // test, shrinking by k(1-c)).
 //
 // k_propose: one workgroup per proposal x'_k = H_s(x + mu_k g) with
-// mu_k = mu / (k(1-c))^k, k = 0 .. kSpec-1 side by side (speculative
-// backtracking).  Each workgroup first finishes mu = |g_G|^2 / (Q1_G g_G).
+// mu_k = mu / (k(1-c))^k, k = base_k .. base_k + kSpec-1 side by side
+// (speculative backtracking).  Each workgroup first finishes mu = |g_G|^2 / (Q1_G g_G).
 // (Q2_G g_G) from the gather partials, in workgroup order.
 //
 // Selection, fast path: off the current support G, a_j = mu g_j, so the
@@ -21,10 +21,10 @@
 // ordered scan of the selection bitmap.  Full path (candidate set too large,
 // or a plain H_s call): the same rank over all n keys held in registers.
 //
-// k_decide: the test mu_k <= (1-c)|x'_k - x|^2 / |Q1 (x'_k - x)|^2 applied in
-// order k = 0, 1, ... (a proposal keeping the support is accepted at once);
-// the first accepted proposal is committed.  If all kSpec proposals fail,
-// the same workgroup continues one shrink at a time.
+// The step-size test itself (decide_pick) and the commit run in the next
+// residual gather, so no launch of its own sits between two iterations; a
+// round whose proposals all fail is followed by one that proposes the next
+// kSpec shrinks (base_k) from the same x.
 #include "solve_common.h"
 
 namespace qiht {
@@ -54,7 +54,7 @@ struct SelShared {
     uint32_t scan[16];
     uint32_t flg[16];
     uint32_t bin, krem, total, nc;
-    int changed, bad, full;
+    int changed, bad, full, dn;
     double red[16];
     double red3[3][16];
 };
@@ -404,7 +404,8 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     // thread's index blocks [t cpw, (t + 1) cpw), and the first PRE
     // candidates of its first block
     // (with `skipped`, the solve's stop flag is read alongside these loads
-    // and an already finished problem returns before touching anything)
+    // and an already finished problem returns at the first barrier, before
+    // writing any global memory)
     const int done_now = skipped ? pd.st->done : 0;
     double gg = 0.0, uv = 0.0, uu = 0.0;
     if (from_partials) {
@@ -441,10 +442,6 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         if (c < 0) bad_cnt = 1;
         else if (gq == 0) mycnt += static_cast<uint32_t>(c);
     }
-    if (done_now) {  // uniform: every thread read the same flag
-        *skipped = true;
-        return false;
-    }
     for (int b = tid; b < 2048; b += kSelectThreads) S.hist[b] = 0u;
     for (int b = tid; b < 1024; b += kSelectThreads) {
         S.hist2[b] = 0u;
@@ -453,9 +450,15 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     if (tid == 0) {
         S.changed = 0;
         S.bad = 0;
+        S.dn = done_now;  // (workgroup 0 of the same launch may stop the problem
+                          // while this one runs: thread 0's reading decides)
     }
     // ---- the step, and this thread's place in the candidate list
     const BlockAgg ag = block_sums_scan(gg, uv, uu, mycnt, bad_cnt != 0, S);
+    if (S.dn) {  // uniform over the workgroup
+        *skipped = true;
+        return false;
+    }
     double mu = mu_in;
     if (from_partials) {
         double den = ag.b;
@@ -708,108 +711,21 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
         propose<SEL_INIT>(pd, 0, 0, 1.0, false, 1.0, &mu0, S);
         return;
     }
-    const int k = blockIdx.x;  // shrink count of this proposal
+    // shrink count of this proposal: after a round whose proposals all failed
+    // the test, the following kSpec shrinks of the same step
+    const int k = st->base_k + static_cast<int>(blockIdx.x);
     bool skipped = false;
-    const bool ok = propose<SEL_STEP>(pd, k, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S, &skipped);
+    const bool ok = propose<SEL_STEP>(pd, blockIdx.x, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S, &skipped);
     if (skipped) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (ok) {
             st->mu = mu0;
+            st->phase = 1;  // the next residual gather takes the step-size test
         } else {
             st->done = 1;
             st->reason = QIHT_REASON_STATIONARY;
         }
     }
-}
-
-// |Q1 dx|^2 of slot 0's difference list, by one workgroup.
-template <int BITS>
-__device__ double omega_den_block(const ProbDev& pd, int dcount, double* red) {
-    constexpr int RPW = rows_per_word<BITS>();
-    const int words = static_cast<int>(pd.col_bytes / 4);
-    double wsum = 0.0;
-    for (int t = 0; t < dcount; ++t) wsum += pd.dw[t];
-    double tot = 0.0;
-    for (int w = threadIdx.x; w < words; w += kSelectThreads) {
-        double acc[RPW];
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) acc[q] = 0.0;
-        for (int t = 0; t < dcount; ++t) {
-            const uint32_t word = *reinterpret_cast<const uint32_t*>(
-                pd.q1 + static_cast<size_t>(pd.dlist[t]) * pd.col_bytes + static_cast<size_t>(w) * 4);
-            const double wt = pd.dw[t];
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) acc[q] = fma(wt, elem_at<BITS>(word, q), acc[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int64_t row = static_cast<int64_t>(w) * RPW + q;
-            if (row < pd.rows) {
-                double v;
-                if constexpr (BITS == 32) v = acc[q];
-                else if constexpr (BITS == 9 || BITS == 16) v = ldexp(acc[q], pd.rowexp[row]);
-                else v = pd.alpha * acc[q] + pd.beta * wsum;
-                tot += v * v;
-            }
-        }
-    }
-    return block_sum<kSelectThreads>(tot, red);
-}
-
-template <int BITS>
-__global__ __launch_bounds__(kSelectThreads) void k_decide(const ProbDev* __restrict__ P,
-                                                           SolveArgs a) {
-    const ProbDev& pd = P[blockIdx.x];
-    SolveState* st = pd.st;
-    __shared__ SelShared S;
-    if (st->done) return;
-    int pick = -1;
-    bool capped = false;
-    for (int t = 0; t < kSpec; ++t) {
-        const CandMeta m = pd.meta[t];
-        if (!m.changed) {
-            pick = t;
-            break;
-        }
-        double den = 0.0;
-        for (int b = threadIdx.x; b < pd.npart; b += kSelectThreads)
-            den += pd.part_om[static_cast<size_t>(t) * pd.nwg + b];
-        den = block_sum<kSelectThreads>(den, S.red);
-        const double omega = den > 0.0 ? m.dx2 / den : INFINITY;
-        if (m.mu <= (1.0 - a.c) * omega) {
-            pick = t;
-            break;
-        }
-        if (m.k >= a.max_backtracks) {
-            pick = t;
-            capped = true;
-            break;
-        }
-    }
-    if (pick < 0) {
-        // every speculative proposal failed: continue one shrink at a time
-        const double shrink = a.k * (1.0 - a.c);
-        for (int k = kSpec;; ++k) {
-            const double mu = shrunk_mu(st->mu, shrink, k);
-            double unused = 0.0;
-            propose<SEL_STEP>(pd, 0, k, mu, false, shrink, &unused, S);
-            const CandMeta m = pd.meta[0];
-            bool accept = !m.changed;
-            if (!accept) {
-                const double den = omega_den_block<BITS>(pd, m.dcount, S.red);
-                const double omega = den > 0.0 ? m.dx2 / den : INFINITY;
-                accept = mu <= (1.0 - a.c) * omega;
-                if (!accept && k >= a.max_backtracks) capped = accept = true;
-            }
-            if (accept) {
-                pick = 0;
-                break;
-            }
-            __syncthreads();
-        }
-    }
-    commit_proposal<kSelectThreads>(pd, pick, a, capped);
-    for (int b = threadIdx.x; b < 2048; b += kSelectThreads) pd.hist[b] = 0u;
 }
 
 __global__ __launch_bounds__(kSelectThreads) void k_hard_threshold(const float* a, int n, int s,
@@ -831,18 +747,6 @@ void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st) {
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st) {
     const dim3 grid(mode == SEL_INIT ? 1 : kSpec, count);
     hipLaunchKernelGGL(k_propose, grid, dim3(kSelectThreads), 0, st, P, a, mode);
-}
-
-void launch_decide(int bits, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
-    switch (bits) {
-        case 1: hipLaunchKernelGGL(k_decide<1>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        case 2: hipLaunchKernelGGL(k_decide<2>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        case 4: hipLaunchKernelGGL(k_decide<4>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        case 8: hipLaunchKernelGGL(k_decide<8>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        case 9: hipLaunchKernelGGL(k_decide<9>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        case 16: hipLaunchKernelGGL(k_decide<16>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-        default: hipLaunchKernelGGL(k_decide<32>, dim3(count), dim3(kSelectThreads), 0, st, P, a); break;
-    }
 }
 
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st) {

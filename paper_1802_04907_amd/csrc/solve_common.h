@@ -22,11 +22,11 @@ struct SolveState {
     int32_t done;
     int32_t iter;       // completed iterations
     int32_t reason;
-    int32_t phase;      // 0 normal, 2 sequential backtracking pending
+    int32_t phase;      // 1 once proposals of a step await the step-size test
     int32_t total_bt;
     int32_t capped;
     int32_t err;        // NaN met in a selection
-    int32_t base_k;     // first shrink index still to be examined
+    int32_t base_k;     // shrink count of the first proposal of the next round
     int32_t full_selects;  // proposals that needed the full n-key rank
     int32_t pad;
     double mu;          // step of this iteration before any shrink
@@ -526,8 +526,66 @@ void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Ta
 void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);
-void launch_decide(int bits, const ProbDev* P, int count, const SolveArgs& a, hipStream_t st);
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st);
+
+// The step-size test of Algorithm 2 (Sec. II-A) on the kSpec proposals of
+// the last round, shrink counts k = base_k, base_k + 1, ... in order: a
+// proposal that keeps the support is taken at once; otherwise proposal k is
+// taken when mu_k <= (1 - c) |x'_k - x|^2 / |Q1 (x'_k - x)|^2, or, failing
+// that, when k reaches the backtracking cap (*capped).  -1: every proposal
+// failed, and the next round proposes the following kSpec shrinks from the
+// same x.  Called by every thread of a workgroup of NT threads (it holds one
+// barrier; red: kSpec * NT / 64 doubles of LDS); all get the same answer.
+// The denominators are summed from the omega gather's partials, per wave and
+// then in wave order.
+template <int NT>
+__device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, double* red) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double den[kSpec];
+#pragma unroll
+    for (int t = 0; t < kSpec; ++t) den[t] = 0.0;
+    for (int b = tid; b < pd.npart; b += NT)
+#pragma unroll
+        for (int t = 0; t < kSpec; ++t) den[t] += pd.part_om[static_cast<size_t>(t) * pd.nwg + b];
+#pragma unroll
+    for (int t = 0; t < kSpec; ++t) {
+        den[t] = wave_sum(den[t]);
+        if (lane == 0) red[t * NW + wv] = den[t];
+    }
+    __syncthreads();
+    int pick = -1;
+    *capped = false;
+#pragma unroll
+    for (int t = 0; t < kSpec; ++t) {
+        if (pick >= 0) continue;
+        const CandMeta m = pd.meta[t];
+        if (!m.changed) {
+            pick = t;
+            continue;
+        }
+        double d = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) d += red[t * NW + w];
+        const double omega = d > 0.0 ? m.dx2 / d : INFINITY;
+        if (m.mu <= (1.0 - a.c) * omega) {
+            pick = t;
+        } else if (m.k >= a.max_backtracks) {
+            pick = t;
+            *capped = true;
+        }
+    }
+    return pick;
+}
+
+// The commit workgroup of a residual gather (one per problem, NT threads):
+// the proposal the step-size test picks replaces x and the support, or, when
+// every proposal failed, the next round's proposals shrink further.  Either
+// way the |g| histogram is cleared for the next full pass.  The other
+// workgroups of the gather read the picked proposal's support and values
+// (or, after a failure, the current ones), never what this one writes.
+template <int NT>
+__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red);
 
 // Device-side commit of proposal `t` (called by one whole workgroup of
 // `nt` threads): x and the support take the proposal's values, the state
@@ -555,7 +613,6 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
         st->mu_last = m.mu;
         st->total_bt += m.k;
         st->capped += capped ? 1 : 0;
-        st->phase = 0;
         st->base_k = 0;
         if (a.tol >= 0.0 && m.dx2 <= a.tol * a.tol * m.xn2) {
             st->done = 1;
@@ -566,6 +623,18 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
         }
     }
     __syncthreads();
+}
+
+template <int NT>
+__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red) {
+    bool capped = false;
+    const int pick = decide_pick<NT>(pd, a, &capped, red);
+    if (pick >= 0) {
+        commit_proposal<NT>(pd, pick, a, capped);
+    } else if (threadIdx.x == 0) {
+        pd.st->base_k += kSpec;
+    }
+    for (int b = threadIdx.x; b < 2048; b += NT) pd.hist[b] = 0u;
 }
 
 }  // namespace qiht

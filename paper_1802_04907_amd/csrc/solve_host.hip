@@ -3,7 +3,7 @@
 // qiht_niht_solve_batched, qiht_gradient and qiht_hard_threshold.
 //
 // All control state lives on the device; the host only enqueues launches
-// and, every kChunk iterations, reads the stop flags back.
+// and, every kChunk rounds, reads the stop flags back.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -17,7 +17,7 @@
 namespace qiht {
 namespace {
 
-constexpr int kChunk = 16;  // iterations enqueued between stop-flag reads
+constexpr int kChunk = 16;  // rounds enqueued between stop-flag reads
 
 struct InfoDev {
     int32_t iterations, reason, backtracks, capped, err, full_selects;
@@ -413,13 +413,15 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }
 
+// One round: the residual gather first takes the step-size test of the
+// previous round's proposals (and commits the pick), then the gradient, mu,
+// the kSpec proposals of this round and their omegas.
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                         const SolveArgs& a, hipStream_t st, PassTimer* tm) {
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
     launch_propose(dP, count, a, SEL_STEP, st);
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
-    launch_decide(pl.bits, dP, count, a, st);
 }
 
 qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
@@ -490,12 +492,21 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_i
     }
     QIHT_HIP(hipGetLastError());
 
+    // Rounds until every problem has stopped.  Iteration i is committed by
+    // the residual gather of round i + 1, so max_iters iterations take
+    // max_iters + 1 rounds when no test needs more than kSpec shrinks; each
+    // further kSpec shrinks of one iteration take one more round, and the
+    // backtracking cap bounds them.
     std::vector<int32_t> hdone(count);
     int32_t* ddone = reinterpret_cast<int32_t*>(ws.base + pl.done_off);
-    for (int it = 1; it <= a.max_iters;) {
-        const int end = std::min(a.max_iters, it + kChunk - 1);
-        for (; it <= end; ++it) iteration_launches(pl, dP, dT, count, a, st, &timer);
-        if (it > a.max_iters) break;
+    const int64_t per_iter = std::max<int64_t>(1, (static_cast<int64_t>(a.max_backtracks) + kSpec) / kSpec);
+    const int64_t first = a.max_iters > 0 ? static_cast<int64_t>(a.max_iters) + 1 : 0;
+    const int64_t max_rounds = a.max_iters > 0 ? static_cast<int64_t>(a.max_iters) * per_iter + 1 : 0;
+    for (int64_t launched = 0; launched < max_rounds;) {
+        const int64_t goal = launched < first ? first : max_rounds;
+        const int64_t nl = std::min<int64_t>(kChunk, goal - launched);
+        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, st, &timer);
+        launched += nl;
         hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
         QIHT_HIP(hipGetLastError());
         QIHT_HIP(hipMemcpyAsync(hdone.data(), ddone, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
