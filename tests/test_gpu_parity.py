@@ -270,6 +270,47 @@ def test_teacher_forced_iterations_256x1024():
         x, sup = xn, gsup.astype(np.int64)
 
 
+@pytest.mark.parametrize("max_bt", [32, 5])
+def test_teacher_forced_deep_backtracking(max_bt):
+    """A gentle shrink factor k(1-c) = 1.05 and a strict test (c = 0.3): most
+    iterations need more shrinks than one round proposes (4), so the solver
+    runs further rounds from the same x; with max_bt = 5 the cap falls in the
+    second round.  Each GPU iteration is checked against the oracle's from
+    the same state: support, shrink count, cap, x and the accepted step."""
+    k, c = 1.5, 0.3
+    p = workloads.gaussian_256x1024(0)
+    q, yhat = _gpu_problem(p, 8)
+    q1, q2, yh = _oracle_mats(p, 8)
+    x = np.zeros(p.n)
+    sup = niht.initial_support(q1, yh, p.s)
+    g0 = q1.T @ yh
+    deep = capped = 0
+    for it in range(12):
+        xg, sg, info = qiht.niht_solve(q, yhat, p.s, max_iters=1, tol=-1.0, k=k, c=c,
+                                       max_backtracks=max_bt,
+                                       x0=_t(x.astype(np.float32)),
+                                       support0=_t(sup.astype(np.int32)))
+        ref = niht.qiht_iteration(q1, q2, yh, x.astype(np.float32).astype(np.float64),
+                                  sup, p.s, k=k, c=c, max_backtracks=max_bt)
+        gsup = sg.cpu().numpy()
+        say(f"  iteration {it}: backtracks gpu {info['backtracks']} oracle {ref.backtracks}"
+            f" capped {info['capped_iterations']}/{int(ref.capped)}")
+        np.testing.assert_array_equal(gsup, ref.support, err_msg=f"iteration {it}")
+        assert info["backtracks"] == ref.backtracks
+        assert info["capped_iterations"] == int(ref.capped)
+        xn = xg.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(xn - ref.x) <= 1e-5 * np.linalg.norm(ref.x), it
+        gG = np.linalg.norm(ref.g[sup])
+        mu_tol = 2e-5 * max(1.0, 1e-3 * np.linalg.norm(g0) / gG)
+        assert abs(info["mu_last"] - ref.mu) <= mu_tol * ref.mu, it
+        deep += ref.backtracks >= 4
+        capped += int(ref.capped)
+        x, sup = xn, gsup.astype(np.int64)
+    assert deep >= 3  # the case this test is for: several multi-round iterations
+    if max_bt == 5:
+        assert capped >= 1
+
+
 def test_determinism_bitwise():
     p = workloads.gaussian(400, 1500, 20, 1e-3, seed=7)
     q, yhat = _gpu_problem(p, 4)
