@@ -336,6 +336,79 @@ def batched_bench(qiht, torch, dev, count=96, iters=100):
     }
 
 
+SYN_PRECISIONS = [(32, 32), (8, 8), (4, 8), (4, 4), (2, 8)]
+SYN_VARIANTS = {"gaussian": (False, None), "equal": (True, None),
+                "gaussian_20dB": (False, 20.0), "gaussian_10dB": (False, 10.0)}
+
+
+def synthetic_sweep(qiht, torch, dev, trials=100, iters=300, tol=1e-7):
+    """The synthetic accuracy experiment (Sec. IV-A): Phi 128 x 1024 i.i.d.
+    N(0, 1), x with s = 4, 8, ..., 128 nonzeros, N(0, 1) or all ones, y = Phi x
+    or noisy at an SNR of 20 or 10 dB (the recipe of workloads.synthetic,
+    drawn on the device with one seeded generator per variant and s).  For
+    each precision pair (bits of Phi / of y; 32 = FP32, i.e. normalized IHT)
+    the `trials` draws are quantized (2 realizations of Phi) and solved in one
+    batched call; reported: mean recovery error |x^n - x| / |x| and mean
+    support recovery |supp x^n  and  supp x| / s, per s, and the largest s
+    with mean support recovery >= 0.9."""
+    m, n = 128, 1024
+    s_values = list(range(4, 129, 4))
+    out = {"workload": (f"Phi {m}x{n} N(0,1), s = 4..128 step 4, {trials} draws per s; "
+                        f"NIHT/QIHT with tol {tol}, at most {iters} iterations"),
+           "precisions": [f"{a}/{b}" for a, b in SYN_PRECISIONS], "s": s_values, "variants": {}}
+    t_solve, solved, iters_done = 0.0, 0, 0
+    for vi, (vname, (equal, snr)) in enumerate(SYN_VARIANTS.items()):
+        curves = {f"{a}/{b}": {"rel_err": [], "support": []} for a, b in SYN_PRECISIONS}
+        for s in s_values:
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(SEED * 1000003 + vi * 1009 + s)
+            phi = torch.randn((trials, m, n), generator=gen, device=dev, dtype=torch.float64)
+            perm = torch.rand((trials, n), generator=gen, device=dev).argsort(dim=1)
+            sup = perm[:, :s].sort(dim=1).values
+            vals = (torch.ones((trials, s), device=dev, dtype=torch.float64) if equal else
+                    torch.randn((trials, s), generator=gen, device=dev, dtype=torch.float64))
+            x = torch.zeros((trials, n), device=dev, dtype=torch.float64).scatter_(1, sup, vals)
+            y = torch.bmm(phi, x.unsqueeze(2)).squeeze(2)
+            if snr is not None:
+                sig = y.norm(dim=1, keepdim=True) / math.sqrt(m) * 10.0 ** (-snr / 20.0)
+                y = y + sig * torch.randn((trials, m), generator=gen, device=dev, dtype=torch.float64)
+            y = y.contiguous()
+            truth = torch.zeros((trials, n), device=dev, dtype=torch.bool).scatter_(1, sup, True)
+            for bp, by in SYN_PRECISIONS:
+                probs = []
+                for t in range(trials):
+                    q = qiht.quantize_matrix(phi[t], bp, 2, t)
+                    yh, _, _ = qiht.quantize_vector(y[t], by, t)
+                    probs.append((q, yh, s))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = qiht.niht_solve_batched(probs, max_iters=iters, tol=tol)
+                torch.cuda.synchronize()
+                t_solve += time.perf_counter() - t0
+                solved += trials
+                iters_done += sum(info["iterations"] for _, _, info in res)
+                X = torch.stack([r[0] for r in res]).double()
+                got = torch.zeros((trials, n), device=dev, dtype=torch.bool).scatter_(
+                    1, torch.stack([r[1] for r in res]).long(), True)
+                err = ((X - x).norm(dim=1) / x.norm(dim=1)).mean().item()
+                rec = ((got & truth).sum(dim=1).double() / s).mean().item()
+                key = f"{bp}/{by}"
+                curves[key]["rel_err"].append(round(err, 5))
+                curves[key]["support"].append(round(rec, 4))
+                for q, _, _ in probs:
+                    q.free()
+        for key, c in curves.items():
+            ok = [s for s, r in zip(s_values, c["support"]) if r >= 0.9]
+            c["largest_s_support_0.9"] = max(ok) if ok else None
+        out["variants"][vname] = curves
+        log(f"synthetic sweep: {vname} done")
+    out["problems_solved"] = solved
+    out["problem_iterations"] = iters_done
+    out["solve_seconds"] = round(t_solve, 3)
+    out["problem_iterations_per_s"] = round(iters_done / t_solve, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,6 +427,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
+    ap.add_argument("--synthetic-sweep", action="store_true",
+                    help="only the synthetic accuracy experiment (Phi 128 x 1024, s = 4..128, "
+                         "100 draws, 5 precision pairs, 4 signal/noise variants; about a minute)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 3 times (known bytes, for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -380,6 +456,9 @@ def main():
         return
     if args.shared_only:
         print(json.dumps(shared_bench(qiht, torch, dev, reps=1, only=args.shared_only)))
+        return
+    if args.synthetic_sweep:
+        print(json.dumps(synthetic_sweep(qiht, torch, dev)))
         return
     log("generating workload ...")
     p = workloads.gaussian_8192x32768(SEED)

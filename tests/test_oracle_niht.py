@@ -301,3 +301,24 @@ def test_argument_checks():
         niht.qiht_solve(phi, phi, np.ones(3), 4)
     with pytest.raises(ValueError):
         niht.qiht_solve(phi, phi[:2], np.ones(3), 1)
+
+
+def test_synthetic_recipe():
+    # the synthetic experiment's draws: shapes, unit-variance entries,
+    # reproducible per (s, trial), and the stated SNR (|Phi x|^2 / m sigma^2)
+    import workloads
+    p = workloads.synthetic(16, 3)
+    q = workloads.synthetic(16, 3)
+    assert p.phi.shape == (128, 1024) and p.s == 16 and p.seed == 3
+    np.testing.assert_array_equal(p.phi, q.phi)
+    np.testing.assert_allclose(p.y, p.phi @ p.x_true, rtol=1e-12, atol=1e-12)
+    assert abs(p.phi.std() - 1.0) < 0.01
+    assert set(np.nonzero(p.x_true)[0]) == set(p.support)
+    e = workloads.synthetic(16, 3, equal=True)
+    assert np.all(e.x_true[e.support] == 1.0)
+    snrs = []
+    for t in range(40):
+        d = workloads.synthetic(16, t, snr_db=10.0)
+        clean = d.phi @ d.x_true
+        snrs.append(10 * np.log10(np.sum(clean ** 2) / np.sum((d.y - clean) ** 2)))
+    assert abs(np.mean(snrs) - 10.0) < 0.5

@@ -21,6 +21,10 @@ Phi -> support -> nonzero values -> noise):
 * ``batch_uneven``: independent Gaussian problems with m drawn uniformly in
   [m_lo, m_hi], n = 4m, s = m // 16, per-instance generator seeds [seed, i].
 * ``shared_phi``: one Gaussian Phi and many sparse right-hand sides.
+* ``synthetic``: the synthetic experiment of Sec. IV-A: Phi 128 x 1024 with
+  i.i.d. N(0, 1) entries (unit variance, as stated there), s-sparse x with
+  N(0, 1) or all-one nonzeros, y = Phi x, or with noise at a given SNR
+  (|Phi x|^2 / |e|^2, in dB); generator seeds [seed, s, trial].
 """
 
 from dataclasses import dataclass
@@ -75,6 +79,23 @@ def _matvec(phi, x):
         blk = blk.astype(np.complex128 if np.iscomplexobj(blk) else np.float64)
         out[r0:r0 + step] = blk @ x[nz]
     return out
+
+
+def synthetic(s, trial, equal=False, snr_db=None, seed=0, m=128, n=1024):
+    """One draw of the synthetic experiment (Sec. IV-A): Phi m x n N(0, 1),
+    x s-sparse (N(0, 1) or, with ``equal``, all-one nonzeros), y = Phi x,
+    plus N(0, sigma^2) noise with |Phi x|^2 / (m sigma^2) = 10^(snr_db/10)
+    when ``snr_db`` is given.  The quantizer seed is the trial index."""
+    rng = np.random.default_rng([seed, s, trial])
+    phi = rng.standard_normal((m, n))
+    sup = np.sort(rng.choice(n, s, replace=False))
+    x = np.zeros(n)
+    x[sup] = 1.0 if equal else rng.standard_normal(s)
+    y = _matvec(phi, x)
+    if snr_db is not None:
+        sigma = np.linalg.norm(y) / math.sqrt(m) * 10.0 ** (-snr_db / 20.0)
+        y = y + sigma * rng.standard_normal(m)
+    return Problem(phi, y, x, sup, s, trial)
 
 
 def gaussian_256x1024(seed=0):
