@@ -118,6 +118,14 @@ typedef struct {
  * max_backtracks 32, mu_mode 0, no warm start, profile 0, refit 0. */
 void qiht_default_params(qiht_params* p);
 
+/* OR'd into the bit width of qiht_quantize_matrix (2, 4 or 8 bits) or
+ * qiht_quantize_vector (2..12 bits): the odd level set of the Remark on
+ * fixed-point hardware in the appendix (after the Lemma on the quantized
+ * vector): 2^(b-1) + 1 levels q_k = -1 + k / 2^(b-2), spacing 1 / 2^(b-2),
+ * codes 0 .. 2^(b-1) stored in the same b bits; same rounding rule and
+ * random stream.  The solver works on such handles unchanged. */
+#define QIHT_ODD_LEVELS 0x100
+
 /* Dense storage formats accepted by qiht_quantize_matrix in place of a bit
  * width (deterministic rounding, no randomness; not in the paper). */
 #define QIHT_FMT_BF16 116  /* bfloat16: 8 exponent, 7 stored significand bits */
@@ -134,7 +142,8 @@ void qiht_default_params(qiht_params* p);
  *   levels q_k = -1 + 2k/(2^b - 1), up with probability equal to the
  *   fractional position (unbiased: E[Q(v)] = v).
  *
- *   bits: 1, 2, 4 or 8 (packed codes), or 32 (plain FP32 copy, no
+ *   bits: 1, 2, 4 or 8 (packed codes; 2, 4 or 8 may carry
+ *   QIHT_ODD_LEVELS), or 32 (plain FP32 copy, no
  *   randomness; realizations is then forced to 1 and Q1 = Q2), or a dense
  *   format QIHT_FMT_BF16 / QIHT_FMT_E4M3: row i is stored as
  *   Phi_ij / 2^e_i rounded to nearest (ties to even significand), e_i the
@@ -170,7 +179,8 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n,
  *            c (2k/(2^b - 1) - 1); for bits = 32 the FP32-rounded y.
  *   codes_out (device, rows bytes, optional, bits <= 8): the codes.
  *   scale_out (host, optional): the scale c (0 for bits = 32).
- *   bits: 1..8 or 32.  Synchronizes stream.
+ *   bits: 1..12 or 32, optionally | QIHT_ODD_LEVELS (2..12 bits; levels
+ *   c (k / 2^(b-2) - 1)).  Synchronizes stream.
  */
 qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype,
                                  int bits, uint64_t seed, void* stream,

@@ -73,6 +73,7 @@ def _ptr(t):
 
 BF16 = _lib.QIHT_FMT_BF16  # dense storage formats for quantize_matrix(bits=...)
 E4M3 = _lib.QIHT_FMT_E4M3
+ODD_LEVELS = _lib.QIHT_ODD_LEVELS  # 2^(b-1) + 1 levels (odd=True below)
 
 
 class QMatrix:
@@ -124,8 +125,10 @@ class QMatrix:
             pass
 
 
-def quantize_matrix(phi, bits, realizations=2, seed=0, stream=None):
-    """Q(Phi, b): ``phi`` is an (m, n) CUDA tensor, row-major (stride (ld, 1))."""
+def quantize_matrix(phi, bits, realizations=2, seed=0, stream=None, odd=False):
+    """Q(Phi, b): ``phi`` is an (m, n) CUDA tensor, row-major (stride (ld, 1));
+    ``odd`` selects the odd level set (2^(b-1) + 1 levels)."""
+    bits = int(bits) | (ODD_LEVELS if odd else 0)
     if phi.dim() != 2 or phi.stride(1) != 1 or not phi.is_cuda:
         raise ValueError("phi must be a 2-D row-major CUDA tensor")
     m, n = phi.shape
@@ -137,9 +140,11 @@ def quantize_matrix(phi, bits, realizations=2, seed=0, stream=None):
     return QMatrix(out.value)
 
 
-def quantize_vector(y, bits, seed=0, stream=None, want_codes=False):
-    """Q(y, b) -> (y_hat FP64 CUDA tensor of the stacked rows, codes, scale)."""
+def quantize_vector(y, bits, seed=0, stream=None, want_codes=False, odd=False):
+    """Q(y, b) -> (y_hat FP64 CUDA tensor of the stacked rows, codes, scale);
+    ``odd`` selects the odd level set (2^(b-1) + 1 levels)."""
     torch = _torch()
+    bits = int(bits) | (ODD_LEVELS if odd else 0)
     if y.dim() != 1 or not y.is_contiguous() or not y.is_cuda:
         raise ValueError("y must be a contiguous 1-D CUDA tensor")
     rows = y.numel() * (2 if y.is_complex() else 1)

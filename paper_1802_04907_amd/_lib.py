@@ -9,6 +9,7 @@ LIB_PATH = os.path.join(HERE, "libqiht.so")
 QIHT_OK = 0
 QIHT_FMT_BF16 = 116  # dense formats (include/qiht.h)
 QIHT_FMT_E4M3 = 108
+QIHT_ODD_LEVELS = 0x100  # odd level set, OR'd into a bit width
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
                 4: "DEVICE", 5: "NUMERIC"}
 DTYPE = {"f64": 0, "f32": 1, "c64": 2, "c128": 3}

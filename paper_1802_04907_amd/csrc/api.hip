@@ -38,7 +38,9 @@ bool bits_ok_matrix(int b) {
 // public bit width / format -> internal id, and back
 int internal_bits(int b) { return b == QIHT_FMT_BF16 ? kFmtBF16 : b == QIHT_FMT_E4M3 ? kFmtE4M3 : b; }
 int public_bits(int b) { return b == kFmtBF16 ? QIHT_FMT_BF16 : b == kFmtE4M3 ? QIHT_FMT_E4M3 : b; }
-bool bits_ok_vector(int b) { return (b >= 1 && b <= 8) || b == 32; }
+bool bits_ok_vector(int b) { return (b >= 1 && b <= 12) || b == 32; }
+// Levels of a b-bit code: 2^b, or with QIHT_ODD_LEVELS 2^(b-1) + 1.
+int num_levels(int b, bool odd) { return odd ? (1 << (b - 1)) + 1 : 1 << b; }
 bool dtype_ok(int d) { return d >= QIHT_F64 && d <= QIHT_C128; }
 bool is_complex(qiht_dtype d) { return d == QIHT_C64 || d == QIHT_C128; }
 
@@ -232,8 +234,12 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     if (n > int64_t(65535) * 64) return fail(QIHT_ERR_UNSUPPORTED, "n above 4194240 columns");
     if (ld < n) return fail(QIHT_ERR_INVALID_ARG, "need ld >= n");
     if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
+    const bool odd = (bits & QIHT_ODD_LEVELS) != 0;
+    bits &= ~QIHT_ODD_LEVELS;
     if (!bits_ok_matrix(bits))
         return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8, 32, QIHT_FMT_BF16 or QIHT_FMT_E4M3");
+    if (odd && (bits < 2 || bits > 8))
+        return fail(QIHT_ERR_UNSUPPORTED, "QIHT_ODD_LEVELS needs packed codes of 2, 4 or 8 bits");
     if (realizations != 1 && realizations != 2)
         return fail(QIHT_ERR_INVALID_ARG, "realizations must be 1 or 2");
     bits = internal_bits(bits);
@@ -261,9 +267,9 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     q->col_bytes = cb;
     q->rows_pad = rows_in_bytes(cb, bits);
     q->scale = (bits == 32) ? 0.0 : c;
+    const int levels = (bits == 32) ? 0 : num_levels(bits, odd);
     if (bits != 32 && c > 0.0) {
-        const double L = static_cast<double>(1 << bits);
-        q->alpha = 2.0 * c / (L - 1.0);
+        q->alpha = 2.0 * c / (levels - 1.0);
         q->beta = -c;
     }
     const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
@@ -274,8 +280,8 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
         return fail(QIHT_ERR_OUT_OF_MEMORY, "code allocation failed");
     }
     q->codes[1] = (R == 2) ? q->codes[0] + bytes : q->codes[0];
-    const double K = (bits == 32 || c == 0.0) ? 0.0 : ((1 << bits) - 1) / (2.0 * c);
-    s0 = launch_quantize_matrix(phi, dtype, m, n, ld, bits, R, seed, c, K, q, st);
+    const double K = (bits == 32 || c == 0.0) ? 0.0 : (levels - 1) / (2.0 * c);
+    s0 = launch_quantize_matrix(phi, dtype, m, n, ld, bits, R, seed, c, K, levels, q, st);
     if (s0 == QIHT_OK) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) s0 = hip_fail(e, "quantize");
@@ -298,8 +304,12 @@ qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype, int
     if (!y || !yhat_out) return fail(QIHT_ERR_INVALID_ARG, "y or yhat_out is NULL");
     if (m < 1) return fail(QIHT_ERR_INVALID_ARG, "need m >= 1");
     if (!dtype_ok(dtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
-    if (!bits_ok_vector(bits)) return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1..8 or 32");
-    if (bits == 32 && codes_out) return fail(QIHT_ERR_INVALID_ARG, "no codes for bits = 32");
+    const bool odd = (bits & QIHT_ODD_LEVELS) != 0;
+    bits &= ~QIHT_ODD_LEVELS;
+    if (!bits_ok_vector(bits)) return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1..12 or 32");
+    if (odd && (bits < 2 || bits > 12))
+        return fail(QIHT_ERR_UNSUPPORTED, "QIHT_ODD_LEVELS needs 2..12 bits");
+    if (bits > 8 && codes_out) return fail(QIHT_ERR_INVALID_ARG, "codes_out is for bits <= 8");
     int dev = 0;
     qiht_status s0 = need_device(&dev);
     if (s0 != QIHT_OK) return s0;
@@ -309,15 +319,16 @@ qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype, int
     if (s0 != QIHT_OK) return s0;
     double* lev = nullptr;
     double K = 0.0;
+    const int levels = (bits == 32) ? 0 : num_levels(bits, odd);
     if (bits != 32) {
-        const int L = 1 << bits;
+        const int L = levels;
         std::vector<double> h(L);
         for (int k = 0; k < L; ++k) h[k] = c * (2.0 * k / static_cast<double>(L - 1) - 1.0);
         K = c > 0.0 ? (L - 1) / (2.0 * c) : 0.0;
         QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&lev), sizeof(double) * L, st));
         QIHT_HIP(hipMemcpyAsync(lev, h.data(), sizeof(double) * L, hipMemcpyHostToDevice, st));
     }
-    s0 = launch_quantize_vector(y, dtype, m, bits, seed, c, K, lev, yhat_out, codes_out, st);
+    s0 = launch_quantize_vector(y, dtype, m, bits, levels, seed, c, K, lev, yhat_out, codes_out, st);
     if (lev) (void)hipFreeAsync(lev, st);
     hipError_t e = hipStreamSynchronize(st);
     if (s0 != QIHT_OK) return s0;

@@ -76,12 +76,12 @@ qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
                           double* c_out);
 qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
                                    int64_t n, int64_t ld, int bits, int R,
-                                   uint64_t seed, double c, double K,
+                                   uint64_t seed, double c, double K, int levels,
                                    qiht_qmatrix* q, hipStream_t st);
 qiht_status launch_store_matrix(const void* src, qiht_dtype dt, int64_t m, int64_t n,
                                 int64_t ld, int fmt, qiht_qmatrix* q, hipStream_t st);
 qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
-                                   int bits, uint64_t seed, double c,
+                                   int bits, int levels, uint64_t seed, double c,
                                    double K, const double* levels_dev,
                                    double* yhat, uint8_t* codes,
                                    hipStream_t st);

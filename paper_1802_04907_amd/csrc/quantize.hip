@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_absmax_f4(const float4* __restrict__ sr
 template <int BITS, typename T, int NC, bool ALIGNED>
 __global__ __launch_bounds__(256) void k_quantize(
     const T* __restrict__ src, int64_t m, int64_t n, int64_t ld, int64_t rows,
-    int64_t col_bytes, int64_t nchunks, double c, double K, uint32_t k0,
+    int64_t col_bytes, int64_t nchunks, double c, double K, int L, uint32_t k0,
     uint32_t k1, int R, uint8_t* __restrict__ out0,
     uint8_t* __restrict__ out1) {
     constexpr int RPC = (BITS == 32) ? 4 : 128 / BITS;
@@ -177,7 +177,6 @@ __global__ __launch_bounds__(256) void k_quantize(
         // rows % 4 == 0: element j rows + i0 + q is word q % 4 of block
         // (j rows + i0) / 4 + q / 4.  Every row of the chunk is loaded first
         // (clamped; padding rows get code 0), then the Philox blocks.
-        constexpr int L = 1 << BITS;
         T v[RPC];  // the input type: every value converts to FP64 exactly
 #pragma unroll
         for (int q = 0; q < RPC; ++q)
@@ -203,7 +202,6 @@ __global__ __launch_bounds__(256) void k_quantize(
             *reinterpret_cast<uint4*>((r == 0 ? out0 : out1) + off) = make_uint4(w[0], w[1], w[2], w[3]);
         }
     } else {
-        constexpr int L = 1 << BITS;
         PhiloxStream s0{k0, k1, 0u, 0u};
         PhiloxStream s1{k0, k1, 0u, 1u};
         uint32_t w0[4] = {0u, 0u, 0u, 0u};
@@ -228,7 +226,7 @@ __global__ __launch_bounds__(256) void k_quantize(
 
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_quantize_vec(
-    const T* __restrict__ y, int64_t m, int64_t rows, int bits, double c,
+    const T* __restrict__ y, int64_t m, int64_t rows, int bits, int L, double c,
     double K, uint32_t k0, uint32_t k1, const double* __restrict__ levels,
     double* __restrict__ yhat, uint8_t* __restrict__ codes) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -239,7 +237,7 @@ __global__ __launch_bounds__(256) void k_quantize_vec(
         return;
     }
     PhiloxStream s{k0, k1, 1u, 0u};
-    const uint32_t code = quantize_one(v, c, K, 1 << bits, s.word(static_cast<uint64_t>(i)));
+    const uint32_t code = quantize_one(v, c, K, L, s.word(static_cast<uint64_t>(i)));
     yhat[i] = levels[code];
     if (codes) codes[i] = static_cast<uint8_t>(code);
 }
@@ -407,7 +405,7 @@ qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
 
 template <int BITS, typename T, int NC>
 void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
-              uint64_t seed, double c, double K, qiht_qmatrix* q,
+              uint64_t seed, double c, double K, int L, qiht_qmatrix* q,
               hipStream_t st) {
     const int64_t nchunks = q->col_bytes / 16;
     dim3 grid(static_cast<unsigned>((nchunks + 3) / 4),
@@ -415,14 +413,14 @@ void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
     if (q->rows % 4 == 0)
         hipLaunchKernelGGL((k_quantize<BITS, T, NC, true>), grid, dim3(256), 0, st,
                            static_cast<const T*>(src), m, n, ld, q->rows,
-                           q->col_bytes, nchunks, c, K,
+                           q->col_bytes, nchunks, c, K, L,
                            static_cast<uint32_t>(seed),
                            static_cast<uint32_t>(seed >> 32), R, q->codes[0],
                            q->codes[1]);
     else
         hipLaunchKernelGGL((k_quantize<BITS, T, NC, false>), grid, dim3(256), 0, st,
                            static_cast<const T*>(src), m, n, ld, q->rows,
-                           q->col_bytes, nchunks, c, K,
+                           q->col_bytes, nchunks, c, K, L,
                            static_cast<uint32_t>(seed),
                            static_cast<uint32_t>(seed >> 32), R, q->codes[0],
                            q->codes[1]);
@@ -430,14 +428,14 @@ void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
 
 template <typename T, int NC>
 qiht_status dispatch_bits(int bits, const void* src, int64_t m, int64_t n,
-                          int64_t ld, int R, uint64_t seed, double c, double K,
+                          int64_t ld, int R, uint64_t seed, double c, double K, int L,
                           qiht_qmatrix* q, hipStream_t st) {
     switch (bits) {
-        case 1: launch_q<1, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
-        case 2: launch_q<2, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
-        case 4: launch_q<4, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
-        case 8: launch_q<8, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
-        case 32: launch_q<32, T, NC>(src, m, n, ld, R, seed, c, K, q, st); break;
+        case 1: launch_q<1, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
+        case 2: launch_q<2, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
+        case 4: launch_q<4, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
+        case 8: launch_q<8, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
+        case 32: launch_q<32, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
         default: return fail(QIHT_ERR_UNSUPPORTED, "unsupported bit width");
     }
     QIHT_HIP(hipGetLastError());
@@ -460,13 +458,13 @@ qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
 
 qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
                                    int64_t n, int64_t ld, int bits, int R,
-                                   uint64_t seed, double c, double K,
+                                   uint64_t seed, double c, double K, int levels,
                                    qiht_qmatrix* q, hipStream_t st) {
     switch (dt) {
-        case QIHT_F32: return dispatch_bits<float, 1>(bits, src, m, n, ld, R, seed, c, K, q, st);
-        case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, q, st);
-        case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
-        case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, q, st);
+        case QIHT_F32: return dispatch_bits<float, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
+        case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
+        case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
+        case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
     }
     return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
 }
@@ -483,7 +481,7 @@ qiht_status launch_store_matrix(const void* src, qiht_dtype dt, int64_t m, int64
 }
 
 qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
-                                   int bits, uint64_t seed, double c,
+                                   int bits, int levels, uint64_t seed, double c,
                                    double K, const double* levels_dev,
                                    double* yhat, uint8_t* codes,
                                    hipStream_t st) {
@@ -495,22 +493,22 @@ qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
     switch (dt) {
         case QIHT_F32:
             hipLaunchKernelGGL((k_quantize_vec<float, 1>), grid, dim3(256), 0, st,
-                               static_cast<const float*>(y), m, rows, bits, c, K, k0, k1,
+                               static_cast<const float*>(y), m, rows, bits, levels, c, K, k0, k1,
                                levels_dev, yhat, codes);
             break;
         case QIHT_F64:
             hipLaunchKernelGGL((k_quantize_vec<double, 1>), grid, dim3(256), 0, st,
-                               static_cast<const double*>(y), m, rows, bits, c, K, k0, k1,
+                               static_cast<const double*>(y), m, rows, bits, levels, c, K, k0, k1,
                                levels_dev, yhat, codes);
             break;
         case QIHT_C64:
             hipLaunchKernelGGL((k_quantize_vec<float, 2>), grid, dim3(256), 0, st,
-                               static_cast<const float*>(y), m, rows, bits, c, K, k0, k1,
+                               static_cast<const float*>(y), m, rows, bits, levels, c, K, k0, k1,
                                levels_dev, yhat, codes);
             break;
         case QIHT_C128:
             hipLaunchKernelGGL((k_quantize_vec<double, 2>), grid, dim3(256), 0, st,
-                               static_cast<const double*>(y), m, rows, bits, c, K, k0, k1,
+                               static_cast<const double*>(y), m, rows, bits, levels, c, K, k0, k1,
                                levels_dev, yhat, codes);
             break;
     }

@@ -73,6 +73,10 @@ def test_quantize_matrix_validation(lib):
     assert f(ptr, 4, 4, 4, 9, 4, 2, 0, None, C.byref(out)) == 2      # dtype
     assert f(ptr, 4, 4, 4, 1, 3, 2, 0, None, C.byref(out)) == 2      # bits
     assert f(ptr, 4, 4, 4, 1, 4, 3, 0, None, C.byref(out)) == 1      # realizations
+    odd = 0x100  # QIHT_ODD_LEVELS
+    assert f(ptr, 4, 4, 4, 1, 1 | odd, 2, 0, None, C.byref(out)) == 2  # odd set needs b >= 2
+    assert f(ptr, 4, 4, 4, 1, 32 | odd, 2, 0, None, C.byref(out)) == 2  # and packed codes
+    assert f(ptr, 4, 4, 4, 1, 116 | odd, 2, 0, None, C.byref(out)) == 2  # not a dense format
     assert out.value in (None, 0), "output touched on error"
     assert "bits" in lib.qiht_last_error().decode() or True
 
@@ -82,8 +86,10 @@ def test_quantize_vector_validation(lib):
     f = lib.qiht_quantize_vector
     assert f(None, 4, 1, 8, 0, None, ptr, None, None) == 1
     assert f(ptr, 0, 1, 8, 0, None, ptr, None, None) == 1
-    assert f(ptr, 4, 1, 9, 0, None, ptr, None, None) == 2
+    assert f(ptr, 4, 1, 13, 0, None, ptr, None, None) == 2   # 1..12 or 32
     assert f(ptr, 4, 1, 32, 0, None, ptr, ptr, None) == 1   # no codes at 32 bits
+    assert f(ptr, 4, 1, 10, 0, None, ptr, ptr, None) == 1   # byte codes only up to 8 bits
+    assert f(ptr, 4, 1, 1 | 0x100, 0, None, ptr, None, None) == 2  # odd set needs b >= 2
 
 
 def test_solve_validation(lib):
