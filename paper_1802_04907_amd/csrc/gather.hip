@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     // (one copy of the matrix: Q2_G g_G = Q1_G g_G, read once)
     const bool two = (MODE == G_MU) && (a.mu_mode == 0) && (pd.q1 != pd.q2);
     // the candidate compaction's inputs go out with the gather's loads
-    CandPre cpre;
+    CandPre<kGatherThreads> cpre;
     if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
     const uint8_t* A = (MODE == G_R) ? pd.q2 : pd.q1;
     const uint8_t* B = pd.q2;
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
             xw = pd.cval + static_cast<size_t>(pick) * pd.s;
         }
     }
-    CandPre cpre;
+    CandPre<kGatherThreads> cpre;
     if constexpr (MODE == G_MU) cpre = cand_preload<kGatherThreads>(pd, wg, pd.npart, true);
     const uint8_t* A = pd.q1;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;

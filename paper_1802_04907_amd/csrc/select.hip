@@ -696,7 +696,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
 __global__ __launch_bounds__(kGatherThreads) void k_candidates(const ProbDev* __restrict__ P) {
     const ProbDev& pd = P[blockIdx.y];
     if (pd.st->done || static_cast<int>(blockIdx.x) >= pd.npart) return;
-    const CandPre pre = cand_preload<kGatherThreads>(pd, blockIdx.x, pd.npart, false);
+    const CandPre<kGatherThreads> pre = cand_preload<kGatherThreads>(pd, blockIdx.x, pd.npart, false);
     compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.npart, false, pre);
 }
 
@@ -719,7 +719,6 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     if (skipped) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (ok) {
-            st->mu = mu0;
             st->phase = 1;  // the next residual gather takes the step-size test
         } else {
             st->done = 1;

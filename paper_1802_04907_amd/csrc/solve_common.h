@@ -29,7 +29,6 @@ struct SolveState {
     int32_t base_k;     // shrink count of the first proposal of the next round
     int32_t full_selects;  // proposals that needed the full n-key rank
     int32_t pad;
-    double mu;          // step of this iteration before any shrink
     double mu_last;     // accepted step of the last iteration
 };
 
@@ -333,20 +332,24 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
 // path cannot be used (t in the subnormal range, or a non-finite g in the
 // block: the full path flags those).
 // Inputs of compact_candidates that do not depend on anything computed in
-// the calling kernel, loaded ahead: the histogram (wave 0, top-down, 32 bins
-// per lane) and this thread's first entry of the index block.
+// the calling kernel, loaded ahead: thread t's 2048 / NT histogram bins
+// (from the top: bins 2047 - (2048 / NT) t - i) and its first entry of the
+// index block.
+template <int NT>
 struct CandPre {
-    uint32_t h[32];
+    static constexpr int PER = 2048 / NT;
+    static_assert(2048 % NT == 0, "the histogram is split evenly over the threads");
+    uint32_t h[PER];
     float g0;
     uint32_t bm0;
 };
 
 template <int NT>
-__device__ __forceinline__ CandPre cand_preload(const ProbDev& pd, int wg, int nw, bool with_support) {
-    CandPre c;
-    const int tid = threadIdx.x, lane = tid & 63;
+__device__ __forceinline__ CandPre<NT> cand_preload(const ProbDev& pd, int wg, int nw, bool with_support) {
+    CandPre<NT> c;
+    const int tid = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) c.h[i] = tid < 64 ? ldg_u32(pd.hist + (2047 - 32 * lane - i)) : 0u;
+    for (int i = 0; i < CandPre<NT>::PER; ++i) c.h[i] = ldg_u32(pd.hist + (2047 - CandPre<NT>::PER * tid - i));
     const int per = (pd.n + nw - 1) / nw;
     const int lo = wg * per, hi = min(pd.n, lo + per);
     const int j = min(lo + tid, hi - 1);  // clamped: a thread past the block ignores it
@@ -357,38 +360,38 @@ __device__ __forceinline__ CandPre cand_preload(const ProbDev& pd, int wg, int n
 
 template <int NT>
 __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_support,
-                                   const CandPre& pre) {
+                                   const CandPre<NT>& pre) {
     constexpr int NW = NT / 64;
+    constexpr int PER = CandPre<NT>::PER;
     __shared__ float s_thr;
     __shared__ int s_fast;
     __shared__ uint32_t s_wc[NW];
+    __shared__ uint32_t s_scan[NW];
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = pd.n, s = pd.s;
     const int nsup = with_support ? s : 0;
+    // more than s entries off the support: the threshold bin of the s-th
+    // largest (no bin found, i.e. counts inconsistent with n: the full path)
+    const bool ranked = n - nsup > s;
     if (tid == 0) {
         s_thr = 0.f;
-        s_fast = 1;
+        s_fast = ranked ? 0 : 1;
         s_bad = 0;
     }
-    __syncthreads();
-    if (wv == 0 && n - nsup > s) {
+    if (ranked) {  // uniform
         uint32_t c = 0;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) c += pre.h[i];
-        const uint32_t x = wave_incl_scan(c);
-        uint32_t run = x - c;
+        for (int i = 0; i < PER; ++i) c += pre.h[i];
+        uint32_t run = block_excl_scan<NT>(c, s_scan, nullptr);  // bins from the top
         const uint32_t want = static_cast<uint32_t>(s);
-        const uint64_t hit = __ballot(run < want && want <= x);
-        if (hit == 0ull) {
-            if (lane == 0) s_fast = 0;  // counts inconsistent with n: full path
-        } else if (lane == __ffsll(static_cast<long long>(hit)) - 1) {
+        if (run < want && want <= run + c) {
             int bin = 0;
             bool found = false;
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < PER; ++i) {
                 if (!found && run + pre.h[i] >= want) {
-                    bin = 2047 - 32 * lane - i;
+                    bin = 2047 - PER * tid - i;
                     found = true;
                 }
                 run += pre.h[i];
