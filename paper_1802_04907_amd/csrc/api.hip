@@ -71,7 +71,7 @@ qiht_status check_params(const qiht_params* p) {
 }
 
 SolveArgs to_args(const qiht_params* p) {
-    SolveArgs a;
+    SolveArgs a{};
     a.max_iters = p->max_iters;
     a.tol = p->tol;
     a.k = p->k;

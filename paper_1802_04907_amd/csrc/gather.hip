@@ -12,10 +12,12 @@
 // row's sum has one fixed order and results are bitwise reproducible.  No
 // workgroup waits on another: the per-workgroup partial dot products of
 // G_MU and G_OMEGA are finished, in workgroup order, by the next kernel.
-// G_R after the first round also takes the step-size test of the previous
-// round's proposals: every workgroup computes the same pick from the omega
-// partials and gathers the picked proposal's support and values, and one
-// extra workgroup per problem commits it (decide_pick, commit_round).
+// For a single problem, G_R after the first round also takes the step-size
+// test of the previous round's proposals: every workgroup computes the same
+// pick from the omega partials and gathers the picked proposal's support and
+// values, and one extra workgroup commits it (decide_pick, commit_round).
+// Batches commit in k_commit before the gather instead (thousands of gather
+// workgroups would each repeat the test's round trip).
 #include "solve_common.h"
 
 namespace qiht {
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     // here, by every workgroup alike; one extra workgroup commits it
     __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
     __shared__ int s_done;
-    const bool decide = MODE == G_R && !zero_x && pd.st->phase == 1;
+    const bool decide = MODE == G_R && !zero_x && a.decide_in_gather && pd.st->phase == 1;
     if (MODE == G_R && wg == pd.nwg) {
         if (decide && !pd.st->done) commit_round<kGatherThreads>(pd, a, s_dec);
         return;
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     // during the launch.
     __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
     __shared__ int s_done;
-    const bool decide = MODE == G_R && !zero_x && pd.st->phase == 1;
+    const bool decide = MODE == G_R && !zero_x && a.decide_in_gather && pd.st->phase == 1;
     const int done_now = pd.st->done;
     if (MODE == G_R && wg == pd.npart) {
         if (decide && !done_now) commit_round<kGatherThreads>(pd, a, s_dec);

@@ -95,6 +95,7 @@ struct SolveArgs {
     int32_t max_backtracks;
     int32_t mu_mode;
     int32_t profile;
+    int32_t decide_in_gather;  // the residual gather takes the step-size test (else k_commit)
 };
 
 

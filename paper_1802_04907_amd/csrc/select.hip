@@ -727,6 +727,15 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     }
 }
 
+// Batches: the step-size test and commit of the last round's proposals, one
+// workgroup per problem, before the residual gather.
+__global__ __launch_bounds__(kGatherThreads) void k_commit(const ProbDev* __restrict__ P, SolveArgs a) {
+    const ProbDev& pd = P[blockIdx.x];
+    __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
+    if (pd.st->done || pd.st->phase != 1) return;
+    commit_round<kGatherThreads>(pd, a, s_dec);
+}
+
 __global__ __launch_bounds__(kSelectThreads) void k_hard_threshold(const float* a, int n, int s,
                                                                    int32_t* out, int* err) {
     __shared__ SelShared S;
@@ -746,6 +755,10 @@ void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st) {
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st) {
     const dim3 grid(mode == SEL_INIT ? 1 : kSpec, count);
     hipLaunchKernelGGL(k_propose, grid, dim3(kSelectThreads), 0, st, P, a, mode);
+}
+
+void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_commit, dim3(count), dim3(kGatherThreads), 0, st, P, a);
 }
 
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st) {

@@ -530,6 +530,7 @@ void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st);
+void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t st);
 
 // The step-size test of Algorithm 2 (Sec. II-A) on the kSpec proposals of
 // the last round, shrink counts k = base_k, base_k + 1, ... in order: a

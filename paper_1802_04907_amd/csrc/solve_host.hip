@@ -413,11 +413,13 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
     if (pl.any_slab) launch_slab_reduce(dP, count, st);
 }
 
-// One round: the residual gather first takes the step-size test of the
-// previous round's proposals (and commits the pick), then the gradient, mu,
-// the kSpec proposals of this round and their omegas.
+// One round: the step-size test of the previous round's proposals and its
+// commit (in the residual gather for a single problem, in k_commit before it
+// for a batch), then the gradient, mu, the kSpec proposals of this round and
+// their omegas.
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                         const SolveArgs& a, hipStream_t st, PassTimer* tm) {
+    if (!a.decide_in_gather) launch_commit(dP, count, a, st);
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
     launch_propose(dP, count, a, SEL_STEP, st);
@@ -449,8 +451,10 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
 
 }  // namespace
 
-qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& a, qiht_info* infos,
+qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qiht_info* infos,
                       hipStream_t st) {
+    SolveArgs a = args;
+    a.decide_in_gather = count == 1 ? 1 : 0;
     Plan pl;
     Workspace ws;
     ProbDev* dP = nullptr;
@@ -559,7 +563,7 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float*
         QIHT_HIP(hipMemcpyAsync(dx0, &x, sizeof(float*), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_warm_start, dim3(1), dim3(256), 0, st, dP, dx0);
     }
-    SolveArgs a{1, -1.0, 2.0, 0.01, 0, 0, 0};
+    SolveArgs a{1, -1.0, 2.0, 0.01, 0, 0, 0, 0};
     gradient_launches(pl, dP, dT, 1, a, s == 0 ? 1 : 0, st, nullptr);
     QIHT_HIP(hipGetLastError());
     QIHT_HIP(hipMemcpyAsync(g_out, h.g, sizeof(float) * h.n, hipMemcpyDeviceToDevice, st));

@@ -363,6 +363,39 @@ def test_teacher_forced_deep_backtracking(max_bt):
         assert capped >= 1
 
 
+def test_batched_deep_backtracking():
+    """A batch (the test and commit then run in their own launch before the
+    residual gather) with k(1-c) = 1.05, c = 0.3: rounds of further shrinks
+    per problem, checked against the oracle's iterations from the FP32 state
+    (support, iterations, shrinks, x)."""
+    k, c, iters = 1.5, 0.3, 10
+    probs = [workloads.gaussian(256, 1024, 16, 1e-3, seed=40 + i) for i in range(3)]
+    gpu = []
+    for p in probs:
+        q, yhat = _gpu_problem(p, 8)
+        gpu.append((q, yhat, p.s))
+    res = qiht.niht_solve_batched(gpu, max_iters=iters, tol=-1.0, k=k, c=c)
+    deep = 0
+    for p, (x, sup, info) in zip(probs, res):
+        q1, q2, yh = _oracle_mats(p, 8)
+        xr, sr = np.zeros(p.n), niht.initial_support(q1, yh, p.s)
+        its = bts = 0
+        for _ in range(iters):
+            r = niht.qiht_iteration(q1, q2, yh, xr.astype(np.float32).astype(np.float64), sr, p.s,
+                                    k=k, c=c)
+            if r.stationary:
+                break
+            its += 1
+            bts += r.backtracks
+            deep += r.backtracks >= 4
+            xr, sr = r.x, r.support
+        say(f"  seed {p.seed}: shrinks gpu {info['backtracks']} oracle {bts}, iterations {its}")
+        np.testing.assert_array_equal(sup.cpu().numpy(), sr)
+        assert info["iterations"] == its and info["backtracks"] == bts
+        assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-5 * np.linalg.norm(xr)
+    assert deep >= 3
+
+
 def test_determinism_bitwise():
     p = workloads.gaussian(400, 1500, 20, 1e-3, seed=7)
     q, yhat = _gpu_problem(p, 4)
