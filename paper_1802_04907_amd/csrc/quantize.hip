@@ -20,15 +20,15 @@ namespace {
 
 constexpr double kTwo32 = 4294967296.0;
 
-// One stochastic rounding decision.  L levels; c the scale; K = (L-1)/(2c)
-// (0 when c == 0, which sends every value to code 0).
+// One stochastic rounding decision.  top = L - 2 for L levels; c the scale;
+// K = (L-1)/(2c) (0 when c == 0, which sends every value to code 0).
 __device__ __forceinline__ uint32_t quantize_one(double v, double c, double K,
-                                                 int L, uint32_t u) {
+                                                 double top, uint32_t u) {
 #pragma clang fp contract(off)
     const double t = v + c;
     const double p = t * K;
     double fi = floor(p);
-    fi = fmin(fmax(fi, 0.0), static_cast<double>(L - 2));
+    fi = fmin(fmax(fi, 0.0), top);
     const double f = p - fi;
     const uint32_t up = (static_cast<double>(u) < f * kTwo32) ? 1u : 0u;
     return static_cast<uint32_t>(fi) + up;
@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void k_quantize(
     if (j >= n || chunk >= nchunks) return;
     const int64_t i0 = chunk * RPC;
     const size_t off = static_cast<size_t>(j) * col_bytes + chunk * 16;
+    const double top = static_cast<double>(L - 2);  // highest floor position
 
     if constexpr (BITS == 32) {
         float vals[4];
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void k_quantize(
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int q = 4 * b + t;
-                    const uint32_t code = q < nlive ? quantize_one(static_cast<double>(v[q]), c, K, L, uu[t]) : 0u;
+                    const uint32_t code = q < nlive ? quantize_one(static_cast<double>(v[q]), c, K, top, uu[t]) : 0u;
                     w[(q * BITS) >> 5] |= code << ((q * BITS) & 31);
                 }
             }
@@ -214,9 +215,9 @@ __global__ __launch_bounds__(256) void k_quantize(
             const double v = load_stacked<T, NC>(src, m, ld, i, j);
             const uint64_t e = ebase + i;
             const int bit = q * BITS;
-            w0[bit >> 5] |= quantize_one(v, c, K, L, s0.word(e)) << (bit & 31);
+            w0[bit >> 5] |= quantize_one(v, c, K, top, s0.word(e)) << (bit & 31);
             if (R > 1)
-                w1[bit >> 5] |= quantize_one(v, c, K, L, s1.word(e)) << (bit & 31);
+                w1[bit >> 5] |= quantize_one(v, c, K, top, s1.word(e)) << (bit & 31);
         }
         *reinterpret_cast<uint4*>(out0 + off) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
         if (R > 1)
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(256) void k_quantize_vec(
         return;
     }
     PhiloxStream s{k0, k1, 1u, 0u};
-    const uint32_t code = quantize_one(v, c, K, L, s.word(static_cast<uint64_t>(i)));
+    const uint32_t code = quantize_one(v, c, K, static_cast<double>(L - 2), s.word(static_cast<uint64_t>(i)));
     yhat[i] = levels[code];
     if (codes) codes[i] = static_cast<uint8_t>(code);
 }
