@@ -459,6 +459,32 @@ def test_zero_observation_is_stationary():
     np.testing.assert_array_equal(sup.cpu().numpy(), [0, 1, 2])
 
 
+def test_batch_with_a_stationary_problem():
+    # one problem stops at once (zero observation) while the others of the
+    # batch iterate: the batch's commit launch and the proposals skip it
+    zero = workloads.gaussian(50, 100, 3, 0.0, seed=1)
+    live = [workloads.gaussian(200, 600, 8, 1e-3, seed=60 + i) for i in range(2)]
+    qz0 = qiht.quantize_matrix(_t(zero.phi), 4, 2, zero.seed)
+    probs = [(qz0, torch.zeros(50, dtype=torch.float64, device=DEV), 3)]
+    for p in live:
+        q, yhat = _gpu_problem(p, 4)
+        probs.append((q, yhat, p.s))
+    res = qiht.niht_solve_batched(probs, max_iters=50, tol=-1.0)
+    x0, s0, i0 = res[0]
+    assert i0["reason"] == "stationary" and i0["iterations"] == 0
+    assert torch.count_nonzero(x0) == 0
+    for p, (x, sup, info) in zip(live, res[1:]):
+        q1, q2, yh = _oracle_mats(p, 4)
+        xr, sr = np.zeros(p.n), niht.initial_support(q1, yh, p.s)
+        for _ in range(50):  # the oracle's iterations from the FP32 state
+            r = niht.qiht_iteration(q1, q2, yh, xr.astype(np.float32).astype(np.float64), sr, p.s)
+            xr, sr = r.x, r.support
+        np.testing.assert_array_equal(sup.cpu().numpy(), sr)
+        assert info["iterations"] == 50
+        err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
+        assert err <= 1e-4, err
+
+
 def test_invalid_s_rejected_on_device_handle():
     p = workloads.gaussian(30, 40, 3, 0.0, seed=1)
     q, yhat = _gpu_problem(p, 4)
