@@ -267,6 +267,30 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
                                     void* stream);
 
 /*
+ * Algorithm 2 with its realizations drawn per iteration, as its input lists
+ * them: 2n* realizations of Q(Phi) and n* of Q(y).  Iteration n uses
+ * Phi_hat_{2n-1} for Phi^T and Phi_hat_{2n} for Phi (matrix realizations
+ * 2n-2 and 2n-1 on the counter of qiht_quantize_matrix) and y_hat_n (vector
+ * realization n-1: counter (e >> 2, 1, n-1)); the initial support uses
+ * Phi_hat_1 and y_hat_1.  Backtracking within an iteration reuses its
+ * draws.  Each iteration re-quantizes Phi and y on the device (a full read
+ * of Phi per iteration).
+ *
+ *   phi: as qiht_quantize_matrix (M x N, row-major, ld, dtype); bits 1, 2,
+ *        4, 8 (optionally | QIHT_ODD_LEVELS) or 32.
+ *   y:   M entries of ydtype (complex exactly when dtype is); ybits as
+ *        qiht_quantize_vector.  Both arrays are read by every iteration and
+ *        must stay valid until the call returns.
+ *   seed, s, p, x_out, support_out, info: as qiht_niht_solve (no warm start,
+ *        no refit: INVALID_ARG / UNSUPPORTED).  Synchronizes stream.
+ */
+qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t ld,
+                                  qiht_dtype dtype, int bits, const void* y,
+                                  qiht_dtype ydtype, int ybits, uint64_t seed, int64_t s,
+                                  const qiht_params* p, float* x_out,
+                                  int32_t* support_out, qiht_info* info, void* stream);
+
+/*
  * One evaluation of the gradient pair at a given sparse x:
  *   r = y_hat - Q2_G x_G (FP64 accumulation, rounded to FP32 for the pass)
  *   g = Q1^T r (FP32)

@@ -47,6 +47,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import quantizer
+
 REASON_CONVERGED = 1
 REASON_MAX_ITERS = 2
 REASON_STATIONARY = 3
@@ -219,6 +221,50 @@ def qiht_solve(phi1, phi2, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01,
             reason = REASON_CONVERGED
             break
     return SolveResult(x, sup, it, reason, total_bt, capped_its, mu_last, trace)
+
+
+def qiht_solve_fresh(phi, y, s, bits, ybits, seed, max_iters=300, tol=1e-8, k=2.0,
+                     c=0.01, max_backtracks=32, mu_mode="cross", x_fp32=False):
+    """Algorithm 2 as its input states: 2n* realizations of Q(Phi) and n* of
+    Q(y).  Iteration n uses Phi_hat_{2n-1} for Phi^T and Phi_hat_{2n} for
+    Phi (matrix realizations 2n-2 and 2n-1) and y_hat_n (vector realization
+    n-1); the initial support uses Phi_hat_1 and y_hat_1.  Realizations are
+    drawn per iteration, not per trial of the step size: backtracking within
+    an iteration reuses them.  ``x_fp32`` rounds x to FP32 between iterations
+    (the state the GPU solver holds)."""
+    def draws(it):
+        q1 = quantizer.dequantized_matrix(phi, bits, seed, 2 * (it - 1))
+        q2 = quantizer.dequantized_matrix(phi, bits, seed, 2 * (it - 1) + 1)
+        yh = quantizer.dequantized_vector(y, ybits, seed, realization=it - 1)
+        return q1, q2, yh
+    q1, q2, yh = draws(1)
+    n = q1.shape[1]
+    if not (1 <= s <= min(q1.shape)):
+        raise ValueError("need 1 <= s <= min(m, n)")
+    x = np.zeros(n)
+    sup = initial_support(q1, yh, s)
+    reason = REASON_MAX_ITERS
+    it = 0
+    total_bt = capped_its = 0
+    mu_last = 0.0
+    for it in range(1, max_iters + 1):
+        if it > 1:
+            q1, q2, yh = draws(it)
+        xs = x.astype(np.float32).astype(np.float64) if x_fp32 else x
+        res = qiht_iteration(q1, q2, yh, xs, sup, s, k, c, max_backtracks, mu_mode)
+        if res.stationary:
+            it -= 1
+            reason = REASON_STATIONARY
+            break
+        dx = float(np.linalg.norm(res.x - xs))
+        x, sup = res.x, res.support
+        mu_last = res.mu
+        total_bt += res.backtracks
+        capped_its += int(res.capped)
+        if dx <= tol * float(np.linalg.norm(x)):
+            reason = REASON_CONVERGED
+            break
+    return SolveResult(x, sup, it, reason, total_bt, capped_its, mu_last, [])
 
 
 def refit(phi, yhat, support):

@@ -120,15 +120,16 @@ def quantize_matrix(phi, bits, seed, realization, odd=False):
     return codes.reshape((rows, n), order="F"), c
 
 
-def quantize_vector(y, bits, seed, odd=False):
-    """Q(y, b): one realization on the vector stream.
+def quantize_vector(y, bits, seed, odd=False, realization=0):
+    """Q(y, b): one realization on the vector stream (realization 0 unless
+    the realizations of Algorithm 2 are drawn one per iteration).
 
     returns (codes int64, c) for bits < 32, or (fp32 values, None).
     """
     a = stack_real(np.asarray(y).reshape(-1, 1)).reshape(-1)
     if int(bits) == 32:
         return a.astype(np.float32).astype(np.float64), None
-    return quantize(a, bits, seed, STREAM_VECTOR, 0, odd)
+    return quantize(a, bits, seed, STREAM_VECTOR, realization, odd)
 
 
 def dequantized_matrix(phi, bits, seed, realization, odd=False):
@@ -139,9 +140,9 @@ def dequantized_matrix(phi, bits, seed, realization, odd=False):
     return dequantize(codes, c, bits, odd)
 
 
-def dequantized_vector(y, bits, seed, odd=False):
+def dequantized_vector(y, bits, seed, odd=False, realization=0):
     """Convenience: the FP64 vector y_hat."""
-    codes, c = quantize_vector(y, bits, seed, odd)
+    codes, c = quantize_vector(y, bits, seed, odd, realization)
     if c is None:
         return codes
     return dequantize(codes, c, bits, odd)

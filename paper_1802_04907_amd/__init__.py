@@ -194,6 +194,30 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
     return x, sup, _info_dict(inf)
 
 
+def niht_solve_fresh(phi, y, s, bits, ybits=8, seed=0, max_iters=300, tol=1e-8, k=2.0,
+                     c=0.01, max_backtracks=32, mu_mode=0, stream=None, odd=False, yodd=False,
+                     profile=False):
+    """Algorithm 2 with new realizations of Q(Phi) and Q(y) every iteration
+    (``phi``: (m, n) row-major CUDA tensor, ``y``: its m observations; both are
+    re-quantized on the device each iteration) -> (x, support, info)."""
+    torch = _torch()
+    if phi.dim() != 2 or phi.stride(1) != 1 or not phi.is_cuda:
+        raise ValueError("phi must be a 2-D row-major CUDA tensor")
+    if y.dim() != 1 or not y.is_contiguous() or not y.is_cuda:
+        raise ValueError("y must be a contiguous 1-D CUDA tensor")
+    m, n = phi.shape
+    x = torch.empty(n, dtype=torch.float32, device=phi.device)
+    sup = torch.empty(s, dtype=torch.int32, device=phi.device)
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, profile=profile)
+    inf = _lib.QihtInfo()
+    _check(_lib.load().qiht_niht_solve_fresh(
+        _ptr(phi), m, n, phi.stride(0), _dtype_code(phi), int(bits) | (ODD_LEVELS if odd else 0),
+        _ptr(y), _dtype_code(y), int(ybits) | (ODD_LEVELS if yodd else 0),
+        C.c_uint64(int(seed) & (2**64 - 1)), int(s), C.byref(p), _ptr(x), _ptr(sup),
+        C.byref(inf), _stream(stream)))
+    return x, sup, _info_dict(inf)
+
+
 def niht_solve_batched(problems, max_iters=300, tol=1e-8, k=2.0, c=0.01,
                        max_backtracks=32, mu_mode=0, stream=None, profile=False, refit=False):
     """Batched solve; ``problems`` is a list of (QMatrix, yhat, s).

@@ -54,6 +54,10 @@ SIGNATURES = {
     "qiht_niht_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
                                   C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
                                   C.POINTER(QihtInfo), C.c_void_p]),
+    "qiht_niht_solve_fresh": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                        C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_uint64,
+                                        C.c_int64, C.POINTER(QihtParams), C.c_void_p,
+                                        C.c_void_p, C.POINTER(QihtInfo), C.c_void_p]),
     "qiht_niht_solve_batched": (C.c_int, [C.c_int32, C.POINTER(QihtProblem),
                                           C.POINTER(QihtParams),
                                           C.POINTER(QihtInfo), C.c_void_p]),

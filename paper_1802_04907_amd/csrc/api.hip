@@ -443,6 +443,98 @@ qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat, int64_t s
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }
 
+qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t ld,
+                                  qiht_dtype dtype, int bits, const void* y,
+                                  qiht_dtype ydtype, int ybits, uint64_t seed, int64_t s,
+                                  const qiht_params* p, float* x_out,
+                                  int32_t* support_out, qiht_info* info, void* stream) try {
+    set_error("");
+    if (!phi || !y || !x_out || !support_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    if (p->x0 || p->support0) return fail(QIHT_ERR_INVALID_ARG, "no warm start with per-iteration draws");
+    if (p->refit) return fail(QIHT_ERR_UNSUPPORTED, "no refit with per-iteration draws");
+    if (!dtype_ok(dtype) || !dtype_ok(ydtype)) return fail(QIHT_ERR_UNSUPPORTED, "unknown dtype");
+    if (is_complex(dtype) != is_complex(ydtype))
+        return fail(QIHT_ERR_INVALID_ARG, "y must be complex exactly when Phi is");
+    const int pbits = bits & ~QIHT_ODD_LEVELS;
+    if (pbits != 1 && pbits != 2 && pbits != 4 && pbits != 8 && pbits != 32)
+        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8 or 32 (packed codes)");
+    const bool yodd = (ybits & QIHT_ODD_LEVELS) != 0;
+    const int yb = ybits & ~QIHT_ODD_LEVELS;
+    if (!bits_ok_vector(yb) || (yodd && (yb < 2 || yb > 12)))
+        return fail(QIHT_ERR_UNSUPPORTED, "ybits must be 1..12 or 32 (odd levels: 2..12)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // iteration 1's draws (matrix realizations 0 and 1, y_hat realization 0),
+    // through the ordinary entry points; they validate the rest
+    qiht_qmatrix* q = nullptr;
+    s0 = qiht_quantize_matrix(phi, m, n, ld, dtype, bits, 2, seed, stream, &q);
+    if (s0 != QIHT_OK) return s0;
+    const int64_t rows = q->rows;
+    double* yhat = nullptr;
+    double* ylev = nullptr;
+    const int ylevels = (yb == 32) ? 0 : num_levels(yb, yodd);
+    auto cleanup = [&]() {
+        if (yhat) (void)hipFree(yhat);
+        if (ylev) (void)hipFree(ylev);
+        qiht_qmatrix_free(q);
+    };
+    if (hipMalloc(reinterpret_cast<void**>(&yhat), sizeof(double) * rows) != hipSuccess ||
+        (ylevels && hipMalloc(reinterpret_cast<void**>(&ylev), sizeof(double) * ylevels) != hipSuccess)) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(QIHT_ERR_OUT_OF_MEMORY, "y_hat allocation failed");
+    }
+    double yc = 0.0;
+    s0 = qiht_quantize_vector(y, m, ydtype, ybits, seed, stream, yhat, nullptr, &yc);
+    if (s0 == QIHT_OK) s0 = check_problem(q, yhat, s, x_out, support_out);
+    if (s0 != QIHT_OK) {
+        const std::string why = last_error_cstr();
+        cleanup();
+        return fail(s0, why);
+    }
+    if (ylevels) {
+        std::vector<double> h(ylevels);
+        for (int k = 0; k < ylevels; ++k) h[k] = yc * (2.0 * k / static_cast<double>(ylevels - 1) - 1.0);
+        if (hipMemcpy(ylev, h.data(), sizeof(double) * ylevels, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            return fail(QIHT_ERR_DEVICE, "level table copy failed");
+        }
+    }
+    FreshSource f{};
+    f.phi = phi;
+    f.dtype = dtype;
+    f.m = m;
+    f.n = n;
+    f.ld = ld;
+    f.bits = q->bits;
+    f.levels = (q->bits == 32) ? 0 : num_levels(q->bits, (bits & QIHT_ODD_LEVELS) != 0);
+    f.seed = seed;
+    f.c = q->scale;
+    f.K = (q->bits == 32 || f.c == 0.0) ? 0.0 : (f.levels - 1) / (2.0 * f.c);
+    f.q = q;
+    f.y = y;
+    f.ydtype = ydtype;
+    f.ybits = yb;
+    f.ylevels = ylevels;
+    f.yc = yc;
+    f.yK = (ylevels && yc > 0.0) ? (ylevels - 1) / (2.0 * yc) : 0.0;
+    f.ylev = ylev;
+    f.yhat = yhat;
+    ProblemIn in{q, yhat, s, x_out, support_out, nullptr, nullptr};
+    qiht_info tmp;
+    s0 = run_solve(&in, 1, to_args(p), &tmp, st, &f);
+    const hipError_t e = hipStreamSynchronize(st);
+    cleanup();
+    if (s0 != QIHT_OK) return s0;
+    if (e != hipSuccess) return hip_fail(e, "solve_fresh");
+    if (info) *info = tmp;
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
 qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
                                     const qiht_params* p, qiht_info* infos,
                                     void* stream) try {

@@ -77,14 +77,16 @@ qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
 qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
                                    int64_t n, int64_t ld, int bits, int R,
                                    uint64_t seed, double c, double K, int levels,
-                                   qiht_qmatrix* q, hipStream_t st);
+                                   qiht_qmatrix* q, hipStream_t st,
+                                   const int32_t* rbase = nullptr, const int32_t* stop = nullptr);
 qiht_status launch_store_matrix(const void* src, qiht_dtype dt, int64_t m, int64_t n,
                                 int64_t ld, int fmt, qiht_qmatrix* q, hipStream_t st);
 qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
                                    int bits, int levels, uint64_t seed, double c,
                                    double K, const double* levels_dev,
                                    double* yhat, uint8_t* codes,
-                                   hipStream_t st);
+                                   hipStream_t st, const int32_t* rbase = nullptr,
+                                   const int32_t* stop = nullptr);
 
 // ---- solver (solve.hip) ----
 struct SolveArgs {
@@ -109,8 +111,26 @@ struct ProblemIn {
     const int32_t* support0;
 };
 
+// Algorithm 2 with its realizations drawn per iteration (one problem): the
+// sources and quantizer constants each round re-quantizes from.
+struct FreshSource {
+    const void* phi;
+    qiht_dtype dtype;
+    int64_t m, n, ld;
+    int bits, levels;       // internal bit width, levels of the code set
+    uint64_t seed;
+    double c, K;            // scale and (levels - 1) / (2c) of the matrix
+    qiht_qmatrix* q;        // the handle whose two code buffers are rewritten
+    const void* y;
+    qiht_dtype ydtype;
+    int ybits, ylevels;
+    double yc, yK;
+    const double* ylev;     // device: the level values of y
+    double* yhat;           // device: the y_hat the solve reads
+};
+
 qiht_status run_solve(const ProblemIn* probs, int count, const SolveArgs& a,
-                      qiht_info* infos, hipStream_t st);
+                      qiht_info* infos, hipStream_t st, const FreshSource* fresh = nullptr);
 
 qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat,
                          const float* x, const int32_t* support, int64_t s,

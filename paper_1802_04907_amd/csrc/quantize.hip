@@ -150,7 +150,8 @@ __global__ __launch_bounds__(256) void k_quantize(
     const T* __restrict__ src, int64_t m, int64_t n, int64_t ld, int64_t rows,
     int64_t col_bytes, int64_t nchunks, double c, double K, int L, uint32_t k0,
     uint32_t k1, int R, uint8_t* __restrict__ out0,
-    uint8_t* __restrict__ out1) {
+    uint8_t* __restrict__ out1, const int32_t* __restrict__ rbase,
+    const int32_t* __restrict__ stop) {
     constexpr int RPC = (BITS == 32) ? 4 : 128 / BITS;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -160,6 +161,11 @@ __global__ __launch_bounds__(256) void k_quantize(
     const int64_t j = static_cast<int64_t>(blockIdx.y) * 64 + lane;
     const int64_t chunk = static_cast<int64_t>(blockIdx.x) * 4 + wave;
     if (j >= n || chunk >= nchunks) return;
+    // realizations drawn per iteration: copies 2 it and 2 it + 1 for the
+    // iteration it + 1 that *rbase = it completed ones precede (else 0, 1);
+    // nothing to do once *stop is set
+    if (stop && *stop) return;
+    const uint32_t rb = rbase ? 2u * static_cast<uint32_t>(*rbase) : 0u;
     const int64_t i0 = chunk * RPC;
     const size_t off = static_cast<size_t>(j) * col_bytes + chunk * 16;
     const double top = static_cast<double>(L - 2);  // highest floor position
@@ -190,7 +196,7 @@ __global__ __launch_bounds__(256) void k_quantize(
             for (int b = 0; b < RPC / 4; ++b) {
                 const uint64_t blk = b0 + b;
                 const uint4 u = philox10(make_uint4(static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
-                                                    0u, static_cast<uint32_t>(r)),
+                                                    0u, rb + static_cast<uint32_t>(r)),
                                          k0, k1);
                 const uint32_t uu[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
@@ -203,8 +209,8 @@ __global__ __launch_bounds__(256) void k_quantize(
             *reinterpret_cast<uint4*>((r == 0 ? out0 : out1) + off) = make_uint4(w[0], w[1], w[2], w[3]);
         }
     } else {
-        PhiloxStream s0{k0, k1, 0u, 0u};
-        PhiloxStream s1{k0, k1, 0u, 1u};
+        PhiloxStream s0{k0, k1, 0u, rb};
+        PhiloxStream s1{k0, k1, 0u, rb + 1u};
         uint32_t w0[4] = {0u, 0u, 0u, 0u};
         uint32_t w1[4] = {0u, 0u, 0u, 0u};
         const uint64_t ebase = static_cast<uint64_t>(j) * rows;
@@ -229,15 +235,17 @@ template <typename T, int NC>
 __global__ __launch_bounds__(256) void k_quantize_vec(
     const T* __restrict__ y, int64_t m, int64_t rows, int bits, int L, double c,
     double K, uint32_t k0, uint32_t k1, const double* __restrict__ levels,
-    double* __restrict__ yhat, uint8_t* __restrict__ codes) {
+    double* __restrict__ yhat, uint8_t* __restrict__ codes, const int32_t* __restrict__ rbase,
+    const int32_t* __restrict__ stop) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= rows) return;
+    if (stop && *stop) return;  // (realization *rbase per iteration, as the matrix)
     const double v = load_stacked<T, NC>(y, m, 1, i, 0);
     if (bits == 32) {
         yhat[i] = static_cast<double>(static_cast<float>(v));
         return;
     }
-    PhiloxStream s{k0, k1, 1u, 0u};
+    PhiloxStream s{k0, k1, 1u, rbase ? static_cast<uint32_t>(*rbase) : 0u};
     const uint32_t code = quantize_one(v, c, K, static_cast<double>(L - 2), s.word(static_cast<uint64_t>(i)));
     yhat[i] = levels[code];
     if (codes) codes[i] = static_cast<uint8_t>(code);
@@ -407,7 +415,7 @@ qiht_status absmax_t(const void* src, int64_t m, int64_t n, int64_t ld,
 template <int BITS, typename T, int NC>
 void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
               uint64_t seed, double c, double K, int L, qiht_qmatrix* q,
-              hipStream_t st) {
+              hipStream_t st, const int32_t* rbase, const int32_t* stop) {
     const int64_t nchunks = q->col_bytes / 16;
     dim3 grid(static_cast<unsigned>((nchunks + 3) / 4),
               static_cast<unsigned>((n + 63) / 64));  // n <= 65535 * 64 (checked by the caller)
@@ -417,26 +425,27 @@ void launch_q(const void* src, int64_t m, int64_t n, int64_t ld, int R,
                            q->col_bytes, nchunks, c, K, L,
                            static_cast<uint32_t>(seed),
                            static_cast<uint32_t>(seed >> 32), R, q->codes[0],
-                           q->codes[1]);
+                           q->codes[1], rbase, stop);
     else
         hipLaunchKernelGGL((k_quantize<BITS, T, NC, false>), grid, dim3(256), 0, st,
                            static_cast<const T*>(src), m, n, ld, q->rows,
                            q->col_bytes, nchunks, c, K, L,
                            static_cast<uint32_t>(seed),
                            static_cast<uint32_t>(seed >> 32), R, q->codes[0],
-                           q->codes[1]);
+                           q->codes[1], rbase, stop);
 }
 
 template <typename T, int NC>
 qiht_status dispatch_bits(int bits, const void* src, int64_t m, int64_t n,
                           int64_t ld, int R, uint64_t seed, double c, double K, int L,
-                          qiht_qmatrix* q, hipStream_t st) {
+                          qiht_qmatrix* q, hipStream_t st, const int32_t* rbase,
+                          const int32_t* stop) {
     switch (bits) {
-        case 1: launch_q<1, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
-        case 2: launch_q<2, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
-        case 4: launch_q<4, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
-        case 8: launch_q<8, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
-        case 32: launch_q<32, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st); break;
+        case 1: launch_q<1, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st, rbase, stop); break;
+        case 2: launch_q<2, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st, rbase, stop); break;
+        case 4: launch_q<4, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st, rbase, stop); break;
+        case 8: launch_q<8, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st, rbase, stop); break;
+        case 32: launch_q<32, T, NC>(src, m, n, ld, R, seed, c, K, L, q, st, rbase, stop); break;
         default: return fail(QIHT_ERR_UNSUPPORTED, "unsupported bit width");
     }
     QIHT_HIP(hipGetLastError());
@@ -460,12 +469,13 @@ qiht_status device_absmax(const void* src, qiht_dtype dt, int64_t m,
 qiht_status launch_quantize_matrix(const void* src, qiht_dtype dt, int64_t m,
                                    int64_t n, int64_t ld, int bits, int R,
                                    uint64_t seed, double c, double K, int levels,
-                                   qiht_qmatrix* q, hipStream_t st) {
+                                   qiht_qmatrix* q, hipStream_t st, const int32_t* rbase,
+                                   const int32_t* stop) {
     switch (dt) {
-        case QIHT_F32: return dispatch_bits<float, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
-        case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
-        case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
-        case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st);
+        case QIHT_F32: return dispatch_bits<float, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st, rbase, stop);
+        case QIHT_F64: return dispatch_bits<double, 1>(bits, src, m, n, ld, R, seed, c, K, levels, q, st, rbase, stop);
+        case QIHT_C64: return dispatch_bits<float, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st, rbase, stop);
+        case QIHT_C128: return dispatch_bits<double, 2>(bits, src, m, n, ld, R, seed, c, K, levels, q, st, rbase, stop);
     }
     return fail(QIHT_ERR_UNSUPPORTED, "unsupported dtype");
 }
@@ -485,7 +495,7 @@ qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
                                    int bits, int levels, uint64_t seed, double c,
                                    double K, const double* levels_dev,
                                    double* yhat, uint8_t* codes,
-                                   hipStream_t st) {
+                                   hipStream_t st, const int32_t* rbase, const int32_t* stop) {
     const bool cplx = (dt == QIHT_C64 || dt == QIHT_C128);
     const int64_t rows = cplx ? 2 * m : m;
     dim3 grid(static_cast<unsigned>((rows + 255) / 256));
@@ -495,22 +505,22 @@ qiht_status launch_quantize_vector(const void* y, qiht_dtype dt, int64_t m,
         case QIHT_F32:
             hipLaunchKernelGGL((k_quantize_vec<float, 1>), grid, dim3(256), 0, st,
                                static_cast<const float*>(y), m, rows, bits, levels, c, K, k0, k1,
-                               levels_dev, yhat, codes);
+                               levels_dev, yhat, codes, rbase, stop);
             break;
         case QIHT_F64:
             hipLaunchKernelGGL((k_quantize_vec<double, 1>), grid, dim3(256), 0, st,
                                static_cast<const double*>(y), m, rows, bits, levels, c, K, k0, k1,
-                               levels_dev, yhat, codes);
+                               levels_dev, yhat, codes, rbase, stop);
             break;
         case QIHT_C64:
             hipLaunchKernelGGL((k_quantize_vec<float, 2>), grid, dim3(256), 0, st,
                                static_cast<const float*>(y), m, rows, bits, levels, c, K, k0, k1,
-                               levels_dev, yhat, codes);
+                               levels_dev, yhat, codes, rbase, stop);
             break;
         case QIHT_C128:
             hipLaunchKernelGGL((k_quantize_vec<double, 2>), grid, dim3(256), 0, st,
                                static_cast<const double*>(y), m, rows, bits, levels, c, K, k0, k1,
-                               levels_dev, yhat, codes);
+                               levels_dev, yhat, codes, rbase, stop);
             break;
     }
     QIHT_HIP(hipGetLastError());

@@ -5,6 +5,7 @@
 // All control state lives on the device; the host only enqueues launches
 // and, every kChunk rounds, reads the stop flags back.
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -418,8 +419,21 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
 // for a batch), then the gradient, mu, the kSpec proposals of this round and
 // their omegas.
 void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
-                        const SolveArgs& a, hipStream_t st, PassTimer* tm) {
+                        const SolveArgs& a, hipStream_t st, PassTimer* tm,
+                        const FreshSource* fresh) {
     if (!a.decide_in_gather) launch_commit(dP, count, a, st);
+    if (fresh) {
+        // the realizations of the iteration to come: matrix copies 2 it and
+        // 2 it + 1 and y_hat realization it, it = the completed iterations
+        // (read on the device; a round of further shrinks redraws the same)
+        const char* stb = reinterpret_cast<const char*>(pl.host[0].st);
+        const int32_t* it = reinterpret_cast<const int32_t*>(stb + offsetof(SolveState, iter));
+        const int32_t* done = reinterpret_cast<const int32_t*>(stb + offsetof(SolveState, done));
+        launch_quantize_matrix(fresh->phi, fresh->dtype, fresh->m, fresh->n, fresh->ld, fresh->bits, 2,
+                               fresh->seed, fresh->c, fresh->K, fresh->levels, fresh->q, st, it, done);
+        launch_quantize_vector(fresh->y, fresh->ydtype, fresh->m, fresh->ybits, fresh->ylevels, fresh->seed,
+                               fresh->yc, fresh->yK, fresh->ylev, fresh->yhat, nullptr, st, it, done);
+    }
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
     launch_propose(dP, count, a, SEL_STEP, st);
@@ -452,9 +466,10 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
 }  // namespace
 
 qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qiht_info* infos,
-                      hipStream_t st) {
+                      hipStream_t st, const FreshSource* fresh) {
     SolveArgs a = args;
-    a.decide_in_gather = count == 1 ? 1 : 0;
+    // (fresh draws are made between the commit and the residual gather)
+    a.decide_in_gather = (count == 1 && !fresh) ? 1 : 0;
     Plan pl;
     Workspace ws;
     ProbDev* dP = nullptr;
@@ -509,7 +524,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     for (int64_t launched = 0; launched < max_rounds;) {
         const int64_t goal = launched < first ? first : max_rounds;
         const int64_t nl = std::min<int64_t>(kChunk, goal - launched);
-        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, st, &timer);
+        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, st, &timer, fresh);
         launched += nl;
         hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
         QIHT_HIP(hipGetLastError());

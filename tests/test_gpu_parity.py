@@ -396,6 +396,39 @@ def test_batched_deep_backtracking():
     assert deep >= 3
 
 
+@pytest.mark.parametrize("bits,ybits", [(8, 8), (4, 8)])
+def test_fresh_realizations_match_oracle(bits, ybits):
+    """Algorithm 2 with new draws of Q(Phi) and Q(y) every iteration, against
+    the oracle's (from the FP32 state the solver holds): support, iterations
+    and x; the shrink counts too at 8 bits (at 4 bits the support boundary
+    is crossed back and forth every iteration)."""
+    p = workloads.gaussian_256x1024(0)
+    iters = 15
+    x, sup, info = qiht.niht_solve_fresh(_t(p.phi), _t(p.y), p.s, bits, ybits, seed=p.seed,
+                                         max_iters=iters, tol=-1.0)
+    ref = niht.qiht_solve_fresh(p.phi, p.y, p.s, bits, ybits, p.seed, max_iters=iters, tol=-1.0,
+                                x_fp32=True)
+    say(f"  fresh {bits}/{ybits}: shrinks gpu {info['backtracks']} oracle {ref.backtracks}, {info}")
+    np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
+    assert info["iterations"] == ref.iterations == iters
+    if bits == 8:
+        assert info["backtracks"] == ref.backtracks
+    err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+    assert err <= 1e-4, err
+
+
+def test_fresh_realizations_at_32_bits_are_the_fixed_solve():
+    # no randomness at 32 bits: every iteration's draw is the same FP32 copy,
+    # so the per-iteration re-quantization must reproduce the ordinary solve
+    p = workloads.gaussian(300, 900, 12, 1e-3, seed=21)
+    x1, s1, i1 = qiht.niht_solve_fresh(_t(p.phi), _t(p.y), p.s, 32, 32, seed=p.seed,
+                                       max_iters=40, tol=-1.0)
+    q, yhat = _gpu_problem(p, 32)
+    x2, s2, i2 = qiht.niht_solve(q, yhat, p.s, max_iters=40, tol=-1.0)
+    assert torch.equal(s1, s2) and torch.equal(x1, x2)
+    assert i1["iterations"] == i2["iterations"] and i1["backtracks"] == i2["backtracks"]
+
+
 def test_determinism_bitwise():
     p = workloads.gaussian(400, 1500, 20, 1e-3, seed=7)
     q, yhat = _gpu_problem(p, 4)

@@ -322,3 +322,27 @@ def test_synthetic_recipe():
         clean = d.phi @ d.x_true
         snrs.append(10 * np.log10(np.sum(clean ** 2) / np.sum((d.y - clean) ** 2)))
     assert abs(np.mean(snrs) - 10.0) < 0.5
+
+
+def test_fresh_realizations_solver():
+    # Algorithm 2 with realizations drawn per iteration: at 32 bits (no
+    # randomness) it is the fixed-realization solve; at 4 bits consecutive
+    # iterations see different draws, and iteration 1 is the fixed solve's
+    # first iteration on realizations 0 and 1 with y_hat realization 0
+    import workloads
+    from oracle import quantizer as qzz
+    p = workloads.gaussian(60, 150, 5, 1e-3, seed=3)
+    f32 = niht.qiht_solve_fresh(p.phi, p.y, p.s, 32, 32, 7, max_iters=25, tol=-1.0)
+    a = qzz.dequantized_matrix(p.phi, 32, 7, 0)
+    ref = niht.qiht_solve(a, a, qzz.dequantized_vector(p.y, 32, 7), p.s, max_iters=25, tol=-1.0)
+    np.testing.assert_array_equal(f32.support, ref.support)
+    np.testing.assert_array_equal(f32.x, ref.x)
+    assert f32.backtracks == ref.backtracks
+    one = niht.qiht_solve_fresh(p.phi, p.y, p.s, 4, 8, 7, max_iters=1, tol=-1.0)
+    q1 = qzz.dequantized_matrix(p.phi, 4, 7, 0)
+    q2 = qzz.dequantized_matrix(p.phi, 4, 7, 1)
+    yh = qzz.dequantized_vector(p.y, 8, 7)
+    fixed = niht.qiht_solve(q1, q2, yh, p.s, max_iters=1, tol=-1.0)
+    np.testing.assert_array_equal(one.x, fixed.x)
+    assert not np.array_equal(qzz.dequantized_vector(p.y, 8, 7, realization=1), yh)
+    assert not np.array_equal(qzz.dequantized_matrix(p.phi, 4, 7, 2), q1)
