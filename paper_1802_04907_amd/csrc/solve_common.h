@@ -340,7 +340,7 @@ struct CandPre {
     static constexpr int PER = 2048 / NT;
     static_assert(2048 % NT == 0, "the histogram is split evenly over the threads");
     uint32_t h[PER];
-    float g0;
+    float g0, x0;   // g and x at the thread's first entry of the block
     uint32_t bm0;
 };
 
@@ -355,6 +355,7 @@ __device__ __forceinline__ CandPre<NT> cand_preload(const ProbDev& pd, int wg, i
     const int j = min(lo + tid, hi - 1);  // clamped: a thread past the block ignores it
     c.g0 = ldg_f32(pd.g + j);
     c.bm0 = with_support ? ldg_u32(pd.bmsup + (j >> 5)) : 0u;
+    c.x0 = with_support ? ldg_f32(pd.x + j) : 0.0f;  // (x is 0 off the support)
     return c;
 }
 
@@ -429,7 +430,7 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
             const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const uint32_t pos = base + before + static_cast<uint32_t>(__popcll(b & lt));
             pd.cidx[lo + pos] = static_cast<uint32_t>(j) | (on_sup ? 0x80000000u : 0u);
-            pd.cgx[lo + pos] = make_float2(gv, on_sup ? pd.x[j] : 0.0f);
+            pd.cgx[lo + pos] = make_float2(gv, on_sup ? (r0 == lo ? pre.x0 : pd.x[j]) : 0.0f);
         }
         base += all;
         __syncthreads();
