@@ -116,17 +116,14 @@ struct StepOut {
     bool hist;
 };
 
-// One step: NCI columns j, j + 4, ... against the digit registers, the
-// chunk scales, the wave sums, and the results into LDS (g of the task's
-// columns after the 2048 histogram bins, and the histogram itself).
+// Per-lane partial sums of one step: NCI columns j, j + 4, ... against the
+// digit registers, with the chunk scales applied (this lane's share of g).
 template <int BITS, int CPL, int NCI>
-__device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
-                                            const uint32_t (&dg)[CPL][4 * QDig<BITS>::H][QDig<BITS>::ND],
-                                            const double (&ac)[CPL], int j, const StepOut& so,
-                                            uint32_t* lx, const uint32_t* lbm) {
+__device__ __forceinline__ void step_partials(const uint4 (&v)[NCI][CPL],
+                                              const uint32_t (&dg)[CPL][4 * QDig<BITS>::H][QDig<BITS>::ND],
+                                              const double (&ac)[CPL], double* col) {
     using D = QDig<BITS>;
     constexpr int ND = D::ND, H = D::H;
-    double col[NCI];
 #pragma unroll
     for (int k = 0; k < NCI; ++k) col[k] = 0.0;
 #pragma unroll
@@ -158,11 +155,80 @@ __device__ __forceinline__ void reduce_step(const uint4 (&v)[NCI][CPL],
             col[k] = fma(ac[c], t, col[k]);
         }
     }
-#pragma unroll
-    for (int k = 0; k < NCI; ++k) {
-        const int jk = j + 4 * k;
-        const double t = wave_total_f64(col[k]);
-        if ((threadIdx.x & 63) == 0 && jk < so.c1) {
+}
+
+// a + b after exchanging the upper 32 lanes of a with the lower 32 of b
+// (lanes 0-31: a's pair sums over lanes l, l + 32; lanes 32-63: b's).
+__device__ __forceinline__ double fold32(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// a + b after exchanging the odd 16-lane rows of a with the even rows of b
+// (rows 0, 2: a's sums over lanes l, l + 16; rows 1, 3: b's).
+__device__ __forceinline__ double fold16(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// Wave sums of G = 2, 4 or 8 columns at once, by a butterfly that halves the
+// live registers at each exchange: partners l ^ 32, l ^ 16, l ^ 8, then
+// l ^ 1, l ^ 2, l ^ 4 within each group of 8 lanes.  Every column is summed
+// in this same pairwise tree whatever G and its slot (FP addition is
+// commutative), so g does not depend on the instance that computed it.
+// On return every lane holds the total of slot gslot(lane).
+template <int G>
+__device__ __forceinline__ double wave_sums(const double (&p)[G]) {
+    double v;
+    if constexpr (G == 8) {
+        const double r0 = fold16(fold32(p[0], p[1]), fold32(p[2], p[3]));  // rows: 0, 2, 1, 3
+        const double r1 = fold16(fold32(p[4], p[5]), fold32(p[6], p[7]));  // rows: 4, 6, 5, 7
+        const bool up = threadIdx.x & 8;  // lanes 8-15 of a row keep r1, 0-7 keep r0
+        v = (up ? r1 : r0) + dpp_f64<0x128, 0xf, 0xf>(up ? r0 : r1);  // row_ror:8
+    } else if constexpr (G == 4) {
+        const double r = fold16(fold32(p[0], p[1]), fold32(p[2], p[3]));  // rows: 0, 2, 1, 3
+        v = r + dpp_f64<0x128, 0xf, 0xf>(r);                              // row_ror:8
+    } else {
+        const double q = fold32(p[0], p[1]);
+        const double r = fold16(q, q);  // rows: 0, 0, 1, 1
+        v = r + dpp_f64<0x128, 0xf, 0xf>(r);
+    }
+    v = v + dpp_f64<0xB1, 0xf, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = v + dpp_f64<0x4E, 0xf, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = v + dpp_f64<0x141, 0xf, 0xf>(v);  // row_half_mirror
+    return v;
+}
+
+// The slot whose total lane l holds after wave_sums<G>.
+template <int G>
+__device__ __forceinline__ int gslot(int l) {
+    if constexpr (G == 8) {
+        const int g = l >> 3;  // 8-lane group, slot = its 3 bits reversed
+        return ((g & 1) << 2) | (g & 2) | (g >> 2);
+    } else if constexpr (G == 4) {
+        const int r = l >> 4;  // row, slot = its 2 bits reversed
+        return ((r & 1) << 1) | (r >> 1);
+    } else {
+        return l >> 5;
+    }
+}
+
+// The columns of one loop turn (slots 0..NCI-1: j, j + 4, ...; slots
+// NCI..2 NCI - 1: j + step, j + step + 4, ...) summed over the wave, g into
+// LDS after the 2048 histogram bins and, off the support, the histogram;
+// one lane per column.
+template <int NCI>
+__device__ __forceinline__ void store_turn(const double (&p)[2 * NCI], int j, int step, const StepOut& so,
+                                           uint32_t* lx, const uint32_t* lbm) {
+    constexpr int G = 2 * NCI;
+    const double t = wave_sums<G>(p);
+    const int lane = threadIdx.x & 63;
+    if ((lane & (64 / G - 1)) == 0) {
+        const int sl = gslot<G>(lane);
+        const int jk = j + (sl < NCI ? 4 * sl : step + 4 * (sl - NCI));
+        if (jk < so.c1) {
             const float gv = static_cast<float>(t + so.bsum);
             lx[2048 + jk - so.c0] = __float_as_uint(gv);
             if (so.hist && !((lbm[(jk >> 5) - so.wbase] >> (jk & 31)) & 1u))
@@ -258,10 +324,14 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
     // Steady state, two buffers in turn: while one step is reduced the other
     // is in flight (a register copy between them would wait for both).
     const StepOut so{bsum, tk.c0, tk.c1, wbase, hist};
+    // The wave sums of both steps are taken together (their registers are
+    // free again before the second buffer is reloaded).
     for (int j = tk.c0 + wv; j < tk.c1; j += 2 * STEP) {
-        reduce_step<BITS, CPL, NCI>(cur, dg, ac, j, so, lx, lbm);
+        double p[2 * NCI];
+        step_partials<BITS, CPL, NCI>(cur, dg, ac, p);
         load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 2 * STEP, tk.c1, off, cur);
-        reduce_step<BITS, CPL, NCI>(nxt, dg, ac, j + STEP, so, lx, lbm);
+        step_partials<BITS, CPL, NCI>(nxt, dg, ac, p + NCI);
+        store_turn<NCI>(p, j, STEP, so, lx, lbm);
         load_step<NCI, CPL>(pd.q1, pd.col_bytes, j + 3 * STEP, tk.c1, off, nxt);
     }
     // no global store inside the loop: a store under a branch would make the
