@@ -32,6 +32,11 @@
  *  - Per-call workspaces are allocated stream-ordered from a memory pool the
  *    library creates per device; the pool keeps freed memory for reuse (it
  *    grows to the largest workspace in use at once) until the process ends.
+ *  - Environment: QIHT_PASS_STREAM=cache or =long pins which instance of the
+ *    full pass g = Q1^T r runs (one tuned for codes that stay in the
+ *    Infinity Cache between passes, one for longer streams from HBM); by
+ *    default the codes' total size picks it.  Both are valid for every
+ *    problem and give the same g bit for bit; only the speed differs.
  */
 #ifndef QIHT_H_
 #define QIHT_H_

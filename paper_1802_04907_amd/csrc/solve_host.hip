@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -228,6 +229,12 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
     // do best there.  Longer streams come from HBM, where three waves per
     // SIMD with one column each hide more of the latency.
     pl.long_stream = total > kInfinityCacheBytes;
+    // QIHT_PASS_STREAM=cache or =long pins the instance (for tuning; both are
+    // valid for any problem and give the same g bit for bit).
+    if (const char* e = std::getenv("QIHT_PASS_STREAM")) {
+        if (std::strcmp(e, "long") == 0) pl.long_stream = true;
+        else if (std::strcmp(e, "cache") == 0) pl.long_stream = false;
+    }
     const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream));
     const double budget = std::max(1.0, std::ceil(total / slots));
     std::vector<std::vector<Task>> wgs(1);

@@ -220,6 +220,37 @@ GRAD_CASES = [
 ]
 
 
+# Both instances of the packed-code pass (codes resident in the Infinity
+# Cache / streamed from HBM) on one problem: different columns per step and
+# wave, so different butterfly widths, but one summation tree per column.
+INSTANCE_CASES = [
+    (2048, 4133, 4),    # 64 chunks a column: one per lane
+    (6000, 3001, 4),    # 188 chunks: three per lane, ragged
+    (3000, 2500, 8),    # 188 chunks of 8-bit codes
+    (20000, 1500, 4),   # 625 chunks: three row slabs of four per lane
+    (4100, 2000, 2),    # 65 chunks: two per lane
+    (9000, 1000, 1),    # 71 chunks of 1-bit codes: two slabs of one per lane
+]
+
+
+@pytest.mark.parametrize("m,n,bits", INSTANCE_CASES)
+def test_pass_instances_bitwise_equal(monkeypatch, m, n, bits):
+    say(f"pass instances m={m} n={n} bits={bits}")
+    p = workloads.gaussian(m, n, 16, 1e-3, seed=m + bits, dtype=np.float32)
+    q, yhat = _gpu_problem(p, bits)
+    out = {}
+    for inst in ("cache", "long"):
+        monkeypatch.setenv("QIHT_PASS_STREAM", inst)
+        g0, _ = qiht.gradient(q, yhat, None, None)
+        x, sup, info = qiht.niht_solve(q, yhat, p.s, max_iters=8, tol=-1.0)
+        g1, r1 = qiht.gradient(q, yhat, x, sup)
+        out[inst] = [t.cpu().numpy() for t in (g0, x, sup, g1, r1)] + [info["iterations"]]
+    for name, a, b in zip(("g0", "x", "support", "g", "r", "iterations"), out["cache"], out["long"]):
+        np.testing.assert_array_equal(a, b, err_msg=name)
+    assert np.all(np.isfinite(out["cache"][0])) and np.any(out["cache"][0] != 0)
+    q.free()
+
+
 @pytest.mark.parametrize("m,n,s,bits,cplx", GRAD_CASES)
 def test_gradient_teacher_forced(m, n, s, bits, cplx):
     say(f"gradient m={m} n={n} s={s} bits={bits} cplx={cplx}")
