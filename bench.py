@@ -282,6 +282,53 @@ def interferometry_bench(qiht, torch, dev, iters=ITERS, reps=3):
     }
 
 
+# Per (visibility, pixel) entry of the on-the-fly gradient: the rotation to
+# the next pixel (2 MUL + 2 FMA) and the add into g, 5 FP32 VALU
+# instructions.  Peak: 256 CUs x 64 lanes x 2.4 GHz = 39.3 T lane-instructions
+# per second (one non-packed FP32 VALU instruction per lane and clock).
+FT_OPS_PER_ENTRY = 5
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12
+
+
+def fourier_bench(qiht, torch, dev, stored_pass_us=None, reps=20):
+    """g = [Re Phi; Im Phi]^T r with Phi computed on the fly (no matrix read):
+    the interferometry workload's 32640 baselines and 128 x 128 sky (same
+    draws as workloads.interferometry), r = the stacked visibilities (the
+    gradient at x = 0).  Timed over `reps` back-to-back calls with events on
+    the launch stream."""
+    import workloads
+    n_vis, side = 32640, 128
+    uv, y, _, _ = workloads.interferometry_visibilities(n_vis, side, 200, 30.0, SEED)
+    uv_d = torch.from_numpy(uv).to(dev)
+    r_d = torch.from_numpy(y.astype(np.float32)).to(dev)
+    for _ in range(2):
+        qiht.fourier_gradient(uv_d, side, r_d)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        qiht.fourier_gradient(uv_d, side, r_d)
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    entries = n_vis * side * side
+    tops = FT_OPS_PER_ENTRY * entries / us / 1e6
+    out = {
+        "workload": (f"Fourier-sampled Phi {n_vis} x {side * side} computed on the fly "
+                     f"(stacked {2 * n_vis} real rows), one gradient g = Phi^T r, FP32 products"),
+        "us_per_gradient": round(us, 2),
+        "entries_per_s": round(entries / us * 1e6, 1),
+        "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_T, 2),
+                     "unit": "T VALU lane-instructions/s", "frac": round(tops / VALU_PEAK_T, 4),
+                     "instructions_per_entry": FT_OPS_PER_ENTRY},
+        "matrix_bytes_read": 0,
+    }
+    if stored_pass_us:
+        out["stored_4bit_pass_us"] = stored_pass_us
+        out["on_the_fly_over_stored_4bit"] = round(us / stored_pass_us, 3)
+    return out
+
+
 def batched_bench(qiht, torch, dev, count=96, iters=100):
     """Uneven independent problems: m uniform in [1024, 8192] (the master draw
     of workloads.batch_uneven), n = 4m, s = m/16, Gaussian Phi N(0, 1/m) in
@@ -445,6 +492,8 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
+    ap.add_argument("--fourier-only", action="store_true",
+                    help="only time the interferometry gradient with Phi computed on the fly")
     ap.add_argument("--synthetic-sweep", action="store_true",
                     help="only the synthetic accuracy experiment (Phi 128 x 1024, s = 4..128, "
                          "100 draws, 5 precision pairs, 4 signal/noise variants; about a minute)")
@@ -474,6 +523,9 @@ def main():
         return
     if args.shared_only:
         print(json.dumps(shared_bench(qiht, torch, dev, reps=1, only=args.shared_only)))
+        return
+    if args.fourier_only:
+        print(json.dumps(fourier_bench(qiht, torch, dev)))
         return
     if args.synthetic_sweep:
         print(json.dumps(synthetic_sweep(qiht, torch, dev)))
@@ -602,6 +654,9 @@ def main():
         out["interferometry"] = interferometry_bench(qiht, torch, dev)
         log(json.dumps(out["interferometry"]))
         torch.cuda.empty_cache()
+        log("interferometry gradient with Phi on the fly ...")
+        out["fourier_on_the_fly"] = fourier_bench(qiht, torch, dev, out["interferometry"]["pass_avg_us"])
+        log(json.dumps(out["fourier_on_the_fly"]))
         log("batched uneven workload ...")
         out["batched_uneven"] = batched_bench(qiht, torch, dev)
         log(json.dumps(out["batched_uneven"]))

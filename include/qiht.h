@@ -309,6 +309,32 @@ qiht_status qiht_gradient(const qiht_qmatrix* q, const double* yhat,
                           float* g_out, float* r_out, void* stream);
 
 /*
+ * Gradient of a Fourier-sampled measurement matrix computed on the fly
+ * (Sec. IV-C), with no matrix in memory.  The matrix is the radio
+ * interferometry model of Sec. IV-B: visibility j at baseline (u_j, v_j)
+ * samples pixel k of a side x side sky at integer coordinates
+ *   l_k = (k mod side) - floor(side/2),  m_k = (k div side) - floor(side/2),
+ *   Phi_jk = exp(-2 pi i (u_j l_k + v_j m_k)),
+ * taken in the stacked real form [Re Phi; Im Phi] (2 n_vis rows), so
+ *   g_k = sum_j cos(2 pi th_jk) r_j - sin(2 pi th_jk) r_{n_vis + j},
+ *   th_jk = u_j l_k + v_j m_k.
+ *   uv: device, n_vis x 2 doubles, row-major (u_j, v_j) in cycles per pixel.
+ *   r: device, 2 n_vis floats, stacked [Re; Im].
+ *   g_out: device, side * side floats, row-major (index k).
+ * Phases are reduced in FP64 to [-1/2, 1/2] turns; the sines and cosines and
+ * the products are FP32, and partial sums over blocks of 128 visibilities are
+ * added in FP64 in a fixed order (deterministic).  1 <= n_vis <=
+ * QIHT_FOURIER_MAX_VIS, 1 <= side <= QIHT_FOURIER_MAX_SIDE, else INVALID_ARG;
+ * a stream-ordered workspace of 4 side^2 ceil(n_vis / 128) bytes comes from
+ * the library's pool (OUT_OF_MEMORY if it cannot be had).  Non-finite uv or r
+ * give non-finite g.  Asynchronous on `stream`.
+ */
+#define QIHT_FOURIER_MAX_VIS 8388480LL
+#define QIHT_FOURIER_MAX_SIDE 4096LL
+qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side,
+                                  const float* r, float* g_out, void* stream);
+
+/*
  * H_s selection alone (Sec. I-A): the indices of the s entries of a
  * (device, n floats) largest in magnitude, ties to the lower index,
  * written ascending to support_out (device, s int32; may be NULL when

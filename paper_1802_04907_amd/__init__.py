@@ -290,6 +290,20 @@ def gradient(q, yhat, x, support, stream=None):
     return g, r
 
 
+def fourier_gradient(uv, side, r, stream=None):
+    """g = [Re Phi; Im Phi]^T r of the Fourier-sampled matrix
+    Phi_jk = exp(-2 pi i (u_j l_k + v_j m_k)) computed on the fly (no matrix
+    in memory).  uv: (n_vis, 2) CUDA tensor of (u, v); r: 2 n_vis stacked
+    [Re; Im]; returns g, side * side float32."""
+    torch = _torch()
+    uv = uv.to(torch.float64).contiguous()
+    r = r.to(torch.float32).contiguous()
+    g = torch.empty(int(side) * int(side), dtype=torch.float32, device=r.device)
+    _check(_lib.load().qiht_fourier_gradient(_ptr(uv), uv.shape[0], int(side), _ptr(r), _ptr(g),
+                                             _stream(stream)))
+    return g
+
+
 def hard_threshold(a, s, stream=None):
     """H_s support (ascending int32 CUDA tensor) of a float32 CUDA vector."""
     torch = _torch()

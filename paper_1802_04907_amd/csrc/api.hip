@@ -604,6 +604,22 @@ qiht_status qiht_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* s
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }
 
+qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side, const float* r,
+                                  float* g_out, void* stream) try {
+    set_error("");
+    if (!uv || !r || !g_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    if (n_vis < 1 || n_vis > QIHT_FOURIER_MAX_VIS)
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= n_vis <= QIHT_FOURIER_MAX_VIS");
+    if (side < 1 || side > QIHT_FOURIER_MAX_SIDE)
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= side <= QIHT_FOURIER_MAX_SIDE");
+    int dev = 0;
+    qiht_status s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    return run_fourier_gradient(uv, n_vis, static_cast<int>(side), r, g_out, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
 qiht_status qiht_refit(const qiht_qmatrix* q, const void* phi, int64_t m, int64_t n, int64_t ld,
                        qiht_dtype dtype, const double* y, const int32_t* support, int64_t s,
                        float* x_out, double* xs_out, void* stream) try {

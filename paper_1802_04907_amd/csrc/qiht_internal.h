@@ -170,4 +170,9 @@ qiht_status run_refit_batch(const RefitIn* in, int count, hipStream_t st);
 // process ends.  Free with hipFreeAsync.
 hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st);
 
+// g = [Re Phi; Im Phi]^T r for a Fourier-sampled Phi evaluated on the fly
+// (fourier.hip); arguments validated by the caller.
+qiht_status run_fourier_gradient(const double* uv, int64_t nvis, int side, const float* r, float* g,
+                                 hipStream_t st);
+
 }  // namespace qiht

@@ -162,3 +162,16 @@ def test_default_params_refit_off(lib):
     info = _lib.QihtInfo()
     assert lib.qiht_niht_solve(ptr, ptr, 1, C.byref(p), ptr, ptr, C.byref(info), None) == 1
     assert "refit" in lib.qiht_last_error().decode()
+
+
+def test_fourier_gradient_validation(lib):
+    ptr = C.c_void_p(64)
+    f = lib.qiht_fourier_gradient
+    # uv, n_vis, side, r, g, stream
+    assert f(None, 4, 4, ptr, ptr, None) == 1
+    assert f(ptr, 4, 4, None, ptr, None) == 1
+    assert f(ptr, 0, 4, ptr, ptr, None) == 1
+    assert f(ptr, 4, 0, ptr, ptr, None) == 1
+    assert f(ptr, 4, 4097, ptr, ptr, None) == 1
+    assert f(ptr, 8388481, 4, ptr, ptr, None) == 1
+    assert "n_vis" in lib.qiht_last_error().decode()

@@ -18,6 +18,8 @@ Phi -> support -> nonzero values -> noise):
   10 log10(|Phi x|^2 / |e|^2) (the definition used for the radio-astronomy
   experiment).  Stands in for the telescope data of the paper, which are not
   available.
+* ``interferometry_visibilities``: the same draws without the matrix (uv,
+  the sky and the stacked visibilities), for Phi computed on the fly.
 * ``batch_uneven``: independent Gaussian problems with m drawn uniformly in
   [m_lo, m_hi], n = 4m, s = m // 16, per-instance generator seeds [seed, i].
 * ``shared_phi``: one Gaussian Phi and many sparse right-hand sides.
@@ -138,6 +140,30 @@ def interferometry(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0,
     p.uv = np.stack([u, v], axis=1)
     p.lm = np.stack([lk, mk], axis=1)
     return p
+
+
+def interferometry_visibilities(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0):
+    """The draws of ``interferometry`` (same order: baselines, support,
+    fluxes, noise) without forming Phi: uv (n_vis, 2), the sky x, and the
+    stacked visibilities y = [Re; Im] (2 n_vis, FP64), with Phi x evaluated
+    over the s sources only.  For the kernels that compute Phi on the fly."""
+    rng = np.random.default_rng(seed)
+    rad = 0.5 * np.sqrt(rng.random(n_vis))
+    th = 2.0 * np.pi * rng.random(n_vis)
+    uv = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+    n = side * side
+    sup = np.sort(rng.choice(n, s, replace=False))
+    x = np.zeros(n)
+    x[sup] = 10.0 ** rng.uniform(-1.0, 1.0, s)
+    lk = (sup % side) - side // 2
+    mk = (sup // side) - side // 2
+    clean = np.zeros(n_vis, dtype=np.complex128)
+    for t in range(s):
+        clean += x[sup[t]] * np.exp(-2j * np.pi * (uv[:, 0] * lk[t] + uv[:, 1] * mk[t]))
+    sig2 = float(np.vdot(clean, clean).real) / (n_vis * 10.0 ** (snr_db / 10.0))
+    e = math.sqrt(sig2 / 2.0) * (rng.standard_normal(n_vis) + 1j * rng.standard_normal(n_vis))
+    y = clean + e
+    return uv, np.concatenate([y.real, y.imag]), x, sup
 
 
 def batch_uneven(count=96, m_lo=1024, m_hi=8192, seed=0, sigma_e=1e-3,
