@@ -335,6 +335,31 @@ qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side,
                                   const float* r, float* g_out, void* stream);
 
 /*
+ * Normalized IHT (Algorithm 1; QIHT at b = 32) on that Fourier-sampled Phi
+ * with every product by Phi computed on the fly: the full pass as in
+ * qiht_fourier_gradient, and Phi times the support's columns (r = y -
+ * Phi_G x_G, Phi_G g_G for the step size, Phi (x+ - x) for the step test)
+ * by one thread per visibility over the column list, FP64 sums.  Same
+ * iteration as qiht_niht_solve with Q1 = Q2 = Phi and y_hat = y: G0 =
+ * supp H_s(Phi^T y), mu = |g_G|^2 / |Phi_G g_G|^2 (mu_mode has no effect,
+ * the two forms coincide), the backtracking rule with k, c, max_backtracks,
+ * the stop rule with tol, max_iters.  State and proposals in FP32 (x, g,
+ * x + mu g), norms and the step in FP64.
+ *   uv: device, n_vis x 2 doubles (u_j, v_j).
+ *   y: device, 2 n_vis doubles, the visibilities stacked [Re; Im].
+ *   1 <= s <= min(2 n_vis, side^2); n_vis and side as for
+ *   qiht_fourier_gradient.  p: as for qiht_niht_solve, without warm start
+ *   (x0, support0 must be NULL) or refit (must be 0): UNSUPPORTED.
+ *   x_out: device, side^2 floats; support_out: device, s int32 ascending.
+ * Reads two or three status words per iteration back to the host (the next
+ * launches depend on them).  Synchronizes stream.
+ */
+qiht_status qiht_fourier_niht_solve(const double* uv, int64_t n_vis, int64_t side,
+                                    const double* y, int64_t s, const qiht_params* p,
+                                    float* x_out, int32_t* support_out, qiht_info* info,
+                                    void* stream);
+
+/*
  * H_s selection alone (Sec. I-A): the indices of the s entries of a
  * (device, n floats) largest in magnitude, ties to the lower index,
  * written ascending to support_out (device, s int32; may be NULL when

@@ -12,7 +12,9 @@ no CPU fallback.
 
 Functions keep the C names without the ``qiht_`` prefix:
 ``quantize_matrix``, ``quantize_vector``, ``niht_solve``,
-``niht_solve_batched``, ``gradient``, ``hard_threshold``, ``last_error``.
+``niht_solve_batched``, ``niht_solve_fresh``, ``gradient``,
+``fourier_gradient``, ``fourier_niht_solve``, ``hard_threshold``,
+``refit``, ``last_error``.
 """
 
 import ctypes as C
@@ -20,7 +22,8 @@ import ctypes as C
 from . import _lib
 
 __all__ = ["QihtError", "QMatrix", "quantize_matrix", "quantize_vector",
-           "niht_solve", "niht_solve_batched", "gradient", "hard_threshold",
+           "niht_solve", "niht_solve_batched", "niht_solve_fresh", "gradient",
+           "fourier_gradient", "fourier_niht_solve", "hard_threshold",
            "last_error", "version", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -302,6 +305,24 @@ def fourier_gradient(uv, side, r, stream=None):
     _check(_lib.load().qiht_fourier_gradient(_ptr(uv), uv.shape[0], int(side), _ptr(r), _ptr(g),
                                              _stream(stream)))
     return g
+
+
+def fourier_niht_solve(uv, side, y, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
+                       stream=None):
+    """Normalized IHT on the Fourier-sampled Phi computed on the fly.  uv:
+    (n_vis, 2) CUDA tensor; y: 2 n_vis stacked [Re; Im] -> (x, support, info)."""
+    torch = _torch()
+    uv = uv.to(torch.float64).contiguous()
+    y = y.to(torch.float64).contiguous()
+    n = int(side) * int(side)
+    x = torch.empty(n, dtype=torch.float32, device=y.device)
+    sup = torch.empty(int(s), dtype=torch.int32, device=y.device)
+    p = _params(max_iters, tol, k, c, max_backtracks, 0)
+    inf = _lib.QihtInfo()
+    _check(_lib.load().qiht_fourier_niht_solve(_ptr(uv), uv.shape[0], int(side), _ptr(y), int(s),
+                                               C.byref(p), _ptr(x), _ptr(sup), C.byref(inf),
+                                               _stream(stream)))
+    return x, sup, _info_dict(inf)
 
 
 def hard_threshold(a, s, stream=None):

@@ -67,6 +67,9 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p]),
     "qiht_fourier_gradient": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64,
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qiht_fourier_niht_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                          C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]),
     "qiht_refit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                              C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p, C.c_void_p]),

@@ -2,6 +2,7 @@
 // the quantization and solver launchers.  Every entry point checks its
 // arguments on the host before touching the device and reports errors as
 // status codes plus a thread-local message; no exception crosses the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -616,6 +617,30 @@ qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side,
     qiht_status s0 = need_device(&dev);
     if (s0 != QIHT_OK) return s0;
     return run_fourier_gradient(uv, n_vis, static_cast<int>(side), r, g_out, static_cast<hipStream_t>(stream));
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_fourier_niht_solve(const double* uv, int64_t n_vis, int64_t side, const double* y, int64_t s,
+                                    const qiht_params* p, float* x_out, int32_t* support_out, qiht_info* info,
+                                    void* stream) try {
+    set_error("");
+    if (!uv || !y || !x_out || !support_out) return fail(QIHT_ERR_INVALID_ARG, "NULL argument");
+    if (n_vis < 1 || n_vis > QIHT_FOURIER_MAX_VIS)
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= n_vis <= QIHT_FOURIER_MAX_VIS");
+    if (side < 1 || side > QIHT_FOURIER_MAX_SIDE)
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= side <= QIHT_FOURIER_MAX_SIDE");
+    if (s < 1 || s > std::min<int64_t>(2 * n_vis, side * side))
+        return fail(QIHT_ERR_INVALID_ARG, "need 1 <= s <= min(2 n_vis, side^2)");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    if (p->x0 || p->support0) return fail(QIHT_ERR_UNSUPPORTED, "no warm start with Phi on the fly");
+    if (p->refit) return fail(QIHT_ERR_UNSUPPORTED, "no refit with Phi on the fly");
+    int dev = 0;
+    s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    return run_fourier_solve(uv, n_vis, static_cast<int>(side), y, s, *p, x_out, support_out, info,
+                             static_cast<hipStream_t>(stream));
 } catch (...) {
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }

@@ -115,7 +115,309 @@ __global__ __launch_bounds__(kRedPix * kRedSeg) void k_fourier_reduce(const floa
     }
 }
 
+// ---------------------------------------------------------------------------
+// Normalized IHT (Algorithm 1: the b = 32 case of QIHT) with every product by
+// Phi computed on the fly.  Besides the full pass above, the iteration needs
+// Phi times short column lists (the support, or the support's changes):
+// one thread per visibility sums over the list in FP64, the entries evaluated
+// as in the pass (FP64 phase reduced to turns, FP32 sincospi).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void fourier_entry(double u, double v, int k, int side, float& c, float& s) {
+    const double lk = static_cast<double>(k % side - side / 2);
+    const double mk = static_cast<double>(k / side - side / 2);
+    const double th = fma(u, lk, v * mk);
+    sincospif(2.0f * static_cast<float>(th - rint(th)), &s, &c);
+}
+
+// p = Phi_L v over the list (cols[t], vals[t]), t < count (entries with
+// cols[t] < 0 are skipped), stacked [Re; Im] in FP64; with y != nullptr
+// r = y - p is written in FP32 instead.
+__global__ __launch_bounds__(256) void k_fourier_cols(const double* __restrict__ uv, int64_t nvis, int side,
+                                                      const int32_t* __restrict__ cols,
+                                                      const float* __restrict__ vals, int count,
+                                                      const double* __restrict__ y, float* __restrict__ r,
+                                                      double* __restrict__ p) {
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= nvis) return;
+    const double u = uv[2 * j], v = uv[2 * j + 1];
+    double are = 0.0, aim = 0.0;
+    for (int t = 0; t < count; ++t) {
+        const int k = cols[t];
+        if (k < 0) continue;
+        float c, sn;
+        fourier_entry(u, v, k, side, c, sn);
+        const double x = static_cast<double>(vals[t]);
+        are = fma(static_cast<double>(c), x, are);
+        aim = fma(-static_cast<double>(sn), x, aim);
+    }
+    if (y) {
+        r[j] = static_cast<float>(y[j] - are);
+        r[nvis + j] = static_cast<float>(y[nvis + j] - aim);
+    } else {
+        p[j] = are;
+        p[nvis + j] = aim;
+    }
+}
+
+// Scalars of the solver, on the device.
+struct FtState {
+    double num;    // |g_G|^2
+    double den;    // |Phi_G g_G|^2
+    double mu;     // current step
+    double mu0;
+    double dx2;    // |x+ - x|^2
+    double x2;     // |x+|^2
+    double w2;     // |Phi (x+ - x)|^2
+    int changed;   // proposal support differs from the current one
+    int status;    // FT_*
+    int nb;        // shrinks in this iteration
+    int capped;
+    int stop;      // accepted and |x+ - x| <= tol |x+|
+};
+enum { FT_GO = 0, FT_STATIONARY = 1, FT_RETRY = 2, FT_ACCEPT = 3 };
+
+constexpr int kCtl = 1024;
+
+__device__ double block_sum_f64(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kCtl / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double t = sh[0];
+    __syncthreads();
+    return t;
+}
+
+// |p|^2 over len doubles into *out (one workgroup, fixed order).
+__global__ __launch_bounds__(kCtl) void k_ft_sumsq(const double* __restrict__ p, int64_t len, double* out) {
+    __shared__ double sh[kCtl];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += kCtl) a = fma(p[i], p[i], a);
+    const double t = block_sum_f64(a, sh);
+    if (threadIdx.x == 0) *out = t;
+}
+
+// g_G into the value list, |g_G|^2 into st->num (one workgroup).
+__global__ __launch_bounds__(kCtl) void k_ft_gsup(const float* __restrict__ g, const int32_t* __restrict__ sup, int s,
+                                                   float* __restrict__ vals, FtState* st) {
+    __shared__ double sh[kCtl];
+    double a = 0.0;
+    for (int t = threadIdx.x; t < s; t += kCtl) {
+        const float v = g[sup[t]];
+        vals[t] = v;
+        a = fma(static_cast<double>(v), static_cast<double>(v), a);
+    }
+    const double num = block_sum_f64(a, sh);
+    if (threadIdx.x == 0) {
+        st->num = num;
+        st->nb = 0;
+        st->capped = 0;
+    }
+}
+
+// mu = |g_G|^2 / |Phi_G g_G|^2, or stationary when either is 0.
+__global__ void k_ft_mu(FtState* st) {
+    if (threadIdx.x != 0) return;
+    const double num = st->num, den = st->den;
+    if (num == 0.0 || !(den > 0.0) || !isfinite(den)) {
+        st->status = FT_STATIONARY;
+        return;
+    }
+    st->mu = num / den;
+    st->mu0 = st->mu;
+    st->status = FT_GO;
+}
+
+// a = x + mu g (FP32, mu rounded once).
+__global__ __launch_bounds__(256) void k_ft_axpy(const float* __restrict__ x, const float* __restrict__ g,
+                                                  const FtState* st, int64_t n, float* __restrict__ a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    a[i] = fmaf(static_cast<float>(st->mu), g[i], x[i]);
+}
+
+// The change x+ - x as a column list: the new support with a - x, then the
+// old support's indices outside the new one with -x (others skipped);
+// |x+ - x|^2, |x+|^2 and whether the support changed (one workgroup).
+__global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, const float* __restrict__ a,
+                                                    const int32_t* __restrict__ sup, const int32_t* __restrict__ sup_new,
+                                                    int s, int32_t* __restrict__ cols, float* __restrict__ vals,
+                                                    FtState* st) {
+    __shared__ double sh[kCtl];
+    __shared__ int s_changed;
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    double d2 = 0.0, x2 = 0.0;
+    for (int t = threadIdx.x; t < s; t += kCtl) {
+        const int k = sup_new[t];
+        const float xn = a[k];
+        const float d = xn - x[k];
+        cols[t] = k;
+        vals[t] = d;
+        d2 = fma(static_cast<double>(d), static_cast<double>(d), d2);
+        x2 = fma(static_cast<double>(xn), static_cast<double>(xn), x2);
+        if (sup[t] != k) s_changed = 1;
+        // the old index: kept if absent from the new (ascending) support
+        const int ko = sup[t];
+        int lo = 0, hi = s;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sup_new[mid] < ko) lo = mid + 1;
+            else hi = mid;
+        }
+        const bool in_new = lo < s && sup_new[lo] == ko;
+        cols[s + t] = in_new ? -1 : ko;
+        const float dold = in_new ? 0.0f : -x[ko];
+        vals[s + t] = dold;
+        d2 = fma(static_cast<double>(dold), static_cast<double>(dold), d2);
+    }
+    const double sd2 = block_sum_f64(d2, sh);
+    const double sx2 = block_sum_f64(x2, sh);
+    if (threadIdx.x == 0) {
+        st->dx2 = sd2;
+        st->x2 = sx2;
+        st->changed = s_changed;
+    }
+}
+
+// The step test of a changed support: mu <= (1 - c) omega, omega =
+// |dx|^2 / |Phi dx|^2 (+inf when |Phi dx| = 0); else shrink and retry, at
+// most max_bt times (then the last proposal is accepted, capped).
+// On acceptance, the stop test |x+ - x| <= tol |x+|.
+__global__ void k_ft_decide(FtState* st, double k, double c, int max_bt, double tol) {
+    if (threadIdx.x != 0) return;
+    st->status = FT_ACCEPT;
+    if (st->changed) {
+        const double w = st->w2 == 0.0 ? INFINITY : st->dx2 / st->w2;
+        if (st->mu > (1.0 - c) * w) {
+            if (st->nb >= max_bt) {
+                st->capped = 1;
+            } else {
+                st->mu = st->mu / (k * (1.0 - c));
+                st->nb += 1;
+                st->status = FT_RETRY;
+            }
+        }
+    }
+    st->stop = st->status == FT_ACCEPT && sqrt(st->dx2) <= tol * sqrt(st->x2);
+}
+
+// x <- x+ (the old support zeroed, the new one written), support <- new.
+__global__ __launch_bounds__(256) void k_ft_accept(float* __restrict__ x, const float* __restrict__ a,
+                                                    int32_t* __restrict__ sup, const int32_t* __restrict__ sup_new,
+                                                    int s) {
+    for (int t = threadIdx.x; t < s; t += 256) x[sup[t]] = 0.0f;
+    __syncthreads();
+    for (int t = threadIdx.x; t < s; t += 256) {
+        const int k = sup_new[t];
+        x[k] = a[k];
+        sup[t] = k;
+    }
+}
+
 }  // namespace
+
+qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const double* y, int64_t s,
+                              const qiht_params& prm, float* x, int32_t* sup, qiht_info* info, hipStream_t st) {
+    const int64_t n = static_cast<int64_t>(side) * side;
+    const int64_t rows = 2 * nvis;
+    const int si = static_cast<int>(s);
+    // one workspace: r, g, a (floats), p (doubles), the lists, the new
+    // support, the scalars
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = (off + 255) / 256 * 256;
+        off = o + bytes;
+        return o;
+    };
+    const size_t o_r = take(sizeof(float) * rows), o_g = take(sizeof(float) * n), o_a = take(sizeof(float) * n);
+    const size_t o_p = take(sizeof(double) * rows), o_cols = take(sizeof(int32_t) * 2 * s);
+    const size_t o_vals = take(sizeof(float) * 2 * s), o_sn = take(sizeof(int32_t) * s);
+    const size_t o_st = take(sizeof(FtState));
+    uint8_t* ws = nullptr;
+    QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&ws), off, st));
+    float* r = reinterpret_cast<float*>(ws + o_r);
+    float* g = reinterpret_cast<float*>(ws + o_g);
+    float* a = reinterpret_cast<float*>(ws + o_a);
+    double* p = reinterpret_cast<double*>(ws + o_p);
+    int32_t* cols = reinterpret_cast<int32_t*>(ws + o_cols);
+    float* vals = reinterpret_cast<float*>(ws + o_vals);
+    int32_t* sn = reinterpret_cast<int32_t*>(ws + o_sn);
+    FtState* dst = reinterpret_cast<FtState*>(ws + o_st);
+    qiht_status ret = QIHT_OK;
+    qiht_info out{};
+    auto body = [&]() -> qiht_status {
+        const unsigned gv = static_cast<unsigned>((nvis + 255) / 256), gn = static_cast<unsigned>((n + 255) / 256);
+        QIHT_HIP(hipMemsetAsync(x, 0, sizeof(float) * n, st));
+        // G0 = supp H_s(Phi^T y): r = y (an empty list), then the pass
+        hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 0, y, r,
+                           static_cast<double*>(nullptr));
+        QIHT_HIP(hipGetLastError());
+        qiht_status s0 = run_fourier_gradient(uv, nvis, side, r, g, st);
+        if (s0 != QIHT_OK) return s0;
+        s0 = run_hard_threshold(g, n, s, sup, st);
+        if (s0 != QIHT_OK) return s0;
+        out.reason = QIHT_REASON_MAX_ITERS;
+        FtState hs{};
+        for (int it = 1; it <= prm.max_iters; ++it) {
+            // r = y - Phi_G x_G, g = Phi^T r
+            hipLaunchKernelGGL(k_ft_gsup, dim3(1), dim3(kCtl), 0, st, x, sup, si, vals, dst);
+            hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, sup, vals, si, y, r,
+                               static_cast<double*>(nullptr));
+            QIHT_HIP(hipGetLastError());
+            s0 = run_fourier_gradient(uv, nvis, side, r, g, st);
+            if (s0 != QIHT_OK) return s0;
+            // mu = |g_G|^2 / |Phi_G g_G|^2
+            hipLaunchKernelGGL(k_ft_gsup, dim3(1), dim3(kCtl), 0, st, g, sup, si, vals, dst);
+            hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, sup, vals, si,
+                               static_cast<const double*>(nullptr), static_cast<float*>(nullptr), p);
+            hipLaunchKernelGGL(k_ft_sumsq, dim3(1), dim3(kCtl), 0, st, p, rows, &dst->den);
+            hipLaunchKernelGGL(k_ft_mu, dim3(1), dim3(64), 0, st, dst);
+            QIHT_HIP(hipGetLastError());
+            QIHT_HIP(hipMemcpyAsync(&hs, dst, sizeof(FtState), hipMemcpyDeviceToHost, st));
+            QIHT_HIP(hipStreamSynchronize(st));
+            if (hs.status == FT_STATIONARY) {
+                out.reason = QIHT_REASON_STATIONARY;
+                break;
+            }
+            for (;;) {
+                hipLaunchKernelGGL(k_ft_axpy, dim3(gn), dim3(256), 0, st, x, g, dst, n, a);
+                QIHT_HIP(hipGetLastError());
+                s0 = run_hard_threshold(a, n, s, sn, st);
+                if (s0 != QIHT_OK) return s0;
+                hipLaunchKernelGGL(k_ft_delta, dim3(1), dim3(kCtl), 0, st, x, a, sup, sn, si, cols, vals, dst);
+                hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 2 * si,
+                                   static_cast<const double*>(nullptr), static_cast<float*>(nullptr), p);
+                hipLaunchKernelGGL(k_ft_sumsq, dim3(1), dim3(kCtl), 0, st, p, rows, &dst->w2);
+                hipLaunchKernelGGL(k_ft_decide, dim3(1), dim3(64), 0, st, dst, prm.k, prm.c, prm.max_backtracks,
+                                   prm.tol);
+                QIHT_HIP(hipGetLastError());
+                QIHT_HIP(hipMemcpyAsync(&hs, dst, sizeof(FtState), hipMemcpyDeviceToHost, st));
+                QIHT_HIP(hipStreamSynchronize(st));
+                if (hs.status != FT_RETRY) break;
+            }
+            hipLaunchKernelGGL(k_ft_accept, dim3(1), dim3(256), 0, st, x, a, sup, sn, si);
+            QIHT_HIP(hipGetLastError());
+            out.iterations = it;
+            out.backtracks += hs.nb;
+            out.capped_iterations += hs.capped;
+            out.mu_last = hs.mu;
+            if (hs.stop) {
+                out.reason = QIHT_REASON_CONVERGED;
+                break;
+            }
+        }
+        QIHT_HIP(hipStreamSynchronize(st));
+        return QIHT_OK;
+    };
+    ret = body();
+    (void)hipFreeAsync(ws, st);
+    if (ret == QIHT_OK && info) *info = out;
+    return ret;
+}
 
 int64_t fourier_partial_blocks(int64_t nvis) { return (nvis + kFtVis - 1) / kFtVis; }
 

@@ -174,5 +174,9 @@ hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st);
 // (fourier.hip); arguments validated by the caller.
 qiht_status run_fourier_gradient(const double* uv, int64_t nvis, int side, const float* r, float* g,
                                  hipStream_t st);
+// Normalized IHT with every product by that Phi computed on the fly
+// (fourier.hip); x and support are the caller's outputs, used as the state.
+qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const double* y, int64_t s,
+                              const qiht_params& prm, float* x, int32_t* sup, qiht_info* info, hipStream_t st);
 
 }  // namespace qiht

@@ -175,3 +175,23 @@ def test_fourier_gradient_validation(lib):
     assert f(ptr, 4, 4097, ptr, ptr, None) == 1
     assert f(ptr, 8388481, 4, ptr, ptr, None) == 1
     assert "n_vis" in lib.qiht_last_error().decode()
+
+
+def test_fourier_solve_validation(lib):
+    from paper_1802_04907_amd import _lib
+    p = _lib.QihtParams()
+    lib.qiht_default_params(C.byref(p))
+    ptr = C.c_void_p(64)
+    info = _lib.QihtInfo()
+    f = lib.qiht_fourier_niht_solve
+    # uv, n_vis, side, y, s, params, x, support, info, stream
+    assert f(None, 4, 4, ptr, 2, C.byref(p), ptr, ptr, C.byref(info), None) == 1
+    assert f(ptr, 4, 4, ptr, 0, C.byref(p), ptr, ptr, C.byref(info), None) == 1
+    assert f(ptr, 4, 4, ptr, 9, C.byref(p), ptr, ptr, C.byref(info), None) == 1   # s > 2 n_vis
+    assert f(ptr, 40, 2, ptr, 5, C.byref(p), ptr, ptr, C.byref(info), None) == 1  # s > side^2
+    assert f(ptr, 4, 4, ptr, 2, None, ptr, ptr, C.byref(info), None) == 1
+    warm = _lib.QihtParams()
+    lib.qiht_default_params(C.byref(warm))
+    warm.refit = 1
+    assert f(ptr, 4, 4, ptr, 2, C.byref(warm), ptr, ptr, C.byref(info), None) == 2
+    assert "refit" in lib.qiht_last_error().decode()

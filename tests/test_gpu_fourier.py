@@ -75,3 +75,28 @@ def test_fourier_gradient_fullsize_sampled_and_deterministic():
     say(f"  dirty-beam peak {gb[k]:.3f} of {nv}, max elsewhere {np.delete(gb, k).max():.1f}")
     assert abs(gb[k] - nv) <= 1e-5 * nv
     assert int(np.argmax(gb)) == k
+
+
+# ------------------------------------------------ the solve, Phi on the fly
+# Normalized IHT (QIHT at b = 32) against the oracle's solver on the
+# definition's FP64 matrix: identical final supports, |x - x_oracle| <=
+# 1e-4 |x_oracle| (the GPU holds x, g and x + mu g in FP32), same stop reason.
+SOLVE_CASES = [(400, 16, 5, 30.0), (2000, 32, 12, 30.0), (1500, 24, 8, 10.0)]
+
+
+@pytest.mark.parametrize("nv,side,s,snr", SOLVE_CASES)
+def test_fourier_solve_matches_oracle(nv, side, s, snr):
+    from oracle import niht
+    say(f"fourier solve n_vis={nv} side={side} s={s} snr={snr}")
+    uv, y, x_true, sup_true = workloads.interferometry_visibilities(nv, side, s, snr, nv + s)
+    A = fourier.stacked_matrix(uv, side)
+    ref = niht.qiht_solve(A, A, y, s, max_iters=60, tol=1e-7)
+    x, sup, info = qiht.fourier_niht_solve(torch.from_numpy(uv).to(DEV), side,
+                                           torch.from_numpy(y).to(DEV), s, max_iters=60, tol=1e-7)
+    xs, ss = x.cpu().numpy().astype(np.float64), sup.cpu().numpy()
+    say(f"  iterations {info['iterations']}/{ref.iterations}, backtracks "
+        f"{info['backtracks']}/{ref.backtracks}, reason {info['reason']}")
+    np.testing.assert_array_equal(ss, ref.support)
+    assert np.linalg.norm(xs - ref.x) <= 1e-4 * np.linalg.norm(ref.x)
+    assert np.count_nonzero(np.delete(xs, ss)) == 0
+    assert len(np.intersect1d(ss, sup_true)) >= s - 1
