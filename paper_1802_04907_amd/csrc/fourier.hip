@@ -123,34 +123,58 @@ __global__ __launch_bounds__(kRedPix * kRedSeg) void k_fourier_reduce(const floa
 // as in the pass (FP64 phase reduced to turns, FP32 sincospi).
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void fourier_entry(double u, double v, int k, int side, float& c, float& s) {
-    const double lk = static_cast<double>(k % side - side / 2);
-    const double mk = static_cast<double>(k / side - side / 2);
+// Pixel k's row k div side by a float reciprocal (k < 2^24 is exact in
+// FP32; the rounded quotient is off by at most one, corrected).
+__device__ __forceinline__ void fourier_entry(double u, double v, int k, int side, float inv_side, float& c,
+                                              float& s) {
+    int row = static_cast<int>(static_cast<float>(k) * inv_side);
+    int col = k - row * side;
+    if (col < 0) {
+        --row;
+        col += side;
+    } else if (col >= side) {
+        ++row;
+        col -= side;
+    }
+    const double lk = static_cast<double>(col - side / 2);
+    const double mk = static_cast<double>(row - side / 2);
     const double th = fma(u, lk, v * mk);
     sincospif(2.0f * static_cast<float>(th - rint(th)), &s, &c);
 }
 
 // p = Phi_L v over the list (cols[t], vals[t]), t < count (entries with
 // cols[t] < 0 are skipped), stacked [Re; Im] in FP64; with y != nullptr
-// r = y - p is written in FP32 instead.
+// r = y - p is written in FP32 instead.  kColLanes lanes share a visibility:
+// lane i takes the entries t = i mod kColLanes, and the lanes' sums meet in
+// a fixed xor butterfly (every lane ends with the same bits).
+constexpr int kColLanes = 8;
+
 __global__ __launch_bounds__(256) void k_fourier_cols(const double* __restrict__ uv, int64_t nvis, int side,
                                                       const int32_t* __restrict__ cols,
                                                       const float* __restrict__ vals, int count,
                                                       const double* __restrict__ y, float* __restrict__ r,
                                                       double* __restrict__ p) {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= nvis) return;
-    const double u = uv[2 * j], v = uv[2 * j + 1];
+    const int64_t j = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / kColLanes;
+    const int lane = static_cast<int>(threadIdx.x) % kColLanes;
+    const bool live = j < nvis;  // no early exit: the whole group takes part in the shuffles
+    const double u = live ? uv[2 * j] : 0.0, v = live ? uv[2 * j + 1] : 0.0;
+    const float inv_side = 1.0f / static_cast<float>(side);
     double are = 0.0, aim = 0.0;
-    for (int t = 0; t < count; ++t) {
+    for (int t = lane; live && t < count; t += kColLanes) {
         const int k = cols[t];
         if (k < 0) continue;
         float c, sn;
-        fourier_entry(u, v, k, side, c, sn);
+        fourier_entry(u, v, k, side, inv_side, c, sn);
         const double x = static_cast<double>(vals[t]);
         are = fma(static_cast<double>(c), x, are);
         aim = fma(-static_cast<double>(sn), x, aim);
     }
+#pragma unroll
+    for (int d = 1; d < kColLanes; d <<= 1) {
+        are += __shfl_xor(are, d, kColLanes);
+        aim += __shfl_xor(aim, d, kColLanes);
+    }
+    if (!live || lane != 0) return;
     if (y) {
         r[j] = static_cast<float>(y[j] - are);
         r[nvis + j] = static_cast<float>(y[nvis + j] - aim);
@@ -174,6 +198,7 @@ struct FtState {
     int nb;        // shrinks in this iteration
     int capped;
     int stop;      // accepted and |x+ - x| <= tol |x+|
+    double part[64];  // per-workgroup sums of squares (k_ft_sumsq)
 };
 enum { FT_GO = 0, FT_STATIONARY = 1, FT_RETRY = 2, FT_ACCEPT = 3 };
 
@@ -191,13 +216,29 @@ __device__ double block_sum_f64(double v, double* sh) {
     return t;
 }
 
-// |p|^2 over len doubles into *out (one workgroup, fixed order).
-__global__ __launch_bounds__(kCtl) void k_ft_sumsq(const double* __restrict__ p, int64_t len, double* out) {
-    __shared__ double sh[kCtl];
+// |p|^2 over len doubles: workgroup b of 64 sums the b-th contiguous part
+// into st->part[b]; the consumer adds the 64 parts in order.
+constexpr int kSqBlocks = 64;
+
+__global__ __launch_bounds__(256) void k_ft_sumsq(const double* __restrict__ p, int64_t len, FtState* st) {
+    __shared__ double sh[256];
+    const int64_t per = (len + kSqBlocks - 1) / kSqBlocks;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * per, i1 = min(len, i0 + per);
     double a = 0.0;
-    for (int64_t i = threadIdx.x; i < len; i += kCtl) a = fma(p[i], p[i], a);
-    const double t = block_sum_f64(a, sh);
-    if (threadIdx.x == 0) *out = t;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) a = fma(p[i], p[i], a);
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st->part[blockIdx.x] = sh[0];
+}
+
+__device__ __forceinline__ double sumsq_total(const FtState* st) {
+    double t = 0.0;
+    for (int b = 0; b < kSqBlocks; ++b) t += st->part[b];
+    return t;
 }
 
 // g_G into the value list, |g_G|^2 into st->num (one workgroup).
@@ -221,6 +262,7 @@ __global__ __launch_bounds__(kCtl) void k_ft_gsup(const float* __restrict__ g, c
 // mu = |g_G|^2 / |Phi_G g_G|^2, or stationary when either is 0.
 __global__ void k_ft_mu(FtState* st) {
     if (threadIdx.x != 0) return;
+    st->den = sumsq_total(st);
     const double num = st->num, den = st->den;
     if (num == 0.0 || !(den > 0.0) || !isfinite(den)) {
         st->status = FT_STATIONARY;
@@ -290,6 +332,7 @@ __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, 
 __global__ void k_ft_decide(FtState* st, double k, double c, int max_bt, double tol) {
     if (threadIdx.x != 0) return;
     st->status = FT_ACCEPT;
+    st->w2 = sumsq_total(st);
     if (st->changed) {
         const double w = st->w2 == 0.0 ? INFINITY : st->dx2 / st->w2;
         if (st->mu > (1.0 - c) * w) {
@@ -350,7 +393,7 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
     qiht_status ret = QIHT_OK;
     qiht_info out{};
     auto body = [&]() -> qiht_status {
-        const unsigned gv = static_cast<unsigned>((nvis + 255) / 256), gn = static_cast<unsigned>((n + 255) / 256);
+        const unsigned gv = static_cast<unsigned>((nvis * kColLanes + 255) / 256), gn = static_cast<unsigned>((n + 255) / 256);
         QIHT_HIP(hipMemsetAsync(x, 0, sizeof(float) * n, st));
         // G0 = supp H_s(Phi^T y): r = y (an empty list), then the pass
         hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 0, y, r,
@@ -374,7 +417,7 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
             hipLaunchKernelGGL(k_ft_gsup, dim3(1), dim3(kCtl), 0, st, g, sup, si, vals, dst);
             hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, sup, vals, si,
                                static_cast<const double*>(nullptr), static_cast<float*>(nullptr), p);
-            hipLaunchKernelGGL(k_ft_sumsq, dim3(1), dim3(kCtl), 0, st, p, rows, &dst->den);
+            hipLaunchKernelGGL(k_ft_sumsq, dim3(kSqBlocks), dim3(256), 0, st, p, rows, dst);
             hipLaunchKernelGGL(k_ft_mu, dim3(1), dim3(64), 0, st, dst);
             QIHT_HIP(hipGetLastError());
             QIHT_HIP(hipMemcpyAsync(&hs, dst, sizeof(FtState), hipMemcpyDeviceToHost, st));
@@ -391,7 +434,7 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
                 hipLaunchKernelGGL(k_ft_delta, dim3(1), dim3(kCtl), 0, st, x, a, sup, sn, si, cols, vals, dst);
                 hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 2 * si,
                                    static_cast<const double*>(nullptr), static_cast<float*>(nullptr), p);
-                hipLaunchKernelGGL(k_ft_sumsq, dim3(1), dim3(kCtl), 0, st, p, rows, &dst->w2);
+                hipLaunchKernelGGL(k_ft_sumsq, dim3(kSqBlocks), dim3(256), 0, st, p, rows, dst);
                 hipLaunchKernelGGL(k_ft_decide, dim3(1), dim3(64), 0, st, dst, prm.k, prm.c, prm.max_backtracks,
                                    prm.tol);
                 QIHT_HIP(hipGetLastError());
