@@ -100,3 +100,22 @@ def test_fourier_solve_matches_oracle(nv, side, s, snr):
     assert np.linalg.norm(xs - ref.x) <= 1e-4 * np.linalg.norm(ref.x)
     assert np.count_nonzero(np.delete(xs, ss)) == 0
     assert len(np.intersect1d(ss, sup_true)) >= s - 1
+
+
+def test_fourier_solve_fullsize_properties():
+    """The benchmark's size (32640 visibilities, 128 x 128 sky, s = 200):
+    a valid s-sparse iterate on an ascending support, the stop bookkeeping,
+    and recovery of the 200 sources at 30 dB."""
+    nv, side, s = 32640, 128, 200
+    say("fourier solve full size: 32640 x 128^2, s = 200, 20 iterations")
+    uv, y, x_true, sup_true = workloads.interferometry_visibilities(nv, side, s, 30.0, 0)
+    x, sup, info = qiht.fourier_niht_solve(torch.from_numpy(uv).to(DEV), side,
+                                           torch.from_numpy(y).to(DEV), s, max_iters=20, tol=-1.0)
+    xs, ss = x.cpu().numpy(), sup.cpu().numpy()
+    assert info["iterations"] == 20 and info["reason"] in ("max_iters", 2)
+    assert ss.size == s and np.all(np.diff(ss) > 0) and ss[0] >= 0 and ss[-1] < side * side
+    assert np.count_nonzero(np.delete(xs, ss)) == 0 and np.all(np.isfinite(xs))
+    rec = len(np.intersect1d(ss, sup_true)) / s
+    err = np.linalg.norm(xs - x_true) / np.linalg.norm(x_true)
+    say(f"  support recovery {rec:.3f}, relative error {err:.2e}, info {info}")
+    assert rec >= 0.99 and err < 1e-2
