@@ -347,13 +347,15 @@ qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side,
  * x + mu g), norms and the step in FP64.
  *   uv: device, n_vis x 2 doubles (u_j, v_j).
  *   y: device, 2 n_vis doubles, the visibilities stacked [Re; Im].
- *   1 <= s <= min(2 n_vis, side^2); n_vis and side as for
- *   qiht_fourier_gradient.  p: as for qiht_niht_solve, without warm start
+ *   1 <= s <= min(2 n_vis, side^2); n_vis as for qiht_fourier_gradient;
+ *   side^2 <= QIHT_FOURIER_SOLVE_MAX_PIXELS (the H_s selection's limit;
+ *   256 x 256, the paper's LOFAR sky), else UNSUPPORTED.  p: as for qiht_niht_solve, without warm start
  *   (x0, support0 must be NULL) or refit (must be 0): UNSUPPORTED.
  *   x_out: device, side^2 floats; support_out: device, s int32 ascending.
  * Reads two or three status words per iteration back to the host (the next
  * launches depend on them).  Synchronizes stream.
  */
+#define QIHT_FOURIER_SOLVE_MAX_PIXELS 65536LL
 qiht_status qiht_fourier_niht_solve(const double* uv, int64_t n_vis, int64_t side,
                                     const double* y, int64_t s, const qiht_params* p,
                                     float* x_out, int32_t* support_out, qiht_info* info,

@@ -632,6 +632,8 @@ qiht_status qiht_fourier_niht_solve(const double* uv, int64_t n_vis, int64_t sid
         return fail(QIHT_ERR_INVALID_ARG, "need 1 <= side <= QIHT_FOURIER_MAX_SIDE");
     if (s < 1 || s > std::min<int64_t>(2 * n_vis, side * side))
         return fail(QIHT_ERR_INVALID_ARG, "need 1 <= s <= min(2 n_vis, side^2)");
+    if (side * side > QIHT_FOURIER_SOLVE_MAX_PIXELS)
+        return fail(QIHT_ERR_UNSUPPORTED, "the solve takes at most QIHT_FOURIER_SOLVE_MAX_PIXELS pixels");
     qiht_status s0 = check_params(p);
     if (s0 != QIHT_OK) return s0;
     if (p->x0 || p->support0) return fail(QIHT_ERR_UNSUPPORTED, "no warm start with Phi on the fly");

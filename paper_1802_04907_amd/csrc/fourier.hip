@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "qiht_internal.h"
+#include "solve_common.h"
 
 namespace qiht {
 namespace {
@@ -199,6 +200,7 @@ struct FtState {
     int capped;
     int stop;      // accepted and |x+ - x| <= tol |x+|
     double part[64];  // per-workgroup sums of squares (k_ft_sumsq)
+    int hs_err;       // set by H_s on a NaN key
 };
 enum { FT_GO = 0, FT_STATIONARY = 1, FT_RETRY = 2, FT_ACCEPT = 3 };
 
@@ -273,11 +275,12 @@ __global__ void k_ft_mu(FtState* st) {
     st->status = FT_GO;
 }
 
-// a = x + mu g (FP32, mu rounded once).
+// a = x + mu g (FP32, mu rounded once).  After a stationary step the
+// proposal kernels do nothing and the decision keeps the status.
 __global__ __launch_bounds__(256) void k_ft_axpy(const float* __restrict__ x, const float* __restrict__ g,
                                                   const FtState* st, int64_t n, float* __restrict__ a) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || st->status == FT_STATIONARY) return;
     a[i] = fmaf(static_cast<float>(st->mu), g[i], x[i]);
 }
 
@@ -290,6 +293,7 @@ __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, 
                                                     FtState* st) {
     __shared__ double sh[kCtl];
     __shared__ int s_changed;
+    if (st->status == FT_STATIONARY) return;  // uniform: one value for the workgroup
     if (threadIdx.x == 0) s_changed = 0;
     __syncthreads();
     double d2 = 0.0, x2 = 0.0;
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, 
 // most max_bt times (then the last proposal is accepted, capped).
 // On acceptance, the stop test |x+ - x| <= tol |x+|.
 __global__ void k_ft_decide(FtState* st, double k, double c, int max_bt, double tol) {
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x != 0 || st->status == FT_STATIONARY) return;
     st->status = FT_ACCEPT;
     st->w2 = sumsq_total(st);
     if (st->changed) {
@@ -360,6 +364,8 @@ __global__ __launch_bounds__(256) void k_ft_accept(float* __restrict__ x, const 
         sup[t] = k;
     }
 }
+
+static_assert(QIHT_FOURIER_SOLVE_MAX_PIXELS == kMaxSelectN, "the solve's pixel limit is the selection's");
 
 }  // namespace
 
@@ -395,14 +401,16 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
     auto body = [&]() -> qiht_status {
         const unsigned gv = static_cast<unsigned>((nvis * kColLanes + 255) / 256), gn = static_cast<unsigned>((n + 255) / 256);
         QIHT_HIP(hipMemsetAsync(x, 0, sizeof(float) * n, st));
+        QIHT_HIP(hipMemsetAsync(dst, 0, sizeof(FtState), st));
+        QIHT_HIP(hipMemsetAsync(a, 0, sizeof(float) * n, st));  // H_s may read it after a stationary step
         // G0 = supp H_s(Phi^T y): r = y (an empty list), then the pass
         hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 0, y, r,
                            static_cast<double*>(nullptr));
         QIHT_HIP(hipGetLastError());
         qiht_status s0 = run_fourier_gradient(uv, nvis, side, r, g, st);
         if (s0 != QIHT_OK) return s0;
-        s0 = run_hard_threshold(g, n, s, sup, st);
-        if (s0 != QIHT_OK) return s0;
+        launch_hard_threshold(g, static_cast<int>(n), si, sup, &dst->hs_err, st);
+        QIHT_HIP(hipGetLastError());
         out.reason = QIHT_REASON_MAX_ITERS;
         FtState hs{};
         for (int it = 1; it <= prm.max_iters; ++it) {
@@ -420,17 +428,10 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
             hipLaunchKernelGGL(k_ft_sumsq, dim3(kSqBlocks), dim3(256), 0, st, p, rows, dst);
             hipLaunchKernelGGL(k_ft_mu, dim3(1), dim3(64), 0, st, dst);
             QIHT_HIP(hipGetLastError());
-            QIHT_HIP(hipMemcpyAsync(&hs, dst, sizeof(FtState), hipMemcpyDeviceToHost, st));
-            QIHT_HIP(hipStreamSynchronize(st));
-            if (hs.status == FT_STATIONARY) {
-                out.reason = QIHT_REASON_STATIONARY;
-                break;
-            }
             for (;;) {
                 hipLaunchKernelGGL(k_ft_axpy, dim3(gn), dim3(256), 0, st, x, g, dst, n, a);
                 QIHT_HIP(hipGetLastError());
-                s0 = run_hard_threshold(a, n, s, sn, st);
-                if (s0 != QIHT_OK) return s0;
+                launch_hard_threshold(a, static_cast<int>(n), si, sn, &dst->hs_err, st);
                 hipLaunchKernelGGL(k_ft_delta, dim3(1), dim3(kCtl), 0, st, x, a, sup, sn, si, cols, vals, dst);
                 hipLaunchKernelGGL(k_fourier_cols, dim3(gv), dim3(256), 0, st, uv, nvis, side, cols, vals, 2 * si,
                                    static_cast<const double*>(nullptr), static_cast<float*>(nullptr), p);
@@ -440,7 +441,12 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
                 QIHT_HIP(hipGetLastError());
                 QIHT_HIP(hipMemcpyAsync(&hs, dst, sizeof(FtState), hipMemcpyDeviceToHost, st));
                 QIHT_HIP(hipStreamSynchronize(st));
+                if (hs.hs_err) return fail(QIHT_ERR_NUMERIC, "NaN met in the iterate");
                 if (hs.status != FT_RETRY) break;
+            }
+            if (hs.status == FT_STATIONARY) {
+                out.reason = QIHT_REASON_STATIONARY;
+                break;
             }
             hipLaunchKernelGGL(k_ft_accept, dim3(1), dim3(256), 0, st, x, a, sup, sn, si);
             QIHT_HIP(hipGetLastError());
