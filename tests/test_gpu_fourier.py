@@ -119,3 +119,34 @@ def test_fourier_solve_fullsize_properties():
     err = np.linalg.norm(xs - x_true) / np.linalg.norm(x_true)
     say(f"  support recovery {rec:.3f}, relative error {err:.2e}, info {info}")
     assert rec >= 0.99 and err < 1e-2
+
+
+def test_fourier_solve_degenerate_cases():
+    from oracle import niht
+    nv, side = 200, 8
+    uv, y, _, _ = workloads.interferometry_visibilities(nv, side, 3, 30.0, 5)
+    uv_d = torch.from_numpy(uv).to(DEV)
+    A = fourier.stacked_matrix(uv, side)
+    # y = 0: the gradient vanishes on the support, stationary before any step
+    z = np.zeros(2 * nv)
+    ref = niht.qiht_solve(A, A, z, 3, max_iters=10)
+    x, sup, info = qiht.fourier_niht_solve(uv_d, side, torch.from_numpy(z).to(DEV), 3, max_iters=10)
+    assert info["reason"] == "stationary" and info["iterations"] == ref.iterations == 0
+    np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
+    assert not x.cpu().numpy().any()
+    # every pixel on the support (s = side^2): no support change, no step test;
+    # the iterates approach the least-squares fit
+    s = side * side
+    ref = niht.qiht_solve(A, A, y, s, max_iters=40, tol=1e-9)
+    x, sup, info = qiht.fourier_niht_solve(uv_d, side, torch.from_numpy(y).to(DEV), s,
+                                           max_iters=40, tol=1e-9)
+    np.testing.assert_array_equal(sup.cpu().numpy(), np.arange(s))
+    assert info["backtracks"] == 0
+    xs = x.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(xs - ref.x) <= 1e-4 * np.linalg.norm(ref.x)
+    # a NaN among the visibilities is reported, not iterated on
+    yn = y.copy()
+    yn[7] = np.nan
+    with pytest.raises(qiht.QihtError) as e:
+        qiht.fourier_niht_solve(uv_d, side, torch.from_numpy(yn).to(DEV), 3, max_iters=5)
+    assert e.value.status_name == "NUMERIC"
