@@ -87,3 +87,36 @@ def test_matrix_free_visibilities_are_the_workload_draws():
     np.testing.assert_array_equal(x, p.x_true)
     want = np.concatenate([p.y.real, p.y.imag])
     np.testing.assert_allclose(y, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_pins_catch_planted_mistakes():
+    """Each plausible mistake in the gradient's formula (planted here, in a
+    copy on the CPU) breaks at least one of the checks above: the sine's
+    sign, swapped pixel axes, the centre rounded up for odd sides, a
+    dropped imaginary term."""
+    def make(sign=-1.0, swap=False, centre=lambda s: s // 2, drop_im=False):
+        def grad(uv, side, r):
+            k = np.arange(side * side)
+            lk, mk = (k % side) - centre(side), (k // side) - centre(side)
+            if swap:
+                lk, mk = mk, lk
+            th = 2.0 * np.pi * (np.outer(uv[:, 0], lk) + np.outer(uv[:, 1], mk))
+            nv = uv.shape[0]
+            g = np.cos(th).T @ r[:nv]
+            if not drop_im:
+                g = g + sign * (np.sin(th).T @ r[nv:])
+            return g
+        return grad
+
+    side, nv = 7, 60
+    uv = _uv(nv, 21)
+    rng = np.random.default_rng(22)
+    y = rng.standard_normal(nv) + 1j * rng.standard_normal(nv)
+    lk, mk = fourier.pixel_coords(side)
+    phi = np.exp(-2j * np.pi * (np.outer(uv[:, 0], lk) + np.outer(uv[:, 1], mk)))
+    want = (np.conj(phi).T @ y).real
+    r = np.concatenate([y.real, y.imag])
+    np.testing.assert_allclose(make()(uv, side, r), want, atol=1e-12 * np.abs(want).max())
+    for bad in (make(sign=+1.0), make(swap=True), make(centre=lambda s: (s + 1) // 2),
+                make(drop_im=True)):
+        assert np.abs(bad(uv, side, r) - want).max() > 1e-3 * np.abs(want).max()
