@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 M, N, S, SIGMA, SEED, ITERS = 8192, 32768, 512, 1e-3, 0, 200
 PEAK_HBM_GBPS = 8000.0
+EQ_ERR_BAR = 2.0  # an equal-error speed-up is reported only for e* <= this x the FP32 floor
 # shared-matrix workload: one Phi, NRHS right-hand sides of sparsity S5
 NRHS, S5, ITERS5 = 256, 256, 30
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
@@ -47,6 +48,14 @@ def pass_bytes(rows, n, bits):
     g written once."""
     codes = rows * n * (32 if bits == 32 else bits) / 8.0
     return codes + rows * 4.0 + n * 4.0
+
+
+def iteration_bytes(rows, n, s, bits):
+    """Algorithmic bytes of one iteration with no shrink: the full pass, the
+    residual gather of s columns of Q2 and the step-size gathers of s
+    columns of Q1 and of Q2 (one copy at 32 bits, Q1 = Q2: read once)."""
+    col = rows * (32 if bits == 32 else bits) / 8.0
+    return pass_bytes(rows, n, bits) + s * col * (2 if bits == 32 else 3)
 
 
 def source_hash():
@@ -627,33 +636,62 @@ def main():
             traj = trajectory(qiht, torch, q, yhat, p.x_true, true_sup, ITERS, 5)
             q.free()
             avg = tot_ms / tot_l / 1e3
+            ib = iteration_bytes(M, N, S, b)
             sweep[str(b)] = {
                 "solve_iterations_per_s": round(its, 1),
                 "pass_avg_us": round(avg * 1e6, 2),
                 "pass_GBps": round(pass_bytes(M, N, b) / avg / 1e9, 1),
+                "pass_frac": round(pass_bytes(M, N, b) / avg / 1e9 / PEAK_HBM_GBPS, 4),
+                "iteration_bytes": ib,
+                "iteration_GBps": round(ib * its / 1e9, 1),
+                "iteration_frac": round(ib * its / 1e9 / PEAK_HBM_GBPS, 4),
                 "final_rel_err": traj[-1][1], "final_support_recovery": traj[-1][2],
                 "iters_to_90pct_support": first_reach(traj, lambda e, r: r >= 0.9),
                 "trajectory_every_5": [(t, round(e, 5), round(r, 4)) for t, e, r in traj],
             }
-        # equal recovery error: e* = 1.05 x max(floor_b, floor_32)
+        # Time to 90% support recovery (the end-to-end criterion of the
+        # paper's speed-up measurements, Sec. IV-C), and time to an equal
+        # recovery error e* = 1.05 max(floor_b, floor_32) -- the latter only
+        # where e* is a meaningful target: at most EQ_ERR_BAR times the FP32
+        # floor and reached by both solves; otherwise null with the reason.
         f32 = sweep["32"]
         for b in ("8", "4", "2"):
             d = sweep[b]
+            t90b = d["iters_to_90pct_support"]
+            t90f = f32["iters_to_90pct_support"]
+            if t90b is None or t90f is None:
+                d["speedup_vs_fp32_to_90pct_support"] = None
+                d["speedup_to_90pct_support_note"] = (
+                    f"90% support recovery not reached by the {b}-bit solve in {ITERS} iterations "
+                    f"(final {d['final_support_recovery']:.3f})" if t90b is None else
+                    "90% support recovery not reached by the FP32 solve")
+            else:
+                d["speedup_vs_fp32_to_90pct_support"] = round(
+                    (t90f / f32["solve_iterations_per_s"]) / (t90b / d["solve_iterations_per_s"]), 3)
             e_star = 1.05 * max(d["final_rel_err"], f32["final_rel_err"])
             it_b = first_reach([tuple(v) for v in d["trajectory_every_5"]], lambda e, r: e <= e_star)
             it_32 = first_reach([tuple(v) for v in f32["trajectory_every_5"]],
                                 lambda e, r: e <= e_star)
             d["equal_error_target"] = e_star
-            d["time_to_target_ms"] = None if it_b is None else round(it_b / d["solve_iterations_per_s"] * 1e3, 3)
-            f32_t = None if it_32 is None else it_32 / f32["solve_iterations_per_s"] * 1e3
-            d["fp32_time_to_target_ms"] = None if f32_t is None else round(f32_t, 3)
-            d["speedup_vs_fp32_at_equal_error"] = (
-                None if (it_b is None or f32_t is None) else round(f32_t / d["time_to_target_ms"], 3))
-            t90b = d["iters_to_90pct_support"]
-            t90f = f32["iters_to_90pct_support"]
-            d["speedup_vs_fp32_to_90pct_support"] = (
-                None if (t90b is None or t90f is None) else
-                round((t90f / f32["solve_iterations_per_s"]) / (t90b / d["solve_iterations_per_s"]), 3))
+            note = None
+            if not math.isfinite(d["final_rel_err"]) or d["final_rel_err"] >= 1.0:
+                note = (f"the {b}-bit solve diverged (final relative error "
+                        f"{d['final_rel_err']:.3g}): no equal recovery error exists")
+            elif e_star > EQ_ERR_BAR * f32["final_rel_err"]:
+                note = (f"the {b}-bit error floor {d['final_rel_err']:.3g} is above "
+                        f"{EQ_ERR_BAR:g}x the FP32 floor {f32['final_rel_err']:.3g}: "
+                        f"an equal error there is not a recovery result")
+            elif it_b is None or it_32 is None:
+                note = "the target was not reached by both solves"
+            if note is not None:
+                d["speedup_vs_fp32_at_equal_error"] = None
+                d["equal_error_note"] = note
+            else:
+                tb = it_b / d["solve_iterations_per_s"] * 1e3
+                tf = it_32 / f32["solve_iterations_per_s"] * 1e3
+                d["time_to_target_ms"] = round(tb, 3)
+                d["fp32_time_to_target_ms"] = round(tf, 3)
+                d["speedup_vs_fp32_at_equal_error"] = round(tf / tb, 3)
         if os.environ.get("QIHT_BENCH_TRAJ") is None:
             for d in sweep.values():
                 d.pop("trajectory_every_5", None)

@@ -5,7 +5,8 @@ can compute one column at a time.
 * codes: bit-exact on sampled columns of both realizations, and the scale;
 * y_hat: bit-exact;
 * g at x = 0 and g at the solve's final x (teacher-forced): sampled
-  entries within 1e-5 max(|g_S|, 1e-3 |g0_S|) of the FP64 oracle;
+  entries within 1e-5 max(|g_S|, 1e-3 |g0_S|) of the FP64 oracle, and each
+  entry within 1e-5 sum_i |q_ij r_i|;
 * final solve: a valid s-sparse iterate on an ascending support that
   recovers most of the true support (the 4-bit floor is about 80%).
 """
@@ -19,7 +20,9 @@ import paper_1802_04907_amd as qiht  # noqa: E402
 import workloads  # noqa: E402
 from oracle import quantizer as qz  # noqa: E402
 
-pytestmark = pytest.mark.gpu
+from parity_util import assert_g_elementwise, chain_oracle, g_bound  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 DEV = "cuda:0"
 M, N, S, BITS = 8192, 32768, 512, 4
 
@@ -77,6 +80,7 @@ def test_fullsize_gradient_and_solve(big):
     g0 = q1c.T @ yh
     err = np.linalg.norm(g0_gpu.cpu().numpy()[cols] - g0)
     assert err <= 1e-5 * np.linalg.norm(g0)
+    assert_g_elementwise(g0_gpu.cpu().numpy()[cols], g0, g_bound(q1c, yh), what="g0 sampled")
 
     say("solve: 200 iterations as timed by the benchmark")
     x, sup, info = qiht.niht_solve(q, yhat, S, max_iters=200, tol=-1.0)
@@ -95,6 +99,7 @@ def test_fullsize_gradient_and_solve(big):
     g_or = q1c.T @ r_or
     err = np.linalg.norm(g_gpu.cpu().numpy()[cols] - g_or)
     assert err <= 1e-5 * max(np.linalg.norm(g_or), 1e-3 * np.linalg.norm(g0))
+    assert_g_elementwise(g_gpu.cpu().numpy()[cols], g_or, g_bound(q1c, r_or), what="g sampled")
     # recovery on this workload: the 4-bit floor (about 80% of the support)
     rec = len(np.intersect1d(ss, p.support)) / S
     say(f"support recovery {rec:.3f}, info {info}")
@@ -148,6 +153,17 @@ def test_fullsize_shared_first_iteration_and_solve(shared_big, fmt):
         say(f"  rhs {j}: rel err {err:.2e}, backtracks {info['backtracks']}/{ref.backtracks}")
         assert err <= 1e-4, j
 
+    say(f"shared {fmt}: five iterations of every problem against the oracle on samples")
+    res = qiht.niht_solve_batched(probs, max_iters=5, tol=-1.0)
+    for j in (0, 97, 200):
+        xr, sr, its, bts = chain_oracle(A, A, Y[:, j], S5, 5)
+        x, sup, info = res[j]
+        np.testing.assert_array_equal(sup.cpu().numpy(), sr, err_msg=f"rhs {j}")
+        assert info["iterations"] == its == 5 and info["backtracks"] == bts, j
+        err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
+        say(f"  rhs {j}: 5 iterations, rel err {err:.2e}, backtracks {bts}")
+        assert err <= 1e-4, j
+
     say(f"shared {fmt}: 30 iterations")
     res = qiht.niht_solve_batched(probs, max_iters=30, tol=-1.0)
     rec = []
@@ -170,4 +186,6 @@ def test_fullsize_shared_first_iteration_and_solve(shared_big, fmt):
     err = np.linalg.norm(g.cpu().numpy() - g_or)
     say(f"  gradient at the final iterate: |dg| {err:.2e}, |g| {np.linalg.norm(g_or):.2e}")
     assert err <= 1e-5 * max(np.linalg.norm(g_or), 1e-3 * g0n)
+    worst = assert_g_elementwise(g.cpu().numpy(), g_or, g_bound(A, r_or), what=f"shared {fmt} g")
+    say(f"  element-wise: worst |dg_j| / sum_i |a_ij r_i| = {worst:.2e}")
     q.free()

@@ -5,7 +5,8 @@ Bars (stated per test):
 * H_s supports: exact (same FP32 input on both sides, ties to the lower
   index);
 * gradient g: |g_gpu - g_orc| <= 1e-5 max(|g_orc|, 1e-3 |g0|) with the oracle
-  evaluated in FP64 at the GPU's x (teacher forcing);
+  evaluated in FP64 at the GPU's x (teacher forcing), and entry by entry
+  |g_gpu_j - g_orc_j| <= 1e-5 sum_i |q_ij r_i|;
 * solves: identical final supports, |x_gpu - x_orc| / |x_orc| <= 1e-4.
 """
 
@@ -18,6 +19,8 @@ import paper_1802_04907_amd as qiht  # noqa: E402
 import workloads  # noqa: E402
 from oracle import niht  # noqa: E402
 from oracle import quantizer as qz  # noqa: E402
+
+from parity_util import TieLog, assert_g_elementwise, check_step, g_bound  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -265,6 +268,7 @@ def test_gradient_teacher_forced(m, n, s, bits, cplx):
     g0 = q1.T @ yh
     tol = lambda ref: 1e-5 * max(np.linalg.norm(ref), 1e-3 * np.linalg.norm(g0))  # noqa: E731
     assert np.linalg.norm(g0_gpu.cpu().numpy() - g0) <= tol(g0)
+    assert_g_elementwise(g0_gpu.cpu().numpy(), g0, g_bound(q1, yh), what="g0")
     np.testing.assert_array_equal(r0.cpu().numpy(), yh.astype(np.float32))
     rng = np.random.default_rng(0)
     for trial in range(3):
@@ -278,6 +282,8 @@ def test_gradient_teacher_forced(m, n, s, bits, cplx):
         rg = r.cpu().numpy()
         assert np.all(np.abs(rg - r_or) <= 2.0 ** -23 * np.abs(r_or) + 1e-30)
         assert np.linalg.norm(g.cpu().numpy() - g_or) <= tol(g_or), trial
+        worst = assert_g_elementwise(g.cpu().numpy(), g_or, g_bound(q1, r_or), what=f"trial {trial}")
+        say(f"  trial {trial}: worst |dg_j| / sum_i |q_ij r_i| = {worst:.2e}")
 
 
 # ---------------------------------------------------------------- solves
@@ -458,6 +464,38 @@ def test_fresh_realizations_at_32_bits_are_the_fixed_solve():
     x2, s2, i2 = qiht.niht_solve(q, yhat, p.s, max_iters=40, tol=-1.0)
     assert torch.equal(s1, s2) and torch.equal(x1, x2)
     assert i1["iterations"] == i2["iterations"] and i1["backtracks"] == i2["backtracks"]
+
+
+def test_two_bit_divergence_teacher_forced():
+    """The fixed-realization 2-bit solve that diverges in the oracle
+    (1024 x 4096 Gaussian, s = 64, 2-bit Phi / 8-bit y; Q1_G^T Q2_G is not
+    positive definite on the support): the GPU follows the oracle iteration
+    by iteration from the same FP32 state, through the iterations where the
+    cross step-size denominator is not positive and the fallback
+    |Q1_G g_G|^2 is taken (support, shrinks, step, x)."""
+    m, n, s, bits = 1024, 4096, 64, 2
+    p = workloads.gaussian(m, n, s, 1e-3, seed=0, dtype=np.float32)
+    q, yhat = _gpu_problem(p, bits)
+    q1, q2, yh = _oracle_mats(p, bits)
+    g0n = float(np.linalg.norm(q1.T @ yh))
+    x = np.zeros(n)
+    sup = niht.initial_support(q1, yh, s)
+    ties = TieLog()
+    fallbacks = 0
+    for it in range(95):
+        g = q1.T @ (yh - q2 @ x)
+        fallbacks += float((q1[:, sup] @ g[sup]) @ (q2[:, sup] @ g[sup])) <= 0.0
+        xg, sg, info = qiht.niht_solve(q, yhat, s, max_iters=1, tol=-1.0,
+                                       x0=_t(x.astype(np.float32)), support0=_t(sup.astype(np.int32)))
+        gx = xg.cpu().numpy().astype(np.float64)
+        gs = sg.cpu().numpy().astype(np.int64)
+        check_step(q1, q2, yh, x, sup, s, gx, gs, info, g0n, ties, f"iteration {it}")
+        x, sup = gx, gs
+    say(f"  |x| after 95 iterations {np.linalg.norm(x):.3g}, fallback iterations {fallbacks}, "
+        f"near-ties {ties.count}")
+    assert fallbacks >= 1 and np.linalg.norm(x) > 100 * np.linalg.norm(p.x_true)
+    assert ties.count <= 2, ties.notes
+    q.free()
 
 
 def test_determinism_bitwise():

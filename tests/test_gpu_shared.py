@@ -6,7 +6,8 @@ one GEMM on the matrix cores.
 Bars (stated per test):
 * stored values and row exponents: bit-exact against oracle.lowprec;
 * gradient g: |g_gpu - g_orc| <= 1e-5 max(|g_orc|, 1e-3 |g0|) with the
-  oracle in FP64 on the effective matrix A = diag(2^e) Phi~ at the GPU's x;
+  oracle in FP64 on the effective matrix A = diag(2^e) Phi~ at the GPU's x,
+  and entry by entry |g_gpu_j - g_orc_j| <= 1e-5 sum_i |a_ij r_i|;
   r: the FP64 residual rounded once to FP32;
 * solves: against the oracle's NIHT on A (the stored operand, exact in
   FP64) with y_hat = y: identical supports, |x_gpu - x_orc| / |x_orc| <= 1e-4;
@@ -25,6 +26,8 @@ import workloads  # noqa: E402
 from oracle import lowprec as lp  # noqa: E402
 from oracle import niht  # noqa: E402
 from oracle import quantizer as qz  # noqa: E402
+
+from parity_util import assert_g_elementwise, g_bound  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -109,6 +112,7 @@ def test_gradient_teacher_forced(fmt, m, n, s, cplx):
     g0 = A.T @ y
     tol = lambda ref: 1e-5 * max(np.linalg.norm(ref), 1e-3 * np.linalg.norm(g0))  # noqa: E731
     assert np.linalg.norm(g0_gpu.cpu().numpy() - g0) <= tol(g0)
+    assert_g_elementwise(g0_gpu.cpu().numpy(), g0, g_bound(A, y), what="g0")
     np.testing.assert_array_equal(r0.cpu().numpy(), y.astype(np.float32))
     rng = np.random.default_rng(0)
     for trial in range(3):
@@ -122,7 +126,9 @@ def test_gradient_teacher_forced(fmt, m, n, s, cplx):
         rg = r.cpu().numpy()
         assert np.all(np.abs(rg - r_or) <= 2.0 ** -23 * np.abs(r_or) + 1e-30), trial
         err = np.linalg.norm(g.cpu().numpy() - g_or)
-        say(f"  trial {trial}: |dg|/|g| {err / np.linalg.norm(g_or):.2e}")
+        worst = assert_g_elementwise(g.cpu().numpy(), g_or, g_bound(A, r_or), what=f"trial {trial}")
+        say(f"  trial {trial}: |dg|/|g| {err / np.linalg.norm(g_or):.2e}, "
+            f"worst |dg_j| / sum_i |a_ij r_i| {worst:.2e}")
         assert err <= tol(g_or), trial
     q.free()
 

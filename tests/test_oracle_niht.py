@@ -346,3 +346,108 @@ def test_fresh_realizations_solver():
     np.testing.assert_array_equal(one.x, fixed.x)
     assert not np.array_equal(qzz.dequantized_vector(p.y, 8, 7, realization=1), yh)
     assert not np.array_equal(qzz.dequantized_matrix(p.phi, 4, 7, 2), q1)
+
+
+def test_step_size_zero_fallback_is_stationary():
+    # The second fallback of the step size (reading N3): the cross
+    # denominator is not positive and |Phi1_G g_G|^2 is 0 as well, with
+    # g_G != 0.  Two identical support columns and g_G = (1, -1) give
+    # Phi1_G g_G = 0 exactly, so no step exists: stationary (mu = None).
+    phi = np.zeros((4, 3))
+    phi[:, 0] = phi[:, 1] = [1.0, -2.0, 0.5, 3.0]
+    phi[:, 2] = [0.0, 1.0, 0.0, 0.0]
+    g = np.array([1.0, -1.0, 5.0])
+    mu, num, den = niht.step_size(g, np.array([0, 1]), phi, phi)
+    assert mu is None and num == 2.0 and den == 0.0
+    mu, num, den = niht.step_size(g, np.array([0, 1]), phi, -phi)
+    assert mu is None and num == 2.0 and den == 0.0
+    # the third column alone (a unit column with g = 5) has the step 1
+    mu, _, _ = niht.step_size(g, np.array([2]), phi, phi)
+    assert mu == 1.0
+
+
+def test_stationary_when_gradient_vanishes_on_support():
+    # With g = Phi1^T r the second fallback coincides with g_G = 0: if
+    # Phi1_G g_G = 0 then |g_G|^2 = g_G^T Phi1_G^T r = (Phi1_G g_G)^T r = 0,
+    # so in exact arithmetic an iteration reaches it only as g_G = 0.  A state
+    # whose residual is orthogonal to the support columns (unit columns and
+    # zero observations there) stops at once, with the warm-start iterate.
+    phi = np.zeros((5, 4))
+    phi[0, 0] = phi[1, 1] = 1.0
+    phi[2:, 2] = [1.0, 2.0, 0.0]
+    phi[2:, 3] = [0.0, 1.0, 1.0]
+    y = np.array([0.0, 0.0, 1.0, 2.0, 3.0])
+    res = niht.qiht_solve(phi, phi, y, 2, max_iters=10, tol=-1.0,
+                          x0=np.zeros(4), support0=np.array([0, 1]))
+    assert res.reason == niht.REASON_STATIONARY and res.iterations == 0
+    np.testing.assert_array_equal(res.x, np.zeros(4))
+    # the same data from x0 = 0 without the warm start moves off at once
+    res = niht.qiht_solve(phi, phi, y, 2, max_iters=10, tol=-1.0)
+    assert res.reason != niht.REASON_STATIONARY and res.iterations >= 1
+
+
+def test_fresh_draw_indices_per_iteration():
+    # Algorithm 2's inputs: iteration n uses Phi_hat_{2n-1} for Phi^T,
+    # Phi_hat_{2n} for Phi and y_hat_n, i.e. matrix realizations 2n-2 and
+    # 2n-1 and vector realization n-1 (0-based).  Chain three iterations by
+    # hand from those realizations and compare with the solver, for every
+    # prefix; a shifted index map (realizations n-1 and n) gives another x.
+    import workloads
+    p = workloads.gaussian(80, 200, 5, 1e-3, seed=11)
+    seed = 5
+
+    def dm(r):
+        return qz.dequantized_matrix(p.phi, 4, seed, r)
+
+    def dv(r):
+        return qz.dequantized_vector(p.y, 8, seed, realization=r)
+
+    x = np.zeros(p.n)
+    sup = niht.initial_support(dm(0), dv(0), p.s)
+    shifted_x = x.copy()
+    shifted_sup = sup.copy()
+    for it in range(1, 4):
+        ref = niht.qiht_iteration(dm(2 * it - 2), dm(2 * it - 1), dv(it - 1), x, sup, p.s)
+        x, sup = ref.x, ref.support
+        got = niht.qiht_solve_fresh(p.phi, p.y, p.s, 4, 8, seed, max_iters=it, tol=-1.0)
+        assert got.iterations == it
+        np.testing.assert_array_equal(got.support, sup)
+        np.testing.assert_array_equal(got.x, x)
+        wrong = niht.qiht_iteration(dm(it - 1), dm(it), dv(it - 1), shifted_x, shifted_sup, p.s)
+        shifted_x, shifted_sup = wrong.x, wrong.support
+        if it >= 2:
+            assert not np.array_equal(shifted_x, x)
+
+
+def test_two_bit_divergence_and_its_cause():
+    # Fixed realizations at 2 bits on a Gaussian Phi (max-abs scale: the
+    # quantization noise is about three times the signal): Q1_G^T Q2_G loses
+    # positive definiteness on the support, the cross step-size denominator
+    # turns non-positive (the fallback of reading N3 is taken) and the
+    # iterate grows without bound.  The same instance at 8 bits converges
+    # and Q1_G^T Q2_G stays positive definite on every support.
+    import workloads
+    m, n, s = 1024, 4096, 64
+    p = workloads.gaussian(m, n, s, 1e-3, seed=0, dtype=np.float32)
+    yh = qz.dequantized_vector(p.y, 8, p.seed)
+    out = {}
+    for bits in (2, 8):
+        q1 = qz.dequantized_matrix(p.phi, bits, p.seed, 0)
+        q2 = qz.dequantized_matrix(p.phi, bits, p.seed, 1)
+        x = np.zeros(n)
+        sup = niht.initial_support(q1, yh, s)
+        min_eig, fallbacks = np.inf, 0
+        for _ in range(100):
+            a = q1[:, sup].T @ q2[:, sup]
+            min_eig = min(min_eig, np.linalg.eigvalsh(0.5 * (a + a.T)).min())
+            g = q1.T @ (yh - q2 @ x)
+            fallbacks += float((q1[:, sup] @ g[sup]) @ (q2[:, sup] @ g[sup])) <= 0.0
+            res = niht.qiht_iteration(q1, q2, yh, x, sup, s)
+            assert not res.stationary
+            x, sup = res.x, res.support
+        err = np.linalg.norm(x - p.x_true) / np.linalg.norm(p.x_true)
+        out[bits] = (err, min_eig, fallbacks)
+    err2, eig2, fb2 = out[2]
+    err8, eig8, fb8 = out[8]
+    assert err2 > 100.0 and eig2 < 0.0 and fb2 >= 1
+    assert err8 < 0.02 and eig8 > 0.3 and fb8 == 0
