@@ -272,6 +272,35 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
                                     void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code that runs while a HIP
+ * graph is being captured elsewhere in the process, tight serving loops,
+ * harnesses that forbid hipMalloc): the solve of qiht_niht_solve, whose
+ * per-call workspace (residual, gradient, iterate, proposals, candidate
+ * lists, partial sums, control state) lives in a fixed device array of
+ * QIHT_NOALLOC_WORKSPACE_BYTES bytes instead of memory from the library's
+ * pool.  Each device the library runs on holds its own copy of the array
+ * until the process ends.  The call allocates and frees no device memory.
+ *
+ *   Arguments, outputs, results and errors as qiht_niht_solve (the same
+ *   kernels run, so results are bitwise those of qiht_niht_solve), and:
+ *   p->profile and p->refit must be 0 (UNSUPPORTED: profiling needs events,
+ *   the refit its own workspace).  A problem whose workspace exceeds the
+ *   array returns UNSUPPORTED before any device work, with the size it needs
+ *   in qiht_last_error(); the workspace grows about as 36 n + 8 rows bytes
+ *   (up to n = 65536 columns it fits for any row count up to a few million).
+ *   The array keeps the last call's contents; each call clears what must
+ *   start at zero.  All calls on one device share the array: the library
+ *   runs the calls of one process on one device one after another (each
+ *   holds the array until it has synchronized its stream).  Synchronizes
+ *   stream.
+ */
+#define QIHT_NOALLOC_WORKSPACE_BYTES (16LL << 20)
+qiht_status qiht_niht_solve_noalloc(const qiht_qmatrix* q, const double* yhat,
+                                    int64_t s, const qiht_params* p,
+                                    float* x_out, int32_t* support_out,
+                                    qiht_info* info, void* stream);
+
+/*
  * Algorithm 2 with its realizations drawn per iteration, as its input lists
  * them: 2n* realizations of Q(Phi) and n* of Q(y).  Iteration n uses
  * Phi_hat_{2n-1} for Phi^T and Phi_hat_{2n} for Phi (matrix realizations

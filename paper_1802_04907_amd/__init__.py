@@ -12,7 +12,7 @@ no CPU fallback.
 
 Functions keep the C names without the ``qiht_`` prefix:
 ``quantize_matrix``, ``quantize_vector``, ``niht_solve``,
-``niht_solve_batched``, ``niht_solve_fresh``, ``gradient``,
+``niht_solve_noalloc``, ``niht_solve_batched``, ``niht_solve_fresh``, ``gradient``,
 ``fourier_gradient``, ``fourier_niht_solve``, ``hard_threshold``,
 ``refit``, ``last_error``.
 """
@@ -22,7 +22,7 @@ import ctypes as C
 from . import _lib
 
 __all__ = ["QihtError", "QMatrix", "quantize_matrix", "quantize_vector",
-           "niht_solve", "niht_solve_batched", "niht_solve_fresh", "gradient",
+           "niht_solve", "niht_solve_noalloc", "niht_solve_batched", "niht_solve_fresh", "gradient",
            "fourier_gradient", "fourier_niht_solve", "hard_threshold",
            "last_error", "version", "library_path"]
 
@@ -194,6 +194,24 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
     inf = _lib.QihtInfo()
     _check(_lib.load().qiht_niht_solve(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
                                        _ptr(sup), C.byref(inf), _stream(stream)))
+    return x, sup, _info_dict(inf)
+
+
+def niht_solve_noalloc(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
+                       mu_mode=0, x0=None, support0=None, stream=None):
+    """The solve of ``niht_solve`` with its workspace in the library's fixed
+    device array (no device allocation by the library; the outputs are the
+    caller's tensors, allocated here by PyTorch) -> (x, support, info)."""
+    torch = _torch()
+    x = torch.empty(q.n, dtype=torch.float32, device=yhat.device)
+    sup = torch.empty(int(s), dtype=torch.int32, device=yhat.device)
+    if x0 is not None:
+        x0 = x0.to(dtype=torch.float32).contiguous()
+        support0 = support0.to(dtype=torch.int32).contiguous()
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0, support0)
+    inf = _lib.QihtInfo()
+    _check(_lib.load().qiht_niht_solve_noalloc(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
+                                               _ptr(sup), C.byref(inf), _stream(stream)))
     return x, sup, _info_dict(inf)
 
 

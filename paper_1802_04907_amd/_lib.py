@@ -10,6 +10,7 @@ QIHT_OK = 0
 QIHT_FMT_BF16 = 116  # dense formats (include/qiht.h)
 QIHT_FMT_E4M3 = 108
 QIHT_ODD_LEVELS = 0x100  # odd level set, OR'd into a bit width
+QIHT_NOALLOC_WORKSPACE_BYTES = 16 << 20  # the no-allocation solve's device array
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
                 4: "DEVICE", 5: "NUMERIC"}
 DTYPE = {"f64": 0, "f32": 1, "c64": 2, "c128": 3}
@@ -54,6 +55,9 @@ SIGNATURES = {
     "qiht_niht_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
                                   C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
                                   C.POINTER(QihtInfo), C.c_void_p]),
+    "qiht_niht_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
+                                          C.POINTER(QihtInfo), C.c_void_p]),
     "qiht_niht_solve_fresh": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int,
                                         C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_uint64,
                                         C.c_int64, C.POINTER(QihtParams), C.c_void_p,

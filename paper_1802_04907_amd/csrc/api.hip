@@ -444,6 +444,33 @@ qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat, int64_t s
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }
 
+qiht_status qiht_niht_solve_noalloc(const qiht_qmatrix* q, const double* yhat, int64_t s,
+                                    const qiht_params* p, float* x_out, int32_t* support_out,
+                                    qiht_info* info, void* stream) try {
+    set_error("");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    if (p->profile) return fail(QIHT_ERR_UNSUPPORTED, "no profiling without allocation (events)");
+    if (p->refit) return fail(QIHT_ERR_UNSUPPORTED, "no refit without allocation (its workspace)");
+    s0 = check_problem(q, yhat, s, x_out, support_out);
+    if (s0 != QIHT_OK) return s0;
+    int dev = 0;
+    s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    if (p->support0) {
+        s0 = check_support(p->support0, s, q->n, static_cast<hipStream_t>(stream));
+        if (s0 != QIHT_OK) return s0;
+    }
+    ProblemIn in{q, yhat, s, x_out, support_out, p->x0, p->support0};
+    qiht_info tmp;
+    s0 = run_solve_noalloc(in, to_args(p), &tmp, static_cast<hipStream_t>(stream));
+    if (s0 != QIHT_OK) return s0;
+    if (info) *info = tmp;
+    return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
 qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t ld,
                                   qiht_dtype dtype, int bits, const void* y,
                                   qiht_dtype ydtype, int ybits, uint64_t seed, int64_t s,

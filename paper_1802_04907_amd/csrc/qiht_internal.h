@@ -129,8 +129,15 @@ struct FreshSource {
     double* yhat;           // device: the y_hat the solve reads
 };
 
+// ext_ws (optional): ext_cap bytes of device memory that hold the workspace
+// instead of the library's pool (UNSUPPORTED when the solve needs more).
 qiht_status run_solve(const ProblemIn* probs, int count, const SolveArgs& a,
-                      qiht_info* infos, hipStream_t st, const FreshSource* fresh = nullptr);
+                      qiht_info* infos, hipStream_t st, const FreshSource* fresh = nullptr,
+                      uint8_t* ext_ws = nullptr, size_t ext_cap = 0);
+// One solve whose workspace is the library's fixed device array (no device
+// allocation); calls on one device take turns.
+qiht_status run_solve_noalloc(const ProblemIn& in, const SolveArgs& a, qiht_info* info,
+                              hipStream_t st);
 
 qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat,
                          const float* x, const int32_t* support, int64_t s,

@@ -403,8 +403,9 @@ struct PassTimer {
 struct Workspace {
     uint8_t* base = nullptr;
     hipStream_t st = nullptr;
+    bool owned = true;  // false: the caller's memory (the no-allocation array)
     ~Workspace() {
-        if (base) (void)hipFreeAsync(base, st);
+        if (base && owned) (void)hipFreeAsync(base, st);
     }
 };
 
@@ -447,16 +448,27 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
 }
 
+// ext (optional): memory of ext_cap bytes to carve the workspace from
+// instead of the pool.
 qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
-                  ProbDev** dP, Task** dT) {
+                  ProbDev** dP, Task** dT, uint8_t* ext = nullptr, size_t ext_cap = 0) {
     qiht_status s0 = make_plan(in, count, pl);
     if (s0 != QIHT_OK) return s0;
     ws.st = st;
-    hipError_t e = pool_malloc(reinterpret_cast<void**>(&ws.base), pl.bytes, st);
-    if (e != hipSuccess || ws.base == nullptr) {
-        ws.base = nullptr;
-        (void)hipGetLastError();
-        return fail(QIHT_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+    if (ext) {
+        if (pl.bytes > ext_cap)
+            return fail(QIHT_ERR_UNSUPPORTED, "the solve needs a workspace of " + std::to_string(pl.bytes) +
+                                                  " bytes, above the no-allocation array's " +
+                                                  std::to_string(ext_cap));
+        ws.base = ext;
+        ws.owned = false;
+    } else {
+        hipError_t e = pool_malloc(reinterpret_cast<void**>(&ws.base), pl.bytes, st);
+        if (e != hipSuccess || ws.base == nullptr) {
+            ws.base = nullptr;
+            (void)hipGetLastError();
+            return fail(QIHT_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        }
     }
     bind(pl, ws.base);
     QIHT_HIP(hipMemsetAsync(ws.base, 0, pl.bytes, st));
@@ -473,7 +485,7 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
 }  // namespace
 
 qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qiht_info* infos,
-                      hipStream_t st, const FreshSource* fresh) {
+                      hipStream_t st, const FreshSource* fresh, uint8_t* ext_ws, size_t ext_cap) {
     SolveArgs a = args;
     // (fresh draws are made between the commit and the residual gather)
     a.decide_in_gather = (count == 1 && !fresh) ? 1 : 0;
@@ -481,7 +493,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     Workspace ws;
     ProbDev* dP = nullptr;
     Task* dT = nullptr;
-    qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT);
+    qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT, ext_ws, ext_cap);
     if (s0 != QIHT_OK) return s0;
     std::vector<float*> xo(count);
     std::vector<int32_t*> so(count);
@@ -610,6 +622,52 @@ qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* su
     QIHT_HIP(hipStreamSynchronize(st));
     if (herr) return fail(QIHT_ERR_NUMERIC, "NaN in the input of H_s");
     return QIHT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The solve without device allocation (qiht_niht_solve_noalloc).  Its
+// workspace is a file-scope device array: every device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, so the array's device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that
+// address is ever handed to kernels or copies.  Calls of one process on one
+// device take turns (a per-device lock held until the call has synchronized
+// its stream), since they all use the same array.
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __align__(256) uint8_t scratch[QIHT_NOALLOC_WORKSPACE_BYTES];
+
+struct ScratchSlot {
+    std::mutex run;          // held for a whole call on this device
+    uint8_t* ptr = nullptr;  // the device address of `scratch` (set once)
+};
+
+ScratchSlot& scratch_slot(int dev) {
+    static std::mutex mu;
+    static std::map<int, ScratchSlot> slots;
+    std::lock_guard<std::mutex> lk(mu);
+    return slots[dev];  // (std::map never moves its elements)
+}
+
+}  // namespace
+
+qiht_status run_solve_noalloc(const ProblemIn& in, const SolveArgs& a, qiht_info* info, hipStream_t st) {
+    int dev = 0;
+    QIHT_HIP(hipGetDevice(&dev));
+    ScratchSlot& slot = scratch_slot(dev);
+    std::lock_guard<std::mutex> lk(slot.run);
+    if (!slot.ptr) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            return fail(QIHT_ERR_DEVICE, "no device address for the no-allocation workspace");
+        }
+        slot.ptr = static_cast<uint8_t*>(p);
+    }
+    return run_solve(&in, 1, a, info, st, nullptr, slot.ptr,
+                     static_cast<size_t>(QIHT_NOALLOC_WORKSPACE_BYTES));
 }
 
 }  // namespace qiht
