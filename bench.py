@@ -30,7 +30,13 @@ sys.path.insert(0, ROOT)
 
 M, N, S, SIGMA, SEED, ITERS = 8192, 32768, 512, 1e-3, 0, 200
 PEAK_HBM_GBPS = 8000.0
-EQ_ERR_BAR = 2.0  # an equal-error speed-up is reported only for e* <= this x the FP32 floor
+# An equal-error speed-up is reported only where e* is a recovery: a relative
+# error of at most EQ_ERR_BAR (5%), reached by both solves.
+EQ_ERR_BAR = 0.05
+# Pass timing: HIP events recorded by every PROFILE_EVERY-th full-pass
+# dispatch (each timed dispatch carries a few microseconds of extra latency,
+# so timing all of them would slow the solve being measured).
+PROFILE_EVERY = 8
 # shared-matrix workload: one Phi, NRHS right-hand sides of sparsity S5
 NRHS, S5, ITERS5 = 256, 256, 30
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
@@ -79,7 +85,7 @@ def measured_traffic(bits):
     return val if (h == want and val is not None) else None
 
 
-def one_step(qiht, phi_d, y_d, bits, profile=True, **kw):
+def one_step(qiht, phi_d, y_d, bits, profile=PROFILE_EVERY, **kw):
     ybits = 32 if bits == 32 else 8
     q = qiht.quantize_matrix(phi_d, bits, 2, SEED)
     yhat, _, _ = qiht.quantize_vector(y_d, ybits, SEED)
@@ -183,7 +189,7 @@ def shared_bench(qiht, torch, dev, reps=2, only=None):
         t0 = time.perf_counter()
         gemm_ms, gemm_n = 0.0, 0
         for _ in range(reps):
-            out = qiht.niht_solve_batched(probs, max_iters=ITERS5, tol=-1.0, profile=True)
+            out = qiht.niht_solve_batched(probs, max_iters=ITERS5, tol=-1.0, profile=PROFILE_EVERY)
             gemm_ms += out[0][2]["pass_ms"]
             gemm_n += out[0][2]["pass_launches"]
         torch.cuda.synchronize()
@@ -271,7 +277,7 @@ def interferometry_bench(qiht, torch, dev, iters=ITERS, reps=3):
     t0 = time.perf_counter()
     tot_ms, tot_l = 0.0, 0
     for _ in range(reps):
-        x, sp, inf = qiht.niht_solve(q, yhat, s, max_iters=iters, tol=-1.0, profile=True)
+        x, sp, inf = qiht.niht_solve(q, yhat, s, max_iters=iters, tol=-1.0, profile=PROFILE_EVERY)
         tot_ms += inf["pass_ms"]
         tot_l += inf["pass_launches"]
     torch.cuda.synchronize()
@@ -357,6 +363,46 @@ def fourier_bench(qiht, torch, dev, stored_pass_us=None, reps=20):
     return out
 
 
+def hbm_resident_bench(qiht, torch, dev, m=16384, n=65536, s=1024, iters=100):
+    """The headline workload at twice the size in both dimensions: 4-bit Q1
+    of 537 MB, more than the 256 MB Infinity Cache holds, so every pass
+    streams its codes from HBM.  Gaussian Phi N(0, 1/m) in FP32 drawn on the
+    device, s-sparse x with N(0, 1) nonzeros, sigma_e = 1e-3, 8-bit y."""
+    g = torch.Generator(device=dev)
+    g.manual_seed(77)
+    phi = torch.randn((m, n), generator=g, device=dev, dtype=torch.float32) * (1.0 / math.sqrt(m))
+    rng = np.random.default_rng(77)
+    sup = np.sort(rng.choice(n, s, replace=False))
+    xv = rng.standard_normal(s)
+    y = phi[:, torch.from_numpy(sup).to(dev)].double() @ torch.from_numpy(xv).to(dev)
+    y = (y + SIGMA * torch.from_numpy(rng.standard_normal(m)).to(dev)).contiguous()
+    q = qiht.quantize_matrix(phi, 4, 2, 77)
+    yhat, _, _ = qiht.quantize_vector(y, 8, 77)
+    del phi
+    torch.cuda.empty_cache()
+    qiht.niht_solve(q, yhat, s, max_iters=3, tol=-1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, sp, inf = qiht.niht_solve(q, yhat, s, max_iters=iters, tol=-1.0, profile=PROFILE_EVERY)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    avg = inf["pass_ms"] / inf["pass_launches"] / 1e3
+    x_true = np.zeros(n)
+    x_true[sup] = xv
+    xs, ss = x.cpu().numpy().astype(np.float64), sp.cpu().numpy()
+    q.free()
+    return {
+        "workload": (f"Gaussian Phi {m}x{n} FP32 N(0,1/{m}), s={s}, sigma_e={SIGMA}, 4-bit Phi "
+                     f"(2 realizations, {m * n // 2 / 1e6:.0f} MB each) / 8-bit y, {iters} iterations"),
+        "iterations_per_s": round(iters / el, 1),
+        "pass_avg_us": round(avg * 1e6, 2),
+        "pass_GBps": round(pass_bytes(m, n, 4) / avg / 1e9, 1),
+        "pass_frac": round(pass_bytes(m, n, 4) / avg / 1e9 / PEAK_HBM_GBPS, 4),
+        "support_recovery": round(len(np.intersect1d(ss, sup)) / s, 4),
+        "rel_err": round(float(np.linalg.norm(xs - x_true) / np.linalg.norm(x_true)), 5),
+    }
+
+
 def batched_bench(qiht, torch, dev, count=96, iters=100):
     """Uneven independent problems: m uniform in [1024, 8192] (the master draw
     of workloads.batch_uneven), n = 4m, s = m/16, Gaussian Phi N(0, 1/m) in
@@ -381,14 +427,23 @@ def batched_bench(qiht, torch, dev, count=96, iters=100):
         del phi
         qs.append(q)
         probs.append((q, yhat, s))
-    qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)
-    qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    qiht.niht_solve_batched(probs, max_iters=iters, tol=-1.0)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    for q, yhat, s in probs[:2]:
+    def timed_batch():
+        qiht.niht_solve_batched(probs, max_iters=2, tol=-1.0)
+        for _ in range(3):  # (captured as HIP graphs from the third solve of a shape on)
+            qiht.niht_solve_batched(probs, max_iters=iters, tol=-1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qiht.niht_solve_batched(probs, max_iters=iters, tol=-1.0)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # the heuristic launch shape, then the autotuned one (tuned on first use)
+    os.environ["QIHT_AUTOTUNE"] = "0"
+    t_default = timed_batch()
+    del os.environ["QIHT_AUTOTUNE"]
+    t_batch = timed_batch()
+    # every single problem once first (each shape is tuned on first use)
+    for q, yhat, s in probs:
         qiht.niht_solve(q, yhat, s, max_iters=2, tol=-1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -403,6 +458,7 @@ def batched_bench(qiht, torch, dev, count=96, iters=100):
         "workload": (f"{count} independent Gaussian problems, m uniform in [1024, 8192], n = 4m, "
                      f"s = m/16, 4-bit Phi / 8-bit y, {iters} iterations"),
         "batched_ms": round(t_batch * 1e3, 2),
+        "batched_ms_default_launch_shape": round(t_default * 1e3, 2),
         "sequential_ms": round(t_seq * 1e3, 2),
         "speedup_vs_sequential": round(t_seq / t_batch, 2),
         "problem_iterations_per_s": round(count * iters / t_batch, 1),
@@ -520,6 +576,11 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
+    ap.add_argument("--hbm-only", action="store_true",
+                    help="only the HBM-resident workload (16384 x 65536, 4-bit; short run for "
+                         "rocprofv3 traces and counters of its pass)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched uneven workload (96 problems)")
     ap.add_argument("--fourier-only", action="store_true",
                     help="only time the interferometry gradient with Phi computed on the fly")
     ap.add_argument("--synthetic-sweep", action="store_true",
@@ -554,6 +615,12 @@ def main():
         return
     if args.fourier_only:
         print(json.dumps(fourier_bench(qiht, torch, dev)))
+        return
+    if args.hbm_only:
+        print(json.dumps(hbm_resident_bench(qiht, torch, dev, iters=20)))
+        return
+    if args.batched_only:
+        print(json.dumps(batched_bench(qiht, torch, dev, iters=20)))
         return
     if args.synthetic_sweep:
         print(json.dumps(synthetic_sweep(qiht, torch, dev)))
@@ -609,9 +676,42 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic,
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_s * 1e6, 3),
-                     "launches_timed": launches},
+                     "launches_timed": launches,
+                     "timing": f"HIP events recorded by every {PROFILE_EVERY}th pass dispatch of the "
+                               f"timed steps, on the solve's stream"},
     }
     log(json.dumps(out["roofline"]))
+    # The solve alone on resident codes, without pass timing: its rounds then
+    # replay as captured HIP graphs.
+    q = qiht.quantize_matrix(phi_d, bits, 2, SEED)
+    yhat, _, _ = qiht.quantize_vector(y_d, 32 if bits == 32 else 8, SEED)
+
+    def timed_solves():
+        # (a launch shape is captured as HIP graphs from its third solve on:
+        # warm up past that)
+        for _ in range(3):
+            qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / 5
+
+    t_solve = timed_solves()
+    os.environ["QIHT_AUTOTUNE"] = "0"
+    t_default = timed_solves()
+    del os.environ["QIHT_AUTOTUNE"]
+    q.free()
+    out["solve_only"] = {"workload": f"the headline solve ({ITERS} iterations) on codes already quantized, "
+                                     f"no pass timing (rounds replayed as captured HIP graphs)",
+                         "iterations_per_s": round(ITERS / t_solve, 1),
+                         "iterations_per_s_default_launch_shape": round(ITERS / t_default, 1),
+                         "us_per_iteration": round(t_solve / ITERS * 1e6, 2),
+                         "iteration_GBps": round(iteration_bytes(M, N, S, bits) / (t_solve / ITERS) / 1e9, 1),
+                         "iteration_frac": round(iteration_bytes(M, N, S, bits) / (t_solve / ITERS) / 1e9
+                                                 / PEAK_HBM_GBPS, 4)}
+    log(json.dumps(out["solve_only"]))
 
     if not args.no_sweep:
         sweep = {}
@@ -628,7 +728,7 @@ def main():
             reps = 3
             tot_ms, tot_l = 0.0, 0
             for _ in range(reps):
-                _, _, inf = qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0, profile=True)
+                _, _, inf = qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0, profile=PROFILE_EVERY)
                 tot_ms += inf["pass_ms"]
                 tot_l += inf["pass_launches"]
             torch.cuda.synchronize()
@@ -652,8 +752,8 @@ def main():
         # Time to 90% support recovery (the end-to-end criterion of the
         # paper's speed-up measurements, Sec. IV-C), and time to an equal
         # recovery error e* = 1.05 max(floor_b, floor_32) -- the latter only
-        # where e* is a meaningful target: at most EQ_ERR_BAR times the FP32
-        # floor and reached by both solves; otherwise null with the reason.
+        # where e* is a recovery (a relative error of at most EQ_ERR_BAR)
+        # reached by both solves; otherwise null with the reason.
         f32 = sweep["32"]
         for b in ("8", "4", "2"):
             d = sweep[b]
@@ -677,10 +777,10 @@ def main():
             if not math.isfinite(d["final_rel_err"]) or d["final_rel_err"] >= 1.0:
                 note = (f"the {b}-bit solve diverged (final relative error "
                         f"{d['final_rel_err']:.3g}): no equal recovery error exists")
-            elif e_star > EQ_ERR_BAR * f32["final_rel_err"]:
-                note = (f"the {b}-bit error floor {d['final_rel_err']:.3g} is above "
-                        f"{EQ_ERR_BAR:g}x the FP32 floor {f32['final_rel_err']:.3g}: "
-                        f"an equal error there is not a recovery result")
+            elif e_star > EQ_ERR_BAR:
+                note = (f"the {b}-bit error floor {d['final_rel_err']:.3g} gives e* = {e_star:.3g}, "
+                        f"above a {EQ_ERR_BAR:.0%} relative error: an equal error there is not a "
+                        f"recovery result (FP32 floor {f32['final_rel_err']:.3g})")
             elif it_b is None or it_32 is None:
                 note = "the target was not reached by both solves"
             if note is not None:
@@ -714,11 +814,16 @@ def main():
         log("interferometry gradient with Phi on the fly ...")
         out["fourier_on_the_fly"] = fourier_bench(qiht, torch, dev, out["interferometry"]["pass_avg_us"])
         log(json.dumps(out["fourier_on_the_fly"]))
+        log("HBM-resident workload ...")
+        out["hbm_resident"] = hbm_resident_bench(qiht, torch, dev)
+        log(json.dumps(out["hbm_resident"]))
+        torch.cuda.empty_cache()
         log("batched uneven workload ...")
         out["batched_uneven"] = batched_bench(qiht, torch, dev)
         log(json.dumps(out["batched_uneven"]))
         torch.cuda.empty_cache()
 
+    out["autotune"] = qiht.tune_report()
     if not args.no_cpu:
         log("cpu baseline (oracle sample) ...")
         out["cpu_baseline"] = cpu_baseline(p)

@@ -95,8 +95,12 @@ typedef struct {
                                 NULL = x0 = 0 and G0 = supp H_s(Q1^T y_hat) */
     const int32_t* support0; /* warm-start support (device, s ascending
                                 indices); required iff x0 != NULL           */
-    int32_t profile;         /* 1: time every full-pass launch with HIP
-                                events on `stream` (qiht_info.pass_ms)      */
+    int32_t profile;         /* N >= 1: time every N-th full-pass launch
+                                with HIP events recorded by the dispatch on
+                                `stream` (qiht_info.pass_ms and
+                                pass_launches cover the timed ones; each
+                                timed dispatch costs a few microseconds of
+                                extra latency); 0: off                      */
     int32_t refit;           /* 1: after the last iteration, replace x on
                                 its support by the FP64 least-squares fit
                                 against Q1 and y_hat (qiht_refit); 0 keeps
@@ -272,6 +276,38 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
                                     void* stream);
 
 /*
+ * QIHT with a complex unknown x in C^N (Sec. I-A states the problem for
+ * complex Phi and x; the MRI images of Sec. IV are complex).  Algorithm 2 in
+ * complex arithmetic: g = Q1^H (y_hat - Q2 x) (^H the conjugate transpose),
+ * mu = |g_G|^2 / Re((Q1_G g_G)^H (Q2_G g_G)) (fallback and stop as for
+ * qiht_niht_solve), H_s keeping the s entries of largest modulus |x_j| (ties
+ * to the lower index; the modulus is ranked as the FP32 rounding of
+ * Re^2 + Im^2 taken in FP64 from the FP32 parts), and the step-size test and
+ * shrinking of Sec. II-A with the norms of complex vectors.
+ *
+ *   q: a handle quantized from complex input (dtype C64 or C128 in
+ *      qiht_quantize_matrix: Q = Q(Re Phi) + i Q(Im Phi), stacked rows
+ *      [Re; Im]); packed codes (1, 2, 4, 8 bits, odd levels too) or 32.
+ *      INVALID_ARG for a handle of real input, UNSUPPORTED for a dense format.
+ *   yhat: device, 2m doubles [Re y_hat; Im y_hat] (qiht_quantize_vector of
+ *      the complex y).
+ *   1 <= s <= min(m, n); n <= QIHT_COMPLEX_MAX_N (UNSUPPORTED above).
+ *   x_out: device, 2n floats: [Re x; Im x].  support_out: device, s int32,
+ *      ascending.  p: as qiht_niht_solve; no warm start (UNSUPPORTED); with
+ *      refit = 1 the final x is the FP64 least-squares fit on its support
+ *      against Q1 and y_hat (complex least squares).
+ * The solve runs the real kernels on the embedding [Q_re -Q_im; Q_im Q_re]
+ * of 2m x 2n (its codes are built on the first complex solve on q, from q's,
+ * and kept with q until qiht_qmatrix_free: twice q's code memory), with H_s
+ * ranking moduli over the pairs of columns (j, j + n).  Synchronizes stream.
+ */
+#define QIHT_COMPLEX_MAX_N 32768LL
+qiht_status qiht_niht_solve_complex(const qiht_qmatrix* q, const double* yhat,
+                                    int64_t s, const qiht_params* p,
+                                    float* x_out, int32_t* support_out,
+                                    qiht_info* info, void* stream);
+
+/*
  * For callers that cannot allocate device memory (code that runs while a HIP
  * graph is being captured elsewhere in the process, tight serving loops,
  * harnesses that forbid hipMalloc): the solve of qiht_niht_solve, whose
@@ -423,6 +459,30 @@ qiht_status qiht_refit(const qiht_qmatrix* q, const void* phi, int64_t m,
                        int64_t n, int64_t ld, qiht_dtype dtype,
                        const double* y, const int32_t* support, int64_t s,
                        float* x_out, double* xs_out, void* stream);
+
+/*
+ * The autotuner's choices so far in this process, as JSON text:
+ *   {"entries": [{"key": ..., "choice": ..., "default": ...,
+ *                 "candidates_us": {name: microseconds, ...}}, ...]}
+ * A solve tunes, on first meeting a problem shape (device architecture,
+ * bit width or format, problem count, column bytes, n, total code size), the
+ * launch shape of its dominant kernel by timing each candidate on the
+ * problem's own codes (median of 7 launches after a warm-up): for packed
+ * codes and FP32 the full pass g = Q1^T r ("cache" = two waves per SIMD with
+ * two columns in flight each, "long" = three waves with one; "/r1" or "/r2" =
+ * its columns cut into one or two rounds of resident workgroups), for a
+ * batch on one dense-format matrix the GEMM's row splits ("ks1", "ks2",
+ * "ks4").  The built-in heuristic ("default") is kept unless a candidate is
+ * more than 3% faster.  QIHT_AUTOTUNE=0 disables tuning; QIHT_TUNE_FILE=path
+ * reads earlier choices from that file and appends new ones to it;
+ * QIHT_TUNE_FORCE=<name> pins one candidate (for comparisons).  The
+ * pass candidates compute every entry of g identically; the GEMM's row
+ * splits change the order of its sums (within the format's tolerance).
+ * buf (host, cap bytes) receives the text, NUL-terminated and truncated to
+ * fit; returns the size the full text needs (including the NUL), 0 on
+ * failure.  buf may be NULL to query the size.
+ */
+int64_t qiht_tune_report(char* buf, int64_t cap);
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* qiht_last_error(void);

@@ -16,10 +16,12 @@ niht       Hard threshold H_s, the normalized step size (Eq. step_size),
            and the least-squares refit on the recovered support.
 lowprec    Deterministic BF16 / FP8-E4M3 storage of Phi with power-of-two
            row scales (the shared-Phi variant; not in the paper).
+complex_niht  Algorithm 2 with a complex unknown x, in complex128
+           arithmetic (conjugate-transpose gradient, H_s by modulus).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against something
 other than itself (rocRAND's Philox, closed forms, brute force, invariants
 stated in the paper).
 """
 
-from . import philox, quantizer, niht, lowprec  # noqa: F401
+from . import philox, quantizer, niht, lowprec, complex_niht  # noqa: F401

@@ -12,7 +12,7 @@ no CPU fallback.
 
 Functions keep the C names without the ``qiht_`` prefix:
 ``quantize_matrix``, ``quantize_vector``, ``niht_solve``,
-``niht_solve_noalloc``, ``niht_solve_batched``, ``niht_solve_fresh``, ``gradient``,
+``niht_solve_noalloc``, ``niht_solve_complex``, ``niht_solve_batched``, ``niht_solve_fresh``, ``gradient``,
 ``fourier_gradient``, ``fourier_niht_solve``, ``hard_threshold``,
 ``refit``, ``last_error``.
 """
@@ -22,9 +22,9 @@ import ctypes as C
 from . import _lib
 
 __all__ = ["QihtError", "QMatrix", "quantize_matrix", "quantize_vector",
-           "niht_solve", "niht_solve_noalloc", "niht_solve_batched", "niht_solve_fresh", "gradient",
+           "niht_solve", "niht_solve_noalloc", "niht_solve_complex", "niht_solve_batched", "niht_solve_fresh", "gradient",
            "fourier_gradient", "fourier_niht_solve", "hard_threshold",
-           "last_error", "version", "library_path"]
+           "last_error", "tune_report", "version", "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -44,6 +44,16 @@ def _torch():
 def _check(status):
     if status != _lib.QIHT_OK:
         raise QihtError(status, last_error())
+
+
+def tune_report():
+    """The autotuner's choices so far in this process (dict)."""
+    import json
+    lib = _lib.load()
+    need = lib.qiht_tune_report(None, 0)
+    buf = C.create_string_buffer(max(1, int(need)))
+    lib.qiht_tune_report(buf, len(buf))
+    return json.loads(buf.value.decode() or "{}")
 
 
 def last_error():
@@ -167,7 +177,8 @@ def _params(max_iters, tol, k, c, max_backtracks, mu_mode, x0=None, support0=Non
     _lib.load().qiht_default_params(C.byref(p))
     p.max_iters, p.tol, p.k, p.c = int(max_iters), float(tol), float(k), float(c)
     p.max_backtracks, p.mu_mode = int(max_backtracks), int(mu_mode)
-    p.profile = 1 if profile else 0
+    # profile: False/0 off, True/1 every pass launch timed, N every N-th
+    p.profile = int(profile) if profile else 0
     p.refit = 1 if refit else 0
     p.x0 = None if x0 is None else x0.data_ptr()
     p.support0 = None if support0 is None else support0.data_ptr()
@@ -194,6 +205,21 @@ def niht_solve(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtrack
     inf = _lib.QihtInfo()
     _check(_lib.load().qiht_niht_solve(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(x),
                                        _ptr(sup), C.byref(inf), _stream(stream)))
+    return x, sup, _info_dict(inf)
+
+
+def niht_solve_complex(q, yhat, s, max_iters=300, tol=1e-8, k=2.0, c=0.01, max_backtracks=32,
+                       mu_mode=0, stream=None, profile=False, refit=False):
+    """QIHT with a complex unknown on a handle quantized from complex Phi
+    -> (x complex64 CUDA tensor of n, support int32, info dict)."""
+    torch = _torch()
+    xr = torch.empty(2 * q.n, dtype=torch.float32, device=yhat.device)
+    sup = torch.empty(int(s), dtype=torch.int32, device=yhat.device)
+    p = _params(max_iters, tol, k, c, max_backtracks, mu_mode, profile=profile, refit=refit)
+    inf = _lib.QihtInfo()
+    _check(_lib.load().qiht_niht_solve_complex(q.handle, _ptr(yhat), int(s), C.byref(p), _ptr(xr),
+                                               _ptr(sup), C.byref(inf), _stream(stream)))
+    x = torch.complex(xr[:q.n], xr[q.n:])
     return x, sup, _info_dict(inf)
 
 

@@ -55,6 +55,9 @@ SIGNATURES = {
     "qiht_niht_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
                                   C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
                                   C.POINTER(QihtInfo), C.c_void_p]),
+    "qiht_niht_solve_complex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
+                                          C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
+                                          C.POINTER(QihtInfo), C.c_void_p]),
     "qiht_niht_solve_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64,
                                           C.POINTER(QihtParams), C.c_void_p, C.c_void_p,
                                           C.POINTER(QihtInfo), C.c_void_p]),
@@ -77,6 +80,7 @@ SIGNATURES = {
     "qiht_refit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                              C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                              C.c_void_p, C.c_void_p]),
+    "qiht_tune_report": (C.c_int64, [C.c_char_p, C.c_int64]),
     "qiht_last_error": (C.c_char_p, []),
     "qiht_version": (C.c_char_p, []),
 }

@@ -23,7 +23,7 @@ COMMON = ["-I" + os.path.join(os.path.dirname(HERE), "include"), "-O3", "-std=c+
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
 PER_FILE = {"quantize.hip": ["-ffp-contract=off"]}
-SOURCES = ["api.hip", "quantize.hip", "gather.hip", "pass.hip", "select.hip", "refit.hip", "gemm.hip", "solve_host.hip", "fourier.hip"]
+SOURCES = ["api.hip", "quantize.hip", "gather.hip", "pass.hip", "select.hip", "refit.hip", "gemm.hip", "solve_host.hip", "fourier.hip", "complex.hip"]
 
 
 def hipcc():

@@ -68,6 +68,7 @@ qiht_status check_params(const qiht_params* p) {
     if ((p->x0 == nullptr) != (p->support0 == nullptr))
         return fail(QIHT_ERR_INVALID_ARG, "x0 and support0 go together");
     if (p->refit != 0 && p->refit != 1) return fail(QIHT_ERR_INVALID_ARG, "refit is 0 or 1");
+    if (p->profile < 0) return fail(QIHT_ERR_INVALID_ARG, "profile must be >= 0");
     return QIHT_OK;
 }
 
@@ -225,6 +226,18 @@ void qiht_default_params(qiht_params* p) {
 const char* qiht_last_error(void) { return last_error_cstr(); }
 
 const char* qiht_version(void) { return "qiht-gfx950 0.1"; }
+
+int64_t qiht_tune_report(char* buf, int64_t cap) try {
+    const std::string r = tune_report();
+    if (buf && cap > 0) {
+        const size_t n = std::min(static_cast<size_t>(cap - 1), r.size());
+        std::memcpy(buf, r.data(), n);
+        buf[n] = '\0';
+    }
+    return static_cast<int64_t>(r.size()) + 1;
+} catch (...) {
+    return 0;
+}
 
 qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t ld,
                                  qiht_dtype dtype, int bits, int realizations, uint64_t seed,
@@ -411,6 +424,7 @@ qiht_status qiht_qmatrix_row_exponents(const qiht_qmatrix* q, int32_t* host_out)
 
 void qiht_qmatrix_free(qiht_qmatrix* q) {
     if (!q) return;
+    if (q->embedded) qiht_qmatrix_free(q->embedded);
     if (q->codes[0]) (void)hipFree(q->codes[0]);
     delete q;
 }
@@ -440,6 +454,31 @@ qiht_status qiht_niht_solve(const qiht_qmatrix* q, const double* yhat, int64_t s
     }
     if (info) *info = tmp;
     return QIHT_OK;
+} catch (...) {
+    return fail(QIHT_ERR_DEVICE, "unexpected exception");
+}
+
+qiht_status qiht_niht_solve_complex(const qiht_qmatrix* q, const double* yhat, int64_t s,
+                                    const qiht_params* p, float* x_out, int32_t* support_out,
+                                    qiht_info* info, void* stream) try {
+    set_error("");
+    qiht_status s0 = check_params(p);
+    if (s0 != QIHT_OK) return s0;
+    if (!q) return fail(QIHT_ERR_INVALID_ARG, "quantized matrix is NULL");
+    if (!yhat) return fail(QIHT_ERR_INVALID_ARG, "yhat is NULL");
+    if (!x_out || !support_out) return fail(QIHT_ERR_INVALID_ARG, "output pointer is NULL");
+    if (q->rows != 2 * q->m)
+        return fail(QIHT_ERR_INVALID_ARG, "the matrix was not quantized from complex input");
+    if (is_dense_format(q->bits)) return fail(QIHT_ERR_UNSUPPORTED, "complex unknowns need packed codes or FP32");
+    if (p->x0 || p->support0) return fail(QIHT_ERR_UNSUPPORTED, "no warm start for a complex unknown");
+    if (s < 1 || s > q->m || s > q->n) return fail(QIHT_ERR_INVALID_ARG, "need 1 <= s <= min(m, n)");
+    if (q->n > QIHT_COMPLEX_MAX_N)
+        return fail(QIHT_ERR_UNSUPPORTED, "n above QIHT_COMPLEX_MAX_N for a complex unknown");
+    int dev = 0;
+    s0 = need_device(&dev);
+    if (s0 != QIHT_OK) return s0;
+    return run_solve_complex(const_cast<qiht_qmatrix*>(q), yhat, s, to_args(p), p->refit, x_out, support_out,
+                             info, static_cast<hipStream_t>(stream));
 } catch (...) {
     return fail(QIHT_ERR_DEVICE, "unexpected exception");
 }

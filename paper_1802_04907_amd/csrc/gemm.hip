@@ -353,12 +353,16 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
 
 // Row splits of the BF16 GEMM: enough workgroups for the device (about one
 // per CU) while each split keeps at least 8 steps of 32 rows.
+bool shared_ksplit_ok(int bits, int rows_pad, int ks) {
+    if (bits != kFmtBF16 && bits != kFmtE4M3) return ks == 1;
+    return (ks == 1 || ks == 2 || ks == 4) && rows_pad % (ks * kBK) == 0 && rows_pad / ks >= 8 * kBK;
+}
+
 int shared_ksplit(int bits, int n, int count, int rows_pad) {
     if (bits != kFmtBF16 && bits != kFmtE4M3) return 1;
     const int tiles = ((n + kBM2 - 1) / kBM2) * ((count + kBN - 1) / kBN);
     int ks = 1;
-    while (ks < 4 && tiles * ks < 256 && rows_pad % (2 * ks * kBK) == 0 && rows_pad / (2 * ks) >= 8 * kBK)
-        ks *= 2;
+    while (ks < 4 && tiles * ks < 256 && shared_ksplit_ok(bits, rows_pad, 2 * ks)) ks *= 2;
     return ks;
 }
 

@@ -484,16 +484,31 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     }
 }
 
+// g of columns split into row slabs: the slab partials summed in slab order
+// (FP32), and the |g| histogram off the support.  Workgroup x takes
+// columns [x kSlabCols, (x + 1) kSlabCols) of its problem; the histogram is
+// counted in LDS and merged with one global atomic per non-empty bin (a
+// global atomic per column made this kernel take a third of an FP32 pass).
+constexpr int kSlabCols = 1024;
+
 __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__ P) {
     const ProbDev& pd = P[blockIdx.y];
-    if (pd.st->done || pd.nslab <= 1) return;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < pd.n; j += gridDim.x * blockDim.x) {
+    __shared__ uint32_t lh[2048];
+    const int j0 = blockIdx.x * kSlabCols;
+    if (pd.st->done || pd.nslab <= 1 || j0 >= pd.n) return;  // uniform over the workgroup
+    for (int b = threadIdx.x; b < 2048; b += 256) lh[b] = 0u;
+    __syncthreads();
+    const int j1 = min(pd.n, j0 + kSlabCols);
+    for (int j = j0 + threadIdx.x; j < j1; j += 256) {
         float s = 0.f;
         for (int sl = 0; sl < pd.nslab; ++sl) s += pd.gpart[static_cast<size_t>(sl) * pd.n + j];
         pd.g[j] = s;
         if (!((pd.bmsup[j >> 5] >> (j & 31)) & 1u))
-            atomicAdd(&pd.hist[(__float_as_uint(s) & 0x7FFFFFFFu) >> 20], 1u);
+            atomicAdd(&lh[(__float_as_uint(s) & 0x7FFFFFFFu) >> 20], 1u);
     }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2048; b += 256)
+        if (lh[b]) atomicAdd(&pd.hist[b], lh[b]);
 }
 
 template <typename K>
@@ -587,8 +602,8 @@ void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Ta
 #undef QIHT_LP
 }
 
-void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_slab_reduce, dim3(64, count), dim3(256), 0, st, P);
+void launch_slab_reduce(const ProbDev* P, int count, int max_n, hipStream_t st) {
+    hipLaunchKernelGGL(k_slab_reduce, dim3((max_n + kSlabCols - 1) / kSlabCols, count), dim3(256), 0, st, P);
 }
 
 }  // namespace qiht

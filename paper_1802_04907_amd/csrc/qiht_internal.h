@@ -34,6 +34,9 @@ struct qiht_qmatrix {
     int64_t rows_pad = 0;  // rows covered by col_bytes
     uint8_t* codes[2] = {nullptr, nullptr};  // codes[1] == codes[0] if R == 1
     int32_t* rexp = nullptr;  // dense formats: row exponents e_i (device, rows)
+    // complex input: the real embedding [Q_re -Q_im; Q_im Q_re] used for a
+    // complex unknown (built on first use by complex.hip, freed with this)
+    qiht_qmatrix* embedded = nullptr;
 };
 
 namespace qiht {
@@ -109,6 +112,8 @@ struct ProblemIn {
     int32_t* support_out;
     const float* x0;
     const int32_t* support0;
+    int64_t group = 0;  // > 0: a complex unknown of `group` entries on the
+                        // embedding (columns j and j + group pair up; s even)
 };
 
 // Algorithm 2 with its realizations drawn per iteration (one problem): the
@@ -134,6 +139,12 @@ struct FreshSource {
 qiht_status run_solve(const ProblemIn* probs, int count, const SolveArgs& a,
                       qiht_info* infos, hipStream_t st, const FreshSource* fresh = nullptr,
                       uint8_t* ext_ws = nullptr, size_t ext_cap = 0);
+// The autotuner's choices so far, as JSON (solve_host.hip).
+std::string tune_report();
+// QIHT with a complex unknown on a complex-input handle (complex.hip):
+// x_out (device, 2n floats) receives [Re x; Im x], support_out the s entries.
+qiht_status run_solve_complex(qiht_qmatrix* q, const double* yhat, int64_t s, const SolveArgs& a, int refit,
+                              float* x_out, int32_t* support_out, qiht_info* info, hipStream_t st);
 // One solve whose workspace is the library's fixed device array (no device
 // allocation); calls on one device take turns.
 qiht_status run_solve_noalloc(const ProblemIn& in, const SolveArgs& a, qiht_info* info,

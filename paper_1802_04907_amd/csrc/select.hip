@@ -74,6 +74,19 @@ __device__ __forceinline__ float value_at(const float* a_in, const float* g, con
     return fmaf(muf, g[j], x[j]);
 }
 
+// Rank key of index j: |a_j| as FP32 bits, or with group > 0 (a complex
+// unknown whose real and imaginary parts are columns j and j + group) the
+// squared modulus a_j^2 + a_{j+group}^2 summed in FP64 from the FP32 parts and
+// rounded once to FP32 (non-negative: the bits order as the values).
+template <int MODE>
+__device__ __forceinline__ uint32_t key_at(const float* a_in, const float* g, const float* x, float muf,
+                                           int j, int group) {
+    if (group == 0) return abs_key(value_at<MODE>(a_in, g, x, muf, j));
+    const double u = value_at<MODE>(a_in, g, x, muf, j);
+    const double v = value_at<MODE>(a_in, g, x, muf, j + group);
+    return abs_key(static_cast<float>(u * u + v * v));
+}
+
 // One radix digit step: bins of `hist` (nb bins, counts already in place)
 // scanned from the top; finds the bin holding the krem-th largest key.
 __device__ void find_bin(SelShared& S, int nb, uint32_t& prefix, uint32_t& krem, int width) {
@@ -174,7 +187,7 @@ __device__ void emit_support(int n, int s, const float* a_in, const float* g, co
 // with.  Sets the selection bitmap S.u.b.bm_new.
 template <int MODE>
 __device__ void select_full(int n, int s, const float* a_in, const float* g, const float* x,
-                            float muf, SelShared& S, int* err) {
+                            float muf, SelShared& S, int* err, int group = 0) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int rounds = (n + kSelectThreads - 1) / kSelectThreads;  // <= 64
@@ -191,7 +204,7 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
             for (int e = 0; e < rounds; ++e) {
                 const int j = tid + kSelectThreads * e;
                 if (j < n) {
-                    const uint32_t key = abs_key(value_at<MODE>(a_in, g, x, muf, j));
+                    const uint32_t key = key_at<MODE>(a_in, g, x, muf, j, group);
                     if (pass == 0 && key > 0x7F800000u) bad = 1;
                     if (pass == 0 || (key >> hsh) == prefix)
                         atomicAdd(&S.hist[(key >> sh) & (nb - 1)], 1u);
@@ -207,7 +220,7 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
     // ties at T ranked in index order: (round, wave, lane) is index order
     for (int e = 0; e < rounds; ++e) {
         const int j = tid + kSelectThreads * e;
-        const bool tie = s > 0 && j < n && abs_key(value_at<MODE>(a_in, g, x, muf, j)) == T;
+        const bool tie = s > 0 && j < n && key_at<MODE>(a_in, g, x, muf, j, group) == T;
         const uint64_t b = __ballot(tie);
         if (lane == 0) S.u.b.cnt[e * 16 + wv] = static_cast<uint32_t>(__popcll(b));
     }
@@ -221,13 +234,33 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
     }
     for (int e = 0; e < rounds; ++e) {
         const int j = tid + kSelectThreads * e;
-        const uint32_t key = j < n ? abs_key(value_at<MODE>(a_in, g, x, muf, j)) : 0u;
+        const uint32_t key = j < n ? key_at<MODE>(a_in, g, x, muf, j, group) : 0u;
         const bool tie = s > 0 && j < n && key == T;
         const uint64_t b = __ballot(tie);
         const uint32_t rank = S.u.b.cnt[e * 16 + wv] + static_cast<uint32_t>(__popcll(b & lanemask_lt()));
         if (s > 0 && j < n && (key > T || (tie && rank < need)))
             atomicOr(&S.u.b.bm_new[j >> 5], 1u << (j & 31));
     }
+    __syncthreads();
+}
+
+// Complex unknowns: the selection bitmap over the `group` entries (bm_new)
+// becomes one over the 2 group real columns, entry p selecting columns p and
+// p + group (bm_tie is the scratch).
+__device__ void expand_group(int group, SelShared& S) {
+    const int words = (2 * group + 31) / 32;
+    for (int w = threadIdx.x; w < words; w += kSelectThreads) {
+        uint32_t bits = 0u;
+        for (int b = 0; b < 32; ++b) {
+            const int j = 32 * w + b;
+            if (j >= 2 * group) break;
+            const int p = j < group ? j : j - group;
+            bits |= ((S.u.b.bm_new[p >> 5] >> (p & 31)) & 1u) << b;
+        }
+        S.u.b.bm_tie[w] = bits;
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < words; w += kSelectThreads) S.u.b.bm_new[w] = S.u.b.bm_tie[w];
     __syncthreads();
 }
 
@@ -473,7 +506,8 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     const int nc = static_cast<int>(ag.total);
     // (the list holds at least s entries unless the counts are inconsistent,
     // which the full path then handles)
-    const bool fast = ag.nf == 0 && nc <= kCandCap && nc >= s;
+    // (complex unknowns rank entry moduli: always the full path)
+    const bool fast = ag.nf == 0 && nc <= kCandCap && nc >= s && pd.group == 0;
     int32_t* out_sup = (MODE == SEL_INIT) ? pd.sup : pd.csup + static_cast<size_t>(slot) * s;
     float* out_val = pd.cval + static_cast<size_t>(slot) * s;
     int32_t* dlist = pd.dlist + static_cast<size_t>(slot) * 2 * s;
@@ -487,7 +521,13 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         }
         __syncthreads();
         if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
-        select_full<MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
+        if (pd.group > 0) {
+            // s / 2 complex entries ranked by modulus, then their 2 columns each
+            select_full<MODE>(pd.group, s / 2, nullptr, pd.g, pd.x, muf, S, &pd.st->err, pd.group);
+            expand_group(pd.group, S);
+        } else {
+            select_full<MODE>(n, s, nullptr, pd.g, pd.x, muf, S, &pd.st->err);
+        }
         if (MODE == SEL_INIT) {
             emit_support<MODE>(n, s, nullptr, pd.g, nullptr, muf, nullptr, pd.sup, nullptr, S);
             for (int w = tid; w < words; w += kSelectThreads) pd.bmsup[w] = S.u.b.bm_new[w];

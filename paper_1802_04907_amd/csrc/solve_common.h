@@ -55,7 +55,8 @@ struct ProbDev {
     int32_t npart;      // gather row segments: nwg, or 1 KB segments for the wide
                         // gathers of a shared matrix (partials, candidate blocks)
     int32_t nslab;      // full-pass row slabs
-    int32_t pad;
+    int32_t group;      // > 0: complex unknown, columns j and j + group are the
+                        // real and imaginary parts of one entry (H_s by modulus)
     double alpha;       // dequantized value = alpha * code + beta
     double beta;
     float alpha_f;
@@ -517,6 +518,8 @@ struct SharedGemm {
     float* gp;          //   ksplit x count x ldg floats (unused when ksplit = 1)
 };
 int shared_ksplit(int bits, int n, int count, int rows_pad);
+// Whether the GEMM can split rows_pad rows ks ways (ks = 1, 2, 4).
+bool shared_ksplit_ok(int bits, int rows_pad, int ks);
 void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipStream_t st,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
@@ -527,7 +530,8 @@ constexpr double kInfinityCacheBytes = 200.0 * 1024 * 1024;
 int pass_slots(int bits, int cpl, bool long_stream);
 void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
                  hipEvent_t ev0, hipEvent_t ev1);
-void launch_slab_reduce(const ProbDev* P, int count, hipStream_t st);
+// max_n: the largest n of the problems
+void launch_slab_reduce(const ProbDev* P, int count, int max_n, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
 void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st);

@@ -5,6 +5,7 @@
 // All control state lives on the device; the host only enqueues launches
 // and, every kChunk rounds, reads the stop flags back.
 #include <algorithm>
+#include <cstdio>
 #include <cstddef>
 #include <cmath>
 #include <cstdlib>
@@ -101,11 +102,23 @@ struct Layout {
         part_om, st;
 };
 
+// Launch-shape choices the autotuner makes (tune.* below); -1 = the
+// built-in heuristic.  None of them changes what a kernel computes for a
+// column or a row, except ksplit (the GEMM's row splits, summed in split
+// order).
+struct TuneChoice {
+    int long_stream = -1;  // full pass: 1 = three waves per SIMD with one
+                           // column per step, 0 = two waves with two columns
+    int rounds = -1;       // full pass: rounds of resident workgroups the
+                           // columns are cut into (1 or 2)
+    int ksplit = -1;       // shared-matrix GEMM: row splits (1, 2 or 4)
+};
+
 struct Plan {
     std::vector<ProbDev> host;
     std::vector<Layout> lay;
     std::vector<Task> tasks;
-    int bits = 0, cpl = 1, maxwg = 1;
+    int bits = 0, cpl = 1, maxwg = 1, max_n = 1;
     bool any_slab = false;
     bool long_stream = false;  // codes of one pass larger than the Infinity Cache
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
@@ -117,7 +130,7 @@ struct Plan {
     size_t gblk_off = 0, bblk_off = 0, gpart_off = 0;
 };
 
-qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
+qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice& tc = TuneChoice()) {
     pl.bits = in[0].q->bits;
     // All problems on one matrix: the pass is a GEMM on the matrix cores.
     // Dense formats have no per-problem pass; FP32 takes the GEMM from two
@@ -133,6 +146,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         max_n = std::max(max_n, in[i].q->n);
     }
     if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    pl.max_n = static_cast<int>(max_n);
     // the kernel is built for the largest column; each problem's row slabs use
     // its own chunks per lane (a task carries them)
     pl.cpl = pass_cmax(pass_cpl(pl.bits, max_cb));
@@ -185,6 +199,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         p.npart = pl.shared ? static_cast<int>((q->col_bytes + 1023) / 1024) : nwg;
         p.nslab = pl.shared ? 1 : nslab;
         p.rowexp = q->rexp;
+        p.group = static_cast<int32_t>(in[i].group);
         p.alpha = q->alpha;
         p.beta = q->beta;
         p.alpha_f = static_cast<float>(q->alpha);
@@ -201,7 +216,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         pl.sg.bits = pl.bits;
         pl.sg.ldg = round_up(q->n, 64);
         pl.gblk_off = cv.take<float>(static_cast<size_t>(count) * pl.sg.ldg);
-        pl.sg.ksplit = shared_ksplit(pl.bits, pl.sg.n, count, pl.sg.rows_pad);
+        pl.sg.ksplit = tc.ksplit > 0 ? tc.ksplit : shared_ksplit(pl.bits, pl.sg.n, count, pl.sg.rows_pad);
         pl.gpart_off = pl.sg.ksplit > 1
                            ? cv.take<float>(static_cast<size_t>(pl.sg.ksplit) * count * pl.sg.ldg)
                            : 0;
@@ -235,7 +250,9 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl) {
         if (std::strcmp(e, "long") == 0) pl.long_stream = true;
         else if (std::strcmp(e, "cache") == 0) pl.long_stream = false;
     }
-    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream));
+    if (tc.long_stream >= 0) pl.long_stream = tc.long_stream != 0;
+    const int rounds = tc.rounds > 0 ? tc.rounds : 1;
+    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream)) * rounds;
     const double budget = std::max(1.0, std::ceil(total / slots));
     std::vector<std::vector<Task>> wgs(1);
     double cur = 0.0;
@@ -365,6 +382,8 @@ EventPool& event_pool() {
 
 struct PassTimer {
     bool on = false;
+    int every = 1;       // time every `every`-th pass dispatch
+    int64_t seen = 0;    // pass dispatches so far
     int dev = 0;
     size_t used = 0;
     std::vector<hipEvent_t> ev;
@@ -380,10 +399,12 @@ struct PassTimer {
             on = false;
         }
     }
-    // Returns false (no events) when profiling is off or the reserve is used up.
+    // Called once per pass dispatch.  Returns false (no events) when
+    // profiling is off, the dispatch is not one of those sampled, or the
+    // reserve is used up.
     bool pair(hipEvent_t* a, hipEvent_t* b) {
         *a = *b = nullptr;
-        if (!on || used + 2 > ev.size()) return false;
+        if (!on || (seen++ % every) != 0 || used + 2 > ev.size()) return false;
         *a = ev[used];
         *b = ev[used + 1];
         used += 2;
@@ -419,7 +440,7 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
         return;
     }
     launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, st, e0, e1);
-    if (pl.any_slab) launch_slab_reduce(dP, count, st);
+    if (pl.any_slab) launch_slab_reduce(dP, count, pl.max_n, st);
 }
 
 // One round: the step-size test of the previous round's proposals and its
@@ -448,11 +469,115 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
 }
 
+// ---------------------------------------------------------------------------
+// Captured chunks: the launches of kChunk rounds recorded once as a HIP graph
+// and replayed on the caller's stream (the device then runs them back to back
+// without a host launch per kernel).  The recording goes to a stream of the
+// library's own (the caller's may be the null stream, which cannot capture);
+// nothing runs while recording.  Executable graphs are kept per device,
+// keyed by everything their kernels receive as arguments or geometry (the
+// workspace addresses, the plan's launch shape, the solver arguments, the
+// round count), so a later solve of the same shape on pool memory at the
+// same address replays them; the control state they act on is in the
+// workspace, which each solve initializes.  Profiling (events around every
+// pass) and draws per iteration run uncaptured.
+// ---------------------------------------------------------------------------
+struct ChunkKey {
+    uintptr_t dP, dT;
+    uintptr_t shared_a;
+    int64_t shared_cb;
+    int64_t nl;
+    int bits, cpl, npass, maxwg, count, ksplit, shared_n;
+    int flags;  // long_stream << 1 | shared << 2 | any_slab << 3
+    int32_t max_iters, max_backtracks, mu_mode, decide_in_gather;
+    double tol, k, c;
+    bool operator<(const ChunkKey& o) const { return std::memcmp(this, &o, sizeof(ChunkKey)) < 0; }
+};
+
+class GraphCache {
+  public:
+    // Solves that ran with launch key `key` (round count 0) on `dev` before
+    // this one; counts this one.  Capturing and instantiating a chunk costs
+    // more than the launches it saves in one solve, so shapes are captured
+    // only once they recur.
+    int64_t count_solve(int dev, const ChunkKey& key) {
+        std::lock_guard<std::mutex> lk(m_);
+        return devs_[dev].solves[key]++;
+    }
+    // The executable graph of `key` on device `dev`, recorded by `record`
+    // (called with the capture stream) on first use; nullptr if capture or
+    // instantiation fails (the caller then launches directly).
+    template <typename F>
+    hipGraphExec_t get(int dev, const ChunkKey& key, F&& record) {
+        std::lock_guard<std::mutex> lk(m_);
+        Dev& d = devs_[dev];
+        for (auto& e : d.items)
+            if (!(e.key < key) && !(key < e.key)) {
+                e.used = ++d.clock;
+                return e.exec;
+            }
+        if (!d.cap && hipStreamCreateWithFlags(&d.cap, hipStreamNonBlocking) != hipSuccess) {
+            d.cap = nullptr;
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(d.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        record(d.cap);
+        const hipError_t le = hipGetLastError();
+        if (hipStreamEndCapture(d.cap, &g) != hipSuccess || le != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess || !ex) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (d.items.size() >= kKeep) {
+            auto old = std::min_element(d.items.begin(), d.items.end(),
+                                        [](const Item& a, const Item& b) { return a.used < b.used; });
+            (void)hipGraphExecDestroy(old->exec);
+            d.items.erase(old);
+        }
+        d.items.push_back(Item{key, ex, ++d.clock});
+        return ex;
+    }
+
+  private:
+    static constexpr size_t kKeep = 64;
+    struct Item {
+        ChunkKey key;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    struct Dev {
+        hipStream_t cap = nullptr;
+        std::vector<Item> items;
+        uint64_t clock = 0;
+        std::map<ChunkKey, int64_t> solves;
+    };
+    std::mutex m_;
+    std::map<int, Dev> devs_;
+};
+
+GraphCache& graph_cache() {
+    static GraphCache* c = new GraphCache();  // kept until the process ends
+    return *c;
+}
+
 // ext (optional): memory of ext_cap bytes to carve the workspace from
-// instead of the pool.
+// instead of the pool.  tc: the launch shapes to plan with.
 qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipStream_t st,
-                  ProbDev** dP, Task** dT, uint8_t* ext = nullptr, size_t ext_cap = 0) {
-    qiht_status s0 = make_plan(in, count, pl);
+                  ProbDev** dP, Task** dT, uint8_t* ext = nullptr, size_t ext_cap = 0,
+                  const TuneChoice& tc = TuneChoice()) {
+    qiht_status s0 = make_plan(in, count, pl, tc);
     if (s0 != QIHT_OK) return s0;
     ws.st = st;
     if (ext) {
@@ -482,6 +607,266 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
     return QIHT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  The launch shape of the full pass (its instance: two waves per
+// SIMD with two columns in flight each, or three with one; and whether its
+// columns are cut into one or two rounds of resident workgroups) and of the
+// shared-matrix GEMM (row splits 1, 2 or 4) is chosen per device architecture
+// and problem shape by timing every candidate on the problem's own codes: one
+// warm-up launch, then the median of kTuneReps launches between stream
+// events.  The built-in heuristic stays unless a candidate beats it by more
+// than kTuneMargin.  Choices are kept for the process and, when QIHT_TUNE_FILE
+// names a file, read from it first and appended to it (one line per shape:
+// key, choice, every candidate's microseconds).  QIHT_AUTOTUNE=0 switches
+// tuning off (the heuristic runs).  Only the GEMM's row splits change a sum's
+// order (its split partials are added in split order); the pass candidates
+// compute every column of g the same way.
+// ---------------------------------------------------------------------------
+constexpr int kTuneReps = 7;
+constexpr double kTuneMargin = 0.03;
+
+struct TuneEntry {
+    std::string key, choice, deflt;
+    std::vector<std::pair<std::string, double>> cand_us;
+};
+
+TuneChoice choice_from_name(const std::string& nm) {
+    TuneChoice c;
+    if (nm.rfind("ks", 0) == 0) {
+        c.ksplit = std::atoi(nm.c_str() + 2);
+    } else {
+        const size_t sl = nm.find("/r");
+        c.long_stream = nm.compare(0, 4, "long") == 0 ? 1 : 0;
+        c.rounds = sl == std::string::npos ? 1 : std::atoi(nm.c_str() + sl + 2);
+    }
+    return c;
+}
+
+class Tuner {
+  public:
+    bool enabled() const {
+        const char* e = std::getenv("QIHT_AUTOTUNE");
+        return !(e && std::strcmp(e, "0") == 0);
+    }
+    bool find(const std::string& key, TuneChoice* c) {
+        std::lock_guard<std::mutex> lk(m_);
+        load_locked();
+        auto it = entries_.find(key);
+        if (it == entries_.end()) return false;
+        *c = choice_from_name(it->second.choice);
+        return true;
+    }
+    void put(const TuneEntry& e) {
+        std::lock_guard<std::mutex> lk(m_);
+        load_locked();
+        entries_[e.key] = e;
+        const char* f = std::getenv("QIHT_TUNE_FILE");
+        if (!f || !*f) return;
+        if (FILE* fp = std::fopen(f, "a")) {
+            std::fprintf(fp, "%s\t%s\t%s", e.key.c_str(), e.choice.c_str(), e.deflt.c_str());
+            for (const auto& cu : e.cand_us) std::fprintf(fp, "\t%s=%.3f", cu.first.c_str(), cu.second);
+            std::fprintf(fp, "\n");
+            std::fclose(fp);
+        }
+    }
+    std::string report() {
+        std::lock_guard<std::mutex> lk(m_);
+        load_locked();
+        std::string o = "{\"entries\": [";
+        bool first = true;
+        for (const auto& kv : entries_) {
+            const TuneEntry& e = kv.second;
+            o += first ? "" : ", ";
+            first = false;
+            o += "{\"key\": \"" + e.key + "\", \"choice\": \"" + e.choice + "\", \"default\": \"" + e.deflt +
+                 "\", \"candidates_us\": {";
+            for (size_t i = 0; i < e.cand_us.size(); ++i) {
+                char b[64];
+                std::snprintf(b, sizeof(b), "%.3f", e.cand_us[i].second);
+                o += (i ? ", \"" : "\"") + e.cand_us[i].first + "\": " + b;
+            }
+            o += "}}";
+        }
+        return o + "]}";
+    }
+
+  private:
+    // Entries of QIHT_TUNE_FILE (later lines of a key win).
+    void load_locked() {
+        if (loaded_) return;
+        loaded_ = true;
+        const char* f = std::getenv("QIHT_TUNE_FILE");
+        if (!f || !*f) return;
+        FILE* fp = std::fopen(f, "r");
+        if (!fp) return;
+        char buf[4096];
+        while (std::fgets(buf, sizeof(buf), fp)) {
+            std::string ln(buf);
+            while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+            std::vector<std::string> fld;
+            size_t a = 0;
+            while (true) {
+                const size_t b = ln.find('\t', a);
+                fld.push_back(ln.substr(a, b == std::string::npos ? std::string::npos : b - a));
+                if (b == std::string::npos) break;
+                a = b + 1;
+            }
+            if (fld.size() < 3) continue;
+            TuneEntry e{fld[0], fld[1], fld[2], {}};
+            for (size_t i = 3; i < fld.size(); ++i) {
+                const size_t eq = fld[i].find('=');
+                if (eq != std::string::npos)
+                    e.cand_us.emplace_back(fld[i].substr(0, eq), std::atof(fld[i].c_str() + eq + 1));
+            }
+            entries_[e.key] = e;
+        }
+        std::fclose(fp);
+    }
+    std::mutex m_;
+    bool loaded_ = false;
+    std::map<std::string, TuneEntry> entries_;
+};
+
+Tuner& tuner() {
+    static Tuner* t = new Tuner();  // kept until the process ends
+    return *t;
+}
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a(prop.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// The shape a tuned choice is kept for.
+std::string tune_key(const ProblemIn* in, int count, const Plan& pl) {
+    int64_t max_cb = 0, max_n = 0;
+    double total = 0.0;
+    for (int i = 0; i < count; ++i) {
+        max_cb = std::max(max_cb, in[i].q->col_bytes);
+        max_n = std::max(max_n, in[i].q->n);
+        total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
+    }
+    char b[256];
+    std::snprintf(b, sizeof(b), "%s|%s|bits%d|count%d|col_bytes%lld|n%lld|MiB%lld", arch_name().c_str(),
+                  pl.shared ? "gemm" : "pass", pl.bits, count, static_cast<long long>(max_cb),
+                  static_cast<long long>(max_n), static_cast<long long>(total / 1048576.0));
+    return b;
+}
+
+std::string choice_name(const Plan& pl, const TuneChoice& c) {
+    if (pl.shared) return "ks" + std::to_string(c.ksplit > 0 ? c.ksplit : pl.sg.ksplit);
+    return std::string(c.long_stream > 0 ? "long" : "cache") + "/r" + std::to_string(c.rounds > 0 ? c.rounds : 1);
+}
+
+// Median microseconds of the product (full pass or GEMM) under choice c.
+qiht_status time_choice(const ProblemIn* in, int count, const TuneChoice& c, hipStream_t st,
+                        hipEvent_t* ev, double* us) {
+    Plan pl;
+    Workspace ws;
+    ProbDev* dP = nullptr;
+    Task* dT = nullptr;
+    qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT, nullptr, 0, c);
+    if (s0 != QIHT_OK) return s0;
+    const SolveArgs a{1, -1.0, 2.0, 0.01, 0, 0, 0, 0};
+    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, 1, pl.shared, st);  // r = y_hat
+    std::vector<double> t;
+    for (int r = 0; r <= kTuneReps; ++r) {
+        QIHT_HIP(hipEventRecord(ev[0], st));
+        if (pl.shared) {
+            launch_shared_pass(pl.sg, dP, count, st);
+        } else {
+            launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, st, nullptr, nullptr);
+            if (pl.any_slab) launch_slab_reduce(dP, count, pl.max_n, st);
+        }
+        QIHT_HIP(hipEventRecord(ev[1], st));
+        QIHT_HIP(hipEventSynchronize(ev[1]));
+        float ms = 0.f;
+        QIHT_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        if (r > 0) t.push_back(ms * 1e3);
+    }
+    std::sort(t.begin(), t.end());
+    *us = t[t.size() / 2];
+    return QIHT_OK;
+}
+
+// The tuned launch shapes of a solve: the kept choice of its shape, or a
+// new tuning of it; the heuristic when tuning is off or not possible.
+qiht_status tuned_choice(const ProblemIn* in, int count, hipStream_t st, bool may_tune, TuneChoice* out) {
+    *out = TuneChoice();
+    if (!tuner().enabled()) return QIHT_OK;
+    Plan p0;
+    qiht_status s0 = make_plan(in, count, p0);
+    if (s0 != QIHT_OK) return s0;
+    if (p0.shared && !is_dense_format(p0.bits)) return QIHT_OK;  // FP32 GEMM: one shape
+    // QIHT_TUNE_FORCE=<choice> pins one candidate of the matching kind (for
+    // tests and comparisons)
+    if (const char* f = std::getenv("QIHT_TUNE_FORCE")) {
+        const std::string nm(f);
+        if (p0.shared == (nm.rfind("ks", 0) == 0)) {
+            TuneChoice c = choice_from_name(nm);
+            if (!p0.shared || shared_ksplit_ok(p0.bits, p0.sg.rows_pad, c.ksplit)) *out = c;
+            return QIHT_OK;
+        }
+    }
+    const std::string key = tune_key(in, count, p0);
+    if (tuner().find(key, out) || !may_tune) return QIHT_OK;
+    std::vector<TuneChoice> cands;
+    TuneChoice def;
+    if (p0.shared) {
+        def.ksplit = p0.sg.ksplit;
+        for (int ks = 1; ks <= 4; ks *= 2)
+            if (shared_ksplit_ok(p0.bits, p0.sg.rows_pad, ks)) {
+                TuneChoice c;
+                c.ksplit = ks;
+                cands.push_back(c);
+            }
+    } else {
+        def.long_stream = p0.long_stream ? 1 : 0;
+        def.rounds = 1;
+        for (int ls = 0; ls <= 1; ++ls)
+            for (int rd = 1; rd <= 2; ++rd) {
+                TuneChoice c;
+                c.long_stream = ls;
+                c.rounds = rd;
+                cands.push_back(c);
+            }
+    }
+    int dev = 0;
+    QIHT_HIP(hipGetDevice(&dev));
+    std::vector<hipEvent_t> ev;
+    if (!event_pool().take(dev, 2, ev)) return QIHT_OK;
+    TuneEntry e{key, "", choice_name(p0, def), {}};
+    double best = 0.0, tdef = 0.0;
+    TuneChoice bestc = def;
+    qiht_status st0 = QIHT_OK;
+    for (const TuneChoice& c : cands) {
+        double us = 0.0;
+        st0 = time_choice(in, count, c, st, ev.data(), &us);
+        if (st0 != QIHT_OK) break;
+        const std::string nm = choice_name(p0, c);
+        e.cand_us.emplace_back(nm, us);
+        if (nm == e.deflt) tdef = us;
+        if (best == 0.0 || us < best) {
+            best = us;
+            bestc = c;
+        }
+    }
+    event_pool().give(dev, ev);
+    if (st0 != QIHT_OK) return st0;
+    if (tdef > 0.0 && tdef <= (1.0 + kTuneMargin) * best) bestc = def;
+    e.choice = choice_name(p0, bestc);
+    tuner().put(e);
+    *out = bestc;
+    return QIHT_OK;
+}
+
 }  // namespace
 
 qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qiht_info* infos,
@@ -493,7 +878,10 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     Workspace ws;
     ProbDev* dP = nullptr;
     Task* dT = nullptr;
-    qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT, ext_ws, ext_cap);
+    TuneChoice tc;
+    qiht_status s0 = tuned_choice(in, count, st, ext_ws == nullptr, &tc);
+    if (s0 != QIHT_OK) return s0;
+    s0 = setup(in, count, pl, ws, st, &dP, &dT, ext_ws, ext_cap, tc);
     if (s0 != QIHT_OK) return s0;
     std::vector<float*> xo(count);
     std::vector<int32_t*> so(count);
@@ -518,7 +906,8 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
 
     PassTimer timer;
     timer.on = a.profile != 0;
-    timer.reserve(static_cast<size_t>(a.max_iters) + 1);
+    timer.every = std::max(1, a.profile);
+    timer.reserve(static_cast<size_t>(a.max_iters) / timer.every + 2);
     if (warm) {
         // x0 restricted to its support (x is zero elsewhere)
         hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
@@ -540,10 +929,51 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     const int64_t per_iter = std::max<int64_t>(1, (static_cast<int64_t>(a.max_backtracks) + kSpec) / kSpec);
     const int64_t first = a.max_iters > 0 ? static_cast<int64_t>(a.max_iters) + 1 : 0;
     const int64_t max_rounds = a.max_iters > 0 ? static_cast<int64_t>(a.max_iters) * per_iter + 1 : 0;
+    // Chunks of rounds run as captured graphs once their launch shape has
+    // recurred (two earlier solves with the same workspace, plan and
+    // arguments), unless profiled, drawn per iteration, on caller-provided
+    // memory (instantiation may allocate), or switched off with QIHT_GRAPH=0.
+    const char* ge = std::getenv("QIHT_GRAPH");
+    const bool graphs = !timer.on && !fresh && !ext_ws && !(ge && std::strcmp(ge, "0") == 0);
+    int dev = 0;
+    QIHT_HIP(hipGetDevice(&dev));
+    auto record_chunk = [&](hipStream_t s, int64_t nl) {
+        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, s, &timer, fresh);
+    };
+    auto chunk_key = [&](int64_t nl) {
+        ChunkKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.dP = reinterpret_cast<uintptr_t>(dP);
+        key.dT = reinterpret_cast<uintptr_t>(dT);
+        key.shared_a = pl.shared ? reinterpret_cast<uintptr_t>(pl.sg.a) : 0;
+        key.nl = nl;
+        key.bits = pl.bits;
+        key.cpl = pl.cpl;
+        key.npass = pl.npass;
+        key.maxwg = pl.maxwg;
+        key.count = count;
+        key.ksplit = pl.shared ? pl.sg.ksplit : 0;
+        key.shared_n = pl.shared ? pl.sg.n : 0;
+        key.shared_cb = pl.shared ? pl.sg.col_bytes : 0;
+        key.flags = (pl.long_stream ? 2 : 0) | (pl.shared ? 4 : 0) | (pl.any_slab ? 8 : 0);
+        key.max_iters = a.max_iters;
+        key.max_backtracks = a.max_backtracks;
+        key.mu_mode = a.mu_mode;
+        key.decide_in_gather = a.decide_in_gather;
+        key.tol = a.tol;
+        key.k = a.k;
+        key.c = a.c;
+        return key;
+    };
+    const bool recurring = graphs && graph_cache().count_solve(dev, chunk_key(0)) >= 2;
     for (int64_t launched = 0; launched < max_rounds;) {
         const int64_t goal = launched < first ? first : max_rounds;
         const int64_t nl = std::min<int64_t>(kChunk, goal - launched);
-        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, st, &timer, fresh);
+        hipGraphExec_t ex = nullptr;
+        if (recurring)
+            ex = graph_cache().get(dev, chunk_key(nl), [&](hipStream_t cs) { record_chunk(cs, nl); });
+        if (ex) QIHT_HIP(hipGraphLaunch(ex, st));
+        else record_chunk(st, nl);
         launched += nl;
         hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
         QIHT_HIP(hipGetLastError());
@@ -669,5 +1099,7 @@ qiht_status run_solve_noalloc(const ProblemIn& in, const SolveArgs& a, qiht_info
     return run_solve(&in, 1, a, info, st, nullptr, slot.ptr,
                      static_cast<size_t>(QIHT_NOALLOC_WORKSPACE_BYTES));
 }
+
+std::string tune_report() { return tuner().report(); }
 
 }  // namespace qiht

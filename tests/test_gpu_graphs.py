@@ -1,0 +1,90 @@
+"""Rounds replayed as captured HIP graphs against the same rounds launched
+one by one (QIHT_GRAPH=0): the kernels and their arguments are the same, so
+x, the support and the solve's counters must be bitwise equal.  A launch
+shape is captured once it recurs (from its third solve on), so each case runs
+four solves with eager work and synchronizations in between: two launched
+directly, then one that captures and replays, then one that replays the
+cached executable graphs; every solve replays its chunk graphs many times
+(16 rounds per chunk)."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1802_04907_amd as qiht  # noqa: E402
+import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+FIELDS = ("iterations", "reason", "backtracks", "capped_iterations", "mu_last", "full_selects")
+
+
+def _gpu(p, bits, ybits=8):
+    q = qiht.quantize_matrix(torch.from_numpy(p.phi).to(DEV), bits, 2, p.seed)
+    yhat, _, _ = qiht.quantize_vector(torch.from_numpy(p.y).to(DEV), ybits, p.seed)
+    return q, yhat
+
+
+def _same(a, b, label):
+    xa, sa, ia = a
+    xb, sb, ib = b
+    assert torch.equal(xa.view(torch.int32), xb.view(torch.int32)), label
+    assert torch.equal(sa, sb), label
+    for f in FIELDS:
+        assert ia[f] == ib[f], (label, f)
+
+
+@pytest.mark.parametrize("bits", [4, 8, 32])
+def test_single_solve_graph_equals_eager(monkeypatch, bits):
+    p = workloads.gaussian(1500, 6000, 60, 1e-3, seed=31, dtype=np.float32)
+    q, yhat = _gpu(p, bits, 32 if bits == 32 else 8)
+    monkeypatch.setenv("QIHT_GRAPH", "0")
+    ref = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
+    monkeypatch.delenv("QIHT_GRAPH")
+    for rep in range(4):
+        got = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
+        torch.cuda.synchronize()
+        _same(ref, got, f"{bits}-bit replay {rep}")
+        torch.zeros(1 << 20, device=DEV).add_(1.0)  # eager work between the solves
+        torch.cuda.synchronize()
+    q.free()
+
+
+def test_batched_solve_graph_equals_eager(monkeypatch):
+    ms = [700, 1200, 300, 900]
+    probs = [workloads.gaussian(m, 4 * m, m // 16, 1e-3, [5, i], np.float32, qseed=i)
+             for i, m in enumerate(ms)]
+    gpu = [(*_gpu(p, 4), p.s) for p in probs]
+    monkeypatch.setenv("QIHT_GRAPH", "0")
+    ref = qiht.niht_solve_batched(gpu, max_iters=60, tol=-1.0)
+    monkeypatch.delenv("QIHT_GRAPH")
+    for rep in range(4):
+        got = qiht.niht_solve_batched(gpu, max_iters=60, tol=-1.0)
+        torch.cuda.synchronize()
+        for i in range(len(ms)):
+            _same(ref[i], got[i], f"batch problem {i} replay {rep}")
+    for q, _, _ in gpu:
+        q.free()
+
+
+def test_shared_matrix_batch_graph_equals_eager(monkeypatch):
+    rng = np.random.default_rng(7)
+    m, n, s, nrhs = 600, 2400, 20, 8
+    phi = (rng.standard_normal((m, n)) / np.sqrt(m)).astype(np.float32)
+    q = qiht.quantize_matrix(torch.from_numpy(phi).to(DEV), qiht.BF16, 1, 0)
+    ys = []
+    for _ in range(nrhs):
+        x = np.zeros(n)
+        x[rng.choice(n, s, replace=False)] = rng.standard_normal(s)
+        ys.append(torch.from_numpy(phi.astype(np.float64) @ x).to(DEV))
+    probs = [(q, y, s) for y in ys]
+    monkeypatch.setenv("QIHT_GRAPH", "0")
+    ref = qiht.niht_solve_batched(probs, max_iters=40, tol=-1.0)
+    monkeypatch.delenv("QIHT_GRAPH")
+    for rep in range(4):
+        got = qiht.niht_solve_batched(probs, max_iters=40, tol=-1.0)
+        torch.cuda.synchronize()
+        for i in range(nrhs):
+            _same(ref[i], got[i], f"shared rhs {i} replay {rep}")
+    q.free()

@@ -11,13 +11,17 @@ Phi -> support -> nonzero values -> noise):
 * ``gaussian``: Phi (m x n) i.i.d. N(0, 1/m) in FP64 or FP32; x s-sparse,
   support uniform without replacement, nonzeros N(0, 1) (or all ones for the
   equal-magnitude variant of the synthetic experiments); e ~ N(0, sigma^2).
+* ``complex_gaussian``: complex Phi (m x n) with i.i.d. circular complex
+  Gaussian entries of variance 1/m, an s-sparse complex x with circular
+  complex N(0, 1) nonzeros, circular complex noise (a complex unknown).
 * ``interferometry``: complex Phi_jk = exp(-2 pi i (u_j l_k + v_j m_k)) with
   (u_j, v_j) uniform in a disk of radius 0.5 and integer pixel coordinates
   l, m in [-side/2, side/2); real sky x with s point sources of log-uniform
   flux in [0.1, 10]; complex noise at a given SNR
   10 log10(|Phi x|^2 / |e|^2) (the definition used for the radio-astronomy
   experiment).  Stands in for the telescope data of the paper, which are not
-  available.
+  available.  ``complex_sky`` gives each source a uniform phase as well (a
+  complex unknown on the same matrix).
 * ``interferometry_visibilities``: the same draws without the matrix (uv,
   the sky and the stacked visibilities), for Phi computed on the fly.
 * ``batch_uneven``: independent Gaussian problems with m drawn uniformly in
@@ -39,7 +43,7 @@ import numpy as np
 class Problem:
     phi: np.ndarray        # (m, n) real or complex, row-major
     y: np.ndarray          # (m,)
-    x_true: np.ndarray     # (n,) real
+    x_true: np.ndarray     # (n,) real (complex for a complex unknown)
     support: np.ndarray    # (s,) sorted true support
     s: int
     seed: int              # the quantizer seed for this instance
@@ -110,10 +114,28 @@ def gaussian_8192x32768(seed=0, m=8192, n=32768, s=512):
     return gaussian(m, n, s, 1e-3, seed, np.float32)
 
 
+def complex_gaussian(m, n, s, sigma_e=1e-3, seed=0, dtype=np.complex64):
+    """Complex instance with a complex unknown: Phi m x n with i.i.d.
+    circular complex Gaussian entries of variance 1/m (real and imaginary
+    parts N(0, 1/(2m))), an s-sparse x with circular complex N(0, 1)
+    nonzeros, and circular complex noise of standard deviation sigma_e."""
+    rng = np.random.default_rng(seed)
+    sc = 1.0 / math.sqrt(2.0 * m)
+    phi = (rng.standard_normal((m, n)) * sc + 1j * (rng.standard_normal((m, n)) * sc)).astype(dtype)
+    sup = np.sort(rng.choice(n, s, replace=False))
+    x = np.zeros(n, dtype=np.complex128)
+    x[sup] = (rng.standard_normal(s) + 1j * rng.standard_normal(s)) / math.sqrt(2.0)
+    e = sigma_e / math.sqrt(2.0) * (rng.standard_normal(m) + 1j * rng.standard_normal(m))
+    y = _matvec(phi, x) + e
+    return Problem(phi, y, x, sup, s, seed)
+
+
 def interferometry(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0,
-                   dtype=np.complex64):
+                   dtype=np.complex64, complex_sky=False):
     """Fourier-sampled complex instance: n_vis visibilities of a side x side
-    sky image (32640 x 16384 at the defaults), s point sources."""
+    sky image (32640 x 16384 at the defaults), s point sources.  With
+    ``complex_sky`` every source also gets a phase uniform in [0, 2 pi) (drawn
+    after the noise), a complex unknown on the same matrix."""
     rng = np.random.default_rng(seed)
     rad = 0.5 * np.sqrt(rng.random(n_vis))
     th = 2.0 * np.pi * rng.random(n_vis)
@@ -136,6 +158,11 @@ def interferometry(n_vis=32640, side=128, s=200, snr_db=30.0, seed=0,
     e = math.sqrt(sig2 / 2.0) * (rng.standard_normal(n_vis)
                                  + 1j * rng.standard_normal(n_vis))
     y = clean + e
+    if complex_sky:
+        x = x * np.exp(2j * np.pi * rng.random(n))
+        x[np.setdiff1d(np.arange(n), sup)] = 0.0
+        clean = _matvec(phi, x)
+        y = clean + e
     p = Problem(phi, y, x, sup, s, seed)
     p.uv = np.stack([u, v], axis=1)
     p.lm = np.stack([lk, mk], axis=1)
