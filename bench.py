@@ -576,6 +576,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="only three solves of the headline workload at --bits on codes quantized "
+                         "once, without pass timing (short run for rocprofv3 traces of an iteration)")
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the HBM-resident workload (16384 x 65536, 4-bit; short run for "
                          "rocprofv3 traces and counters of its pass)")
@@ -640,6 +643,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_pass": True, "bits": bits, "launches": 5,
                           "bytes_per_launch": pass_bytes(M, N, bits)}))
+        return
+    if args.solve_only:
+        q = qiht.quantize_matrix(phi_d, bits, 2, SEED)
+        yhat, _, _ = qiht.quantize_vector(y_d, 32 if bits == 32 else 8, SEED)
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, inf = qiht.niht_solve(q, yhat, S, max_iters=ITERS, tol=-1.0)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        q.free()
+        print(json.dumps({"solve_only": True, "bits": bits, "iterations": ITERS,
+                          "ms_per_solve": [round(t * 1e3, 3) for t in times]}))
         return
     log(f"warmup {args.warmup} steps, bits {bits}")
     for _ in range(args.warmup):

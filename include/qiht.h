@@ -301,7 +301,7 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
  * and kept with q until qiht_qmatrix_free: twice q's code memory), with H_s
  * ranking moduli over the pairs of columns (j, j + n).  Synchronizes stream.
  */
-#define QIHT_COMPLEX_MAX_N 32768LL
+#define QIHT_COMPLEX_MAX_N 131072LL
 qiht_status qiht_niht_solve_complex(const qiht_qmatrix* q, const double* yhat,
                                     int64_t s, const qiht_params* p,
                                     float* x_out, int32_t* support_out,
@@ -322,8 +322,9 @@ qiht_status qiht_niht_solve_complex(const qiht_qmatrix* q, const double* yhat,
  *   p->profile and p->refit must be 0 (UNSUPPORTED: profiling needs events,
  *   the refit its own workspace).  A problem whose workspace exceeds the
  *   array returns UNSUPPORTED before any device work, with the size it needs
- *   in qiht_last_error(); the workspace grows about as 36 n + 8 rows bytes
- *   (up to n = 65536 columns it fits for any row count up to a few million).
+ *   in qiht_last_error() (about 24 n bytes, 4 n more per extra row slab of
+ *   the full pass, plus 8 bytes per row: 1 MB for 8192 x 32768 at 4 bits,
+ *   about 3 MB for 65280 x 16384).
  *   The array keeps the last call's contents; each call clears what must
  *   start at zero.  All calls on one device share the array: the library
  *   runs the calls of one process on one device one after another (each
@@ -414,13 +415,13 @@ qiht_status qiht_fourier_gradient(const double* uv, int64_t n_vis, int64_t side,
  *   y: device, 2 n_vis doubles, the visibilities stacked [Re; Im].
  *   1 <= s <= min(2 n_vis, side^2); n_vis as for qiht_fourier_gradient;
  *   side^2 <= QIHT_FOURIER_SOLVE_MAX_PIXELS (the H_s selection's limit;
- *   256 x 256, the paper's LOFAR sky), else UNSUPPORTED.  p: as for qiht_niht_solve, without warm start
+ *   512 x 512, the size of the paper's MRI image), else UNSUPPORTED.  p: as for qiht_niht_solve, without warm start
  *   (x0, support0 must be NULL) or refit (must be 0): UNSUPPORTED.
  *   x_out: device, side^2 floats; support_out: device, s int32 ascending.
  * Reads two or three status words per iteration back to the host (the next
  * launches depend on them).  Synchronizes stream.
  */
-#define QIHT_FOURIER_SOLVE_MAX_PIXELS 65536LL
+#define QIHT_FOURIER_SOLVE_MAX_PIXELS 262144LL
 qiht_status qiht_fourier_niht_solve(const double* uv, int64_t n_vis, int64_t side,
                                     const double* y, int64_t s, const qiht_params* p,
                                     float* x_out, int32_t* support_out, qiht_info* info,

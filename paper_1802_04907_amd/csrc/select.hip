@@ -30,9 +30,14 @@
 namespace qiht {
 namespace {
 
-constexpr int kBmWords = kMaxSelectN / 32;
 
+// LDS of a proposal workgroup; NMAX bounds the entries the full path ranks
+// (its bitmaps and tie counts), and with it the workgroup's LDS: the
+// 65536-entry instance leaves room for two workgroups per CU.
+template <int NMAX>
 struct SelShared {
+    static constexpr int kNMax = NMAX;
+    static constexpr int kBmWords = NMAX / 32;
     uint32_t hist[2048];
     uint32_t hist2[1024];        // second and third radix digits
     uint32_t hist3[1024];
@@ -46,9 +51,8 @@ struct SelShared {
         struct {                 // full path: bitmaps over all n
             uint32_t bm_old[kBmWords];   // current support
             uint32_t bm_new[kBmWords];   // selected set
-            uint32_t bm_tie[kBmWords];   // keys equal to the threshold key
-            uint32_t wpre[kBmWords];     // per-word prefix counts
-            uint32_t cnt[kSelectThreads];
+            uint32_t wpre[kBmWords];     // per-word prefix counts (scratch before)
+            uint32_t cnt[NMAX / 64];     // threshold ties per wave and round
         } b;
     } u;
     uint32_t scan[16];
@@ -89,7 +93,8 @@ __device__ __forceinline__ uint32_t key_at(const float* a_in, const float* g, co
 
 // One radix digit step: bins of `hist` (nb bins, counts already in place)
 // scanned from the top; finds the bin holding the krem-th largest key.
-__device__ void find_bin(SelShared& S, int nb, uint32_t& prefix, uint32_t& krem, int width) {
+template <class SS>
+__device__ void find_bin(SS& S, int nb, uint32_t& prefix, uint32_t& krem, int width) {
     const int tid = threadIdx.x;
     const int PB = nb / kSelectThreads;  // 1 or 2
     const uint32_t c0 = S.hist[nb - 1 - tid * PB];
@@ -115,8 +120,8 @@ __device__ void find_bin(SelShared& S, int nb, uint32_t& prefix, uint32_t& krem,
 // Bin of the krem-th largest key of a histogram of NB bins (scanned from
 // the top), found by wave 0 alone; every thread gets (S.bin, S.krem) after
 // the closing barrier.
-template <int NB>
-__device__ void find_bin_w0(const uint32_t* hist, uint32_t krem, SelShared& S) {
+template <int NB, class SS>
+__device__ void find_bin_w0(const uint32_t* hist, uint32_t krem, SS& S) {
     constexpr int PER = NB / 64;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -148,10 +153,10 @@ __device__ void find_bin_w0(const uint32_t* hist, uint32_t krem, SelShared& S) {
 
 // Writes the support (ascending) from the selection bitmap, the values on
 // it, and compares with the old support.  Returns through S.changed.
-template <int MODE>
+template <int MODE, class SS>
 __device__ void emit_support(int n, int s, const float* a_in, const float* g, const float* x,
                              float muf, const int32_t* old_sup, int32_t* out_sup, float* out_val,
-                             SelShared& S) {
+                             SS& S) {
     const int tid = threadIdx.x;
     const int words = (n + 31) / 32;
     const int wpt = (words + kSelectThreads - 1) / kSelectThreads;
@@ -185,12 +190,12 @@ __device__ void emit_support(int n, int s, const float* a_in, const float* g, co
 // pass instead of being held in registers, which keeps this rarely taken path
 // from inflating the register budget of the fast path it shares a kernel
 // with.  Sets the selection bitmap S.u.b.bm_new.
-template <int MODE>
+template <int MODE, class SS>
 __device__ void select_full(int n, int s, const float* a_in, const float* g, const float* x,
-                            float muf, SelShared& S, int* err, int group = 0) {
+                            float muf, SS& S, int* err, int group = 0) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
-    const int rounds = (n + kSelectThreads - 1) / kSelectThreads;  // <= 64
+    const int rounds = (n + kSelectThreads - 1) / kSelectThreads;  // <= 256
     int bad = 0;
     uint32_t prefix = 0, krem = static_cast<uint32_t>(s);
     for (int pass = 0; pass < 3; ++pass) {
@@ -226,10 +231,23 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
     }
     __syncthreads();
     {
+        // exclusive prefix of the nc counts, CPT consecutive ones per thread
+        constexpr int CPT = SS::kNMax / 64 / kSelectThreads;
         const int nc = rounds * 16;
-        const uint32_t v = tid < nc ? S.u.b.cnt[tid] : 0u;
-        const uint32_t before = block_excl_scan<kSelectThreads>(v, S.scan, nullptr);
-        if (tid < nc) S.u.b.cnt[tid] = before;
+        uint32_t v[CPT], sum = 0;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = CPT * tid + i;
+            v[i] = c < nc ? S.u.b.cnt[c] : 0u;
+            sum += v[i];
+        }
+        uint32_t before = block_excl_scan<kSelectThreads>(sum, S.scan, nullptr);
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = CPT * tid + i;
+            if (c < nc) S.u.b.cnt[c] = before;
+            before += v[i];
+        }
         __syncthreads();
     }
     for (int e = 0; e < rounds; ++e) {
@@ -246,8 +264,9 @@ __device__ void select_full(int n, int s, const float* a_in, const float* g, con
 
 // Complex unknowns: the selection bitmap over the `group` entries (bm_new)
 // becomes one over the 2 group real columns, entry p selecting columns p and
-// p + group (bm_tie is the scratch).
-__device__ void expand_group(int group, SelShared& S) {
+// p + group (wpre is the scratch; its prefix counts come later).
+template <class SS>
+__device__ void expand_group(int group, SS& S) {
     const int words = (2 * group + 31) / 32;
     for (int w = threadIdx.x; w < words; w += kSelectThreads) {
         uint32_t bits = 0u;
@@ -257,15 +276,16 @@ __device__ void expand_group(int group, SelShared& S) {
             const int p = j < group ? j : j - group;
             bits |= ((S.u.b.bm_new[p >> 5] >> (p & 31)) & 1u) << b;
         }
-        S.u.b.bm_tie[w] = bits;
+        S.u.b.wpre[w] = bits;
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < words; w += kSelectThreads) S.u.b.bm_new[w] = S.u.b.bm_tie[w];
+    for (int w = threadIdx.x; w < words; w += kSelectThreads) S.u.b.bm_new[w] = S.u.b.wpre[w];
     __syncthreads();
 }
 
 // Sum of three values over the block, fixed order; every thread gets them.
-__device__ void block_sum3(double& a, double& b, double& c, SelShared& S) {
+template <class SS>
+__device__ void block_sum3(double& a, double& b, double& c, SS& S) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
@@ -296,7 +316,8 @@ struct BlockAgg {
     uint32_t before, total, nf;
 };
 
-__device__ BlockAgg block_sums_scan(double a, double b, double c, uint32_t v, bool f, SelShared& S) {
+template <class SS>
+__device__ BlockAgg block_sums_scan(double a, double b, double c, uint32_t v, bool f, SS& S) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
@@ -327,33 +348,32 @@ __device__ BlockAgg block_sums_scan(double a, double b, double c, uint32_t v, bo
 }
 
 // Bitmap words scanned by word_prefix.
-enum { BM_TIE = 0, BM_NEW = 1, BM_UNION = 2 };
+enum { BM_NEW = 1, BM_UNION = 2 };
 
-template <int WHICH>
-__device__ __forceinline__ uint32_t bm_word(const SelShared& S, int w) {
-    if (WHICH == BM_TIE) return S.u.b.bm_tie[w];
+template <int WHICH, class SS>
+__device__ __forceinline__ uint32_t bm_word(const SS& S, int w) {
     if (WHICH == BM_NEW) return S.u.b.bm_new[w];
     return S.u.b.bm_old[w] | S.u.b.bm_new[w];
 }
 
 // Per-word exclusive prefix of popcount(bitmap word) into S.u.b.wpre (index
 // order), computed by wave 0 alone (no block-wide scan); returns the total.
-template <int WHICH>
-__device__ uint32_t word_prefix(int words, SelShared& S) {
-    constexpr int MAXW = kBmWords / 64;  // words per lane at the largest n
+template <int WHICH, class SS>
+__device__ uint32_t word_prefix(int words, SS& S) {
+    constexpr int MAXW = SS::kBmWords / 64;  // words per lane at the largest n
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         const int wpl = (words + 63) / 64;
         const int w0 = lane * wpl;
         uint32_t c = 0;
-#pragma unroll
+#pragma unroll 8
         for (int i = 0; i < MAXW; ++i) {
             const int w = w0 + i;
             if (i < wpl && w < words) c += static_cast<uint32_t>(__popc(bm_word<WHICH>(S, w)));
         }
         const uint32_t x = wave_incl_scan(c);
         uint32_t pos = x - c;
-#pragma unroll
+#pragma unroll 8
         for (int i = 0; i < MAXW; ++i) {
             const int w = w0 + i;
             if (i < wpl && w < words) {
@@ -377,7 +397,8 @@ __device__ __forceinline__ uint32_t rank_in_word(uint32_t bits, int b) {
 // taken whole; the selection rule is then (key >> sh) > P, or == P within
 // the first `need` such entries in index order.  S.hist, hist2, hist3 must
 // be zero on entry.
-__device__ void rank_merged(int nc, int s, SelShared& S, int& sh, uint32_t& P, uint32_t& need,
+template <class SS>
+__device__ void rank_merged(int nc, int s, SS& S, int& sh, uint32_t& P, uint32_t& need,
                             uint32_t& eq) {
     const int tid = threadIdx.x;
     for (int c = tid; c < nc; c += kSelectThreads) atomicAdd(&S.hist[S.u.f.mkey[c] >> 20], 1u);
@@ -423,9 +444,9 @@ __device__ void rank_merged(int nc, int s, SelShared& S, int& sh, uint32_t& P, u
 // (support, values, difference list) are positions of a prefix sum over that
 // order.  Full path (too many candidates, or a threshold the fast path cannot
 // use): every key of the n in registers and bitmaps over all n.
-template <int MODE>
+template <int MODE, class SS>
 __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool from_partials,
-                        double shrink, double* mu0_out, SelShared& S, bool* skipped = nullptr) {
+                        double shrink, double* mu0_out, SS& S, bool* skipped = nullptr) {
     constexpr int MPT = kCandCap / kSelectThreads;  // merged positions per thread
     constexpr int PRE = 4;                          // candidates loaded ahead per thread
     const int tid = threadIdx.x;
@@ -517,7 +538,6 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         for (int w = tid; w < words; w += kSelectThreads) {
             S.u.b.bm_old[w] = (MODE == SEL_STEP) ? pd.bmsup[w] : 0u;
             S.u.b.bm_new[w] = 0u;
-            S.u.b.bm_tie[w] = 0u;
         }
         __syncthreads();
         if (tid == 0) atomicAdd(&pd.st->full_selects, 1);
@@ -740,11 +760,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_candidates(const ProbDev* __
     compact_candidates<kGatherThreads>(pd, blockIdx.x, pd.npart, false, pre);
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __restrict__ P,
                                                             SolveArgs a, int mode) {
     const ProbDev& pd = P[blockIdx.y];
     SolveState* st = pd.st;
-    __shared__ SelShared S;
+    __shared__ SelShared<NMAX> S;
     double mu0 = 0.0;
     if (mode == SEL_INIT) {
         if (st->done) return;
@@ -776,9 +797,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_commit(const ProbDev* __rest
     commit_round<kGatherThreads>(pd, a, s_dec);
 }
 
+template <int NMAX>
 __global__ __launch_bounds__(kSelectThreads) void k_hard_threshold(const float* a, int n, int s,
                                                                    int32_t* out, int* err) {
-    __shared__ SelShared S;
+    __shared__ SelShared<NMAX> S;
     for (int w = threadIdx.x; w < (n + 31) / 32; w += kSelectThreads) S.u.b.bm_new[w] = 0u;
     if (threadIdx.x == 0) S.changed = 0;
     __syncthreads();
@@ -792,9 +814,16 @@ void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st) {
     hipLaunchKernelGGL(k_candidates, dim3(maxwg, count), dim3(kGatherThreads), 0, st, P);
 }
 
-void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st) {
+// (the 65536-entry instance up to that n: its LDS leaves room for two
+// proposal workgroups per CU, which a batch of many problems uses)
+constexpr int kSmallSelectN = kSelectThreads * 64;
+
+void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, int max_n, hipStream_t st) {
     const dim3 grid(mode == SEL_INIT ? 1 : kSpec, count);
-    hipLaunchKernelGGL(k_propose, grid, dim3(kSelectThreads), 0, st, P, a, mode);
+    if (max_n <= kSmallSelectN)
+        hipLaunchKernelGGL(k_propose<kSmallSelectN>, grid, dim3(kSelectThreads), 0, st, P, a, mode);
+    else
+        hipLaunchKernelGGL(k_propose<kMaxSelectN>, grid, dim3(kSelectThreads), 0, st, P, a, mode);
 }
 
 void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t st) {
@@ -802,7 +831,10 @@ void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t 
 }
 
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st) {
-    hipLaunchKernelGGL(k_hard_threshold, dim3(1), dim3(kSelectThreads), 0, st, a, n, s, out, err);
+    if (n <= kSmallSelectN)
+        hipLaunchKernelGGL(k_hard_threshold<kSmallSelectN>, dim3(1), dim3(kSelectThreads), 0, st, a, n, s, out, err);
+    else
+        hipLaunchKernelGGL(k_hard_threshold<kMaxSelectN>, dim3(1), dim3(kSelectThreads), 0, st, a, n, s, out, err);
 }
 
 }  // namespace qiht

@@ -14,7 +14,7 @@ constexpr int kGatherThreads = 256;   // column gathers
 constexpr int kPassThreads = 256;     // full pass
 constexpr int kPassMaxCols = 4096;    // columns of one full-pass task (at most)
 constexpr int kSpec = 4;              // step sizes proposed at once
-constexpr int kMaxSelectN = kSelectThreads * 64;
+constexpr int kMaxSelectN = kSelectThreads * 256;  // 262144: a 512 x 512 image
 constexpr int kCandCap = 3072;        // candidate keys a fast proposal holds in LDS
 
 // Per-problem control state (device memory).
@@ -533,7 +533,8 @@ void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Ta
 // max_n: the largest n of the problems
 void launch_slab_reduce(const ProbDev* P, int count, int max_n, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);
-void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, hipStream_t st);
+// max_n: the largest n of the problems (picks the selection's LDS size)
+void launch_propose(const ProbDev* P, int count, const SolveArgs& a, int mode, int max_n, hipStream_t st);
 void launch_hard_threshold(const float* a, int n, int s, int32_t* out, int* err, hipStream_t st);
 void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t st);
 

@@ -145,7 +145,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
         max_cb = std::max(max_cb, in[i].q->col_bytes);
         max_n = std::max(max_n, in[i].q->n);
     }
-    if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 262144");
     pl.max_n = static_cast<int>(max_n);
     // the kernel is built for the largest column; each problem's row slabs use
     // its own chunks per lane (a task carries them)
@@ -465,7 +465,7 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
     }
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
     launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
-    launch_propose(dP, count, a, SEL_STEP, st);
+    launch_propose(dP, count, a, SEL_STEP, pl.max_n, st);
     launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
 }
 
@@ -915,7 +915,7 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
         // x0 = 0; G0 = supp H_s(Q1^T y_hat).
         gradient_launches(pl, dP, dT, count, a, 1, st, &timer);
         launch_candidates(dP, count, pl.maxwg, st);
-        launch_propose(dP, count, a, SEL_INIT, st);
+        launch_propose(dP, count, a, SEL_INIT, pl.max_n, st);
     }
     QIHT_HIP(hipGetLastError());
 
@@ -1039,7 +1039,7 @@ qiht_status run_gradient(const qiht_qmatrix* q, const double* yhat, const float*
 
 qiht_status run_hard_threshold(const float* a, int64_t n, int64_t s, int32_t* support_out,
                                hipStream_t st) {
-    if (n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 65536");
+    if (n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 262144");
     int* err = nullptr;
     QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&err), sizeof(int), st));
     QIHT_HIP(hipMemsetAsync(err, 0, sizeof(int), st));

@@ -190,7 +190,7 @@ def test_fourier_solve_validation(lib):
     assert f(ptr, 4, 4, ptr, 9, C.byref(p), ptr, ptr, C.byref(info), None) == 1   # s > 2 n_vis
     assert f(ptr, 40, 2, ptr, 5, C.byref(p), ptr, ptr, C.byref(info), None) == 1  # s > side^2
     assert f(ptr, 4, 4, ptr, 2, None, ptr, ptr, C.byref(info), None) == 1
-    assert f(ptr, 4, 257, ptr, 2, C.byref(p), ptr, ptr, C.byref(info), None) == 2  # > 65536 pixels
+    assert f(ptr, 4, 513, ptr, 2, C.byref(p), ptr, ptr, C.byref(info), None) == 2  # > 512^2 pixels
     warm = _lib.QihtParams()
     lib.qiht_default_params(C.byref(warm))
     warm.refit = 1
