@@ -10,9 +10,10 @@ Prints ONE JSON line.  Extra fields:
   roofline      the dominant kernel (g = Q1^T r) from HIP events recorded on
                 its launch stream during the timed steps
   cpu_baseline  the CPU oracle timed on a bounded sample of the workload
-  sweep         b = 32 / 8 / 4 / 2: iterations/s of the solve, pass GB/s,
-                error floors, time to 90% support recovery and to an equal
-                recovery error
+  sweep         b = 32 / 8 / 5 / 4 / 3 / 2: iterations/s of the solve, pass
+                GB/s, error floors, time to 90% support recovery and to an
+                equal recovery error (5-bit codes are stored in 8-bit fields,
+                3-bit in 4-bit ones)
 """
 
 import argparse
@@ -49,10 +50,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def stored_bits(bits):
+    """Width of the field a code occupies: 1, 2, 4 or 8 (3 -> 4, 5..7 -> 8), or 32."""
+    return bits if bits in (1, 2, 32) else (4 if bits <= 4 else 8)
+
+
 def pass_bytes(rows, n, bits):
-    """Algorithmic bytes of one g = Q1^T r launch: the codes once, r once,
-    g written once."""
-    codes = rows * n * (32 if bits == 32 else bits) / 8.0
+    """Algorithmic bytes of one g = Q1^T r launch: the codes once (in their
+    stored fields), r once, g written once."""
+    codes = rows * n * stored_bits(bits) / 8.0
     return codes + rows * 4.0 + n * 4.0
 
 
@@ -60,7 +66,7 @@ def iteration_bytes(rows, n, s, bits):
     """Algorithmic bytes of one iteration with no shrink: the full pass, the
     residual gather of s columns of Q2 and the step-size gathers of s
     columns of Q1 and of Q2 (one copy at 32 bits, Q1 = Q2: read once)."""
-    col = rows * (32 if bits == 32 else bits) / 8.0
+    col = rows * stored_bits(bits) / 8.0
     return pass_bytes(rows, n, bits) + s * col * (2 if bits == 32 else 3)
 
 
@@ -485,7 +491,7 @@ def fresh_bench(qiht, torch, phi_d, y_d, bits, iters=20):
             "ms_per_iteration": round(dt * 1e3 / info["iterations"], 3)}
 
 
-SYN_PRECISIONS = [(32, 32), (8, 8), (4, 8), (4, 4), (2, 8)]
+SYN_PRECISIONS = [(32, 32), (8, 8), (6, 8), (5, 8), (4, 8), (4, 4), (3, 8), (2, 8)]
 SYN_VARIANTS = {"gaussian": (False, None), "equal": (True, None),
                 "gaussian_20dB": (False, 20.0), "gaussian_10dB": (False, 10.0)}
 
@@ -733,7 +739,7 @@ def main():
     if not args.no_sweep:
         sweep = {}
         true_sup = p.support
-        for b in (32, 8, 4, 2):
+        for b in (32, 8, 5, 4, 3, 2):
             log(f"sweep b={b}")
             one_step(qiht, phi_d, y_d, b)
             torch.cuda.synchronize()
@@ -772,7 +778,7 @@ def main():
         # where e* is a recovery (a relative error of at most EQ_ERR_BAR)
         # reached by both solves; otherwise null with the reason.
         f32 = sweep["32"]
-        for b in ("8", "4", "2"):
+        for b in ("8", "5", "4", "3", "2"):
             d = sweep[b]
             t90b = d["iters_to_90pct_support"]
             t90f = f32["iters_to_90pct_support"]

@@ -151,8 +151,11 @@ void qiht_default_params(qiht_params* p);
  *   levels q_k = -1 + 2k/(2^b - 1), up with probability equal to the
  *   fractional position (unbiased: E[Q(v)] = v).
  *
- *   bits: 1, 2, 4 or 8 (packed codes; 2, 4 or 8 may carry
- *   QIHT_ODD_LEVELS), or 32 (plain FP32 copy, no
+ *   bits: 1..8 (packed codes; 2..8 may carry QIHT_ODD_LEVELS; a b-bit
+ *   code occupies a field of 1, 2, 4 or 8 bits: 3 -> 4 and 5..7 -> 8, so
+ *   that a byte holds whole codes: a 3-bit matrix takes the memory and the
+ *   full-pass bandwidth of a 4-bit one, 5 to 7 bits those of 8; the solver
+ *   reads every width alike), or 32 (plain FP32 copy, no
  *   randomness; realizations is then forced to 1 and Q1 = Q2), or a dense
  *   format QIHT_FMT_BF16 / QIHT_FMT_E4M3: row i is stored as
  *   Phi_ij / 2^e_i rounded to nearest (ties to even significand), e_i the
@@ -198,8 +201,9 @@ qiht_status qiht_quantize_vector(const void* y, int64_t m, qiht_dtype dtype,
 
 /*
  * Shape of a quantized matrix (host outputs, each optional): stacked row
- * count, column count, bit width, realizations, scale c, and the byte
- * stride between packed columns in device memory.
+ * count, column count, bit width b of the codes (as requested, without
+ * QIHT_ODD_LEVELS; 32 or the dense format otherwise), realizations, scale c,
+ * and the byte stride between packed columns in device memory.
  */
 qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows,
                               int64_t* n, int* bits, int* realizations,
@@ -287,7 +291,7 @@ qiht_status qiht_niht_solve_batched(int32_t count, const qiht_problem* probs,
  *
  *   q: a handle quantized from complex input (dtype C64 or C128 in
  *      qiht_quantize_matrix: Q = Q(Re Phi) + i Q(Im Phi), stacked rows
- *      [Re; Im]); packed codes (1, 2, 4, 8 bits, odd levels too) or 32.
+ *      [Re; Im]); packed codes (1..8 bits, odd levels too) or 32.
  *      INVALID_ARG for a handle of real input, UNSUPPORTED for a dense format.
  *   yhat: device, 2m doubles [Re y_hat; Im y_hat] (qiht_quantize_vector of
  *      the complex y).

@@ -34,8 +34,11 @@ qiht_status hip_fail(hipError_t e, const char* what) {
 namespace {
 
 bool bits_ok_matrix(int b) {
-    return b == 1 || b == 2 || b == 4 || b == 8 || b == 32 || b == QIHT_FMT_BF16 || b == QIHT_FMT_E4M3;
+    return (b >= 1 && b <= 8) || b == 32 || b == QIHT_FMT_BF16 || b == QIHT_FMT_E4M3;
 }
+// Stored width of a b-bit code: 1, 2, 4 or 8 (3 -> 4, 5..7 -> 8), so that a
+// byte holds whole codes and the pass reads one layout per width.
+int container_bits(int b) { return b <= 2 ? b : (b <= 4 ? 4 : 8); }
 // public bit width / format -> internal id, and back
 int internal_bits(int b) { return b == QIHT_FMT_BF16 ? kFmtBF16 : b == QIHT_FMT_E4M3 ? kFmtE4M3 : b; }
 int public_bits(int b) { return b == kFmtBF16 ? QIHT_FMT_BF16 : b == kFmtE4M3 ? QIHT_FMT_E4M3 : b; }
@@ -251,12 +254,14 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     const bool odd = (bits & QIHT_ODD_LEVELS) != 0;
     bits &= ~QIHT_ODD_LEVELS;
     if (!bits_ok_matrix(bits))
-        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8, 32, QIHT_FMT_BF16 or QIHT_FMT_E4M3");
+        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1..8, 32, QIHT_FMT_BF16 or QIHT_FMT_E4M3");
     if (odd && (bits < 2 || bits > 8))
-        return fail(QIHT_ERR_UNSUPPORTED, "QIHT_ODD_LEVELS needs packed codes of 2, 4 or 8 bits");
+        return fail(QIHT_ERR_UNSUPPORTED, "QIHT_ODD_LEVELS needs packed codes of 2..8 bits");
     if (realizations != 1 && realizations != 2)
         return fail(QIHT_ERR_INVALID_ARG, "realizations must be 1 or 2");
-    bits = internal_bits(bits);
+    const int code_bits = bits;
+    const int levels = (bits == 32 || bits > 8) ? 0 : num_levels(bits, odd);
+    bits = (bits <= 8) ? container_bits(bits) : internal_bits(bits);
     const int64_t rows = is_complex(dtype) ? 2 * m : m;
     if (rows > (1LL << 31) - 1 || n > (1LL << 31) - 1)
         return fail(QIHT_ERR_UNSUPPORTED, "dimension above 2^31 - 1");
@@ -277,11 +282,12 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
     q->n = n;
     q->rows = rows;
     q->bits = bits;
+    q->code_bits = code_bits;
+    q->levels = levels;
     q->realizations = R;
     q->col_bytes = cb;
     q->rows_pad = rows_in_bytes(cb, bits);
     q->scale = (bits == 32) ? 0.0 : c;
-    const int levels = (bits == 32) ? 0 : num_levels(bits, odd);
     if (bits != 32 && c > 0.0) {
         q->alpha = 2.0 * c / (levels - 1.0);
         q->beta = -c;
@@ -358,7 +364,7 @@ qiht_status qiht_qmatrix_info(const qiht_qmatrix* q, int64_t* rows, int64_t* n, 
     if (!q) return fail(QIHT_ERR_INVALID_ARG, "handle is NULL");
     if (rows) *rows = q->rows;
     if (n) *n = q->n;
-    if (bits) *bits = public_bits(q->bits);
+    if (bits) *bits = (q->bits <= 8) ? q->code_bits : public_bits(q->bits);
     if (realizations) *realizations = q->realizations;
     if (scale) *scale = q->scale;
     if (col_bytes) *col_bytes = q->col_bytes;
@@ -525,8 +531,8 @@ qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t
     if (is_complex(dtype) != is_complex(ydtype))
         return fail(QIHT_ERR_INVALID_ARG, "y must be complex exactly when Phi is");
     const int pbits = bits & ~QIHT_ODD_LEVELS;
-    if (pbits != 1 && pbits != 2 && pbits != 4 && pbits != 8 && pbits != 32)
-        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1, 2, 4, 8 or 32 (packed codes)");
+    if (!((pbits >= 1 && pbits <= 8) || pbits == 32))
+        return fail(QIHT_ERR_UNSUPPORTED, "bits must be 1..8 or 32 (packed codes)");
     const bool yodd = (ybits & QIHT_ODD_LEVELS) != 0;
     const int yb = ybits & ~QIHT_ODD_LEVELS;
     if (!bits_ok_vector(yb) || (yodd && (yb < 2 || yb > 12)))
@@ -576,7 +582,7 @@ qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t
     f.n = n;
     f.ld = ld;
     f.bits = q->bits;
-    f.levels = (q->bits == 32) ? 0 : num_levels(q->bits, (bits & QIHT_ODD_LEVELS) != 0);
+    f.levels = q->levels;
     f.seed = seed;
     f.c = q->scale;
     f.K = (q->bits == 32 || f.c == 0.0) ? 0.0 : (f.levels - 1) / (2.0 * f.c);

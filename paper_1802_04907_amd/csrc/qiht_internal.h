@@ -24,8 +24,10 @@ struct qiht_qmatrix {
     int64_t m = 0;         // rows of the caller's Phi
     int64_t n = 0;         // columns
     int64_t rows = 0;      // m, or 2m for complex input ([Re; Im])
-    int bits = 0;          // 1, 2, 4, 8 or 32 (codes / plain floats), or a dense
-                           // format: kFmtBF16 (16) or kFmtE4M3 (9)
+    int bits = 0;          // stored width: 1, 2, 4, 8 or 32 (codes / plain floats),
+                           // or a dense format: kFmtBF16 (16) or kFmtE4M3 (9)
+    int code_bits = 0;     // width b of the codes (1..8, held in `bits`-wide fields)
+    int levels = 0;        // levels of the code set (0 for 32 and dense formats)
     int realizations = 0;  // 1 or 2
     double scale = 0.0;    // c = max |Phi_ij| (0 for bits 32)
     double alpha = 0.0;    // dequantized value = alpha * code + beta

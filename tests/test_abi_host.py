@@ -71,7 +71,9 @@ def test_quantize_matrix_validation(lib):
     assert f(ptr, 0, 4, 4, 1, 4, 2, 0, None, C.byref(out)) == 1
     assert f(ptr, 4, 4, 3, 1, 4, 2, 0, None, C.byref(out)) == 1      # ld < n
     assert f(ptr, 4, 4, 4, 9, 4, 2, 0, None, C.byref(out)) == 2      # dtype
-    assert f(ptr, 4, 4, 4, 1, 3, 2, 0, None, C.byref(out)) == 2      # bits
+    assert f(ptr, 4, 4, 4, 1, 0, 2, 0, None, C.byref(out)) == 2      # bits
+    assert f(ptr, 4, 4, 4, 1, 9, 2, 0, None, C.byref(out)) == 2
+    assert f(ptr, 4, 4, 4, 1, 16, 2, 0, None, C.byref(out)) == 2
     assert f(ptr, 4, 4, 4, 1, 4, 3, 0, None, C.byref(out)) == 1      # realizations
     odd = 0x100  # QIHT_ODD_LEVELS
     assert f(ptr, 4, 4, 4, 1, 1 | odd, 2, 0, None, C.byref(out)) == 2  # odd set needs b >= 2

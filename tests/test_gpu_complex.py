@@ -68,10 +68,14 @@ def _compare(p, bits, ybits, iters, tol, label, shrinks=True):
     q.free()
 
 
-@pytest.mark.parametrize("bits,ybits", [(32, 32), (8, 8), (4, 8)])
+@pytest.mark.parametrize("bits,ybits", [(32, 32), (8, 8), (5, 8), (4, 8), (3, 8)])
 def test_complex_gaussian_matches_oracle(bits, ybits):
     p = workloads.complex_gaussian(192, 640, 8, 1e-3, seed=7)
-    _compare(p, bits, ybits, 150, 1e-7, f"complex Gaussian {bits}/{ybits}", shrinks=bits != 4)
+    # At 3 bits the iterate settles with |x - x_prev| / |x| near 1e-7, the
+    # size of the FP32 rounding differences between the two x: a stop test at
+    # 1e-7 would be decided by that noise, so it is taken at 1e-5.
+    tol = 1e-5 if bits == 3 else 1e-7
+    _compare(p, bits, ybits, 150, tol, f"complex Gaussian {bits}/{ybits}", shrinks=bits >= 5)
 
 
 def test_complex_gaussian_ragged():

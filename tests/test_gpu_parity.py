@@ -66,6 +66,11 @@ CODE_CASES = [
     (129, 65, 4, np.float32, 1),
     (256, 1024, 8, np.float64, 2),
     (3, 1, 8, np.float64, 2),
+    # widths held in wider fields: 3 bits in 4, 5..7 bits in 8
+    (301, 130, 3, np.float32, 2),
+    (257, 70, 5, np.float64, 2),
+    (129, 64, 6, np.float32, 2),
+    (200, 33, 7, np.float32, 1),
 ]
 
 
@@ -138,7 +143,8 @@ def test_vector_exact(bits, cplx):
 
 
 # ------------------------------------------- odd level set, wide y codes
-@pytest.mark.parametrize("m,n,bits", [(300, 129, 4), (1000, 67, 2), (257, 90, 8)])
+@pytest.mark.parametrize("m,n,bits", [(300, 129, 4), (1000, 67, 2), (257, 90, 8), (129, 40, 3),
+                                      (300, 77, 5), (200, 50, 7)])
 def test_codes_odd_levels_bit_exact(m, n, bits):
     # 2^(b-1) + 1 levels (the appendix's fixed-point remark)
     rng = np.random.default_rng(m + 7 * n)
@@ -220,6 +226,9 @@ GRAD_CASES = [
     (4500, 1300, 25, 4, True),      # complex: 9000 stacked rows, two slabs
     (5000, 1100, 30, 4, False),     # 157 chunks a column: three per lane, ragged
     (2500, 900, 20, 8, False),      # 157 chunks a column: three per lane, ragged
+    (2100, 1000, 20, 3, False),     # 3-bit codes in 4-bit fields
+    (1300, 800, 20, 5, False),      # 5-bit codes in 8-bit fields
+    (1100, 600, 15, 6, True),       # complex, 6-bit codes in 8-bit fields
 ]
 
 
@@ -312,11 +321,11 @@ def test_solve_gaussian_256x1024():
     _compare_solve(p, 8, 300, 1e-8)
 
 
-@pytest.mark.parametrize("bits", [2, 4, 8, 32])
+@pytest.mark.parametrize("bits", [2, 3, 4, 5, 6, 7, 8, 32])
 @pytest.mark.parametrize("mu_mode", [0, 1])
 def test_solve_bits_and_step_modes(bits, mu_mode):
     say(f"solve bits={bits} mu_mode={mu_mode}")
-    p = workloads.gaussian(300, 900, 6 if bits == 2 else 12, 1e-3, seed=bits)
+    p = workloads.gaussian(300, 900, {2: 6, 3: 9}.get(bits, 12), 1e-3, seed=bits)
     _compare_solve(p, bits, 300, 1e-7, mu_mode)
 
 
@@ -433,7 +442,7 @@ def test_batched_deep_backtracking():
     assert deep >= 3
 
 
-@pytest.mark.parametrize("bits,ybits", [(8, 8), (4, 8)])
+@pytest.mark.parametrize("bits,ybits", [(8, 8), (5, 8), (4, 8)])
 def test_fresh_realizations_match_oracle(bits, ybits):
     """Algorithm 2 with new draws of Q(Phi) and Q(y) every iteration, against
     the oracle's (from the FP32 state the solver holds): support, iterations
@@ -448,7 +457,7 @@ def test_fresh_realizations_match_oracle(bits, ybits):
     say(f"  fresh {bits}/{ybits}: shrinks gpu {info['backtracks']} oracle {ref.backtracks}, {info}")
     np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
     assert info["iterations"] == ref.iterations == iters
-    if bits == 8:
+    if bits >= 5:
         assert info["backtracks"] == ref.backtracks
     err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
     assert err <= 1e-4, err

@@ -69,12 +69,15 @@ def _oracle_fp32_state(q1, q2, yh, s):
 
 # (precision of Phi, of y, equal-magnitude nonzeros, SNR in dB).  On these
 # draws the oracle's s-th and (s+1)-th |x + mu g| differ by at least 3.3e-4
-# relative at every iteration; 4/4 bits with noise is left out: one of its
-# draws meets an exact tie, which both sides break by index only if FP32
-# keeps it a tie.
+# relative at every iteration and every step size tried; 4/4 bits with noise
+# is left out: one of its draws meets an exact tie, which both sides break by
+# index only if FP32 keeps it a tie.  Of the 6- and 5-bit pairs (codes held in
+# 8-bit fields) the variants with such a margin are kept (6/8 equal-magnitude
+# and 5/8 noisy come within 3e-5 and 5e-6).
 CASES = [(bp, by, eq, snr) for bp, by in [(32, 32), (8, 8), (4, 8)]
          for eq, snr in [(False, None), (True, None), (False, 20.0)]] + \
-        [(4, 4, False, None), (4, 4, True, None)]
+        [(4, 4, False, None), (4, 4, True, None)] + \
+        [(6, 8, False, None), (6, 8, False, 20.0), (5, 8, False, None), (5, 8, True, None)]
 
 
 @pytest.mark.parametrize("bp,by,equal,snr", CASES)

@@ -23,7 +23,7 @@ def _vec(n, seed=0):
     return v
 
 
-@pytest.mark.parametrize("bits", [1, 2, 3, 4, 5, 8, 12])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 5, 6, 7, 8, 12])
 def test_codes_are_a_neighbouring_level(bits):
     v = _vec(5000, bits)
     codes, c = qz.quantize(v, bits, 11, 0, 0)
@@ -41,7 +41,7 @@ def test_codes_are_a_neighbouring_level(bits):
     assert np.all(deq <= lev[lo + 1] + 1e-12 * c)
 
 
-@pytest.mark.parametrize("bits", [1, 2, 4, 8])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 5, 7, 8])
 def test_endpoints_are_deterministic(bits):
     v = _vec(64, 1)
     L = qz.num_levels(bits)
@@ -59,7 +59,7 @@ def test_one_bit_levels_are_plus_minus_c():
 
 
 def test_level_values_equispaced():
-    for bits in (1, 2, 4, 8):
+    for bits in (1, 2, 3, 4, 5, 6, 7, 8):
         lev = qz.level_values(bits)
         assert lev[0] == -1.0 and lev[-1] == 1.0
         assert lev.size == 2 ** bits
@@ -84,7 +84,7 @@ def _realizations(v, bits, R, seed=21):
     return out, c
 
 
-@pytest.mark.parametrize("bits", [2, 4])
+@pytest.mark.parametrize("bits", [2, 3, 4, 5])
 def test_unbiased_with_exact_variance(bits):
     """E[Q(v)] = v (Sec. III-A) and Var = (q_{j+1} - v)(v - q_j)."""
     v = _vec(256, 3)
@@ -107,7 +107,7 @@ def test_unbiased_with_exact_variance(bits):
                                                        (lev[1] - lev[0]) ** 2 / 4))
 
 
-@pytest.mark.parametrize("bits", [1, 2, 4, 8])
+@pytest.mark.parametrize("bits", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_lemma_error_bound(bits):
     """E|Q(v) - v| <= c sqrt(M) / 2^(b-1) (appendix lemma)."""
     v = _vec(512, 4)
