@@ -37,6 +37,11 @@
  *    Infinity Cache between passes, one for longer streams from HBM); by
  *    default the codes' total size picks it.  Both are valid for every
  *    problem and give the same g bit for bit; only the speed differs.
+ *    QIHT_FAIL_ALLOC_AFTER=N (tests of the error paths): N more device
+ *    allocations of the library succeed, every later one fails as if the
+ *    device were out of memory (the call returns QIHT_ERR_OUT_OF_MEMORY);
+ *    the count starts again whenever the value changes, and unsetting it
+ *    ends the injection.
  */
 #ifndef QIHT_H_
 #define QIHT_H_
@@ -60,7 +65,12 @@ typedef enum {
     QIHT_F64 = 0,   /* double                                   */
     QIHT_F32 = 1,   /* float                                    */
     QIHT_C64 = 2,   /* complex float, interleaved (re, im)      */
-    QIHT_C128 = 3   /* complex double, interleaved (re, im)     */
+    QIHT_C128 = 3,  /* complex double, interleaved (re, im)     */
+    /* range markers, not dtypes: they make every 32-bit int a value of the
+     * type, so that an unknown value passed in is rejected (UNSUPPORTED)
+     * rather than being undefined on the C++ side */
+    QIHT_DTYPE_MIN_ = -2147483647 - 1,
+    QIHT_DTYPE_MAX_ = 2147483647
 } qiht_dtype;
 
 /* Why a solve stopped (qiht_info.reason). */

@@ -4,7 +4,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqiht.so")
+# QIHT_LIB_PATH selects another build of the same library (the host-
+# sanitizer build of build.py, for instance).
+LIB_PATH = os.environ.get("QIHT_LIB_PATH") or os.path.join(HERE, "libqiht.so")
 
 QIHT_OK = 0
 QIHT_FMT_BF16 = 116  # dense formats (include/qiht.h)

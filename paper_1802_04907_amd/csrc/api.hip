@@ -4,6 +4,7 @@
 // status codes plus a thread-local message; no exception crosses the ABI.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -139,7 +140,35 @@ qiht_status check_support(const int32_t* dev_sup, int64_t s, int64_t n, hipStrea
 
 const char* last_error_cstr() { return g_last_error.c_str(); }
 
+// Allocation-failure injection, for tests of the error paths:
+// QIHT_FAIL_ALLOC_AFTER=N lets N more device allocations of the library
+// succeed and fails every later one with hipErrorOutOfMemory (no device call
+// is made for those).  The count starts again whenever the variable's value
+// changes; unset or empty switches the injection off.
+bool alloc_fault() {
+    static std::mutex mu;
+    static std::string seen;
+    static long long left = -1;
+    const char* v = std::getenv("QIHT_FAIL_ALLOC_AFTER");
+    const std::string now = v ? v : "";
+    std::lock_guard<std::mutex> lk(mu);
+    if (now != seen) {
+        seen = now;
+        left = now.empty() ? -1 : std::max(0LL, std::atoll(now.c_str()));
+    }
+    if (left < 0) return false;
+    if (left == 0) return true;
+    --left;
+    return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (alloc_fault()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
 hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st) {
+    if (alloc_fault()) return hipErrorOutOfMemory;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -190,7 +219,7 @@ qiht_status store_dense(const void* phi, qiht_dtype dtype, int64_t m, int64_t n,
     q->rows_pad = rows_in_bytes(cb, bits);
     const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
     const size_t rbytes = static_cast<size_t>(round_up(rows * 4, 256));
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&q->codes[0]), bytes + rbytes);
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&q->codes[0]), bytes + rbytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete q;
@@ -293,7 +322,7 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
         q->beta = -c;
     }
     const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&q->codes[0]), bytes * R);
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&q->codes[0]), bytes * R);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete q;
@@ -552,8 +581,8 @@ qiht_status qiht_niht_solve_fresh(const void* phi, int64_t m, int64_t n, int64_t
         if (ylev) (void)hipFree(ylev);
         qiht_qmatrix_free(q);
     };
-    if (hipMalloc(reinterpret_cast<void**>(&yhat), sizeof(double) * rows) != hipSuccess ||
-        (ylevels && hipMalloc(reinterpret_cast<void**>(&ylev), sizeof(double) * ylevels) != hipSuccess)) {
+    if (dev_malloc(reinterpret_cast<void**>(&yhat), sizeof(double) * rows) != hipSuccess ||
+        (ylevels && dev_malloc(reinterpret_cast<void**>(&ylev), sizeof(double) * ylevels) != hipSuccess)) {
         (void)hipGetLastError();
         cleanup();
         return fail(QIHT_ERR_OUT_OF_MEMORY, "y_hat allocation failed");

@@ -60,7 +60,7 @@ qiht_status embedding(qiht_qmatrix* q, hipStream_t st, qiht_qmatrix** out) {
     e->n = 2 * q->n;
     const size_t bytes = static_cast<size_t>(e->col_bytes) * static_cast<size_t>(e->n);
     uint8_t* mem = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&mem), bytes * q->realizations) != hipSuccess) {
+    if (dev_malloc(reinterpret_cast<void**>(&mem), bytes * q->realizations) != hipSuccess) {
         (void)hipGetLastError();
         delete e;
         return fail(QIHT_ERR_OUT_OF_MEMORY, "no memory for the complex embedding");

@@ -189,6 +189,9 @@ qiht_status run_refit_batch(const RefitIn* in, int count, hipStream_t st);
 // grows to the largest workspace in use at once and is held until the
 // process ends.  Free with hipFreeAsync.
 hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st);
+// hipMalloc for memory that outlives the call (handles).  Both allocators
+// honour QIHT_FAIL_ALLOC_AFTER (allocation-failure injection for tests).
+hipError_t dev_malloc(void** p, size_t bytes);
 
 // g = [Re Phi; Im Phi]^T r for a Fourier-sampled Phi evaluated on the fly
 // (fourier.hip); arguments validated by the caller.
