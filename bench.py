@@ -34,10 +34,14 @@ PEAK_HBM_GBPS = 8000.0
 # An equal-error speed-up is reported only where e* is a recovery: a relative
 # error of at most EQ_ERR_BAR (5%), reached by both solves.
 EQ_ERR_BAR = 0.05
-# Pass timing: HIP events recorded by every PROFILE_EVERY-th full-pass
-# dispatch (each timed dispatch carries a few microseconds of extra latency,
-# so timing all of them would slow the solve being measured).
-PROFILE_EVERY = 8
+# Pass timing: HIP events recorded by every full-pass dispatch of every
+# PROFILE_EVERY-th chunk of 16 rounds (those chunks run uncaptured, the others
+# replay as captured HIP graphs; each timed dispatch carries a few
+# microseconds of extra latency and an uncaptured chunk runs at the host's
+# launch rate, so timing all of them would slow the solve being measured).
+# At 16, a 200-iteration solve (13 chunks) times its initial pass and its
+# first chunk: 17 launches per step.
+PROFILE_EVERY = 16
 # shared-matrix workload: one Phi, NRHS right-hand sides of sparsity S5
 NRHS, S5, ITERS5 = 256, 256, 30
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
@@ -700,8 +704,8 @@ def main():
                      "traffic": traffic,
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_s * 1e6, 3),
                      "launches_timed": launches,
-                     "timing": f"HIP events recorded by every {PROFILE_EVERY}th pass dispatch of the "
-                               f"timed steps, on the solve's stream"},
+                     "timing": f"HIP events recorded by the pass dispatches of every {PROFILE_EVERY}th "
+                               f"chunk of 16 rounds of the timed steps, on the solve's stream"},
     }
     log(json.dumps(out["roofline"]))
     # The solve alone on resident codes, without pass timing: its rounds then

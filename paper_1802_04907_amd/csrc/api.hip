@@ -167,18 +167,25 @@ hipError_t dev_malloc(void** p, size_t bytes) {
     return hipMalloc(p, bytes);
 }
 
-hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st) {
+hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st, bool handle) {
     if (alloc_fault()) return hipErrorOutOfMemory;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    // Three pools per device: per-call workspaces, small temporaries (flags,
+    // level tables) and the codes of handles.  Kept apart so that neither a
+    // temporary nor a handle splits a freed solve workspace: the next solve
+    // of the same shape gets its workspace back at the same address (which
+    // its captured graphs were recorded with).
     static std::mutex mu;
     static std::vector<hipMemPool_t> pools;
+    const size_t kind = handle ? 2 : (bytes <= (size_t(64) << 10) ? 1 : 0);
+    const size_t at = 3 * static_cast<size_t>(dev) + kind;
     hipMemPool_t pool = nullptr;
     {
         std::lock_guard<std::mutex> lk(mu);
-        if (pools.size() <= static_cast<size_t>(dev)) pools.resize(dev + 1, nullptr);
-        if (!pools[dev]) {
+        if (pools.size() <= at) pools.resize(at + 1, nullptr);
+        if (!pools[at]) {
             hipMemPoolProps props{};
             props.allocType = hipMemAllocationTypePinned;
             props.handleTypes = hipMemHandleTypeNone;
@@ -193,9 +200,9 @@ hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st) {
                 (void)hipMemPoolDestroy(np);
                 return e;
             }
-            pools[dev] = np;
+            pools[at] = np;
         }
-        pool = pools[dev];
+        pool = pools[at];
     }
     return hipMallocFromPoolAsync(p, bytes, pool, st);
 }
@@ -322,12 +329,13 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
         q->beta = -c;
     }
     const size_t bytes = static_cast<size_t>(cb) * static_cast<size_t>(n);
-    hipError_t e = dev_malloc(reinterpret_cast<void**>(&q->codes[0]), bytes * R);
+    hipError_t e = pool_malloc(reinterpret_cast<void**>(&q->codes[0]), bytes * R, st, true);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         delete q;
         return fail(QIHT_ERR_OUT_OF_MEMORY, "code allocation failed");
     }
+    q->pooled = true;
     q->codes[1] = (R == 2) ? q->codes[0] + bytes : q->codes[0];
     const double K = (bits == 32 || c == 0.0) ? 0.0 : (levels - 1) / (2.0 * c);
     s0 = launch_quantize_matrix(phi, dtype, m, n, ld, bits, R, seed, c, K, levels, q, st);
@@ -336,8 +344,7 @@ qiht_status qiht_quantize_matrix(const void* phi, int64_t m, int64_t n, int64_t 
         if (e != hipSuccess) s0 = hip_fail(e, "quantize");
     }
     if (s0 != QIHT_OK) {
-        (void)hipFree(q->codes[0]);
-        delete q;
+        qiht_qmatrix_free(q);
         return s0;
     }
     *out = q;
@@ -460,7 +467,17 @@ qiht_status qiht_qmatrix_row_exponents(const qiht_qmatrix* q, int32_t* host_out)
 void qiht_qmatrix_free(qiht_qmatrix* q) {
     if (!q) return;
     if (q->embedded) qiht_qmatrix_free(q->embedded);
-    if (q->codes[0]) (void)hipFree(q->codes[0]);
+    if (q->codes[0]) {
+        if (q->pooled) {
+            // like hipFree: wait for all work on the device, then hand the
+            // codes back to the pool (kept for the next handle)
+            (void)hipDeviceSynchronize();
+            (void)hipFreeAsync(q->codes[0], nullptr);
+            (void)hipStreamSynchronize(nullptr);
+        } else {
+            (void)hipFree(q->codes[0]);
+        }
+    }
     delete q;
 }
 

@@ -57,6 +57,7 @@ qiht_status embedding(qiht_qmatrix* q, hipStream_t st, qiht_qmatrix** out) {
     }
     qiht_qmatrix* e = new qiht_qmatrix(*q);
     e->embedded = nullptr;
+    e->pooled = false;  // (its codes come from hipMalloc below)
     e->n = 2 * q->n;
     const size_t bytes = static_cast<size_t>(e->col_bytes) * static_cast<size_t>(e->n);
     uint8_t* mem = nullptr;

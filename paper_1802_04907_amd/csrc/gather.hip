@@ -18,6 +18,8 @@
 // values, and one extra workgroup commits it (decide_pick, commit_round).
 // Batches commit in k_commit before the gather instead (thousands of gather
 // workgroups would each repeat the test's round trip).
+#include <type_traits>
+
 #include "solve_common.h"
 
 namespace qiht {
@@ -93,16 +95,23 @@ __device__ __forceinline__ int xcd_row_group(int x, int y) {
 
 template <int BITS, int MODE>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __restrict__ P,
-                                                           SolveArgs a, int zero_x) {
+                                                           SolveArgs a, int zero_x,
+                                                           const int2* __restrict__ tab) {
     constexpr int RPW = rows_per_word<BITS>();  // rows per 32-bit word
     constexpr int NSET = (MODE == G_OMEGA) ? kSpec : 1;
     constexpr int NM = (MODE == G_MU) ? 2 : 1;
     constexpr int NW = kGatherThreads / 64;
     constexpr int SLOTS = NW * 16;
-    const int p = blockIdx.y / NSET;
-    const int set = blockIdx.y % NSET;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (tab) {  // (groups of 64 keep the XCD of a workgroup at bx mod 8)
+        const int2 e = tab[blockIdx.x >> 6];
+        by = e.x;
+        bx = e.y + static_cast<int>(blockIdx.x & 63u);
+    }
+    const int p = by / NSET;
+    const int set = by % NSET;
     const ProbDev& pd = P[p];
-    const int wg = xcd_row_group(blockIdx.x, blockIdx.y);  // 16-byte row group
+    const int wg = xcd_row_group(bx, by);  // 16-byte row group
     // G_R after the first round: the last round's step-size test is taken
     // here, by every workgroup alike; one extra workgroup commits it
     __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
@@ -169,11 +178,16 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         for (int q = 0; q < RPW; ++q) acc[mi][q] = 0.0;
     double wsum = 0.0;
 
-    constexpr int U = 8;
-    // Every load of a batch is issued unconditionally (a list position past
-    // the end reads the last entry and gets weight 0), so that the batch's
-    // loads are in flight together.
-    for (int t0 = slot; t0 < ncols; t0 += SLOTS * U) {
+    // One step over U list positions per slot.  Every load of a step is
+    // issued unconditionally (a position past the end reads the last entry
+    // and gets weight 0), so that its loads are in flight together.  The
+    // step length is picked per wave (8, 4, 2 or 1 positions, the fewest
+    // covering what is left for its lowest slot), so that no step loads and
+    // sums positions no lane of the wave has; the sums run over each lane's
+    // positions in the same order whatever the steps.
+    bool stop = false;
+    auto step = [&](int t0, auto u_c) {
+        constexpr int U = decltype(u_c)::value;
         int cidx[U];
         bool valid[U];
 #pragma unroll
@@ -182,7 +196,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
             valid[u] = t < ncols;
             cidx[u] = static_cast<int>(ldg_u32(cols + min(t, ncols - 1)));
         }
-        if (done_now) return;  // uniform over the workgroup
+        if (done_now) {  // uniform over the workgroup
+            stop = true;
+            return;
+        }
         double wt[U];
         uint32_t wa[U], wb[U];
 #pragma unroll
@@ -217,24 +234,49 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
                 }
             }
         }
+    };
+    for (int t0 = slot; t0 < ncols && !stop;) {
+        // positions left for the wave's lowest slot (its lane 0)
+        const int left = __builtin_amdgcn_readfirstlane((ncols - (t0 - (lane >> 2)) + SLOTS - 1) / SLOTS);
+        if (left > 4) {
+            step(t0, std::integral_constant<int, 8>{});
+            t0 += SLOTS * 8;
+        } else if (left > 2) {
+            step(t0, std::integral_constant<int, 4>{});
+            t0 += SLOTS * 4;
+        } else if (left > 1) {
+            step(t0, std::integral_constant<int, 2>{});
+            t0 += SLOTS * 2;
+        } else {
+            step(t0, std::integral_constant<int, 1>{});
+            t0 += SLOTS;
+        }
     }
-
+    if (stop) return;
     if (done_now) return;  // (a workgroup whose lanes had no list entries)
-    // ---- sum over the 16 slots of the wave (lane bits 2..5); lanes 0..3 hold it
+    // ---- sum over the 16 slots of the wave (lane bits 2..5), the NM RPW
+    // row sums of each word halving at every exchange (lanes 0..3 hold the
+    // weight sum)
     wsum = slot_sum(wsum);
+    constexpr int V = NM * RPW;
+    double v[V];
 #pragma unroll
     for (int mi = 0; mi < NM; ++mi)
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) acc[mi][q] = slot_sum(acc[mi][q]);
+        for (int q = 0; q < RPW; ++q) v[mi * RPW + q] = acc[mi][q];
+    int vbase = 0, vdup = 0;
+    slot_sums_halving<V>(v, lane, &vbase, &vdup);
     // ---- then the waves, in wave order
     __shared__ double sh[NW][4][NM][RPW];
     __shared__ double shw[NW];
     __shared__ double shr[NW];
-    if (lane < 4) {
+    if ((lane & vdup) == 0) {
+        constexpr int C = V >= 16 ? V / 16 : 1;
 #pragma unroll
-        for (int mi = 0; mi < NM; ++mi)
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) sh[wv][lane][mi][q] = acc[mi][q];
+        for (int i = 0; i < C; ++i) {
+            const int idx = vbase + i;
+            sh[wv][lane & 3][idx / RPW][idx % RPW] = v[i];
+        }
     }
     if (lane == 0) shw[wv] = wsum;
     __syncthreads();
@@ -469,7 +511,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
 
 template <int MODE>
 void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveArgs& a,
-                 int zero_x, bool wide, hipStream_t st) {
+                 int zero_x, bool wide, hipStream_t st, const GatherGrid& gg) {
     const int nset = (MODE == G_OMEGA) ? kSpec : 1;
     // G_R: one more workgroup per problem, the commit of the last round's step
     const int extra = MODE == G_R ? 1 : 0;
@@ -482,26 +524,28 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
         }
         return;
     }
-    dim3 grid((maxwg + extra + 63) / 64 * 64, count * nset);
+    const dim3 grid = gg.tab ? dim3(static_cast<unsigned>(gg.ngroups) * 64u, 1u)
+                             : dim3((maxwg + extra + 63) / 64 * 64, count * nset);
+    const int2* tab = gg.tab;
     switch (bits) {
-        case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        case 4: hipLaunchKernelGGL((k_gather<4, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        case 8: hipLaunchKernelGGL((k_gather<8, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        case 9: hipLaunchKernelGGL((k_gather<9, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        case 16: hipLaunchKernelGGL((k_gather<16, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
-        default: hipLaunchKernelGGL((k_gather<32, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x); break;
+        case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 4: hipLaunchKernelGGL((k_gather<4, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 8: hipLaunchKernelGGL((k_gather<8, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 9: hipLaunchKernelGGL((k_gather<9, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 16: hipLaunchKernelGGL((k_gather<16, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        default: hipLaunchKernelGGL((k_gather<32, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
     }
 }
 
 }  // namespace
 
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg, const SolveArgs& a,
-                   int zero_x, bool wide, hipStream_t st) {
+                   int zero_x, bool wide, hipStream_t st, const GatherGrid& gg) {
     switch (mode) {
-        case G_R: launch_mode<G_R>(bits, P, count, maxwg, a, zero_x, wide, st); break;
-        case G_MU: launch_mode<G_MU>(bits, P, count, maxwg, a, 0, wide, st); break;
-        default: launch_mode<G_OMEGA>(bits, P, count, maxwg, a, 0, wide, st); break;
+        case G_R: launch_mode<G_R>(bits, P, count, maxwg, a, zero_x, wide, st, gg); break;
+        case G_MU: launch_mode<G_MU>(bits, P, count, maxwg, a, 0, wide, st, gg); break;
+        default: launch_mode<G_OMEGA>(bits, P, count, maxwg, a, 0, wide, st, gg); break;
     }
 }
 

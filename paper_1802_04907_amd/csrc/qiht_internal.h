@@ -35,6 +35,7 @@ struct qiht_qmatrix {
     int64_t col_bytes = 0; // stride between columns
     int64_t rows_pad = 0;  // rows covered by col_bytes
     uint8_t* codes[2] = {nullptr, nullptr};  // codes[1] == codes[0] if R == 1
+    bool pooled = false;   // codes from the handle memory pool (else hipMalloc)
     int32_t* rexp = nullptr;  // dense formats: row exponents e_i (device, rows)
     // complex input: the real embedding [Q_re -Q_im; Q_im Q_re] used for a
     // complex unknown (built on first use by complex.hip, freed with this)
@@ -188,7 +189,8 @@ qiht_status run_refit_batch(const RefitIn* in, int count, hipStream_t st);
 // (re-mapping a workspace of hundreds of MB cost milliseconds per solve); it
 // grows to the largest workspace in use at once and is held until the
 // process ends.  Free with hipFreeAsync.
-hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st);
+// handle: memory that a qiht_qmatrix keeps (its own pool).
+hipError_t pool_malloc(void** p, size_t bytes, hipStream_t st, bool handle = false);
 // hipMalloc for memory that outlives the call (handles).  Both allocators
 // honour QIHT_FAIL_ALLOC_AFTER (allocation-failure injection for tests).
 hipError_t dev_malloc(void** p, size_t bytes);

@@ -275,6 +275,71 @@ __device__ __forceinline__ T slot_sum(T v) {
     return swap32_sum(v);
 }
 
+// Value of lane l ^ (1 << BIT) for a slot bit BIT of 2..5 (lane bits 2..5
+// index the 16 column slots of a wave): gfx950 half-wave and row swaps for
+// bits 5 and 4, row rotations for bits 3 and 2 (bit 2: the lane 4 below or
+// above within its row of 16).
+template <int BIT>
+__device__ __forceinline__ double slot_partner(double x, int lane) {
+    if constexpr (BIT == 5 || BIT == 4) {
+        const uint32_t lo = static_cast<uint32_t>(__double2loint(x)), hi = static_cast<uint32_t>(__double2hiint(x));
+        const auto a = BIT == 5 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                                : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto b = BIT == 5 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                                : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        // [0]: the lower lane's value of the pair, [1]: the upper lane's
+        const bool up = (lane >> BIT) & 1;
+        return up ? __hiloint2double(static_cast<int>(b[0]), static_cast<int>(a[0]))
+                  : __hiloint2double(static_cast<int>(b[1]), static_cast<int>(a[1]));
+    } else if constexpr (BIT == 3) {
+        return dpp<0x128>(x);  // row_ror:8
+    } else {
+        const double below = dpp<0x124>(x);  // row_ror:4: lane l - 4
+        const double above = dpp<0x12C>(x);  // row_ror:12: lane l + 4
+        return ((lane >> 2) & 1) ? below : above;
+    }
+}
+
+// One exchange of the slot sums over slot bit BIT with C live values: while
+// C > 1, the lanes with the bit set keep the upper half (adding the
+// partner's upper half), the others the lower half, so the live values
+// halve; with one left it is summed in full (both partners then hold the
+// same bits: a + b = b + a).
+template <int BIT, int C>
+__device__ __forceinline__ void slot_exchange(double* v, int lane, int& base, int& dup) {
+    if constexpr (C > 1) {
+        constexpr int H = C / 2;
+        const bool up = (lane >> BIT) & 1;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double give = up ? v[i] : v[H + i];
+            const double keep = up ? v[H + i] : v[i];
+            v[i] = keep + slot_partner<BIT>(give, lane);
+        }
+        if (up) base += H;
+    } else {
+        v[0] = v[0] + slot_partner<BIT>(v[0], lane);
+        dup |= 1 << BIT;
+    }
+}
+
+// Sums of V values over the 16 column slots of a wave, halving the live
+// values at each of the slot bits 5, 4, 3, 2 while more than one is live.
+// Afterwards lane l holds max(1, V / 16) totals in v[0..], of the value
+// indices *base, *base + 1, ...; lanes that differ from l only in the bits
+// of *dup hold the same totals.
+template <int V>
+__device__ __forceinline__ void slot_sums_halving(double (&v)[V], int lane, int* base, int* dup) {
+    constexpr int C5 = V, C4 = C5 > 1 ? C5 / 2 : 1, C3 = C4 > 1 ? C4 / 2 : 1, C2 = C3 > 1 ? C3 / 2 : 1;
+    int b = 0, d = 0;
+    slot_exchange<5, C5>(v, lane, b, d);
+    slot_exchange<4, C4>(v, lane, b, d);
+    slot_exchange<3, C3>(v, lane, b, d);
+    slot_exchange<2, C2>(v, lane, b, d);
+    *base = b;
+    *dup = d;
+}
+
 // Sum over the wave in a fixed order, lane 0's result in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -496,8 +561,18 @@ __device__ __forceinline__ double elem_at(uint32_t w, int q) {
 }
 
 // Launchers (defined in the kernel files).
+// Workgroups of a batch's gather: groups of 64 workgroups, entry g of the
+// table = (grid row, first row group) of group g, a grid row being problem
+// p's set t as p * sets + t; every row gets just the groups its own row
+// groups need (a plain grid would give each row as many as the widest
+// problem's, most of them returning at once).  tab NULL: that plain grid.
+struct GatherGrid {
+    const int2* tab = nullptr;
+    int ngroups = 0;
+};
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
-                   const SolveArgs& a, int zero_x, bool wide, hipStream_t st);
+                   const SolveArgs& a, int zero_x, bool wide, hipStream_t st,
+                   const GatherGrid& gg = GatherGrid());
 // ev0/ev1 (optional): events recorded by the dispatch itself around the
 // kernel (timing of the bandwidth-bound pass).
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <string>
@@ -41,10 +42,13 @@ __global__ void k_warm_start(const ProbDev* __restrict__ P, const float* const* 
     }
 }
 
-// Stop flags of every problem, gathered for one read-back.
+// Stop flags of every problem, gathered for one read-back (into device
+// memory, or into mapped host memory that the host reads once the launch's
+// event has completed).
 __global__ void k_done_flags(const ProbDev* __restrict__ P, int count, int32_t* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) out[i] = P[i].st->done;
+    __threadfence_system();
 }
 
 __global__ void k_finalize(const ProbDev* __restrict__ P, float* const* xouts,
@@ -128,6 +132,12 @@ struct Plan {
     bool shared = false;
     SharedGemm sg{};
     size_t gblk_off = 0, bblk_off = 0, gpart_off = 0;
+    // batches of per-problem matrices: the gathers' group tables (G_R,
+    // G_MU, G_OMEGA), host copies, their workspace offsets, and (after
+    // bind) the grids handed to the launches
+    std::vector<int2> gtab[3];
+    size_t gtab_off[3] = {0, 0, 0};
+    GatherGrid gg[3];
 };
 
 qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice& tc = TuneChoice()) {
@@ -290,6 +300,20 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
             prev = at;
         }
     }
+    // a batch's gather groups: row p * sets + t gets ceil((row groups +
+    // extra) / 64) groups of 64 workgroups (the residual gather has one
+    // extra workgroup per problem, its commit; the omega gather kSpec sets)
+    if (count > 1 && !pl.shared) {
+        for (int mode = 0; mode < 3; ++mode) {
+            const int sets = mode == G_OMEGA ? kSpec : 1, extra = mode == G_R ? 1 : 0;
+            std::vector<int2>& t = pl.gtab[mode];
+            for (int i = 0; i < count; ++i)
+                for (int k = 0; k < sets; ++k)
+                    for (int g = 0; g < (pl.host[i].nwg + extra + 63) / 64; ++g)
+                        t.push_back(make_int2(i * sets + k, 64 * g));
+            pl.gtab_off[mode] = cv.take<int2>(t.size());
+        }
+    }
     pl.probs_off = cv.take<ProbDev>(count);
     pl.tasks_off = cv.take<Task>(pl.tasks.size());
     pl.xptr_off = cv.take<float*>(count);
@@ -302,6 +326,13 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
 }
 
 void bind(Plan& pl, uint8_t* base) {
+    for (int mode = 0; mode < 3; ++mode) {
+        pl.gg[mode] = GatherGrid();
+        if (!pl.gtab[mode].empty()) {
+            pl.gg[mode].tab = reinterpret_cast<const int2*>(base + pl.gtab_off[mode]);
+            pl.gg[mode].ngroups = static_cast<int>(pl.gtab[mode].size());
+        }
+    }
     if (pl.shared) {
         pl.sg.g = reinterpret_cast<float*>(base + pl.gblk_off);
         pl.sg.b = base + pl.bblk_off;
@@ -380,10 +411,13 @@ EventPool& event_pool() {
     return p;
 }
 
+// Profiling (qiht_params.profile = N): the full-pass dispatches of every
+// N-th chunk of rounds carry HIP events; such a chunk runs uncaptured, the
+// others may replay as captured graphs.
 struct PassTimer {
     bool on = false;
-    int every = 1;       // time every `every`-th pass dispatch
-    int64_t seen = 0;    // pass dispatches so far
+    int every = 1;       // time the passes of every `every`-th chunk
+    bool active = false; // the chunk being launched is a timed one
     int dev = 0;
     size_t used = 0;
     std::vector<hipEvent_t> ev;
@@ -400,11 +434,11 @@ struct PassTimer {
         }
     }
     // Called once per pass dispatch.  Returns false (no events) when
-    // profiling is off, the dispatch is not one of those sampled, or the
-    // reserve is used up.
+    // profiling is off, the dispatch is not in a timed chunk, or the reserve
+    // is used up.
     bool pair(hipEvent_t* a, hipEvent_t* b) {
         *a = *b = nullptr;
-        if (!on || (seen++ % every) != 0 || used + 2 > ev.size()) return false;
+        if (!on || !active || used + 2 > ev.size()) return false;
         *a = ev[used];
         *b = ev[used + 1];
         used += 2;
@@ -421,6 +455,39 @@ struct PassTimer {
     int launches() const { return static_cast<int>(used / 2); }
 };
 
+// Host memory the stop-flag launches write into directly: pinned, mapped and
+// coherent, two slots of `count` flags (one per chunk in flight), per thread
+// and device, grown to the largest batch met and kept until the process ends.
+struct FlagSlots {
+    int32_t* host = nullptr;
+    int32_t* dev = nullptr;
+    size_t cap = 0;  // flags per slot
+};
+
+FlagSlots* flag_slots(int dev, size_t count) {
+    thread_local std::map<int, FlagSlots> slots;
+    FlagSlots& f = slots[dev];
+    if (f.cap < count) {
+        void* h = nullptr;
+        const size_t cap = std::max<size_t>(count, 256);
+        if (hipHostMalloc(&h, 2 * cap * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(h);
+            return nullptr;
+        }
+        if (f.host) (void)hipHostFree(f.host);  // (no launch of this thread still writes it)
+        f.host = static_cast<int32_t*>(h);
+        f.dev = static_cast<int32_t*>(d);
+        f.cap = cap;
+    }
+    return &f;
+}
+
 struct Workspace {
     uint8_t* base = nullptr;
     hipStream_t st = nullptr;
@@ -432,7 +499,7 @@ struct Workspace {
 
 void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int count,
                        const SolveArgs& a, int zero_x, hipStream_t st, PassTimer* tm) {
-    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, pl.shared, st);
+    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, zero_x, pl.shared, st, pl.gg[G_R]);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (tm) tm->pair(&e0, &e1);
     if (pl.shared) {
@@ -464,9 +531,9 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
                                fresh->yc, fresh->yK, fresh->ylev, fresh->yhat, nullptr, st, it, done);
     }
     gradient_launches(pl, dP, dT, count, a, 0, st, tm);
-    launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
+    launch_gather(G_MU, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st, pl.gg[G_MU]);
     launch_propose(dP, count, a, SEL_STEP, pl.max_n, st);
-    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st);
+    launch_gather(G_OMEGA, pl.bits, dP, count, pl.maxwg, a, 0, pl.shared, st, pl.gg[G_OMEGA]);
 }
 
 // ---------------------------------------------------------------------------
@@ -485,9 +552,11 @@ void iteration_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int c
 struct ChunkKey {
     uintptr_t dP, dT;
     uintptr_t shared_a;
+    uintptr_t gtab[3];  // a batch's gather group tables and their sizes
+    int64_t gtab_n[3];
     int64_t shared_cb;
     int64_t nl;
-    int bits, cpl, npass, maxwg, count, ksplit, shared_n;
+    int bits, cpl, npass, maxwg, max_n, count, ksplit, shared_n;
     int flags;  // long_stream << 1 | shared << 2 | any_slab << 3
     int32_t max_iters, max_backtracks, mu_mode, decide_in_gather;
     double tol, k, c;
@@ -603,6 +672,10 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
                             st));
     QIHT_HIP(hipMemcpyAsync(*dT, pl.tasks.data(), sizeof(Task) * pl.tasks.size(),
                             hipMemcpyHostToDevice, st));
+    for (int mode = 0; mode < 3; ++mode)
+        if (!pl.gtab[mode].empty())
+            QIHT_HIP(hipMemcpyAsync(const_cast<int2*>(pl.gg[mode].tab), pl.gtab[mode].data(),
+                                    sizeof(int2) * pl.gtab[mode].size(), hipMemcpyHostToDevice, st));
 
     return QIHT_OK;
 }
@@ -775,7 +848,7 @@ qiht_status time_choice(const ProblemIn* in, int count, const TuneChoice& c, hip
     qiht_status s0 = setup(in, count, pl, ws, st, &dP, &dT, nullptr, 0, c);
     if (s0 != QIHT_OK) return s0;
     const SolveArgs a{1, -1.0, 2.0, 0.01, 0, 0, 0, 0};
-    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, 1, pl.shared, st);  // r = y_hat
+    launch_gather(G_R, pl.bits, dP, count, pl.maxwg, a, 1, pl.shared, st, pl.gg[G_R]);  // r = y_hat
     std::vector<double> t;
     for (int r = 0; r <= kTuneReps; ++r) {
         QIHT_HIP(hipEventRecord(ev[0], st));
@@ -907,7 +980,10 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     PassTimer timer;
     timer.on = a.profile != 0;
     timer.every = std::max(1, a.profile);
-    timer.reserve(static_cast<size_t>(a.max_iters) / timer.every + 2);
+    // (the initial pass, and every pass of the timed chunks among those of
+    // the first max_iters + 1 rounds)
+    timer.reserve(static_cast<size_t>((a.max_iters + 1) / (kChunk * timer.every) + 1) * kChunk + 1);
+    timer.active = timer.on;
     if (warm) {
         // x0 restricted to its support (x is zero elsewhere)
         hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
@@ -931,14 +1007,15 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     const int64_t max_rounds = a.max_iters > 0 ? static_cast<int64_t>(a.max_iters) * per_iter + 1 : 0;
     // Chunks of rounds run as captured graphs once their launch shape has
     // recurred (two earlier solves with the same workspace, plan and
-    // arguments), unless profiled, drawn per iteration, on caller-provided
-    // memory (instantiation may allocate), or switched off with QIHT_GRAPH=0.
+    // arguments), unless timed (profiling), drawn per iteration, on
+    // caller-provided memory (instantiation may allocate), or switched off
+    // with QIHT_GRAPH=0.
     const char* ge = std::getenv("QIHT_GRAPH");
-    const bool graphs = !timer.on && !fresh && !ext_ws && !(ge && std::strcmp(ge, "0") == 0);
+    const bool graphs = !fresh && !ext_ws && !(ge && std::strcmp(ge, "0") == 0);
     int dev = 0;
     QIHT_HIP(hipGetDevice(&dev));
-    auto record_chunk = [&](hipStream_t s, int64_t nl) {
-        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, s, &timer, fresh);
+    auto record_chunk = [&](hipStream_t s, int64_t nl, PassTimer* tm) {
+        for (int64_t r = 0; r < nl; ++r) iteration_launches(pl, dP, dT, count, a, s, tm, fresh);
     };
     auto chunk_key = [&](int64_t nl) {
         ChunkKey key;
@@ -951,6 +1028,11 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
         key.cpl = pl.cpl;
         key.npass = pl.npass;
         key.maxwg = pl.maxwg;
+        key.max_n = pl.max_n;
+        for (int mode = 0; mode < 3; ++mode) {
+            key.gtab[mode] = reinterpret_cast<uintptr_t>(pl.gg[mode].tab);
+            key.gtab_n[mode] = pl.gg[mode].ngroups;
+        }
         key.count = count;
         key.ksplit = pl.shared ? pl.sg.ksplit : 0;
         key.shared_n = pl.shared ? pl.sg.n : 0;
@@ -966,22 +1048,84 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
         return key;
     };
     const bool recurring = graphs && graph_cache().count_solve(dev, chunk_key(0)) >= 2;
-    for (int64_t launched = 0; launched < max_rounds;) {
+    int64_t chunk_no = 0;
+    auto launch_chunk = [&](int64_t launched) -> qiht_status {
         const int64_t goal = launched < first ? first : max_rounds;
         const int64_t nl = std::min<int64_t>(kChunk, goal - launched);
+        timer.active = timer.on && (chunk_no++ % timer.every) == 0;
         hipGraphExec_t ex = nullptr;
-        if (recurring)
-            ex = graph_cache().get(dev, chunk_key(nl), [&](hipStream_t cs) { record_chunk(cs, nl); });
+        if (recurring && !timer.active)
+            ex = graph_cache().get(dev, chunk_key(nl), [&](hipStream_t cs) { record_chunk(cs, nl, nullptr); });
         if (ex) QIHT_HIP(hipGraphLaunch(ex, st));
-        else record_chunk(st, nl);
-        launched += nl;
-        hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
-        QIHT_HIP(hipGetLastError());
-        QIHT_HIP(hipMemcpyAsync(hdone.data(), ddone, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
-        QIHT_HIP(hipStreamSynchronize(st));
-        bool all_done = true;
-        for (int i = 0; i < count; ++i) all_done = all_done && hdone[i] != 0;
-        if (all_done) break;
+        else record_chunk(st, nl, &timer);
+        return QIHT_OK;
+    };
+    auto chunk_rounds = [&](int64_t launched) {
+        return std::min<int64_t>(kChunk, (launched < first ? first : max_rounds) - launched);
+    };
+    // Stop flags: with pool memory, the chunks of the first max_iters + 1
+    // rounds (which every solve runs unless it stops early) are launched one
+    // ahead of the check of the previous chunk's flags, written by the device
+    // into mapped host memory: the device is not left idle while the host
+    // reads them.  Past those rounds, or when the flags or events cannot be
+    // had (or on caller-provided memory, which allows no allocation), each
+    // chunk is checked before the next is launched.  A chunk launched ahead
+    // of a solve that has already stopped finds every problem done and
+    // returns at once.
+    FlagSlots* fs = ext_ws ? nullptr : flag_slots(dev, static_cast<size_t>(count));
+    std::vector<hipEvent_t> fev;
+    if (fs && !event_pool().take(dev, 2, fev)) fs = nullptr;
+    if (fs) {
+        std::deque<int> pend;  // slots of chunks launched and not yet checked
+        int slot = 0;
+        int64_t launched = 0;
+        qiht_status sl = QIHT_OK;
+        bool all_done = false;
+        while (!all_done && sl == QIHT_OK) {
+            while (launched < max_rounds && (pend.empty() || (pend.size() < 2 && launched < first))) {
+                const int64_t nl = chunk_rounds(launched);
+                sl = launch_chunk(launched);
+                if (sl != QIHT_OK) break;
+                launched += nl;
+                int32_t* out = fs->dev + static_cast<size_t>(slot) * fs->cap;
+                hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, out);
+                if (hipGetLastError() != hipSuccess || hipEventRecord(fev[slot], st) != hipSuccess) {
+                    sl = fail(QIHT_ERR_DEVICE, "stop-flag launch failed");
+                    break;
+                }
+                pend.push_back(slot);
+                slot ^= 1;
+            }
+            if (sl != QIHT_OK || pend.empty()) break;
+            const int chk = pend.front();
+            pend.pop_front();
+            if (hipEventSynchronize(fev[chk]) != hipSuccess) {
+                sl = fail(QIHT_ERR_DEVICE, "stop-flag wait failed");
+                break;
+            }
+            const volatile int32_t* h = fs->host + static_cast<size_t>(chk) * fs->cap;
+            all_done = true;
+            for (int i = 0; i < count; ++i) all_done = all_done && h[i] != 0;
+        }
+        // (the events are recorded on st: the stream order below keeps the
+        // solve's later work behind any chunk still in flight)
+        if (sl != QIHT_OK) (void)hipStreamSynchronize(st);
+        event_pool().give(dev, fev);
+        if (sl != QIHT_OK) return sl;
+    } else {
+        for (int64_t launched = 0; launched < max_rounds;) {
+            const int64_t nl = chunk_rounds(launched);
+            qiht_status sl = launch_chunk(launched);
+            if (sl != QIHT_OK) return sl;
+            launched += nl;
+            hipLaunchKernelGGL(k_done_flags, dim3((count + 255) / 256), dim3(256), 0, st, dP, count, ddone);
+            QIHT_HIP(hipGetLastError());
+            QIHT_HIP(hipMemcpyAsync(hdone.data(), ddone, sizeof(int32_t) * count, hipMemcpyDeviceToHost, st));
+            QIHT_HIP(hipStreamSynchronize(st));
+            bool all_done = true;
+            for (int i = 0; i < count; ++i) all_done = all_done && hdone[i] != 0;
+            if (all_done) break;
+        }
     }
     QIHT_HIP(hipGetLastError());
 

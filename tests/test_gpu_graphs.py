@@ -88,3 +88,23 @@ def test_shared_matrix_batch_graph_equals_eager(monkeypatch):
         for i in range(nrhs):
             _same(ref[i], got[i], f"shared rhs {i} replay {rep}")
     q.free()
+
+
+def test_profiled_solves_mix_timed_chunks_and_graphs():
+    """profile = N times the passes of every N-th chunk of 16 rounds (those
+    chunks run uncaptured, the rest replay as graphs once the shape recurs):
+    the results equal the unprofiled solve's bit for bit, and the timed
+    launches are the initial pass plus the passes of the timed chunks."""
+    p = workloads.gaussian(1500, 6000, 60, 1e-3, seed=32, dtype=np.float32)
+    q, yhat = _gpu(p, 4)
+    ref = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
+    for rep in range(4):
+        x, sup, info = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0, profile=3)
+        torch.cuda.synchronize()
+        _same(ref, (x, sup, info), f"profiled solve {rep}")
+        # 101 rounds = chunks of 16 x 6 + 5: chunks 0, 3 and 6 timed (more
+        # chunks only if some iteration needed more than four shrinks)
+        assert info["pass_launches"] >= 1 + 16 + 16 + 5, info
+        avg_us = info["pass_ms"] * 1e3 / info["pass_launches"]
+        assert 0.5 < avg_us < 5000.0, avg_us
+    q.free()
