@@ -82,6 +82,56 @@ __device__ void digitize_chunk(double r, int wg, const ProbDev& pd) {
     }
 }
 
+// The residual rows of the RG row chunks of segment seg (chunk k held by
+// threads [k NR, (k + 1) NR), NR = 4 RPW <= 64 rows, one row each) as
+// fixed-point digits, as digitize_chunk does for one chunk; chunks past the
+// last row group (live) are not written.  The chunk's maximum and sum are
+// taken over its NR lanes alone (xor offsets below NR).
+template <int BITS, int RG>
+__device__ void digitize_seg(double r, int seg, const ProbDev& pd) {
+    using D = QDig<BITS>;
+    constexpr int NR = 4 * D::RPW;
+    constexpr int H = D::H;
+    static_assert(NR <= 64 && RG * NR <= kGatherThreads, "one chunk per wave at most");
+    __shared__ int snr[RG][NR];
+    const int tid = threadIdx.x;
+    const int k = tid / NR;
+    const bool holds = tid < RG * NR;
+    double m = holds ? fabs(r) : 0.0;
+#pragma unroll
+    for (int o = NR / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    int e = 0;
+    if (m > 0.0) {
+        int ex;
+        frexp(m, &ex);  // m = f 2^ex, f in [0.5, 1)
+        e = ex - 22;    // m 2^-e in [2^21, 2^22)
+    }
+    const int nv = holds ? static_cast<int>(rint(ldexp(r, -e))) : 0;
+    if (holds) snr[k][tid % NR] = nv;
+    int sn = nv;  // |sum| <= 64 * 2^22
+#pragma unroll
+    for (int o = NR / 2; o > 0; o >>= 1) sn += __shfl_xor(sn, o, 64);
+    __syncthreads();
+    const int rgi0 = seg * RG;
+    const size_t words = static_cast<size_t>(pd.nwg) * 4 * H;  // digit words per digit
+    if (tid < RG * 4 * H) {  // digit word of chunk kk: code word j / H, rows offset j % H
+        const int kk = tid / (4 * H), j = tid % (4 * H);
+        if (rgi0 + kk < pd.nwg) {
+            const int cw = j / H, h = j % H;
+            uint32_t u[D::RPD];
+#pragma unroll
+            for (int t = 0; t < D::RPD; ++t) u[t] = (static_cast<uint32_t>(snr[kk][cw * D::RPW + t * H + h]) + D::OFF) ^ D::OFF;
+            transpose_digits<BITS>(u);
+#pragma unroll
+            for (int d = 0; d < D::ND; ++d) pd.rdig[d * words + static_cast<size_t>(rgi0 + kk) * 4 * H + j] = u[d];
+        }
+    }
+    if (holds && tid % NR == 0 && rgi0 + k < pd.nwg) {
+        pd.rexp[rgi0 + k] = e;
+        pd.rsum[rgi0 + k] = sn;
+    }
+}
+
 // Row group of workgroup x in grid row y.  Workgroups are handed to the
 // eight XCDs in turn (linear id mod 8; the grid's width is a multiple of
 // 64), and each XCD has its own L2: the eight 16-byte row groups of one
@@ -93,7 +143,7 @@ __device__ __forceinline__ int xcd_row_group(int x, int y) {
     return (x & ~63) + 8 * ((c - y) & 7) + i;
 }
 
-template <int BITS, int MODE>
+template <int BITS, int MODE, int RG>
 __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __restrict__ P,
                                                            SolveArgs a, int zero_x,
                                                            const int2* __restrict__ tab) {
@@ -101,7 +151,14 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     constexpr int NSET = (MODE == G_OMEGA) ? kSpec : 1;
     constexpr int NM = (MODE == G_MU) ? 2 : 1;
     constexpr int NW = kGatherThreads / 64;
-    constexpr int SLOTS = NW * 16;
+    // a workgroup owns RG 16-byte row groups (a segment) of every listed
+    // column: LPS lanes per column slot, one 32-bit word each
+    static_assert(RG == 1 || RG == 2 || RG == 4, "1, 2 or 4 row groups per workgroup");
+    static_assert(RG == 1 || (BITS != 9 && BITS != 16), "dense formats take one row group");
+    constexpr int LPS = 4 * RG;                 // lanes per slot
+    constexpr int SPW = 64 / LPS;               // slots per wave
+    constexpr int LB = RG == 1 ? 2 : (RG == 2 ? 3 : 4);  // lowest slot bit of the lane
+    constexpr int SLOTS = NW * SPW;
     int bx = blockIdx.x, by = blockIdx.y;
     if (tab) {  // (groups of 64 keep the XCD of a workgroup at bx mod 8)
         const int2 e = tab[blockIdx.x >> 6];
@@ -111,17 +168,17 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const int p = by / NSET;
     const int set = by % NSET;
     const ProbDev& pd = P[p];
-    const int wg = xcd_row_group(bx, by);  // 16-byte row group
+    const int wg = xcd_row_group(bx, by);  // segment (RG row groups; with RG = 1 one)
     // G_R after the first round: the last round's step-size test is taken
     // here, by every workgroup alike; one extra workgroup commits it
     __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
     __shared__ int s_done;
     const bool decide = MODE == G_R && !zero_x && a.decide_in_gather && pd.st->phase == 1;
-    if (MODE == G_R && wg == pd.nwg) {
+    if (MODE == G_R && wg == pd.npart) {
         if (decide && !pd.st->done) commit_round<kGatherThreads>(pd, a, s_dec);
         return;
     }
-    if (wg >= pd.nwg) return;
+    if (wg >= pd.npart) return;
     // the stop flag is read alongside the first loads and checked once they
     // are issued (every address stays valid after the solve has stopped)
     int done_now = pd.st->done;
@@ -167,9 +224,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const uint8_t* A = (MODE == G_R) ? pd.q2 : pd.q1;
     const uint8_t* B = pd.q2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int w = lane & 3;                    // word within the 16-byte group
-    const int slot = wv * 16 + (lane >> 2);    // column slot
-    const size_t woff = static_cast<size_t>(wg) * 16 + static_cast<size_t>(w) * 4;
+    const int w = lane % LPS;                  // word within the segment
+    const int slot = wv * SPW + lane / LPS;    // column slot
+    // (a word past the column's last row group reads its last word; those
+    // rows are not written)
+    const size_t woff = min(static_cast<size_t>(wg) * 16 * RG + static_cast<size_t>(w) * 4,
+                            static_cast<size_t>(pd.col_bytes) - 4);
 
     double acc[NM][RPW];
 #pragma unroll
@@ -237,7 +297,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     };
     for (int t0 = slot; t0 < ncols && !stop;) {
         // positions left for the wave's lowest slot (its lane 0)
-        const int left = __builtin_amdgcn_readfirstlane((ncols - (t0 - (lane >> 2)) + SLOTS - 1) / SLOTS);
+        const int left = __builtin_amdgcn_readfirstlane((ncols - (t0 - lane / LPS) + SLOTS - 1) / SLOTS);
         if (left > 4) {
             step(t0, std::integral_constant<int, 8>{});
             t0 += SLOTS * 8;
@@ -254,10 +314,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     }
     if (stop) return;
     if (done_now) return;  // (a workgroup whose lanes had no list entries)
-    // ---- sum over the 16 slots of the wave (lane bits 2..5), the NM RPW
-    // row sums of each word halving at every exchange (lanes 0..3 hold the
-    // weight sum)
-    wsum = slot_sum(wsum);
+    // ---- sum over the slots of the wave (lane bits LB..5), the NM RPW row
+    // sums of each word halving at every exchange (lane 0 holds the weight
+    // sum)
+    if constexpr (RG == 1) wsum = slot_sum(wsum);
+    else wsum = slot_total<LB>(wsum, lane);
     constexpr int V = NM * RPW;
     double v[V];
 #pragma unroll
@@ -265,17 +326,17 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
 #pragma unroll
         for (int q = 0; q < RPW; ++q) v[mi * RPW + q] = acc[mi][q];
     int vbase = 0, vdup = 0;
-    slot_sums_halving<V>(v, lane, &vbase, &vdup);
+    slot_sums_halving<V, LB>(v, lane, &vbase, &vdup);
     // ---- then the waves, in wave order
-    __shared__ double sh[NW][4][NM][RPW];
+    __shared__ double sh[NW][LPS][NM][RPW];
     __shared__ double shw[NW];
     __shared__ double shr[NW];
     if ((lane & vdup) == 0) {
-        constexpr int C = V >= 16 ? V / 16 : 1;
+        constexpr int C = V >= SPW ? V / SPW : 1;
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int idx = vbase + i;
-            sh[wv][lane & 3][idx / RPW][idx % RPW] = v[i];
+            sh[wv][lane % LPS][idx / RPW][idx % RPW] = v[i];
         }
     }
     if (lane == 0) shw[wv] = wsum;
@@ -284,9 +345,12 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
 #pragma unroll
     for (int v = 0; v < NW; ++v) wtot += shw[v];
     double l1 = 0.0, l2 = 0.0, rres = 0.0;
-    if (threadIdx.x < 4 * RPW) {
+    static_assert(LPS * RPW <= kGatherThreads, "one thread per row of the segment");
+    // (rows of a row group past the column's last: not written)
+    const bool exists = threadIdx.x < LPS * RPW && wg * RG + static_cast<int>(threadIdx.x) / (4 * RPW) < pd.nwg;
+    if (exists) {
         const int ww = threadIdx.x / RPW, q = threadIdx.x % RPW;
-        const size_t row = (static_cast<size_t>(wg) * 4 + ww) * RPW + q;
+        const size_t row = (static_cast<size_t>(wg) * LPS + ww) * RPW + q;
         double val[NM];
 #pragma unroll
         for (int mi = 0; mi < NM; ++mi) {
@@ -312,7 +376,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         }
     }
     if constexpr (MODE == G_R) {
-        if constexpr (BITS <= 8) {
+        if constexpr (BITS <= 8 && RG > 1) {
+            digitize_seg<BITS, RG>(rres, wg, pd);
+        } else if constexpr (BITS <= 8) {
             digitize_chunk<BITS>(rres, wg, pd);
         } else if constexpr (BITS == 9 || BITS == 16) {
             // the GEMM's operand: 2^e r as a pair of BF16 (hi + lo), both
@@ -527,14 +593,23 @@ void launch_mode(int bits, const ProbDev* P, int count, int maxwg, const SolveAr
     const dim3 grid = gg.tab ? dim3(static_cast<unsigned>(gg.ngroups) * 64u, 1u)
                              : dim3((maxwg + extra + 63) / 64 * 64, count * nset);
     const int2* tab = gg.tab;
+    if (gg.rg == 4) {  // (batches: 2, 4, 8 bits and FP32; make_plan picks it)
+        switch (bits) {
+            case 2: hipLaunchKernelGGL((k_gather<2, MODE, 4>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+            case 4: hipLaunchKernelGGL((k_gather<4, MODE, 4>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+            case 8: hipLaunchKernelGGL((k_gather<8, MODE, 4>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+            default: hipLaunchKernelGGL((k_gather<32, MODE, 4>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        }
+        return;
+    }
     switch (bits) {
-        case 1: hipLaunchKernelGGL((k_gather<1, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        case 2: hipLaunchKernelGGL((k_gather<2, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        case 4: hipLaunchKernelGGL((k_gather<4, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        case 8: hipLaunchKernelGGL((k_gather<8, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        case 9: hipLaunchKernelGGL((k_gather<9, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        case 16: hipLaunchKernelGGL((k_gather<16, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
-        default: hipLaunchKernelGGL((k_gather<32, MODE>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 1: hipLaunchKernelGGL((k_gather<1, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 2: hipLaunchKernelGGL((k_gather<2, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 4: hipLaunchKernelGGL((k_gather<4, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 8: hipLaunchKernelGGL((k_gather<8, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 9: hipLaunchKernelGGL((k_gather<9, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        case 16: hipLaunchKernelGGL((k_gather<16, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
+        default: hipLaunchKernelGGL((k_gather<32, MODE, 1>), grid, dim3(kGatherThreads), 0, st, P, a, zero_x, tab); break;
     }
 }
 

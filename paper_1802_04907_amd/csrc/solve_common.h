@@ -323,21 +323,34 @@ __device__ __forceinline__ void slot_exchange(double* v, int lane, int& base, in
     }
 }
 
-// Sums of V values over the 16 column slots of a wave, halving the live
-// values at each of the slot bits 5, 4, 3, 2 while more than one is live.
-// Afterwards lane l holds max(1, V / 16) totals in v[0..], of the value
-// indices *base, *base + 1, ...; lanes that differ from l only in the bits
-// of *dup hold the same totals.
-template <int V>
+// Sums of V values over the column slots of a wave (lane bits LB..5; the
+// bits below LB index the word), halving the live values at each of the
+// slot bits 5, 4, ..., LB while more than one is live.  Afterwards lane l
+// holds max(1, V >> (6 - LB)) totals in v[0..], of the value indices *base,
+// *base + 1, ...; lanes that differ from l only in the bits of *dup hold the
+// same totals.
+template <int V, int LB = 2>
 __device__ __forceinline__ void slot_sums_halving(double (&v)[V], int lane, int* base, int* dup) {
+    static_assert(LB >= 2 && LB <= 5, "slot bits 2..5");
     constexpr int C5 = V, C4 = C5 > 1 ? C5 / 2 : 1, C3 = C4 > 1 ? C4 / 2 : 1, C2 = C3 > 1 ? C3 / 2 : 1;
     int b = 0, d = 0;
     slot_exchange<5, C5>(v, lane, b, d);
-    slot_exchange<4, C4>(v, lane, b, d);
-    slot_exchange<3, C3>(v, lane, b, d);
-    slot_exchange<2, C2>(v, lane, b, d);
+    if constexpr (LB <= 4) slot_exchange<4, C4>(v, lane, b, d);
+    if constexpr (LB <= 3) slot_exchange<3, C3>(v, lane, b, d);
+    if constexpr (LB <= 2) slot_exchange<2, C2>(v, lane, b, d);
     *base = b;
     *dup = d;
+}
+
+// Total of v over the column slots of a wave (lane bits LB..5); every lane
+// of a word holds the same bits.
+template <int LB>
+__device__ __forceinline__ double slot_total(double v, int lane) {
+    v = v + slot_partner<5>(v, lane);
+    if constexpr (LB <= 4) v = v + slot_partner<4>(v, lane);
+    if constexpr (LB <= 3) v = v + slot_partner<3>(v, lane);
+    if constexpr (LB <= 2) v = v + slot_partner<2>(v, lane);
+    return v;
 }
 
 // Sum over the wave in a fixed order, lane 0's result in every lane.
@@ -569,6 +582,8 @@ __device__ __forceinline__ double elem_at(uint32_t w, int q) {
 struct GatherGrid {
     const int2* tab = nullptr;
     int ngroups = 0;
+    int rg = 1;  // 16-byte row groups per workgroup (4 for batches: one
+                 // 64-byte piece of each listed column per workgroup)
 };
 void launch_gather(int mode, int bits, const ProbDev* P, int count, int maxwg,
                    const SolveArgs& a, int zero_x, bool wide, hipStream_t st,

@@ -123,6 +123,7 @@ struct Plan {
     std::vector<Layout> lay;
     std::vector<Task> tasks;
     int bits = 0, cpl = 1, maxwg = 1, max_n = 1;
+    int rg = 1;  // 16-byte row groups per gather workgroup
     bool any_slab = false;
     bool long_stream = false;  // codes of one pass larger than the Infinity Cache
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
@@ -150,6 +151,11 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
     if (is_dense_format(pl.bits) && !same)
         return fail(QIHT_ERR_UNSUPPORTED, "problems on a dense-format matrix must share one handle");
     pl.shared = same && (is_dense_format(pl.bits) || (pl.bits == 32 && count > 1));
+    // Gathers of a batch of per-problem matrices take 64 bytes of each listed
+    // column per workgroup (4 row groups): a single problem needs every
+    // workgroup it can get to hide the gathers' latency, a batch has
+    // workgroups to spare and gains from fewer, wider column reads.
+    pl.rg = (count > 1 && !pl.shared && (pl.bits == 2 || pl.bits == 4 || pl.bits == 8 || pl.bits == 32)) ? 4 : 1;
     int64_t max_cb = 0, max_n = 0;
     for (int i = 0; i < count; ++i) {
         max_cb = std::max(max_cb, in[i].q->col_bytes);
@@ -206,7 +212,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
         p.n = static_cast<int32_t>(q->n);
         p.s = static_cast<int32_t>(s);
         p.nwg = nwg;
-        p.npart = pl.shared ? static_cast<int>((q->col_bytes + 1023) / 1024) : nwg;
+        p.npart = pl.shared ? static_cast<int>((q->col_bytes + 1023) / 1024) : (nwg + pl.rg - 1) / pl.rg;
         p.nslab = pl.shared ? 1 : nslab;
         p.rowexp = q->rexp;
         p.group = static_cast<int32_t>(in[i].group);
@@ -309,7 +315,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
             std::vector<int2>& t = pl.gtab[mode];
             for (int i = 0; i < count; ++i)
                 for (int k = 0; k < sets; ++k)
-                    for (int g = 0; g < (pl.host[i].nwg + extra + 63) / 64; ++g)
+                    for (int g = 0; g < (pl.host[i].npart + extra + 63) / 64; ++g)
                         t.push_back(make_int2(i * sets + k, 64 * g));
             pl.gtab_off[mode] = cv.take<int2>(t.size());
         }
@@ -328,6 +334,7 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
 void bind(Plan& pl, uint8_t* base) {
     for (int mode = 0; mode < 3; ++mode) {
         pl.gg[mode] = GatherGrid();
+        pl.gg[mode].rg = pl.rg;
         if (!pl.gtab[mode].empty()) {
             pl.gg[mode].tab = reinterpret_cast<const int2*>(base + pl.gtab_off[mode]);
             pl.gg[mode].ngroups = static_cast<int>(pl.gtab[mode].size());

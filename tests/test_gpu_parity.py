@@ -531,6 +531,25 @@ def test_batched_uneven_matches_oracle():
         assert err <= 1e-4
 
 
+@pytest.mark.parametrize("bits", [2, 8, 32])
+def test_batched_widths_match_oracle(bits):
+    # batches gather 64 bytes of each listed column per workgroup (four row
+    # groups, their digits written per row group): every width they run at
+    probs = [workloads.gaussian(m, 900, 6 if bits == 2 else 12, 1e-3, seed=60 + m) for m in (300, 520, 777)]
+    gpu = []
+    for p in probs:
+        q, yhat = _gpu_problem(p, bits)
+        gpu.append((q, yhat, p.s))
+    res = qiht.niht_solve_batched(gpu, max_iters=150, tol=1e-7)
+    for p, (x, sup, info) in zip(probs, res):
+        q1, q2, yh = _oracle_mats(p, bits)
+        ref = niht.qiht_solve(q1, q2, yh, p.s, max_iters=150, tol=1e-7)
+        np.testing.assert_array_equal(sup.cpu().numpy(), ref.support)
+        err = np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x)
+        say(f"  batch {bits}-bit m={p.m} err {err:.1e} {info}")
+        assert err <= 1e-4
+
+
 def test_batched_mixed_chunks_per_lane_matches_oracle():
     # columns of 22, 79, 157 and 219 chunks: the batch's spans run with one,
     # two, three and four chunks per lane in one launch
