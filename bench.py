@@ -34,14 +34,13 @@ PEAK_HBM_GBPS = 8000.0
 # An equal-error speed-up is reported only where e* is a recovery: a relative
 # error of at most EQ_ERR_BAR (5%), reached by both solves.
 EQ_ERR_BAR = 0.05
-# Pass timing: HIP events recorded by every full-pass dispatch of every
-# PROFILE_EVERY-th chunk of 16 rounds (those chunks run uncaptured, the others
-# replay as captured HIP graphs; each timed dispatch carries a few
-# microseconds of extra latency and an uncaptured chunk runs at the host's
-# launch rate, so timing all of them would slow the solve being measured).
-# At 16, a 200-iteration solve (13 chunks) times its initial pass and its
-# first chunk: 17 launches per step.
-PROFILE_EVERY = 16
+# Pass timing: HIP events recorded by the full-pass dispatch of the first
+# round of every PROFILE_EVERY-th chunk of 16 rounds (that round is launched
+# directly, the rest of the chunk replays as a captured HIP graph; a timed
+# round costs tens of microseconds more than a replayed one, so timing every
+# dispatch would slow the solve being measured).  At 4, a 200-iteration solve
+# (13 chunks) times 4 passes spread over the whole solve.
+PROFILE_EVERY = 4
 # shared-matrix workload: one Phi, NRHS right-hand sides of sparsity S5
 NRHS, S5, ITERS5 = 256, 256, 30
 PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "e4m3": 2500.0}  # E4M3 runs on BF16 MFMA
@@ -571,8 +570,8 @@ def synthetic_sweep(qiht, torch, dev, trials=100, iters=300, tol=1e-7):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--bits", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
@@ -704,8 +703,8 @@ def main():
                      "traffic": traffic,
                      "bytes_per_launch": bpl, "avg_launch_us": round(avg_s * 1e6, 3),
                      "launches_timed": launches,
-                     "timing": f"HIP events recorded by the pass dispatches of every {PROFILE_EVERY}th "
-                               f"chunk of 16 rounds of the timed steps, on the solve's stream"},
+                     "timing": f"HIP events recorded by the pass dispatch of the first round of every "
+                               f"{PROFILE_EVERY}th chunk of 16 rounds of the timed steps, on the solve's stream"},
     }
     log(json.dumps(out["roofline"]))
     # The solve alone on resident codes, without pass timing: its rounds then

@@ -105,15 +105,16 @@ typedef struct {
                                 NULL = x0 = 0 and G0 = supp H_s(Q1^T y_hat) */
     const int32_t* support0; /* warm-start support (device, s ascending
                                 indices); required iff x0 != NULL           */
-    int32_t profile;         /* N >= 1: time the full-pass launches of
-                                every N-th chunk of 16 rounds (and the
-                                initial pass) with HIP events recorded by
-                                the dispatch on `stream`; such chunks run
-                                uncaptured, the others may replay as
-                                captured HIP graphs (qiht_info.pass_ms and
-                                pass_launches cover the timed launches;
-                                each timed dispatch costs a few microseconds
-                                of extra latency); 0: off                   */
+    int32_t profile;         /* N >= 1: time the full-pass launch of the
+                                first round of every N-th chunk of 16
+                                rounds with HIP events recorded by the
+                                dispatch on `stream` (that round is
+                                launched directly, the rest of the chunk
+                                may replay as a captured HIP graph;
+                                qiht_info.pass_ms and pass_launches cover
+                                the timed launches; each timed dispatch
+                                costs a few microseconds of extra
+                                latency); 0: off                           */
     int32_t refit;           /* 1: after the last iteration, replace x on
                                 its support by the FP64 least-squares fit
                                 against Q1 and y_hat (qiht_refit); 0 keeps

@@ -71,14 +71,14 @@ __device__ void digitize_chunk(double r, int wg, const ProbDev& pd) {
         for (int t = 0; t < D::RPD; ++t) u[t] = (static_cast<uint32_t>(snr[cw * D::RPW + t * H + h]) + D::OFF) ^ D::OFF;
         transpose_digits<BITS>(u);
 #pragma unroll
-        for (int d = 0; d < D::ND; ++d) pd.rdig[d * words + static_cast<size_t>(wg) * 4 * H + tid] = u[d];
+        for (int d = 0; d < D::ND; ++d) stg(pd.rdig + d * words + static_cast<size_t>(wg) * 4 * H + tid, u[d]);
     }
     if (tid == 0) {
         int sn = ssn[0];
 #pragma unroll
         for (int w = 1; w < NWR; ++w) sn += ssn[w];
-        pd.rexp[wg] = e;
-        pd.rsum[wg] = sn;
+        stg(pd.rexp + wg, static_cast<int32_t>(e));
+        stg(pd.rsum + wg, static_cast<int32_t>(sn));
     }
 }
 
@@ -123,12 +123,12 @@ __device__ void digitize_seg(double r, int seg, const ProbDev& pd) {
             for (int t = 0; t < D::RPD; ++t) u[t] = (static_cast<uint32_t>(snr[kk][cw * D::RPW + t * H + h]) + D::OFF) ^ D::OFF;
             transpose_digits<BITS>(u);
 #pragma unroll
-            for (int d = 0; d < D::ND; ++d) pd.rdig[d * words + static_cast<size_t>(rgi0 + kk) * 4 * H + j] = u[d];
+            for (int d = 0; d < D::ND; ++d) stg(pd.rdig + d * words + static_cast<size_t>(rgi0 + kk) * 4 * H + j, u[d]);
         }
     }
     if (holds && tid % NR == 0 && rgi0 + k < pd.nwg) {
-        pd.rexp[rgi0 + k] = e;
-        pd.rsum[rgi0 + k] = sn;
+        stg(pd.rexp + rgi0 + k, static_cast<int32_t>(e));
+        stg(pd.rsum + rgi0 + k, static_cast<int32_t>(sn));
     }
 }
 
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         if (MODE == G_MU && wg == 0 && w == 0) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (valid[u]) pd.gs[t0 + SLOTS * u] = static_cast<float>(wt[u]);
+                if (valid[u]) stg(pd.gs + t0 + SLOTS * u, static_cast<float>(wt[u]));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         const bool live = row < static_cast<size_t>(pd.rows);
         if (MODE == G_R) {
             rres = live ? ldg_f64(pd.yhat + row) - val[0] : 0.0;
-            pd.r32[row] = static_cast<float>(rres);
+            stg(pd.r32 + row, static_cast<float>(rres));
         } else if (live) {
             if (MODE == G_MU) {
                 l1 = two ? val[0] * val[NM - 1] : val[0] * val[0];
@@ -400,11 +400,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     if (MODE == G_MU) {
         const double s2 = block_sum<kGatherThreads>(l2, shr);
         if (threadIdx.x == 0) {
-            pd.part_mu[2 * wg + 0] = s1;
-            pd.part_mu[2 * wg + 1] = s2;
+            stg(pd.part_mu + 2 * wg + 0, s1);
+            stg(pd.part_mu + 2 * wg + 1, s2);
         }
     } else if (threadIdx.x == 0) {
-        pd.part_om[static_cast<size_t>(set) * pd.nwg + wg] = s1;
+        stg(pd.part_om + static_cast<size_t>(set) * pd.nwg + wg, s1);
     }
     // g is final here: the off-support candidates of this iteration's proposals
     if constexpr (MODE == G_MU) compact_candidates<kGatherThreads>(pd, wg, pd.npart, true, cpre);

@@ -306,7 +306,7 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
     if (hist) {
         for (int b = tid; b < 2048; b += kPassThreads) lx[b] = 0u;
         const int nwords = ((tk.c1 - 1) >> 5) - wbase + 1;
-        for (int w = tid; w < nwords; w += kPassThreads) lbm[w] = pd.bmsup[wbase + w];
+        for (int w = tid; w < nwords; w += kPassThreads) lbm[w] = ldg_u32(pd.bmsup + wbase + w);
     }
     // chunk weights: alpha 2^e on the code sums, and the slab's
     // column-independent part 2^e (alpha off + beta) sum_i N_i
@@ -338,7 +338,7 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
     // compiler wait for the prefetched loads as well
     __syncthreads();
     float* out = (pd.nslab == 1) ? pd.g : pd.gpart + static_cast<size_t>(tk.slab) * pd.n;
-    for (int i = tid; i < tk.c1 - tk.c0; i += kPassThreads) out[tk.c0 + i] = __uint_as_float(lx[2048 + i]);
+    for (int i = tid; i < tk.c1 - tk.c0; i += kPassThreads) stg(out + tk.c0 + i, __uint_as_float(lx[2048 + i]));
     if (hist)
         for (int b = tid; b < 2048; b += kPassThreads)
             if (lx[b]) atomicAdd(&pd.hist[b], lx[b]);
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kPassThreads, (LONG && !(BITS == 8 && CMAX == 8)) ?
     if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
     t = tk.next;
     const ProbDev& pd = P[tk.p];
-    const int dn = pd.st->done;  // checked inside, once the first loads are issued
+    const int dn = ldg_i32(&pd.st->done);  // checked inside, once the first loads are issued
     switch (tk.cpl) {
         case 1: pass_q_body<BITS, 1, LONG>(pd, tk, L, dn); break;
         case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2, LONG>(pd, tk, L, dn); break;
@@ -391,10 +391,12 @@ __device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, P
     for (int c = 0; c < CPL; ++c) {
         const int ch = chunk0 + 64 * c;
         ok[c] = ch < col_chunks;
-        const float4* src = reinterpret_cast<const float4*>(pd.r32 + static_cast<size_t>(ch) * RPC);
+        const float* src = pd.r32 + static_cast<size_t>(ch) * RPC;
 #pragma unroll
         for (int q4 = 0; q4 < RPC / 4; ++q4) {
-            const float4 v = ok[c] ? src[q4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const uint4 u = ok[c] ? ldg_u4(src + 4 * q4) : make_uint4(0u, 0u, 0u, 0u);
+            const float4 v = make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z),
+                                         __uint_as_float(u.w));
             rr[c][4 * q4 + 0] = v.x;
             rr[c][4 * q4 + 1] = v.y;
             rr[c][4 * q4 + 2] = v.z;
@@ -415,7 +417,7 @@ __device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, P
     if (hist) {
         for (int b = threadIdx.x; b < 2048; b += kPassThreads) lh[b] = 0u;
         const int nwords = ((tk.c1 - 1) >> 5) - wbase + 1;
-        for (int w = threadIdx.x; w < nwords; w += kPassThreads) lbm[w] = pd.bmsup[wbase + w];
+        for (int w = threadIdx.x; w < nwords; w += kPassThreads) lbm[w] = ldg_u32(pd.bmsup + wbase + w);
         __syncthreads();
     }
     const uint8_t* base = pd.q1 + static_cast<size_t>(chunk0) * 16;
@@ -430,9 +432,8 @@ __device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, P
         for (int c = 0; c < CPL; ++c) {
             constexpr int RW = RPC / 4;  // rows per 32-bit word
             const size_t oc = static_cast<size_t>(64 * c) * 16;
-            const uint4 va = ok[c] ? *reinterpret_cast<const uint4*>(pa + oc) : make_uint4(0u, 0u, 0u, 0u);
-            const uint4 vb = (ok[c] && has2) ? *reinterpret_cast<const uint4*>(pb + oc)
-                                             : make_uint4(0u, 0u, 0u, 0u);
+            const uint4 va = ok[c] ? ldg_u4(pa + oc) : make_uint4(0u, 0u, 0u, 0u);
+            const uint4 vb = (ok[c] && has2) ? ldg_u4(pb + oc) : make_uint4(0u, 0u, 0u, 0u);
             dot_word<BITS>(va.x, &rr[c][0 * RW], a0, a1);
             dot_word<BITS>(va.y, &rr[c][1 * RW], a0, a1);
             dot_word<BITS>(va.z, &rr[c][2 * RW], a0, a1);
@@ -446,12 +447,12 @@ __device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, P
         const float sb = wave_sum(b0 + b1);
         if (lane == 0) {
             const float ga = (BITS == 32) ? sa : fmaf(pd.alpha_f, sa, bsum);
-            out[j] = ga;
+            stg(out + j, ga);
             if (hist && !((lbm[(j >> 5) - wbase] >> (j & 31)) & 1u))
                 atomicAdd(&lh[(__float_as_uint(ga) & 0x7FFFFFFFu) >> 20], 1u);
             if (has2) {
                 const float gb = (BITS == 32) ? sb : fmaf(pd.alpha_f, sb, bsum);
-                out[j2] = gb;
+                stg(out + j2, gb);
                 if (hist && !((lbm[(j2 >> 5) - wbase] >> (j2 & 31)) & 1u))
                     atomicAdd(&lh[(__float_as_uint(gb) & 0x7FFFFFFFu) >> 20], 1u);
             }
@@ -473,7 +474,7 @@ __global__ __launch_bounds__(kPassThreads) void k_fullpass(
     if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
     t = tk.next;
     const ProbDev& pd = P[tk.p];
-    if (pd.st->done) continue;  // uniform over the workgroup
+    if (ldg_i32(&pd.st->done)) continue;  // uniform over the workgroup
     switch (tk.cpl) {
         case 1: pass_f_body<BITS, 1>(pd, tk, L); break;
         case 2: if constexpr (CMAX >= 2) pass_f_body<BITS, 2>(pd, tk, L); break;

@@ -73,9 +73,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 template <int MODE>
 __device__ __forceinline__ float value_at(const float* a_in, const float* g, const float* x,
                                           float muf, int j) {
-    if (MODE == SEL_RAW) return a_in[j];
-    if (MODE == SEL_INIT) return g[j];
-    return fmaf(muf, g[j], x[j]);
+    if (MODE == SEL_RAW) return ldg_f32(a_in + j);
+    if (MODE == SEL_INIT) return ldg_f32(g + j);
+    return fmaf(muf, ldg_f32(g + j), ldg_f32(x + j));
 }
 
 // Rank key of index j: |a_j| as FP32 bits, or with group > 0 (a complex
@@ -172,10 +172,10 @@ __device__ void emit_support(int n, int s, const float* a_in, const float* g, co
             u &= u - 1;
             const int j = w * 32 + b;
             if (pos < static_cast<uint32_t>(s)) {
-                out_sup[pos] = j;
+                stg(out_sup + pos, static_cast<int32_t>(j));
                 if (MODE == SEL_STEP) {
-                    out_val[pos] = value_at<MODE>(a_in, g, x, muf, j);
-                    if (old_sup[pos] != j) changed = 1;
+                    stg(out_val + pos, value_at<MODE>(a_in, g, x, muf, j));
+                    if (ldg_i32(old_sup + pos) != j) changed = 1;
                 }
             }
             ++pos;
@@ -460,16 +460,16 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     // (with `skipped`, the solve's stop flag is read alongside these loads
     // and an already finished problem returns at the first barrier, before
     // writing any global memory)
-    const int done_now = skipped ? pd.st->done : 0;
+    const int done_now = skipped ? ldg_i32(&pd.st->done) : 0;
     double gg = 0.0, uv = 0.0, uu = 0.0;
     if (from_partials) {
         for (int i = tid; i < nsup; i += kSelectThreads) {
-            const double v = static_cast<double>(pd.gs[i]);
+            const double v = static_cast<double>(ldg_f32(pd.gs + i));
             gg += v * v;
         }
         for (int b = tid; b < nw; b += kSelectThreads) {
-            uv += pd.part_mu[2 * b + 0];
-            uu += pd.part_mu[2 * b + 1];
+            uv += ldg_f64(pd.part_mu + 2 * b + 0);
+            uu += ldg_f64(pd.part_mu + 2 * b + 1);
         }
     }
     // Few index blocks: G = 2 or 4 threads share one, thread gq of the group
@@ -485,13 +485,13 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
 #pragma unroll
     for (int i = 0; i < PRE; ++i) {
         const int e = gq + G * i;
-        pidx[i] = e < len0 ? pd.cidx[lo0 + e] : 0u;
-        pgx[i] = e < len0 ? pd.cgx[lo0 + e] : make_float2(0.f, 0.f);
+        pidx[i] = e < len0 ? ldg_u32(pd.cidx + lo0 + e) : 0u;
+        pgx[i] = e < len0 ? ldg_f2(pd.cgx + lo0 + e) : make_float2(0.f, 0.f);
     }
     uint32_t mycnt = 0;  // (counted by the group's first thread)
     int c0 = 0, bad_cnt = 0;
     for (int w = w0; w < w1; ++w) {
-        const int c = pd.ccnt[w];
+        const int c = ldg_i32(pd.ccnt + w);
         if (w == w0) c0 = c;
         if (c < 0) bad_cnt = 1;
         else if (gq == 0) mycnt += static_cast<uint32_t>(c);
@@ -536,7 +536,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     if (!fast) {
         // ---- full path: every key
         for (int w = tid; w < words; w += kSelectThreads) {
-            S.u.b.bm_old[w] = (MODE == SEL_STEP) ? pd.bmsup[w] : 0u;
+            S.u.b.bm_old[w] = (MODE == SEL_STEP) ? ldg_u32(pd.bmsup + w) : 0u;
             S.u.b.bm_new[w] = 0u;
         }
         __syncthreads();
@@ -566,12 +566,12 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
                 const int b = __ffs(u) - 1;
                 u &= u - 1;
                 const int j = w * 32 + b;
-                const float xo = pd.x[j];
-                const float xn = ((S.u.b.bm_new[w] >> b) & 1u) ? fmaf(muf, pd.g[j], xo) : 0.0f;
+                const float xo = ldg_f32(pd.x + j);
+                const float xn = ((S.u.b.bm_new[w] >> b) & 1u) ? fmaf(muf, ldg_f32(pd.g + j), xo) : 0.0f;
                 const double d = static_cast<double>(xn) - static_cast<double>(xo);
                 if (pos < static_cast<uint32_t>(2 * s)) {
-                    dlist[pos] = j;
-                    dw[pos] = d;
+                    stg(dlist + pos, static_cast<int32_t>(j));
+                    stg(dw + pos, d);
                 }
                 ++pos;
                 dx2 += d * d;
@@ -589,7 +589,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             m.dx2 = dx2;
             m.xn2 = xn2;
             m.omega = 0.0;
-            pd.meta[slot] = m;
+            store_meta(pd.meta + slot, m);
         }
         __syncthreads();
         return true;
@@ -619,8 +619,8 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
 #pragma unroll
                 for (int q = 0; q < B; ++q) {
                     const int i = min(ib + q * step, c - 1);
-                    ti[q] = pd.cidx[lo + i];
-                    tg[q] = pd.cgx[lo + i];
+                    ti[q] = ldg_u32(pd.cidx + lo + i);
+                    tg[q] = ldg_f2(pd.cgx + lo + i);
                 }
 #pragma unroll
                 for (int q = 0; q < B; ++q)
@@ -636,7 +636,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             pos += static_cast<uint32_t>(max(c0, 0));
         }
         for (int w = w0 + 1; w < w1; ++w) {  // (G = 1 only)
-            const int c = pd.ccnt[w];
+            const int c = ldg_i32(pd.ccnt + w);
             put_block(pos, w * per, 0, c, 1);
             pos += static_cast<uint32_t>(max(c, 0));
         }
@@ -706,14 +706,14 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
             const int j = static_cast<int>(mi & 0x7FFFFFFFu);
             const uint32_t ps = pos & 0xFFFFu, pu = pos >> 16;
             if (sel[q] && ps < static_cast<uint32_t>(s)) {
-                out_sup[ps] = j;
-                if (MODE == SEL_STEP) out_val[ps] = S.u.f.mval[m];
+                stg(out_sup + ps, static_cast<int32_t>(j));
+                if (MODE == SEL_STEP) stg(out_val + ps, S.u.f.mval[m]);
             }
             if (MODE == SEL_STEP && (sel[q] || on) && pu < static_cast<uint32_t>(2 * s)) {
                 const float xo = S.u.f.mxo[m];
                 const float xn = sel[q] ? S.u.f.mval[m] : 0.0f;
-                dlist[pu] = j;
-                dw[pu] = static_cast<double>(xn) - static_cast<double>(xo);
+                stg(dlist + pu, static_cast<int32_t>(j));
+                stg(dw + pu, static_cast<double>(xn) - static_cast<double>(xo));
             }
             pos += (sel[q] ? 1u : 0u) + ((sel[q] || on) ? 0x10000u : 0u);
         }
@@ -746,7 +746,7 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
         mt.dx2 = out.a;
         mt.xn2 = out.b;
         mt.omega = 0.0;
-        pd.meta[slot] = mt;
+        store_meta(pd.meta + slot, mt);
     }
     __syncthreads();
     return true;
@@ -774,16 +774,16 @@ __global__ __launch_bounds__(kSelectThreads) void k_propose(const ProbDev* __res
     }
     // shrink count of this proposal: after a round whose proposals all failed
     // the test, the following kSpec shrinks of the same step
-    const int k = st->base_k + static_cast<int>(blockIdx.x);
+    const int k = ldg_i32(&st->base_k) + static_cast<int>(blockIdx.x);
     bool skipped = false;
     const bool ok = propose<SEL_STEP>(pd, blockIdx.x, k, 0.0, true, a.k * (1.0 - a.c), &mu0, S, &skipped);
     if (skipped) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (ok) {
-            st->phase = 1;  // the next residual gather takes the step-size test
+            stg(&st->phase, 1);  // the next residual gather takes the step-size test
         } else {
-            st->done = 1;
-            st->reason = QIHT_REASON_STATIONARY;
+            stg(&st->done, 1);
+            stg(&st->reason, static_cast<int32_t>(QIHT_REASON_STATIONARY));
         }
     }
 }

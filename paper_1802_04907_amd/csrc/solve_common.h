@@ -205,6 +205,20 @@ __device__ __forceinline__ float ldg_f32(const void* p) {
 __device__ __forceinline__ double ldg_f64(const void* p) {
     return *(const __attribute__((address_space(1))) double*)(p);
 }
+__device__ __forceinline__ int32_t ldg_i32(const void* p) {
+    return *(const __attribute__((address_space(1))) int32_t*)(p);
+}
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ldg_f2(const void* p) {
+    const f32x2_t v = *(const __attribute__((address_space(1))) f32x2_t*)(p);
+    return make_float2(v.x, v.y);
+}
+// Store through a global-address-space pointer (a generic store also counts
+// against the LDS counter, so every later LDS wait would wait for it).
+template <typename T>
+__device__ __forceinline__ void stg(T* p, const T& v) {
+    *(__attribute__((address_space(1))) T*)(p) = v;
+}
 
 // Cross-lane moves without LDS: DPP within rows of 16 lanes and the gfx950
 // row / half-wave swaps.  dpp<CTRL>(v) reads lane CTRL(l) (0 where the
@@ -508,15 +522,28 @@ __device__ void compact_candidates(const ProbDev& pd, int wg, int nw, bool with_
         if (cand) {
             const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
             const uint32_t pos = base + before + static_cast<uint32_t>(__popcll(b & lt));
-            pd.cidx[lo + pos] = static_cast<uint32_t>(j) | (on_sup ? 0x80000000u : 0u);
-            pd.cgx[lo + pos] = make_float2(gv, on_sup ? (r0 == lo ? pre.x0 : pd.x[j]) : 0.0f);
+            stg(pd.cidx + lo + pos, static_cast<uint32_t>(j) | (on_sup ? 0x80000000u : 0u));
+            const float xj = on_sup ? (r0 == lo ? pre.x0 : ldg_f32(pd.x + j)) : 0.0f;
+            stg(reinterpret_cast<f32x2_t*>(pd.cgx + lo + pos), f32x2_t{gv, xj});
         }
         base += all;
         __syncthreads();
     }
     if (bad) s_bad = 1;
     __syncthreads();
-    if (tid == 0) pd.ccnt[wg] = (s_fast && !s_bad) ? static_cast<int32_t>(base) : -1;
+    if (tid == 0) stg(pd.ccnt + wg, (s_fast && !s_bad) ? static_cast<int32_t>(base) : -1);
+}
+
+// A proposal's metadata, stored field by field through global pointers.
+__device__ __forceinline__ void store_meta(CandMeta* p, const CandMeta& m) {
+    stg(&p->changed, m.changed);
+    stg(&p->dcount, m.dcount);
+    stg(&p->k, m.k);
+    stg(&p->pad, m.pad);
+    stg(&p->mu, m.mu);
+    stg(&p->dx2, m.dx2);
+    stg(&p->xn2, m.xn2);
+    stg(&p->omega, m.omega);
 }
 
 // Step after k shrinks: k successive divisions, the same rounding sequence
@@ -642,12 +669,23 @@ template <int NT>
 __device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, double* red) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // the proposals' metadata, loaded with the partials (one round trip)
+    int mch[kSpec], mk[kSpec];
+    double mmu[kSpec], mdx2[kSpec];
+#pragma unroll
+    for (int t = 0; t < kSpec; ++t) {
+        const CandMeta* m = pd.meta + t;
+        mch[t] = ldg_i32(&m->changed);
+        mk[t] = ldg_i32(&m->k);
+        mmu[t] = ldg_f64(&m->mu);
+        mdx2[t] = ldg_f64(&m->dx2);
+    }
     double den[kSpec];
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) den[t] = 0.0;
     for (int b = tid; b < pd.npart; b += NT)
 #pragma unroll
-        for (int t = 0; t < kSpec; ++t) den[t] += pd.part_om[static_cast<size_t>(t) * pd.nwg + b];
+        for (int t = 0; t < kSpec; ++t) den[t] += ldg_f64(pd.part_om + static_cast<size_t>(t) * pd.nwg + b);
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) {
         den[t] = wave_sum(den[t]);
@@ -659,18 +697,17 @@ __device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, 
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) {
         if (pick >= 0) continue;
-        const CandMeta m = pd.meta[t];
-        if (!m.changed) {
+        if (!mch[t]) {
             pick = t;
             continue;
         }
         double d = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) d += red[t * NW + w];
-        const double omega = d > 0.0 ? m.dx2 / d : INFINITY;
-        if (m.mu <= (1.0 - a.c) * omega) {
+        const double omega = d > 0.0 ? mdx2[t] / d : INFINITY;
+        if (mmu[t] <= (1.0 - a.c) * omega) {
             pick = t;
-        } else if (m.k >= a.max_backtracks) {
+        } else if (mk[t] >= a.max_backtracks) {
             pick = t;
             *capped = true;
         }
@@ -697,15 +734,16 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
     const int32_t* cs = pd.csup + static_cast<size_t>(t) * pd.s;
     const float* cv = pd.cval + static_cast<size_t>(t) * pd.s;
     const int words = (pd.n + 31) / 32;
-    for (int i = threadIdx.x; i < pd.s; i += NT) pd.x[pd.sup[i]] = 0.0f;
-    for (int w = threadIdx.x; w < words; w += NT) pd.bmsup[w] = 0u;
+    for (int i = threadIdx.x; i < pd.s; i += NT) stg(pd.x + ldg_i32(pd.sup + i), 0.0f);
+    for (int w = threadIdx.x; w < words; w += NT) stg(pd.bmsup + w, 0u);
     __syncthreads();
     __threadfence_block();
     for (int i = threadIdx.x; i < pd.s; i += NT) {
-        const int j = cs[i];
-        pd.x[j] = cv[i];
-        pd.xs[i] = cv[i];
-        pd.sup[i] = j;
+        const int j = ldg_i32(cs + i);
+        const float v = ldg_f32(cv + i);
+        stg(pd.x + j, v);
+        stg(pd.xs + i, v);
+        stg(pd.sup + i, static_cast<int32_t>(j));
         atomicOr(&pd.bmsup[j >> 5], 1u << (j & 31));
     }
     if (threadIdx.x == 0) {
@@ -734,7 +772,7 @@ __device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red)
     } else if (threadIdx.x == 0) {
         pd.st->base_k += kSpec;
     }
-    for (int b = threadIdx.x; b < 2048; b += NT) pd.hist[b] = 0u;
+    for (int b = threadIdx.x; b < 2048; b += NT) stg(pd.hist + b, 0u);
 }
 
 }  // namespace qiht

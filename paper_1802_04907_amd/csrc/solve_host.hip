@@ -151,16 +151,17 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
     if (is_dense_format(pl.bits) && !same)
         return fail(QIHT_ERR_UNSUPPORTED, "problems on a dense-format matrix must share one handle");
     pl.shared = same && (is_dense_format(pl.bits) || (pl.bits == 32 && count > 1));
-    // Gathers of a batch of per-problem matrices take 64 bytes of each listed
-    // column per workgroup (4 row groups): a single problem needs every
-    // workgroup it can get to hide the gathers' latency, a batch has
-    // workgroups to spare and gains from fewer, wider column reads.
-    pl.rg = (count > 1 && !pl.shared && (pl.bits == 2 || pl.bits == 4 || pl.bits == 8 || pl.bits == 32)) ? 4 : 1;
-    int64_t max_cb = 0, max_n = 0;
-    for (int i = 0; i < count; ++i) {
-        max_cb = std::max(max_cb, in[i].q->col_bytes);
-        max_n = std::max(max_n, in[i].q->n);
-    }
+    // Gathers take 64 bytes of each listed column per workgroup (4 row
+    // groups) where workgroups are plentiful -- a batch of per-problem
+    // matrices, or columns of 1024 row groups or more (FP32 at 8192 rows) --
+    // and fewer, wider column reads pay; a single problem with shorter
+    // columns needs every workgroup it can get to hide the gathers' latency.
+    int64_t max_cb = 0;
+    for (int i = 0; i < count; ++i) max_cb = std::max(max_cb, in[i].q->col_bytes);
+    pl.rg = ((count > 1 || max_cb / 16 >= 1024) && !pl.shared &&
+             (pl.bits == 2 || pl.bits == 4 || pl.bits == 8 || pl.bits == 32)) ? 4 : 1;
+    int64_t max_n = 0;
+    for (int i = 0; i < count; ++i) max_n = std::max(max_n, in[i].q->n);
     if (max_n > kMaxSelectN) return fail(QIHT_ERR_UNSUPPORTED, "n above 262144");
     pl.max_n = static_cast<int>(max_n);
     // the kernel is built for the largest column; each problem's row slabs use
@@ -418,13 +419,13 @@ EventPool& event_pool() {
     return p;
 }
 
-// Profiling (qiht_params.profile = N): the full-pass dispatches of every
-// N-th chunk of rounds carry HIP events; such a chunk runs uncaptured, the
-// others may replay as captured graphs.
+// Profiling (qiht_params.profile = N): the full-pass dispatch of the first
+// round of every N-th chunk of rounds carries HIP events; that round is
+// launched directly, the rest of the chunk may replay as a captured graph.
 struct PassTimer {
     bool on = false;
-    int every = 1;       // time the passes of every `every`-th chunk
-    bool active = false; // the chunk being launched is a timed one
+    int every = 1;       // time the first pass of every `every`-th chunk
+    bool active = false; // the round being launched is a timed one
     int dev = 0;
     size_t used = 0;
     std::vector<hipEvent_t> ev;
@@ -987,10 +988,10 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     PassTimer timer;
     timer.on = a.profile != 0;
     timer.every = std::max(1, a.profile);
-    // (the initial pass, and every pass of the timed chunks among those of
-    // the first max_iters + 1 rounds)
-    timer.reserve(static_cast<size_t>((a.max_iters + 1) / (kChunk * timer.every) + 1) * kChunk + 1);
-    timer.active = timer.on;
+    // (the first round's pass of every timed chunk; the initial pass, which
+    // follows the quantization's stream through the caches, is not timed)
+    timer.reserve(static_cast<size_t>(2 * (static_cast<int64_t>(a.max_iters) + 1) / (kChunk * timer.every) + 2));
+    timer.active = false;
     if (warm) {
         // x0 restricted to its support (x is zero elsewhere)
         hipLaunchKernelGGL(k_warm_start, dim3(count), dim3(256), 0, st, dP, dx0);
@@ -1058,10 +1059,17 @@ qiht_status run_solve(const ProblemIn* in, int count, const SolveArgs& args, qih
     int64_t chunk_no = 0;
     auto launch_chunk = [&](int64_t launched) -> qiht_status {
         const int64_t goal = launched < first ? first : max_rounds;
-        const int64_t nl = std::min<int64_t>(kChunk, goal - launched);
-        timer.active = timer.on && (chunk_no++ % timer.every) == 0;
+        int64_t nl = std::min<int64_t>(kChunk, goal - launched);
+        // a timed chunk launches its first round itself, that round's pass
+        // carrying the events; the rest of the chunk as usual
+        if (timer.on && (chunk_no++ % timer.every) == 0) {
+            timer.active = true;
+            record_chunk(st, 1, &timer);
+            timer.active = false;
+            if (--nl == 0) return QIHT_OK;
+        }
         hipGraphExec_t ex = nullptr;
-        if (recurring && !timer.active)
+        if (recurring)
             ex = graph_cache().get(dev, chunk_key(nl), [&](hipStream_t cs) { record_chunk(cs, nl, nullptr); });
         if (ex) QIHT_HIP(hipGraphLaunch(ex, st));
         else record_chunk(st, nl, &timer);

@@ -91,10 +91,10 @@ def test_shared_matrix_batch_graph_equals_eager(monkeypatch):
 
 
 def test_profiled_solves_mix_timed_chunks_and_graphs():
-    """profile = N times the passes of every N-th chunk of 16 rounds (those
-    chunks run uncaptured, the rest replay as graphs once the shape recurs):
-    the results equal the unprofiled solve's bit for bit, and the timed
-    launches are the initial pass plus the passes of the timed chunks."""
+    """profile = N times the first pass of every N-th chunk of 16 rounds
+    (that round launched directly, the rest of the chunk replaying as a
+    graph once the shape recurs): the results equal the unprofiled solve's
+    bit for bit, and one launch is timed per timed chunk."""
     p = workloads.gaussian(1500, 6000, 60, 1e-3, seed=32, dtype=np.float32)
     q, yhat = _gpu(p, 4)
     ref = qiht.niht_solve(q, yhat, p.s, max_iters=100, tol=-1.0)
@@ -104,7 +104,7 @@ def test_profiled_solves_mix_timed_chunks_and_graphs():
         _same(ref, (x, sup, info), f"profiled solve {rep}")
         # 101 rounds = chunks of 16 x 6 + 5: chunks 0, 3 and 6 timed (more
         # chunks only if some iteration needed more than four shrinks)
-        assert info["pass_launches"] >= 1 + 16 + 16 + 5, info
+        assert info["pass_launches"] >= 3, info
         avg_us = info["pass_ms"] * 1e3 / info["pass_launches"]
         assert 0.5 < avg_us < 5000.0, avg_us
     q.free()
