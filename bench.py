@@ -412,7 +412,7 @@ def hbm_resident_bench(qiht, torch, dev, m=16384, n=65536, s=1024, iters=100):
     }
 
 
-def batched_bench(qiht, torch, dev, count=96, iters=100):
+def batched_bench(qiht, torch, dev, count=96, iters=100, compare=True):
     """Uneven independent problems: m uniform in [1024, 8192] (the master draw
     of workloads.batch_uneven), n = 4m, s = m/16, Gaussian Phi N(0, 1/m) in
     FP32 drawn on the device with a per-problem seeded generator, 4-bit Phi /
@@ -446,6 +446,12 @@ def batched_bench(qiht, torch, dev, count=96, iters=100):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    if not compare:  # the batched solves alone (for a kernel trace of the batch)
+        t_batch = timed_batch()
+        for q in qs:
+            q.free()
+        return {"workload": f"{count} independent Gaussian problems (batched solves only), {iters} iterations",
+                "batched_ms": round(t_batch * 1e3, 2)}
     # the heuristic launch shape, then the autotuned one (tuned on first use)
     os.environ["QIHT_AUTOTUNE"] = "0"
     t_default = timed_batch()
@@ -591,6 +597,8 @@ def main():
     ap.add_argument("--hbm-only", action="store_true",
                     help="only the HBM-resident workload (16384 x 65536, 4-bit; short run for "
                          "rocprofv3 traces and counters of its pass)")
+    ap.add_argument("--batch-solves-only", action="store_true",
+                    help="only the batched solves of the uneven-batch workload, 100 iterations (for a kernel trace)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload (96 problems)")
     ap.add_argument("--fourier-only", action="store_true",
@@ -633,6 +641,9 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(batched_bench(qiht, torch, dev, iters=20)))
+        return
+    if args.batch_solves_only:
+        print(json.dumps(batched_bench(qiht, torch, dev, compare=False)))
         return
     if args.synthetic_sweep:
         print(json.dumps(synthetic_sweep(qiht, torch, dev)))
