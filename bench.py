@@ -246,6 +246,34 @@ def shared_bench(qiht, torch, dev, reps=2, only=None):
     return res
 
 
+def gemm_reference(torch, dev, reps=20):
+    """The vendor library's BF16 GEMM (torch.matmul, hipBLASLt on ROCm) on the
+    shared-matrix shape, for comparison with the library's own kernel: A
+    32768 x 8192 (the stored columns of Phi, K contiguous) times 8192 x N with
+    N = 256 (one BF16 term of R') and N = 512 (hi and lo side by side, the
+    work the library's kernel issues), B given K-contiguous per column.
+    Random operands; timed with events over `reps` calls after 3 untimed."""
+    a = torch.randn(N, M, device=dev, dtype=torch.bfloat16)
+    out = {"shape": f"{N} x {M} times {M} x nrhs, bf16 in, fp32 accumulation (torch.matmul)"}
+    for nr in (NRHS, 2 * NRHS):
+        bt = torch.randn(nr, M, device=dev, dtype=torch.bfloat16)
+        f = lambda: a @ bt.t()  # noqa: E731
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        tf = 2.0 * N * M * nr / us / 1e6
+        out[f"nrhs_{nr}"] = {"us": round(us, 1), "tflops": round(tf, 1),
+                             "frac_of_bf16_peak": round(tf / PEAK_MFMA_TFLOPS["bf16"], 4)}
+    return out
+
+
 def interferometry_bench(qiht, torch, dev, iters=ITERS, reps=3):
     """Fourier-sampled complex instance at full size: 32640 visibilities (u, v
     uniform in a disk of radius 0.5), a 128 x 128 sky (n = 16384), 200 point
@@ -588,6 +616,8 @@ def main():
     ap.add_argument("--shared-only", default=None, choices=["f32", "bf16", "e4m3"],
                     help="only the shared-matrix workload in one format (short run for "
                          "rocprofv3 traces of its kernels)")
+    ap.add_argument("--gemm-reference", action="store_true",
+                    help="only time the vendor BF16 GEMM (torch.matmul) on the shared-matrix shape")
     ap.add_argument("--profile-pass", action="store_true",
                     help="only quantize the workload and evaluate the gradient pair 5 times "
                          "(short run for rocprofv3 counter passes on the full-pass kernel)")
@@ -629,6 +659,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": 4 << 28, "bytes_written": 4 << 28,
                           "launches": 3}))
+        return
+    if args.gemm_reference:
+        print(json.dumps(gemm_reference(torch, dev)))
         return
     if args.shared_only:
         print(json.dumps(shared_bench(qiht, torch, dev, reps=1, only=args.shared_only)))

@@ -190,7 +190,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const float* wcol = nullptr;    // per-column weights (G_MU: g)
     if (MODE == G_OMEGA) {
         const CandMeta& m = pd.meta[set];
-        if (!m.changed) return;  // no omega needed for this proposal
+        // no omega needed for this proposal, nor for any when the first
+        // keeps the support (the test takes it at once)
+        if (!m.changed || (set > 0 && !ldg_i32(&pd.meta[0].changed))) return;
         ncols = m.dcount;
         cols = pd.dlist + static_cast<size_t>(set) * 2 * pd.s;
         wlist = pd.dw + static_cast<size_t>(set) * 2 * pd.s;
@@ -461,7 +463,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     int ncols;
     if (MODE == G_OMEGA) {
         const CandMeta& m = pd.meta[set];
-        if (!m.changed) return;
+        if (!m.changed || (set > 0 && !ldg_i32(&pd.meta[0].changed))) return;  // as in k_gather
         ncols = m.dcount;
         cols = pd.dlist + static_cast<size_t>(set) * 2 * pd.s;
     } else {

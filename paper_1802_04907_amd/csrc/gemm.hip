@@ -10,11 +10,16 @@
 //     way into LDS), R' as two BF16 terms (hi + lo, about 16 significant
 //     bits), FP32 accumulation.  FP32 storage: FP32 MFMA on the FP32 r.
 //
-// Tiling: a workgroup of 4 waves computes 128 columns x 256 right-hand sides
-// (so each element of A is read once), K in steps of 32 rows staged through
-// LDS with the next step's global loads in flight; wave w takes columns
-// 64 (w & 1) .. + 64 and right-hand sides 128 (w >> 1) .. + 128 as 4 x 8
-// tiles of 16 x 16.
+// Tiling: every right-hand side of a workgroup's tile shares its reads of A
+// (so each element of A is read once per 256 right-hand sides), K in steps
+// of 32 rows staged through LDS.
+//   k_gemm_bf16_dma (BF16, even step counts): 256 columns x 256 right-hand
+//     sides, LDS-direct loads two steps ahead, details below.
+//   k_gemm_bf16 (E4M3, and BF16 with an odd step count): the same tile,
+//     loads through registers one step ahead, LDS double-buffered.
+//   k_gemm_f32 (FP32): 128 columns x 256 right-hand sides.
+// A wave of the BF16 kernels holds a 128 x 128 block of G (8 x 8 tiles of
+// 16 x 16 in 256 accumulator registers).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -225,6 +230,146 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
     store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
 }
 
+// BF16 storage, loads straight into LDS (even step counts).  The same
+// 256 x 256 workgroup tile and MFMA order as k_gemm_bf16, but the global
+// loads are gfx950's LDS-direct loads (global_load_lds_dwordx4: 16 bytes per
+// lane into LDS at M0 + 16 lane): no registers stage the data, no LDS writes
+// sit between the MFMAs, and the loads of two steps ahead are in flight
+// while a step computes.  The A tile is loaded two steps at a time, so both
+// 64-byte halves of each 128-byte line of a column are requested together
+// and HBM serves whole lines.  LDS: A in two buffers of two steps (64 KiB),
+// R' (hi and lo) in a ring of three steps (96 KiB); 160 KiB in all.
+//
+// LDS rows are 64 bytes (the 32 rows of one step of one column or right-hand
+// side), unpadded; the four 16-byte pieces of row r sit at piece ^ ((r >> 1)
+// & 3).  A fragment read (16 consecutive lanes: rows r..r+15 of one piece)
+// then touches every bank once: on gfx950 a 16-byte LDS read serves 16 lanes
+// per cycle over 64 banks, and this is the placement a probe of the bank
+// counter found conflict-free (the 80-byte padded rows of k_gemm_bf16 cost
+// one extra cycle per read).
+constexpr int kStages = 3;
+constexpr int kAPair = 2 * 16384;
+constexpr int kBStage = 32768;
+
+__device__ __forceinline__ int dma_swz(int r) { return (r >> 1) & 3; }
+
+// 16 bytes per lane from g into LDS at lds + 16 lane (lds wave-uniform).  The
+// compiler does not see these loads: every wait on them is explicit (vmcnt),
+// and the kernel waits for all of them before it ends.
+__device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory");
+}
+
+// Step t's loads: R' of step t + 2 every step, A of steps t + 2 and t + 3 at
+// even t.
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16_dma(GemmArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kAPair + kStages * kBStage];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int j0 = blockIdx.x * kBM2;
+    const int n0 = blockIdx.y * kBN;
+    const int kper = p.rows / p.ksplit;
+    const int kbeg = blockIdx.z * kper;
+    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 128;
+    const int rsub = lane >> 2;
+    const int piece = (lane & 3) ^ dma_swz(rsub);
+    const uint8_t* ga[4];
+    const uint8_t* gh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int col = min(j0 + 16 * (4 * wv + i) + rsub, p.n - 1);
+        ga[i] = p.a + static_cast<int64_t>(col) * p.col_bytes + 16 * piece;
+        const int rhs = min(n0 + 16 * (4 * wv + i) + rsub, p.nrhs - 1);
+        gh[i] = static_cast<const uint8_t*>(p.b) + 2 * (static_cast<int64_t>(rhs) * p.ldb) + 16 * piece;
+    }
+    const int64_t lo_bytes = 2 * p.lo_off;
+    const uint32_t lds_base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+        (__attribute__((address_space(3))) uint8_t*)(lds)));
+    const uint32_t wdst = __builtin_amdgcn_readfirstlane(lds_base + wv * 4096);
+    const int ksteps = kper / kBK;  // even, >= 8
+    // A of steps t, t + 1 (t even) into buffer (t / 2) % 2; past the end the
+    // last pair again (into a buffer no step still reads)
+    auto issue_a = [&](int t) {
+        const int tt = min(t, ksteps - 2);
+        const uint32_t d = wdst + ((t >> 1) & 1) * kAPair;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t kb = 2 * static_cast<int64_t>(kbeg + (tt + h) * kBK);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lds_dma16(ga[i] + kb, d + h * 16384 + i * 1024);
+        }
+    };
+    auto issue_b = [&](int t) {
+        const int tt = min(t, ksteps - 1);
+        const int64_t kb = 2 * static_cast<int64_t>(kbeg + tt * kBK);
+        const uint32_t d = wdst + 2 * kAPair + (t % kStages) * kBStage;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds_dma16(gh[i] + kb, d + i * 1024);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds_dma16(gh[i] + lo_bytes + kb, d + 16384 + i * 1024);
+    };
+
+    f32x4_t acc[8][8];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int foff = (lane & 15) * 64 + 16 * ((lane >> 4) ^ dma_swz(lane & 15));
+    auto compute = [&](int t) {
+        const uint8_t* sa = lds + ((t >> 1) & 1) * kAPair + (t & 1) * 16384 + foff;
+        const uint8_t* sb = lds + 2 * kAPair + (t % kStages) * kBStage + foff;
+        bf16x8_t af[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(sa + (wm + 16 * mt) * 64));
+        auto bfrag = [&](int term, int nt) {
+            return as_bf16x8(*reinterpret_cast<const uint4*>(sb + 16384 * term + (wn + 16 * nt) * 64));
+        };
+        bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            const bf16x8_t bh8 = bhn, bl8 = bln;
+            if (nt + 1 < 8) {
+                bhn = bfrag(0, nt + 1);
+                bln = bfrag(1, nt + 1);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) {
+            if (nt + 1 < 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+        }
+    };
+
+    // prologue: A of steps 0-1, R' of steps 0 and 1
+    issue_a(0);
+    issue_b(0);
+    issue_b(1);
+    for (int t = 0; t < ksteps; ++t) {
+        // even t: newer than R'(t) only R'(t + 1) (8 loads); odd t: A(t + 1),
+        // A(t + 2) and R'(t + 1) (16)
+        if (t & 1) {
+            asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
+        } else {
+            asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+            issue_a(t + 2);
+        }
+        issue_b(t + 2);
+        compute(t);
+    }
+    // no load may still be writing LDS when the workgroup ends
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
+    store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
+}
+
 // FP32 storage: FP32 MFMA (16 x 16 x 4), r in FP32.
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs p) {
     __shared__ float la[kBM][kBK + 4];
@@ -344,7 +489,10 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
         if (ev0) hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, st, ev0, ev1, 0, a);
         else hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
     };
-    if (sg.bits == kFmtBF16) go(k_gemm_bf16<16>);
+    if (sg.bits == kFmtBF16) {
+        if ((a.rows / a.ksplit / kBK) % 2 == 0) go(k_gemm_bf16_dma);
+        else go(k_gemm_bf16<16>);
+    }
     else if (sg.bits == kFmtE4M3) go(k_gemm_bf16<9>);
     else go(k_gemm_f32);
     hipLaunchKernelGGL(k_hist_g, dim3(std::max(1, std::min(64, (sg.n + 2047) / 2048)), count), dim3(256), 0, st,
