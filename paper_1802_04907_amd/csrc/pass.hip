@@ -344,6 +344,28 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
             if (lx[b]) atomicAdd(&pd.hist[b], lx[b]);
 }
 
+// Span queue of a full-pass launch: workgroup w runs span w, then takes the
+// next unclaimed span, spans [gridDim.x, ntasks) in order, with one atomic
+// on qctr[0]; the last workgroup to finish sets both counters back to zero
+// for the next launch.  (A one-round static split into equal bytes left a
+// sixth of the batch pass's workgroup time idle at its end: workgroups of
+// equal bytes ran 530-920 us, those on odd XCDs about 9% slower.)  Each
+// column is still summed by one workgroup in one order, so g does not
+// depend on which workgroup takes a span.
+__device__ __forceinline__ int next_span(uint32_t* qctr, int* s_next) {
+    __syncthreads();  // the span's LDS reads are done, and s_next is free
+    if (threadIdx.x == 0) *s_next = static_cast<int>(gridDim.x + atomicAdd(qctr, 1u));
+    __syncthreads();
+    return *s_next;
+}
+
+__device__ __forceinline__ void finish_queue(uint32_t* qctr) {
+    if (threadIdx.x == 0 && atomicAdd(qctr + 1, 1u) == gridDim.x - 1) {
+        atomicExch(qctr, 0u);
+        atomicExch(qctr + 1, 0u);
+    }
+}
+
 // One launch over the spans of a batch: workgroup w runs span w, then the
 // spans its `next` links name; each span carries the chunks per lane of its
 // problem (small columns would leave most lanes idle at the batch's largest
@@ -353,22 +375,25 @@ __device__ __forceinline__ void pass_q_body(const ProbDev& pd, const Task& tk, P
 // Infinity Cache.
 template <int BITS, int CMAX, bool LONG>
 __global__ __launch_bounds__(kPassThreads, (LONG && !(BITS == 8 && CMAX == 8)) ? 3 : 2) void k_fullpass_q(
-    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+    const ProbDev* __restrict__ P, const Task* __restrict__ tasks, int ntasks, uint32_t* qctr) {
     __shared__ PassLds L;
-    for (int t = blockIdx.x; t >= 0;) {
-    const Task tk = tasks[t];
-    if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
-    t = tk.next;
-    const ProbDev& pd = P[tk.p];
-    const int dn = ldg_i32(&pd.st->done);  // checked inside, once the first loads are issued
-    switch (tk.cpl) {
-        case 1: pass_q_body<BITS, 1, LONG>(pd, tk, L, dn); break;
-        case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2, LONG>(pd, tk, L, dn); break;
-        case 3: if constexpr (CMAX >= 4) pass_q_body<BITS, 3, LONG>(pd, tk, L, dn); break;
-        case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4, LONG>(pd, tk, L, dn); break;
-        default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8, LONG>(pd, tk, L, dn); break;
+    __shared__ int s_next;
+    const bool queue = ntasks > static_cast<int>(gridDim.x);
+    for (int t = blockIdx.x; t < ntasks;) {
+        const Task tk = tasks[t];
+        const ProbDev& pd = P[tk.p];
+        const int dn = ldg_i32(&pd.st->done);  // checked inside, once the first loads are issued
+        switch (tk.cpl) {
+            case 1: pass_q_body<BITS, 1, LONG>(pd, tk, L, dn); break;
+            case 2: if constexpr (CMAX >= 2) pass_q_body<BITS, 2, LONG>(pd, tk, L, dn); break;
+            case 3: if constexpr (CMAX >= 4) pass_q_body<BITS, 3, LONG>(pd, tk, L, dn); break;
+            case 4: if constexpr (CMAX >= 4) pass_q_body<BITS, 4, LONG>(pd, tk, L, dn); break;
+            default: if constexpr (CMAX >= 8) pass_q_body<BITS, 8, LONG>(pd, tk, L, dn); break;
+        }
+        if (!queue) break;
+        t = next_span(qctr, &s_next);
     }
-    }
+    if (queue) finish_queue(qctr);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,22 +492,26 @@ __device__ __forceinline__ void pass_f_body(const ProbDev& pd, const Task& tk, P
 
 template <int BITS, int CMAX>
 __global__ __launch_bounds__(kPassThreads) void k_fullpass(
-    const ProbDev* __restrict__ P, const Task* __restrict__ tasks) {
+    const ProbDev* __restrict__ P, const Task* __restrict__ tasks, int ntasks, uint32_t* qctr) {
     __shared__ PassLds L;
-    for (int t = blockIdx.x; t >= 0;) {
-    const Task tk = tasks[t];
-    if (t != static_cast<int>(blockIdx.x)) __syncthreads();  // the previous span's LDS reads are done
-    t = tk.next;
-    const ProbDev& pd = P[tk.p];
-    if (ldg_i32(&pd.st->done)) continue;  // uniform over the workgroup
-    switch (tk.cpl) {
-        case 1: pass_f_body<BITS, 1>(pd, tk, L); break;
-        case 2: if constexpr (CMAX >= 2) pass_f_body<BITS, 2>(pd, tk, L); break;
-        case 4: if constexpr (CMAX >= 4) pass_f_body<BITS, 4>(pd, tk, L); break;
-        case 8: if constexpr (CMAX >= 8) pass_f_body<BITS, 8>(pd, tk, L); break;
-        default: if constexpr (CMAX >= 16) pass_f_body<BITS, 16>(pd, tk, L); break;
+    __shared__ int s_next;
+    const bool queue = ntasks > static_cast<int>(gridDim.x);
+    for (int t = blockIdx.x; t < ntasks;) {
+        const Task tk = tasks[t];
+        const ProbDev& pd = P[tk.p];
+        if (!ldg_i32(&pd.st->done)) {  // uniform over the workgroup
+            switch (tk.cpl) {
+                case 1: pass_f_body<BITS, 1>(pd, tk, L); break;
+                case 2: if constexpr (CMAX >= 2) pass_f_body<BITS, 2>(pd, tk, L); break;
+                case 4: if constexpr (CMAX >= 4) pass_f_body<BITS, 4>(pd, tk, L); break;
+                case 8: if constexpr (CMAX >= 8) pass_f_body<BITS, 8>(pd, tk, L); break;
+                default: if constexpr (CMAX >= 16) pass_f_body<BITS, 16>(pd, tk, L); break;
+            }
+        }
+        if (!queue) break;
+        t = next_span(qctr, &s_next);
     }
-    }
+    if (queue) finish_queue(qctr);
 }
 
 // g of columns split into row slabs: the slab partials summed in slab order
@@ -514,24 +543,26 @@ __global__ __launch_bounds__(256) void k_slab_reduce(const ProbDev* __restrict__
 
 template <typename K>
 void launch_k(K kern, int nwg, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, const ProbDev* P,
-              const Task* T) {
+              const Task* T, int ntasks) {
+    // the queue counters follow the task list
+    uint32_t* qctr = reinterpret_cast<uint32_t*>(const_cast<Task*>(T) + ntasks);
     if (ev0)
-        hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, ev0, ev1, 0, P, T);
+        hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, ev0, ev1, 0, P, T, ntasks, qctr);
     else
-        hipLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, P, T);
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(kPassThreads), 0, st, P, T, ntasks, qctr);
 }
 
 template <int BITS, bool LONG>
-void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
+void launch_pass_b(int cpl, const ProbDev* P, const Task* T, int nwg, int ntasks, hipStream_t st,
                    hipEvent_t ev0, hipEvent_t ev1) {
     switch (cpl) {
 #define QIHT_PASS_CASE(C)                                                                   \
     case C:                                                                                 \
         if constexpr (C <= (BITS == 32 ? 16 : BITS)) {                                      \
             if constexpr (BITS == 32)                                                       \
-                launch_k(k_fullpass<BITS, C>, nwg, st, ev0, ev1, P, T);                     \
+                launch_k(k_fullpass<BITS, C>, nwg, st, ev0, ev1, P, T, ntasks);                     \
             else                                                                            \
-                launch_k(k_fullpass_q<BITS, C, LONG>, nwg, st, ev0, ev1, P, T);                \
+                launch_k(k_fullpass_q<BITS, C, LONG>, nwg, st, ev0, ev1, P, T, ntasks);                \
         }                                                                                   \
         break;
         QIHT_PASS_CASE(1)
@@ -589,16 +620,16 @@ int pass_slots(int bits, int cpl, bool long_stream) {
 }
 
 void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg,
-                 hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                 int ntasks, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
 #define QIHT_LP(B)                                                                   \
-    (long_stream ? launch_pass_b<B, true>(cpl, P, T, nwg, st, ev0, ev1)              \
-                 : launch_pass_b<B, false>(cpl, P, T, nwg, st, ev0, ev1))
+    (long_stream ? launch_pass_b<B, true>(cpl, P, T, nwg, ntasks, st, ev0, ev1)      \
+                 : launch_pass_b<B, false>(cpl, P, T, nwg, ntasks, st, ev0, ev1))
     switch (bits) {
         case 1: QIHT_LP(1); break;
         case 2: QIHT_LP(2); break;
         case 4: QIHT_LP(4); break;
         case 8: QIHT_LP(8); break;
-        default: launch_pass_b<32, false>(cpl, P, T, nwg, st, ev0, ev1); break;
+        default: launch_pass_b<32, false>(cpl, P, T, nwg, ntasks, st, ev0, ev1); break;
     }
 #undef QIHT_LP
 }

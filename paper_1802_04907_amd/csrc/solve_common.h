@@ -89,10 +89,12 @@ struct ProbDev {
     SolveState* st;
 };
 
+// A span of the full pass: columns [c0, c1) of row slab `slab` of problem p.
+// The task list of a launch is followed in memory by two uint32 counters,
+// zero between launches (the span queue of the pass kernels).
 struct Task {
     int32_t p, slab, c0, c1;
     int32_t cpl;   // 16-byte chunks per lane of the problem's row slabs
-    int32_t next;  // the workgroup's next span, or -1
 };
 
 // ---------------------------------------------------------------------------
@@ -645,8 +647,9 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
 constexpr double kInfinityCacheBytes = 200.0 * 1024 * 1024;
 // Workgroups of the full pass that the device holds at once (0 if unknown).
 int pass_slots(int bits, int cpl, bool long_stream);
-void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg, hipStream_t st,
-                 hipEvent_t ev0, hipEvent_t ev1);
+// T: ntasks spans (then the queue counters); workgroup w of nwg starts with span w
+void launch_pass(int bits, int cpl, bool long_stream, const ProbDev* P, const Task* T, int nwg, int ntasks,
+                 hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 // max_n: the largest n of the problems
 void launch_slab_reduce(const ProbDev* P, int count, int max_n, hipStream_t st);
 void launch_candidates(const ProbDev* P, int count, int maxwg, hipStream_t st);

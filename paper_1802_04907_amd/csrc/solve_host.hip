@@ -113,8 +113,8 @@ struct Layout {
 struct TuneChoice {
     int long_stream = -1;  // full pass: 1 = three waves per SIMD with one
                            // column per step, 0 = two waves with two columns
-    int rounds = -1;       // full pass: rounds of resident workgroups the
-                           // columns are cut into (1 or 2)
+    int rounds = -1;       // full pass: spans per resident workgroup in its
+                           // queue (1, 2, 4 or 8)
     int ksplit = -1;       // shared-matrix GEMM: row splits (1, 2 or 4)
 };
 
@@ -128,7 +128,9 @@ struct Plan {
     bool long_stream = false;  // codes of one pass larger than the Infinity Cache
     size_t bytes = 0, probs_off = 0, tasks_off = 0, xptr_off = 0, sptr_off = 0, info_off = 0;
     size_t x0ptr_off = 0, done_off = 0;
-    int npass = 0;  // full-pass workgroups
+    int npass = 0;   // full-pass workgroups
+    int ntasks = 0;  // full-pass spans (pl.tasks holds one more entry: the queue counters)
+    int per_wg = 1;  // full-pass spans per workgroup the spans were cut for
     // shared-matrix path: one GEMM per iteration instead of per-problem passes
     bool shared = false;
     SharedGemm sg{};
@@ -247,12 +249,14 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
             pl.bblk_off = cv.take<uint16_t>(static_cast<size_t>(count) * 2 * q->rows_pad);
         }
     }
-    // Full-pass work: one round of the workgroups the device holds at once
-    // (a second, partial round would leave most CUs idle at the end).  The
-    // columns of every problem's row slabs are cut into spans so that each
-    // workgroup gets the same number of code bytes, a workgroup's spans
-    // running on across problem boundaries.  Workgroup w starts at span w;
-    // its further spans follow the `next` links (after the first spans).
+    // Full-pass work: the workgroups the device holds at once (a second,
+    // partial round would leave most CUs idle at the end), fed from a queue
+    // of spans.  The columns of every problem's row slabs are cut into spans
+    // of equal code bytes, spans running on across problem boundaries in
+    // problem order; workgroup w starts with span w and then takes the next
+    // unclaimed one (see the pass kernels), so workgroups that run faster
+    // take more spans.  Spans per workgroup: 1 (a static split) for streams of
+    // up to 1 MiB per workgroup, up to 8 for longer ones.
     double total = 0.0;
     for (int i = 0; i < count; ++i)
         total += static_cast<double>(in[i].q->n) * static_cast<double>(in[i].q->col_bytes);
@@ -268,10 +272,13 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
         else if (std::strcmp(e, "cache") == 0) pl.long_stream = false;
     }
     if (tc.long_stream >= 0) pl.long_stream = tc.long_stream != 0;
-    const int rounds = tc.rounds > 0 ? tc.rounds : 1;
-    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream)) * rounds;
-    const double budget = std::max(1.0, std::ceil(total / slots));
-    std::vector<std::vector<Task>> wgs(1);
+    const int slots = pl.shared ? 1 : std::max(1, pass_slots(pl.bits, pl.cpl, pl.long_stream));
+    const double wg_bytes = std::max(1.0, std::ceil(total / slots));
+    int per_wg = 1;
+    while (per_wg < 8 && wg_bytes > static_cast<double>(per_wg) * (1 << 20)) per_wg *= 2;
+    if (tc.rounds > 0) per_wg = tc.rounds;
+    pl.per_wg = per_wg;
+    const double budget = std::max(1.0, std::ceil(wg_bytes / per_wg));
     double cur = 0.0;
     for (int i = 0; i < count && !pl.shared; ++i) {
         const qiht_qmatrix* q = in[i].q;
@@ -284,29 +291,16 @@ qiht_status make_plan(const ProblemIn* in, int count, Plan& pl, const TuneChoice
             while (c0 < q->n) {
                 const int64_t fit = std::max<int64_t>(1, static_cast<int64_t>(std::ceil((budget - cur) / sb)));
                 const int64_t take = std::min<int64_t>({q->n - c0, fit, static_cast<int64_t>(kPassMaxCols)});
-                wgs.back().push_back(Task{i, sl, static_cast<int32_t>(c0), static_cast<int32_t>(c0 + take), cpl, -1});
+                pl.tasks.push_back(Task{i, sl, static_cast<int32_t>(c0), static_cast<int32_t>(c0 + take), cpl});
                 c0 += take;
                 cur += static_cast<double>(take) * sb;
-                if (cur >= budget) {
-                    wgs.emplace_back();
-                    cur = 0.0;
-                }
+                if (cur >= budget) cur = 0.0;
             }
         }
     }
-    if (wgs.back().empty()) wgs.pop_back();
-    pl.npass = static_cast<int>(wgs.size());
-    pl.tasks.resize(wgs.size());
-    for (size_t w = 0; w < wgs.size(); ++w) {
-        int32_t prev = -1;  // index of the workgroup's previous span
-        for (size_t k = 0; k < wgs[w].size(); ++k) {
-            const int32_t at = k == 0 ? static_cast<int32_t>(w) : static_cast<int32_t>(pl.tasks.size());
-            if (k == 0) pl.tasks[w] = wgs[w][0];
-            else pl.tasks.push_back(wgs[w][k]);
-            if (prev >= 0) pl.tasks[prev].next = at;
-            prev = at;
-        }
-    }
+    pl.ntasks = static_cast<int>(pl.tasks.size());
+    pl.npass = std::min(slots, pl.ntasks);
+    pl.tasks.push_back(Task{0, 0, 0, 0, 0});  // the queue counters (two zero words)
     // a batch's gather groups: row p * sets + t gets ceil((row groups +
     // extra) / 64) groups of 64 workgroups (the residual gather has one
     // extra workgroup per problem, its commit; the omega gather kSpec sets)
@@ -514,7 +508,7 @@ void gradient_launches(const Plan& pl, const ProbDev* dP, const Task* dT, int co
         launch_shared_pass(pl.sg, dP, count, st, e0, e1);
         return;
     }
-    launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, st, e0, e1);
+    launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, pl.ntasks, st, e0, e1);
     if (pl.any_slab) launch_slab_reduce(dP, count, pl.max_n, st);
 }
 
@@ -690,8 +684,8 @@ qiht_status setup(const ProblemIn* in, int count, Plan& pl, Workspace& ws, hipSt
 
 // ---------------------------------------------------------------------------
 // Autotuner.  The launch shape of the full pass (its instance: two waves per
-// SIMD with two columns in flight each, or three with one; and whether its
-// columns are cut into one or two rounds of resident workgroups) and of the
+// SIMD with two columns in flight each, or three with one; and how many spans
+// per workgroup its queue holds: 1, 2, 4 or 8) and of the
 // shared-matrix GEMM (row splits 1, 2 or 4) is chosen per device architecture
 // and problem shape by timing every candidate on the problem's own codes: one
 // warm-up launch, then the median of kTuneReps launches between stream
@@ -863,7 +857,7 @@ qiht_status time_choice(const ProblemIn* in, int count, const TuneChoice& c, hip
         if (pl.shared) {
             launch_shared_pass(pl.sg, dP, count, st);
         } else {
-            launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, st, nullptr, nullptr);
+            launch_pass(pl.bits, pl.cpl, pl.long_stream, dP, dT, pl.npass, pl.ntasks, st, nullptr, nullptr);
             if (pl.any_slab) launch_slab_reduce(dP, count, pl.max_n, st);
         }
         QIHT_HIP(hipEventRecord(ev[1], st));
@@ -910,9 +904,9 @@ qiht_status tuned_choice(const ProblemIn* in, int count, hipStream_t st, bool ma
             }
     } else {
         def.long_stream = p0.long_stream ? 1 : 0;
-        def.rounds = 1;
+        def.rounds = p0.per_wg;
         for (int ls = 0; ls <= 1; ++ls)
-            for (int rd = 1; rd <= 2; ++rd) {
+            for (int rd = 1; rd <= 8; rd *= 2) {
                 TuneChoice c;
                 c.long_stream = ls;
                 c.rounds = rd;

@@ -13,7 +13,9 @@ import workloads  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-PASS_CANDIDATES = ["cache/r1", "cache/r2", "long/r1", "long/r2"]
+# instance (cache: two waves per SIMD, long: three) x spans per workgroup in the
+# pass's span queue (r2 and up: workgroups take further spans from the queue)
+PASS_CANDIDATES = [f"{inst}/r{r}" for inst in ("cache", "long") for r in (1, 2, 4, 8)]
 
 
 def _gpu(p, bits):
