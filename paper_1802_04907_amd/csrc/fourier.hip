@@ -152,7 +152,7 @@ constexpr int kColLanes = 8;
 
 __global__ __launch_bounds__(256) void k_fourier_cols(const double* __restrict__ uv, int64_t nvis, int side,
                                                       const int32_t* __restrict__ cols,
-                                                      const float* __restrict__ vals, int count,
+                                                      const double* __restrict__ vals, int count,
                                                       const double* __restrict__ y, float* __restrict__ r,
                                                       double* __restrict__ p) {
     const int64_t j = (static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x) / kColLanes;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_fourier_cols(const double* __restrict__
         if (k < 0) continue;
         float c, sn;
         fourier_entry(u, v, k, side, inv_side, c, sn);
-        const double x = static_cast<double>(vals[t]);
+        const double x = vals[t];
         are = fma(static_cast<double>(c), x, are);
         aim = fma(-static_cast<double>(sn), x, aim);
     }
@@ -245,12 +245,12 @@ __device__ __forceinline__ double sumsq_total(const FtState* st) {
 
 // g_G into the value list, |g_G|^2 into st->num (one workgroup).
 __global__ __launch_bounds__(kCtl) void k_ft_gsup(const float* __restrict__ g, const int32_t* __restrict__ sup, int s,
-                                                   float* __restrict__ vals, FtState* st) {
+                                                   double* __restrict__ vals, FtState* st) {
     __shared__ double sh[kCtl];
     double a = 0.0;
     for (int t = threadIdx.x; t < s; t += kCtl) {
         const float v = g[sup[t]];
-        vals[t] = v;
+        vals[t] = static_cast<double>(v);
         a = fma(static_cast<double>(v), static_cast<double>(v), a);
     }
     const double num = block_sum_f64(a, sh);
@@ -285,11 +285,13 @@ __global__ __launch_bounds__(256) void k_ft_axpy(const float* __restrict__ x, co
 }
 
 // The change x+ - x as a column list: the new support with a - x, then the
-// old support's indices outside the new one with -x (others skipped);
-// |x+ - x|^2, |x+|^2 and whether the support changed (one workgroup).
+// old support's indices outside the new one with -x (others skipped), each
+// difference of the FP32 values taken exactly in FP64 (as the packed-code
+// path's proposal lists hold them); |x+ - x|^2, |x+|^2 and whether the
+// support changed (one workgroup).
 __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, const float* __restrict__ a,
                                                     const int32_t* __restrict__ sup, const int32_t* __restrict__ sup_new,
-                                                    int s, int32_t* __restrict__ cols, float* __restrict__ vals,
+                                                    int s, int32_t* __restrict__ cols, double* __restrict__ vals,
                                                     FtState* st) {
     __shared__ double sh[kCtl];
     __shared__ int s_changed;
@@ -300,10 +302,10 @@ __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, 
     for (int t = threadIdx.x; t < s; t += kCtl) {
         const int k = sup_new[t];
         const float xn = a[k];
-        const float d = xn - x[k];
+        const double d = static_cast<double>(xn) - static_cast<double>(x[k]);
         cols[t] = k;
         vals[t] = d;
-        d2 = fma(static_cast<double>(d), static_cast<double>(d), d2);
+        d2 = fma(d, d, d2);
         x2 = fma(static_cast<double>(xn), static_cast<double>(xn), x2);
         if (sup[t] != k) s_changed = 1;
         // the old index: kept if absent from the new (ascending) support
@@ -316,9 +318,9 @@ __global__ __launch_bounds__(kCtl) void k_ft_delta(const float* __restrict__ x, 
         }
         const bool in_new = lo < s && sup_new[lo] == ko;
         cols[s + t] = in_new ? -1 : ko;
-        const float dold = in_new ? 0.0f : -x[ko];
+        const double dold = in_new ? 0.0 : -static_cast<double>(x[ko]);
         vals[s + t] = dold;
-        d2 = fma(static_cast<double>(dold), static_cast<double>(dold), d2);
+        d2 = fma(dold, dold, d2);
     }
     const double sd2 = block_sum_f64(d2, sh);
     const double sx2 = block_sum_f64(x2, sh);
@@ -384,7 +386,7 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
     };
     const size_t o_r = take(sizeof(float) * rows), o_g = take(sizeof(float) * n), o_a = take(sizeof(float) * n);
     const size_t o_p = take(sizeof(double) * rows), o_cols = take(sizeof(int32_t) * 2 * s);
-    const size_t o_vals = take(sizeof(float) * 2 * s), o_sn = take(sizeof(int32_t) * s);
+    const size_t o_vals = take(sizeof(double) * 2 * s), o_sn = take(sizeof(int32_t) * s);
     const size_t o_st = take(sizeof(FtState));
     uint8_t* ws = nullptr;
     QIHT_HIP(pool_malloc(reinterpret_cast<void**>(&ws), off, st));
@@ -393,7 +395,7 @@ qiht_status run_fourier_solve(const double* uv, int64_t nvis, int side, const do
     float* a = reinterpret_cast<float*>(ws + o_a);
     double* p = reinterpret_cast<double*>(ws + o_p);
     int32_t* cols = reinterpret_cast<int32_t*>(ws + o_cols);
-    float* vals = reinterpret_cast<float*>(ws + o_vals);
+    double* vals = reinterpret_cast<double*>(ws + o_vals);
     int32_t* sn = reinterpret_cast<int32_t*>(ws + o_sn);
     FtState* dst = reinterpret_cast<FtState*>(ws + o_st);
     qiht_status ret = QIHT_OK;
