@@ -13,13 +13,13 @@
 // Tiling: every right-hand side of a workgroup's tile shares its reads of A
 // (so each element of A is read once per 256 right-hand sides), K in steps
 // of 32 rows staged through LDS.
-//   k_gemm_bf16_dma (BF16, even step counts): 256 columns x 256 right-hand
-//     sides, LDS-direct loads two steps ahead, details below.
-//   k_gemm_bf16 (E4M3, and BF16 with an odd step count): the same tile,
-//     loads through registers one step ahead, LDS double-buffered.
+//   k_gemm_bf16_half (BF16): 256 columns x 128 right-hand sides, two
+//     workgroups per CU, LDS-direct loads one step ahead, details below.
+//   k_gemm_bf16<9> (E4M3): 256 columns x 256 right-hand sides, one
+//     workgroup per CU (a wave holds a 128 x 128 block of G: 8 x 8 tiles of
+//     16 x 16 in 256 accumulator registers), loads through registers one
+//     step ahead, LDS double-buffered.
 //   k_gemm_f32 (FP32): 128 columns x 256 right-hand sides.
-// A wave of the BF16 kernels holds a 128 x 128 block of G (8 x 8 tiles of
-// 16 x 16 in 256 accumulator registers).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -32,7 +32,6 @@ namespace {
 constexpr int kBM = 128;  // FP32 kernel: columns of Phi per workgroup
 constexpr int kBN = 256;  // right-hand sides per workgroup (at most)
 constexpr int kBK = 32;   // rows per step
-constexpr int kPadH = 8;  // LDS row padding in 16-bit elements
 constexpr int kBM2 = 256; // BF16 kernel: columns of Phi per workgroup
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -99,6 +98,16 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& p, float* out, const
 // fragment read feeds 8 or 16 MFMAs.  Steps of 32 rows.  The next step's global loads
 // are in flight during the MFMAs; LDS is double-buffered, so one barrier per
 // step both publishes a buffer and retires the other.
+// LDS rows of the BF16 kernels are 64 bytes (the 32 rows of one step of one
+// column or right-hand side), unpadded; the four 16-byte pieces of row r sit
+// at piece ^ dma_swz(r % 16).  A fragment read (16 consecutive lanes: rows
+// r..r+15 of one piece) then touches every bank once: on gfx950 a 16-byte
+// LDS read serves 16 lanes per cycle over 64 banks, and this is the placement
+// a probe of the bank counter found conflict-free (80-byte padded rows cost
+// one extra cycle per read).
+__device__ __forceinline__ int dma_swz(int r) { return (r >> 1) & 3; }
+__device__ __forceinline__ int lds_slot(int r, int piece) { return r * 64 + 16 * (piece ^ dma_swz(r & 15)); }
+
 template <int FMT>
 struct Stage {
     uint4 a[FMT == 16 ? 4 : 2];  // A: 16 bytes of each of this thread's columns
@@ -107,8 +116,8 @@ struct Stage {
 
 template <int FMT>  // 16: BF16 storage, 9: E4M3 storage
 __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
-    __shared__ uint16_t la[2][kBM2][kBK + kPadH];
-    __shared__ uint16_t lb[2][2][kBN][kBK + kPadH];
+    __shared__ __attribute__((aligned(16))) uint8_t la[2][kBM2 * 64];
+    __shared__ __attribute__((aligned(16))) uint8_t lb[2][2][kBN * 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int j0 = blockIdx.x * kBM2;
     const int n0 = blockIdx.y * kBN;
@@ -152,21 +161,21 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
         if constexpr (FMT == 16) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                *reinterpret_cast<uint4*>(&la[buf][tid / 4 + 64 * i][8 * akc]) = r.a[i];
+                *reinterpret_cast<uint4*>(&la[buf][lds_slot(tid / 4 + 64 * i, akc)]) = r.a[i];
         } else {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const uint2 a0 = e4m3x4_to_bf16(r.a[i].x), a1 = e4m3x4_to_bf16(r.a[i].y);
                 const uint2 a2 = e4m3x4_to_bf16(r.a[i].z), a3 = e4m3x4_to_bf16(r.a[i].w);
-                uint4* dst = reinterpret_cast<uint4*>(&la[buf][tid / 2 + 128 * i][16 * akc]);
-                dst[0] = make_uint4(a0.x, a0.y, a1.x, a1.y);
-                dst[1] = make_uint4(a2.x, a2.y, a3.x, a3.y);
+                const int col = tid / 2 + 128 * i;  // 16 codes: BF16 pieces 2 akc and 2 akc + 1
+                *reinterpret_cast<uint4*>(&la[buf][lds_slot(col, 2 * akc)]) = make_uint4(a0.x, a0.y, a1.x, a1.y);
+                *reinterpret_cast<uint4*>(&la[buf][lds_slot(col, 2 * akc + 1)]) = make_uint4(a2.x, a2.y, a3.x, a3.y);
             }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            *reinterpret_cast<uint4*>(&lb[buf][0][tid / 4 + 64 * i][8 * bkc]) = r.bh[i];
-            *reinterpret_cast<uint4*>(&lb[buf][1][tid / 4 + 64 * i][8 * bkc]) = r.bl[i];
+            *reinterpret_cast<uint4*>(&lb[buf][0][lds_slot(tid / 4 + 64 * i, bkc)]) = r.bh[i];
+            *reinterpret_cast<uint4*>(&lb[buf][1][lds_slot(tid / 4 + 64 * i, bkc)]) = r.bl[i];
         }
     };
 
@@ -176,15 +185,17 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
+    // this lane's fragment piece: row lane % 16 of a 16-row block, piece
+    // lane / 16 (8 rows of the step)
+    const int foff = lds_slot(lane & 15, lane >> 4);
     auto compute = [&](int buf) {
-        const int kq = (lane >> 4) * 8;  // this lane's 8 rows of the step
         bf16x8_t af[8];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
-            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[buf][wm + 16 * mt + (lane & 15)][kq]));
+            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[buf][(wm + 16 * mt) * 64 + foff]));
         // B fragments one tile column ahead of the MFMAs that use them
         auto bfrag = [&](int term, int nt) {
-            return as_bf16x8(*reinterpret_cast<const uint4*>(&lb[buf][term][wn + 16 * nt + (lane & 15)][kq]));
+            return as_bf16x8(*reinterpret_cast<const uint4*>(&lb[buf][term][(wn + 16 * nt) * 64 + foff]));
         };
         bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
 #pragma unroll
@@ -230,29 +241,6 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
     store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
 }
 
-// BF16 storage, loads straight into LDS (even step counts).  The same
-// 256 x 256 workgroup tile and MFMA order as k_gemm_bf16, but the global
-// loads are gfx950's LDS-direct loads (global_load_lds_dwordx4: 16 bytes per
-// lane into LDS at M0 + 16 lane): no registers stage the data, no LDS writes
-// sit between the MFMAs, and the loads of two steps ahead are in flight
-// while a step computes.  The A tile is loaded two steps at a time, so both
-// 64-byte halves of each 128-byte line of a column are requested together
-// and HBM serves whole lines.  LDS: A in two buffers of two steps (64 KiB),
-// R' (hi and lo) in a ring of three steps (96 KiB); 160 KiB in all.
-//
-// LDS rows are 64 bytes (the 32 rows of one step of one column or right-hand
-// side), unpadded; the four 16-byte pieces of row r sit at piece ^ ((r >> 1)
-// & 3).  A fragment read (16 consecutive lanes: rows r..r+15 of one piece)
-// then touches every bank once: on gfx950 a 16-byte LDS read serves 16 lanes
-// per cycle over 64 banks, and this is the placement a probe of the bank
-// counter found conflict-free (the 80-byte padded rows of k_gemm_bf16 cost
-// one extra cycle per read).
-constexpr int kStages = 3;
-constexpr int kAPair = 2 * 16384;
-constexpr int kBStage = 32768;
-
-__device__ __forceinline__ int dma_swz(int r) { return (r >> 1) & 3; }
-
 // 16 bytes per lane from g into LDS at lds + 16 lane (lds wave-uniform).  The
 // compiler does not see these loads: every wait on them is explicit (vmcnt),
 // and the kernel waits for all of them before it ends.
@@ -260,76 +248,79 @@ __device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds) {
     asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory");
 }
 
-// Step t's loads: R' of step t + 2 every step, A of steps t + 2 and t + 3 at
-// even t.
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_dma(GemmArgs p) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kAPair + kStages * kBStage];
+// BF16 storage, two workgroups per CU: 256 columns x 128 right-hand sides
+// per workgroup (each wave 128 x 64: 8 x 4 tiles of 16 x 16, 128
+// accumulators), the operands loaded straight into LDS with gfx950's
+// LDS-direct loads (global_load_lds_dwordx4: 16 bytes per lane at M0 +
+// 16 lane), one step ahead in a two-stage ring of 32 KiB stages (A 16 KiB,
+// R' hi and lo 8 KiB each), rows placed by lds_slot.  No registers stage the
+// data and no LDS writes sit between the MFMAs; with two workgroups on a CU
+// one workgroup's MFMAs run while the other waits at its barrier or for its
+// loads.  (One workgroup of 256 x 256 per CU with 256 accumulators a wave
+// and loads two steps ahead ran 8% slower; the register-staged kernel 22%.)
+constexpr int kHN = 128;
+constexpr int kHStage = 16384 + 2 * 8192;
+
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16_half(GemmArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[2 * kHStage];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int j0 = blockIdx.x * kBM2;
-    const int n0 = blockIdx.y * kBN;
+    const int n0 = blockIdx.y * kHN;
     const int kper = p.rows / p.ksplit;
     const int kbeg = blockIdx.z * kper;
-    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 128;
+    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 64;
     const int rsub = lane >> 2;
     const int piece = (lane & 3) ^ dma_swz(rsub);
     const uint8_t* ga[4];
-    const uint8_t* gh[4];
+    const uint8_t* gh[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int col = min(j0 + 16 * (4 * wv + i) + rsub, p.n - 1);
         ga[i] = p.a + static_cast<int64_t>(col) * p.col_bytes + 16 * piece;
-        const int rhs = min(n0 + 16 * (4 * wv + i) + rsub, p.nrhs - 1);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int rhs = min(n0 + 16 * (2 * wv + i) + rsub, p.nrhs - 1);
         gh[i] = static_cast<const uint8_t*>(p.b) + 2 * (static_cast<int64_t>(rhs) * p.ldb) + 16 * piece;
     }
     const int64_t lo_bytes = 2 * p.lo_off;
     const uint32_t lds_base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
         (__attribute__((address_space(3))) uint8_t*)(lds)));
-    const uint32_t wdst = __builtin_amdgcn_readfirstlane(lds_base + wv * 4096);
-    const int ksteps = kper / kBK;  // even, >= 8
-    // A of steps t, t + 1 (t even) into buffer (t / 2) % 2; past the end the
-    // last pair again (into a buffer no step still reads)
-    auto issue_a = [&](int t) {
-        const int tt = min(t, ksteps - 2);
-        const uint32_t d = wdst + ((t >> 1) & 1) * kAPair;
+    const uint32_t wa = __builtin_amdgcn_readfirstlane(lds_base + wv * 4096);
+    const uint32_t wb = __builtin_amdgcn_readfirstlane(lds_base + wv * 2048);
+    const int ksteps = kper / kBK;
+    auto issue = [&](int t) {
+        const int64_t kb = 2 * static_cast<int64_t>(kbeg + t * kBK);
+        const uint32_t st = (t & 1) * kHStage;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t kb = 2 * static_cast<int64_t>(kbeg + (tt + h) * kBK);
+        for (int i = 0; i < 4; ++i) lds_dma16(ga[i] + kb, wa + st + i * 1024);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) lds_dma16(ga[i] + kb, d + h * 16384 + i * 1024);
-        }
-    };
-    auto issue_b = [&](int t) {
-        const int tt = min(t, ksteps - 1);
-        const int64_t kb = 2 * static_cast<int64_t>(kbeg + tt * kBK);
-        const uint32_t d = wdst + 2 * kAPair + (t % kStages) * kBStage;
+        for (int i = 0; i < 2; ++i) lds_dma16(gh[i] + kb, wb + st + 16384 + i * 1024);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lds_dma16(gh[i] + kb, d + i * 1024);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) lds_dma16(gh[i] + lo_bytes + kb, d + 16384 + i * 1024);
+        for (int i = 0; i < 2; ++i) lds_dma16(gh[i] + lo_bytes + kb, wb + st + 16384 + 8192 + i * 1024);
     };
 
-    f32x4_t acc[8][8];
+    f32x4_t acc[8][4];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-    const int foff = (lane & 15) * 64 + 16 * ((lane >> 4) ^ dma_swz(lane & 15));
+    const int foff = lds_slot(lane & 15, lane >> 4);
     auto compute = [&](int t) {
-        const uint8_t* sa = lds + ((t >> 1) & 1) * kAPair + (t & 1) * 16384 + foff;
-        const uint8_t* sb = lds + 2 * kAPair + (t % kStages) * kBStage + foff;
+        const uint8_t* sa = lds + (t & 1) * kHStage + foff;
         bf16x8_t af[8];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
             af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(sa + (wm + 16 * mt) * 64));
         auto bfrag = [&](int term, int nt) {
-            return as_bf16x8(*reinterpret_cast<const uint4*>(sb + 16384 * term + (wn + 16 * nt) * 64));
+            return as_bf16x8(*reinterpret_cast<const uint4*>(sa + 16384 + 8192 * term + (wn + 16 * nt) * 64));
         };
         bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
+        for (int nt = 0; nt < 4; ++nt) {
             const bf16x8_t bh8 = bhn, bl8 = bln;
-            if (nt + 1 < 8) {
+            if (nt + 1 < 4) {
                 bhn = bfrag(0, nt + 1);
                 bln = bfrag(1, nt + 1);
             }
@@ -342,32 +333,23 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_dma(GemmArgs p) {
         }
         __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            if (nt + 1 < 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        for (int nt = 0; nt < 4; ++nt) {
+            if (nt + 1 < 4) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
         }
     };
 
-    // prologue: A of steps 0-1, R' of steps 0 and 1
-    issue_a(0);
-    issue_b(0);
-    issue_b(1);
+    issue(0);
     for (int t = 0; t < ksteps; ++t) {
-        // even t: newer than R'(t) only R'(t + 1) (8 loads); odd t: A(t + 1),
-        // A(t + 2) and R'(t + 1) (16)
-        if (t & 1) {
-            asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
-        } else {
-            asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
-            issue_a(t + 2);
-        }
-        issue_b(t + 2);
+        // step t's loads (the only ones outstanding) have landed in every
+        // wave, and stage (t + 1) % 2 (step t - 1) is no longer read
+        asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        if (t + 1 < ksteps) issue(t + 1);
         compute(t);
     }
-    // no load may still be writing LDS when the workgroup ends
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
-    store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
+    store_tiles<8, 4>(p, out, acc, j0 + wm, n0 + wn, lane);
 }
 
 // FP32 storage: FP32 MFMA (16 x 16 x 4), r in FP32.
@@ -481,7 +463,8 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
     dim3 grid;
     if (bf) {
         a.ksplit = sg.ksplit;
-        grid = dim3((sg.n + kBM2 - 1) / kBM2, (count + kBN - 1) / kBN, a.ksplit);
+        const int nb = sg.bits == kFmtBF16 ? kHN : kBN;  // right-hand sides per workgroup
+        grid = dim3((sg.n + kBM2 - 1) / kBM2, (count + nb - 1) / nb, a.ksplit);
     } else {
         grid = dim3((sg.n + kBM - 1) / kBM, (count + kBN - 1) / kBN);
     }
@@ -489,18 +472,16 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
         if (ev0) hipExtLaunchKernelGGL(kern, grid, dim3(256), 0, st, ev0, ev1, 0, a);
         else hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
     };
-    if (sg.bits == kFmtBF16) {
-        if ((a.rows / a.ksplit / kBK) % 2 == 0) go(k_gemm_bf16_dma);
-        else go(k_gemm_bf16<16>);
-    }
+    if (sg.bits == kFmtBF16) go(k_gemm_bf16_half);
     else if (sg.bits == kFmtE4M3) go(k_gemm_bf16<9>);
     else go(k_gemm_f32);
     hipLaunchKernelGGL(k_hist_g, dim3(std::max(1, std::min(64, (sg.n + 2047) / 2048)), count), dim3(256), 0, st,
                        P, a.ksplit, static_cast<const float*>(sg.gp), static_cast<int64_t>(count) * sg.ldg, sg.ldg);
 }
 
-// Row splits of the BF16 GEMM: enough workgroups for the device (about one
-// per CU) while each split keeps at least 8 steps of 32 rows.
+// Row splits of the BF16 / E4M3 GEMMs: enough workgroups for the device (two
+// per CU for BF16, one for E4M3) while each split keeps at least 8 steps of
+// 32 rows.
 bool shared_ksplit_ok(int bits, int rows_pad, int ks) {
     if (bits != kFmtBF16 && bits != kFmtE4M3) return ks == 1;
     return (ks == 1 || ks == 2 || ks == 4) && rows_pad % (ks * kBK) == 0 && rows_pad / ks >= 8 * kBK;
@@ -508,9 +489,11 @@ bool shared_ksplit_ok(int bits, int rows_pad, int ks) {
 
 int shared_ksplit(int bits, int n, int count, int rows_pad) {
     if (bits != kFmtBF16 && bits != kFmtE4M3) return 1;
-    const int tiles = ((n + kBM2 - 1) / kBM2) * ((count + kBN - 1) / kBN);
+    const int nb = bits == kFmtBF16 ? kHN : kBN;
+    const int want = bits == kFmtBF16 ? 512 : 256;
+    const int tiles = ((n + kBM2 - 1) / kBM2) * ((count + nb - 1) / nb);
     int ks = 1;
-    while (ks < 4 && tiles * ks < 256 && shared_ksplit_ok(bits, rows_pad, 2 * ks)) ks *= 2;
+    while (ks < 4 && tiles * ks < want && shared_ksplit_ok(bits, rows_pad, 2 * ks)) ks *= 2;
     return ks;
 }
 

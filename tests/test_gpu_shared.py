@@ -96,9 +96,8 @@ def test_storage_zero_matrix():
 
 # ---------------------------------------------------------------- gradient
 @pytest.mark.parametrize("fmt", list(FMTS))
-# (1100, 2000): BF16 rows padded to 1152, four row splits of 9 steps each:
-# the odd step count takes the register-staged kernel instead of the
-# LDS-direct one
+# (1100, 2000): BF16 rows padded to 1152, four row splits of 9 steps each
+# (an odd step count through the GEMM's two-stage ring)
 @pytest.mark.parametrize("m,n,s,cplx", [(300, 1200, 12, False), (1000, 3000, 40, False),
                                         (1100, 2000, 30, False), (140, 300, 9, True)])
 def test_gradient_teacher_forced(fmt, m, n, s, cplx):
