@@ -11,14 +11,11 @@
 //     bits), FP32 accumulation.  FP32 storage: FP32 MFMA on the FP32 r.
 //
 // Tiling: every right-hand side of a workgroup's tile shares its reads of A
-// (so each element of A is read once per 256 right-hand sides), K in steps
+// (each element of A is read once per tile of right-hand sides), K in steps
 // of 32 rows staged through LDS.
-//   k_gemm_bf16_half (BF16): 256 columns x 128 right-hand sides, two
-//     workgroups per CU, LDS-direct loads one step ahead, details below.
-//   k_gemm_bf16<9> (E4M3): 256 columns x 256 right-hand sides, one
-//     workgroup per CU (a wave holds a 128 x 128 block of G: 8 x 8 tiles of
-//     16 x 16 in 256 accumulator registers), loads through registers one
-//     step ahead, LDS double-buffered.
+//   k_gemm_bf16_half (BF16) and k_gemm_e4m3_half (E4M3): 256 columns x 128
+//     right-hand sides, two workgroups per CU, LDS-direct loads, details
+//     below.
 //   k_gemm_f32 (FP32): 128 columns x 256 right-hand sides.
 #include <hip/hip_ext.h>
 
@@ -30,9 +27,9 @@ namespace qiht {
 namespace {
 
 constexpr int kBM = 128;  // FP32 kernel: columns of Phi per workgroup
-constexpr int kBN = 256;  // right-hand sides per workgroup (at most)
+constexpr int kBN = 256;  // FP32 kernel: right-hand sides per workgroup
 constexpr int kBK = 32;   // rows per step
-constexpr int kBM2 = 256; // BF16 kernel: columns of Phi per workgroup
+constexpr int kBM2 = 256; // BF16 / E4M3 kernels: columns of Phi per workgroup
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -92,13 +89,7 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& p, float* out, const
     }
 }
 
-// BF16 and E4M3 storage.  A workgroup of 4 waves computes 256 columns of Phi
-// x 256 right-hand sides over its row split, each wave a 128 x 128 block (8 x 8
-// tiles of 16 x 16, two MFMAs per tile and step: hi and lo), so every LDS
-// fragment read feeds 8 or 16 MFMAs.  Steps of 32 rows.  The next step's global loads
-// are in flight during the MFMAs; LDS is double-buffered, so one barrier per
-// step both publishes a buffer and retires the other.
-// LDS rows of the BF16 kernels are 64 bytes (the 32 rows of one step of one
+// LDS rows of the BF16 operands are 64 bytes (the 32 rows of one step of one
 // column or right-hand side), unpadded; the four 16-byte pieces of row r sit
 // at piece ^ dma_swz(r % 16).  A fragment read (16 consecutive lanes: rows
 // r..r+15 of one piece) then touches every bank once: on gfx950 a 16-byte
@@ -107,139 +98,6 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& p, float* out, const
 // one extra cycle per read).
 __device__ __forceinline__ int dma_swz(int r) { return (r >> 1) & 3; }
 __device__ __forceinline__ int lds_slot(int r, int piece) { return r * 64 + 16 * (piece ^ dma_swz(r & 15)); }
-
-template <int FMT>
-struct Stage {
-    uint4 a[FMT == 16 ? 4 : 2];  // A: 16 bytes of each of this thread's columns
-    uint4 bh[4], bl[4];          // R': 16 bytes of each of its 4 right-hand sides, both terms
-};
-
-template <int FMT>  // 16: BF16 storage, 9: E4M3 storage
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16(GemmArgs p) {
-    __shared__ __attribute__((aligned(16))) uint8_t la[2][kBM2 * 64];
-    __shared__ __attribute__((aligned(16))) uint8_t lb[2][2][kBN * 64];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int j0 = blockIdx.x * kBM2;
-    const int n0 = blockIdx.y * kBN;
-    const int kper = p.rows / p.ksplit;
-    const int kbeg = blockIdx.z * kper;
-    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 128;
-
-    // Global -> LDS mapping: consecutive lanes share a column (so a wave's
-    // load touches a few long contiguous pieces, not 64 scattered ones).
-    // BF16 A and both R' terms: 4 lanes x 16 bytes = the 32 rows of one
-    // column, lanes tid / 4 + 64 i, i < 4.  E4M3 A: 2 lanes x 16 bytes, columns
-    // tid / 2 + 128 i, i < 2.
-    constexpr int AL = FMT == 16 ? 4 : 2;       // lanes per column of A
-    constexpr int AI = 256 * AL / 256;          // columns of A per thread (= AL)
-    const int akc = tid % AL;                   // 16-byte piece of the column
-    const uint8_t* ap[AI];
-#pragma unroll
-    for (int i = 0; i < AI; ++i) {
-        const int col = min(j0 + tid / AL + (256 / AL) * i, p.n - 1);
-        ap[i] = p.a + static_cast<int64_t>(col) * p.col_bytes + 16 * akc;
-    }
-    const int bkc = tid % 4;
-    const uint16_t* bp[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int rhs = min(n0 + tid / 4 + 64 * i, p.nrhs - 1);
-        bp[i] = static_cast<const uint16_t*>(p.b) + static_cast<int64_t>(rhs) * p.ldb + 8 * bkc;
-    }
-
-    // k0 in rows; a 16-bit element is 2 bytes, an E4M3 one 1
-    auto load = [&](Stage<FMT>& r, int k0) {
-#pragma unroll
-        for (int i = 0; i < AI; ++i) r.a[i] = ldg_u4(ap[i] + (FMT == 16 ? 2 : 1) * k0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            r.bh[i] = ldg_u4(bp[i] + k0);
-            r.bl[i] = ldg_u4(bp[i] + p.lo_off + k0);
-        }
-    };
-    auto stash = [&](const Stage<FMT>& r, int buf) {
-        if constexpr (FMT == 16) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                *reinterpret_cast<uint4*>(&la[buf][lds_slot(tid / 4 + 64 * i, akc)]) = r.a[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const uint2 a0 = e4m3x4_to_bf16(r.a[i].x), a1 = e4m3x4_to_bf16(r.a[i].y);
-                const uint2 a2 = e4m3x4_to_bf16(r.a[i].z), a3 = e4m3x4_to_bf16(r.a[i].w);
-                const int col = tid / 2 + 128 * i;  // 16 codes: BF16 pieces 2 akc and 2 akc + 1
-                *reinterpret_cast<uint4*>(&la[buf][lds_slot(col, 2 * akc)]) = make_uint4(a0.x, a0.y, a1.x, a1.y);
-                *reinterpret_cast<uint4*>(&la[buf][lds_slot(col, 2 * akc + 1)]) = make_uint4(a2.x, a2.y, a3.x, a3.y);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            *reinterpret_cast<uint4*>(&lb[buf][0][lds_slot(tid / 4 + 64 * i, bkc)]) = r.bh[i];
-            *reinterpret_cast<uint4*>(&lb[buf][1][lds_slot(tid / 4 + 64 * i, bkc)]) = r.bl[i];
-        }
-    };
-
-    f32x4_t acc[8][8];
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    // this lane's fragment piece: row lane % 16 of a 16-row block, piece
-    // lane / 16 (8 rows of the step)
-    const int foff = lds_slot(lane & 15, lane >> 4);
-    auto compute = [&](int buf) {
-        bf16x8_t af[8];
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
-            af[mt] = as_bf16x8(*reinterpret_cast<const uint4*>(&la[buf][(wm + 16 * mt) * 64 + foff]));
-        // B fragments one tile column ahead of the MFMAs that use them
-        auto bfrag = [&](int term, int nt) {
-            return as_bf16x8(*reinterpret_cast<const uint4*>(&lb[buf][term][(wn + 16 * nt) * 64 + foff]));
-        };
-        bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            const bf16x8_t bh8 = bhn, bl8 = bln;
-            if (nt + 1 < 8) {
-                bhn = bfrag(0, nt + 1);
-                bln = bfrag(1, nt + 1);
-            }
-            // hi terms of the 8 tiles, then the lo terms: consecutive MFMAs
-            // never wait on each other's accumulator
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
-#pragma unroll
-            for (int mt = 0; mt < 8; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
-        }
-        // instruction order of the step: the A fragments and the first B pair,
-        // then per tile column the next B pair ahead of its 16 MFMAs (so an
-        // LDS read's latency hides behind MFMAs already issued)
-        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
-#pragma unroll
-        for (int nt = 0; nt < 8; ++nt) {
-            if (nt + 1 < 8) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
-        }
-    };
-
-    // step t's data: registers (loaded one step ahead), then LDS buffer t % 2
-    const int ksteps = kper / kBK;  // >= 8, see shared_ksplit
-    Stage<FMT> r;
-    load(r, kbeg);
-    for (int ks = 0; ks < ksteps; ++ks) {
-        const int buf = ks & 1;
-        stash(r, buf);
-        if (ks + 1 < ksteps) load(r, kbeg + (ks + 1) * kBK);
-        // the stash is visible, and buffer buf ^ 1 (step ks - 1) is no longer read
-        __syncthreads();
-        compute(buf);
-    }
-    float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
-    store_tiles<8, 8>(p, out, acc, j0 + wm, n0 + wn, lane);
-}
 
 // 16 bytes per lane from g into LDS at lds + 16 lane (lds wave-uniform).  The
 // compiler does not see these loads: every wait on them is explicit (vmcnt),
@@ -257,7 +115,8 @@ __device__ __forceinline__ void lds_dma16(const void* g, uint32_t lds) {
 // data and no LDS writes sit between the MFMAs; with two workgroups on a CU
 // one workgroup's MFMAs run while the other waits at its barrier or for its
 // loads.  (One workgroup of 256 x 256 per CU with 256 accumulators a wave
-// and loads two steps ahead ran 8% slower; the register-staged kernel 22%.)
+// and loads two steps ahead ran 8% slower; loads staged through registers
+// into padded LDS 22%.)
 constexpr int kHN = 128;
 constexpr int kHStage = 16384 + 2 * 8192;
 
@@ -345,6 +204,112 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16_half(GemmArgs p) {
         // wave, and stage (t + 1) % 2 (step t - 1) is no longer read
         asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
         if (t + 1 < ksteps) issue(t + 1);
+        compute(t);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    float* out = p.ksplit > 1 ? p.gp + static_cast<int64_t>(blockIdx.z) * p.nrhs * p.ldg : p.g;
+    store_tiles<8, 4>(p, out, acc, j0 + wm, n0 + wn, lane);
+}
+
+// E4M3 storage, two workgroups per CU: the tile and MFMA order of
+// k_gemm_bf16_half, the codes (one byte a row) landing in LDS as stored and
+// widened to BF16 as a fragment is read (8 codes, one 8-byte LDS read, two
+// hardware FP8 conversions per 4 codes).  Stages of 24 KiB (A 8 KiB: rows of
+// 32 bytes, the two 16-byte halves of row r at half ^ ((r >> 3) & 1); R' hi
+// and lo 8 KiB each), three of them (72 KiB): loads two steps ahead.
+constexpr int kE8Stage = 8192 + 2 * 8192;
+
+__device__ __forceinline__ int e8_swz(int r) { return (r >> 3) & 1; }
+
+__global__ __launch_bounds__(256, 2) void k_gemm_e4m3_half(GemmArgs p) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[3 * kE8Stage];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int j0 = blockIdx.x * kBM2;
+    const int n0 = blockIdx.y * kHN;
+    const int kper = p.rows / p.ksplit;
+    const int kbeg = blockIdx.z * kper;
+    const int wm = (wv & 1) * 128, wn = (wv >> 1) * 64;
+    // A: wave w loads columns 64 w + 32 i + lane / 2 (i < 2), half lane % 2 of
+    // the column's LDS row; R' as in k_gemm_bf16_half
+    const uint8_t* ga[2];
+    const uint8_t* gh[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int cl = 64 * wv + 32 * i + (lane >> 1);
+        const int col = min(j0 + cl, p.n - 1);
+        ga[i] = p.a + static_cast<int64_t>(col) * p.col_bytes + 16 * ((lane & 1) ^ e8_swz(cl));
+    }
+    const int rsub = lane >> 2;
+    const int piece = (lane & 3) ^ dma_swz(rsub);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int rhs = min(n0 + 16 * (2 * wv + i) + rsub, p.nrhs - 1);
+        gh[i] = static_cast<const uint8_t*>(p.b) + 2 * (static_cast<int64_t>(rhs) * p.ldb) + 16 * piece;
+    }
+    const int64_t lo_bytes = 2 * p.lo_off;
+    const uint32_t lds_base = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+        (__attribute__((address_space(3))) uint8_t*)(lds)));
+    const uint32_t wd = __builtin_amdgcn_readfirstlane(lds_base + wv * 2048);
+    const int ksteps = kper / kBK;
+    auto issue = [&](int t) {
+        const int64_t k0 = kbeg + static_cast<int64_t>(t) * kBK;
+        const uint32_t st = (t % 3) * kE8Stage;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) lds_dma16(ga[i] + k0, wd + st + i * 1024);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) lds_dma16(gh[i] + 2 * k0, wd + st + 8192 + i * 1024);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) lds_dma16(gh[i] + lo_bytes + 2 * k0, wd + st + 16384 + i * 1024);
+    };
+
+    f32x4_t acc[8][4];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    // A fragment: row lane % 16 of a 16-row block, codes 8 g .. 8 g + 7 (g =
+    // lane / 16): half g / 2 of the row, bytes 8 (g % 2) ..
+    const int r16 = lane & 15, g = lane >> 4;
+    const int aoff = r16 * 32 + 16 * ((g >> 1) ^ e8_swz(r16)) + 8 * (g & 1);
+    const int foff = lds_slot(lane & 15, lane >> 4);
+    auto compute = [&](int t) {
+        const uint8_t* sa = lds + (t % 3) * kE8Stage;
+        bf16x8_t af[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            const uint2 w = *reinterpret_cast<const uint2*>(sa + (wm + 16 * mt) * 32 + aoff);
+            const uint2 c0 = e4m3x4_to_bf16(w.x), c1 = e4m3x4_to_bf16(w.y);
+            af[mt] = as_bf16x8(make_uint4(c0.x, c0.y, c1.x, c1.y));
+        }
+        auto bfrag = [&](int term, int nt) {
+            return as_bf16x8(*reinterpret_cast<const uint4*>(sa + 8192 + 8192 * term + (wn + 16 * nt) * 64 + foff));
+        };
+        bf16x8_t bhn = bfrag(0, 0), bln = bfrag(1, 0);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x8_t bh8 = bhn, bl8 = bln;
+            if (nt + 1 < 4) {
+                bhn = bfrag(0, nt + 1);
+                bln = bfrag(1, nt + 1);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bh8, acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bl8, acc[mt][nt], 0, 0, 0);
+        }
+    };
+
+    issue(0);
+    if (ksteps > 1) issue(1);
+    for (int t = 0; t < ksteps; ++t) {
+        // step t's loads have landed in every wave (step t + 1's 6 may still
+        // be in flight), and stage (t + 2) % 3 (step t - 1) is no longer read
+        if (t + 1 < ksteps) asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+        else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+        if (t + 2 < ksteps) issue(t + 2);
         compute(t);
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -463,7 +428,7 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
     dim3 grid;
     if (bf) {
         a.ksplit = sg.ksplit;
-        const int nb = sg.bits == kFmtBF16 ? kHN : kBN;  // right-hand sides per workgroup
+        const int nb = kHN;  // right-hand sides per workgroup
         grid = dim3((sg.n + kBM2 - 1) / kBM2, (count + nb - 1) / nb, a.ksplit);
     } else {
         grid = dim3((sg.n + kBM - 1) / kBM, (count + kBN - 1) / kBN);
@@ -473,15 +438,14 @@ void launch_shared_pass(const SharedGemm& sg, const ProbDev* P, int count, hipSt
         else hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, a);
     };
     if (sg.bits == kFmtBF16) go(k_gemm_bf16_half);
-    else if (sg.bits == kFmtE4M3) go(k_gemm_bf16<9>);
+    else if (sg.bits == kFmtE4M3) go(k_gemm_e4m3_half);
     else go(k_gemm_f32);
     hipLaunchKernelGGL(k_hist_g, dim3(std::max(1, std::min(64, (sg.n + 2047) / 2048)), count), dim3(256), 0, st,
                        P, a.ksplit, static_cast<const float*>(sg.gp), static_cast<int64_t>(count) * sg.ldg, sg.ldg);
 }
 
 // Row splits of the BF16 / E4M3 GEMMs: enough workgroups for the device (two
-// per CU for BF16, one for E4M3) while each split keeps at least 8 steps of
-// 32 rows.
+// per CU) while each split keeps at least 8 steps of 32 rows.
 bool shared_ksplit_ok(int bits, int rows_pad, int ks) {
     if (bits != kFmtBF16 && bits != kFmtE4M3) return ks == 1;
     return (ks == 1 || ks == 2 || ks == 4) && rows_pad % (ks * kBK) == 0 && rows_pad / ks >= 8 * kBK;
@@ -489,8 +453,8 @@ bool shared_ksplit_ok(int bits, int rows_pad, int ks) {
 
 int shared_ksplit(int bits, int n, int count, int rows_pad) {
     if (bits != kFmtBF16 && bits != kFmtE4M3) return 1;
-    const int nb = bits == kFmtBF16 ? kHN : kBN;
-    const int want = bits == kFmtBF16 ? 512 : 256;
+    const int nb = kHN;
+    const int want = 512;
     const int tiles = ((n + kBM2 - 1) / kBM2) * ((count + nb - 1) / nb);
     int ks = 1;
     while (ks < 4 && tiles * ks < want && shared_ksplit_ok(bits, rows_pad, 2 * ks)) ks *= 2;
