@@ -68,6 +68,31 @@ def test_batched_solve_graph_equals_eager(monkeypatch):
         q.free()
 
 
+def test_pass_span_queue_in_graphs_equals_static_split(monkeypatch):
+    """The full pass's span queue (8 spans per workgroup, forced) under graph
+    replay: its counters are reset by each launch's last workgroup, so every
+    replayed pass takes all its spans; the iterates equal the static split's
+    (one span per workgroup, launched directly) bit for bit."""
+    ms = [700, 1200, 300, 900]
+    probs = [workloads.gaussian(m, 4 * m, m // 16, 1e-3, [6, i], np.float32, qseed=i)
+             for i, m in enumerate(ms)]
+    gpu = [(*_gpu(p, 4), p.s) for p in probs]
+    monkeypatch.setenv("QIHT_GRAPH", "0")
+    monkeypatch.setenv("QIHT_TUNE_FORCE", "long/r1")
+    ref = qiht.niht_solve_batched(gpu, max_iters=60, tol=-1.0)
+    monkeypatch.delenv("QIHT_GRAPH")
+    monkeypatch.setenv("QIHT_TUNE_FORCE", "long/r8")
+    for rep in range(4):
+        got = qiht.niht_solve_batched(gpu, max_iters=60, tol=-1.0)
+        torch.cuda.synchronize()
+        for i in range(len(ms)):
+            _same(ref[i], got[i], f"queue problem {i} replay {rep}")
+        torch.zeros(1 << 20, device=DEV).add_(1.0)  # eager work between the solves
+        torch.cuda.synchronize()
+    for q, _, _ in gpu:
+        q.free()
+
+
 def test_shared_matrix_batch_graph_equals_eager(monkeypatch):
     rng = np.random.default_rng(7)
     m, n, s, nrhs = 600, 2400, 20, 8
