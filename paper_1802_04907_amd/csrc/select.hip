@@ -461,16 +461,18 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     // and an already finished problem returns at the first barrier, before
     // writing any global memory)
     const int done_now = skipped ? ldg_i32(&pd.st->done) : 0;
+    // Every load of this first round trip is issued before any is used, with
+    // its index clamped into its array (a clamped load's value is not used):
+    // a load used inside a loop or a branch is waited for before the next
+    // one goes out.
     double gg = 0.0, uv = 0.0, uu = 0.0;
+    float gs0 = 0.0f;
+    double pm0 = 0.0, pm1 = 0.0;
     if (from_partials) {
-        for (int i = tid; i < nsup; i += kSelectThreads) {
-            const double v = static_cast<double>(ldg_f32(pd.gs + i));
-            gg += v * v;
-        }
-        for (int b = tid; b < nw; b += kSelectThreads) {
-            uv += ldg_f64(pd.part_mu + 2 * b + 0);
-            uu += ldg_f64(pd.part_mu + 2 * b + 1);
-        }
+        gs0 = ldg_f32(pd.gs + min(tid, max(nsup - 1, 0)));
+        const int b0 = min(tid, nw - 1);
+        pm0 = ldg_f64(pd.part_mu + 2 * b0 + 0);
+        pm1 = ldg_f64(pd.part_mu + 2 * b0 + 1);
     }
     // Few index blocks: G = 2 or 4 threads share one, thread gq of the group
     // taking its entries gq, gq + G, ... (so PRE G of them arrive with the
@@ -484,15 +486,35 @@ __device__ bool propose(const ProbDev& pd, int slot, int k, double mu_in, bool f
     const int lo0 = w0 * per, len0 = w0 < w1 ? min(n, lo0 + per) - lo0 : 0;
 #pragma unroll
     for (int i = 0; i < PRE; ++i) {
-        const int e = gq + G * i;
-        pidx[i] = e < len0 ? ldg_u32(pd.cidx + lo0 + e) : 0u;
-        pgx[i] = e < len0 ? ldg_f2(pd.cgx + lo0 + e) : make_float2(0.f, 0.f);
+        const int at = min(lo0 + min(gq + G * i, max(len0 - 1, 0)), n - 1);
+        pidx[i] = ldg_u32(pd.cidx + at);
+        pgx[i] = ldg_f2(pd.cgx + at);
+    }
+    const int cw0 = ldg_i32(pd.ccnt + min(w0, nw - 1));
+    if (from_partials) {
+        if (tid < nsup) gg += static_cast<double>(gs0) * static_cast<double>(gs0);
+        for (int i = tid + kSelectThreads; i < nsup; i += kSelectThreads) {
+            const double v = static_cast<double>(ldg_f32(pd.gs + i));
+            gg += v * v;
+        }
+        if (tid < nw) {
+            uv += pm0;
+            uu += pm1;
+        }
+        for (int b = tid + kSelectThreads; b < nw; b += kSelectThreads) {
+            uv += ldg_f64(pd.part_mu + 2 * b + 0);
+            uu += ldg_f64(pd.part_mu + 2 * b + 1);
+        }
     }
     uint32_t mycnt = 0;  // (counted by the group's first thread)
     int c0 = 0, bad_cnt = 0;
-    for (int w = w0; w < w1; ++w) {
+    if (w0 < w1) {
+        c0 = cw0;
+        if (cw0 < 0) bad_cnt = 1;
+        else if (gq == 0) mycnt += static_cast<uint32_t>(cw0);
+    }
+    for (int w = w0 + 1; w < w1; ++w) {
         const int c = ldg_i32(pd.ccnt + w);
-        if (w == w0) c0 = c;
         if (c < 0) bad_cnt = 1;
         else if (gq == 0) mycnt += static_cast<uint32_t>(c);
     }
