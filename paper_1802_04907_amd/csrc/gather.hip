@@ -173,15 +173,20 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     // here, by every workgroup alike; one extra workgroup commits it
     __shared__ double s_dec[kSpec * (kGatherThreads / 64)];
     __shared__ int s_done;
-    const bool decide = MODE == G_R && !zero_x && a.decide_in_gather && pd.st->phase == 1;
+    // the state flags and (G_R) the step-size test's inputs in one round trip,
+    // before it is known whether a test is due; the stop flag is checked once
+    // the column loads are issued (every address stays valid after the solve
+    // has stopped)
+    const int phase_now = MODE == G_R ? ldg_i32(&pd.st->phase) : 0;
+    int done_now = ldg_i32(&pd.st->done);
+    PickIn pin;
+    if constexpr (MODE == G_R) pin = pick_load<kGatherThreads>(pd);
+    const bool decide = MODE == G_R && !zero_x && a.decide_in_gather && phase_now == 1;
     if (MODE == G_R && wg == pd.npart) {
-        if (decide && !pd.st->done) commit_round<kGatherThreads>(pd, a, s_dec);
+        if (decide && !done_now) commit_round<kGatherThreads>(pd, a, s_dec, pin);
         return;
     }
     if (wg >= pd.npart) return;
-    // the stop flag is read alongside the first loads and checked once they
-    // are issued (every address stays valid after the solve has stopped)
-    int done_now = pd.st->done;
 
     const int32_t* cols;
     int ncols;
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
         // the picked proposal's support and values (after a failed test the
         // current ones: the next round proposes further shrinks from this x)
         bool capped;
-        const int pick = decide_pick<kGatherThreads>(pd, a, &capped, s_dec);
+        const int pick = decide_pick<kGatherThreads>(pd, a, &capped, s_dec, pin);
         done_now = s_done;
         if (done_now) return;  // uniform over the workgroup
         if (pick >= 0) {

@@ -668,25 +668,41 @@ void launch_commit(const ProbDev* P, int count, const SolveArgs& a, hipStream_t 
 // barrier; red: kSpec * NT / 64 doubles of LDS); all get the same answer.
 // The denominators are summed from the omega gather's partials, per wave and
 // then in wave order.
-template <int NT>
-__device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, double* red) {
-    constexpr int NW = NT / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // the proposals' metadata, loaded with the partials (one round trip)
+// The test's inputs: the proposals' metadata and this thread's first omega
+// partials.  Every load is unconditional (the partial's index clamped into the
+// array; a thread past the partials does not use it), so a kernel can issue
+// them with its other first loads, before it knows whether a test is due.
+struct PickIn {
     int mch[kSpec], mk[kSpec];
-    double mmu[kSpec], mdx2[kSpec];
+    double mmu[kSpec], mdx2[kSpec], om0[kSpec];
+};
+template <int NT>
+__device__ __forceinline__ PickIn pick_load(const ProbDev& pd) {
+    PickIn in;
+    const int b0 = min(static_cast<int>(threadIdx.x), pd.npart - 1);
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) {
         const CandMeta* m = pd.meta + t;
-        mch[t] = ldg_i32(&m->changed);
-        mk[t] = ldg_i32(&m->k);
-        mmu[t] = ldg_f64(&m->mu);
-        mdx2[t] = ldg_f64(&m->dx2);
+        in.mch[t] = ldg_i32(&m->changed);
+        in.mk[t] = ldg_i32(&m->k);
+        in.mmu[t] = ldg_f64(&m->mu);
+        in.mdx2[t] = ldg_f64(&m->dx2);
+        in.om0[t] = ldg_f64(pd.part_om + static_cast<size_t>(t) * pd.nwg + b0);
     }
+    return in;
+}
+
+template <int NT>
+__device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, double* red, const PickIn& in) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double den[kSpec];
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) den[t] = 0.0;
-    for (int b = tid; b < pd.npart; b += NT)
+    if (tid < pd.npart)
+#pragma unroll
+        for (int t = 0; t < kSpec; ++t) den[t] += in.om0[t];
+    for (int b = tid + NT; b < pd.npart; b += NT)
 #pragma unroll
         for (int t = 0; t < kSpec; ++t) den[t] += ldg_f64(pd.part_om + static_cast<size_t>(t) * pd.nwg + b);
 #pragma unroll
@@ -700,22 +716,26 @@ __device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, 
 #pragma unroll
     for (int t = 0; t < kSpec; ++t) {
         if (pick >= 0) continue;
-        if (!mch[t]) {
+        if (!in.mch[t]) {
             pick = t;
             continue;
         }
         double d = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) d += red[t * NW + w];
-        const double omega = d > 0.0 ? mdx2[t] / d : INFINITY;
-        if (mmu[t] <= (1.0 - a.c) * omega) {
+        const double omega = d > 0.0 ? in.mdx2[t] / d : INFINITY;
+        if (in.mmu[t] <= (1.0 - a.c) * omega) {
             pick = t;
-        } else if (mk[t] >= a.max_backtracks) {
+        } else if (in.mk[t] >= a.max_backtracks) {
             pick = t;
             *capped = true;
         }
     }
     return pick;
+}
+template <int NT>
+__device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, double* red) {
+    return decide_pick<NT>(pd, a, capped, red, pick_load<NT>(pd));
 }
 
 // The commit workgroup of a residual gather (one per problem, NT threads):
@@ -725,7 +745,11 @@ __device__ int decide_pick(const ProbDev& pd, const SolveArgs& a, bool* capped, 
 // workgroups of the gather read the picked proposal's support and values
 // (or, after a failure, the current ones), never what this one writes.
 template <int NT>
-__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red);
+__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red, const PickIn& in);
+template <int NT>
+__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red) {
+    commit_round<NT>(pd, a, red, pick_load<NT>(pd));
+}
 
 // Device-side commit of proposal `t` (called by one whole workgroup of
 // `nt` threads): x and the support take the proposal's values, the state
@@ -767,9 +791,9 @@ __device__ void commit_proposal(const ProbDev& pd, int t, const SolveArgs& a, bo
 }
 
 template <int NT>
-__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red) {
+__device__ void commit_round(const ProbDev& pd, const SolveArgs& a, double* red, const PickIn& in) {
     bool capped = false;
-    const int pick = decide_pick<NT>(pd, a, &capped, red);
+    const int pick = decide_pick<NT>(pd, a, &capped, red, in);
     if (pick >= 0) {
         commit_proposal<NT>(pd, pick, a, capped);
     } else if (threadIdx.x == 0) {
