@@ -194,11 +194,14 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather(const ProbDev* __rest
     const float* wpos = nullptr;    // per-list-position weights (G_R: x on the support)
     const float* wcol = nullptr;    // per-column weights (G_MU: g)
     if (MODE == G_OMEGA) {
-        const CandMeta& m = pd.meta[set];
         // no omega needed for this proposal, nor for any when the first
-        // keeps the support (the test takes it at once)
-        if (!m.changed || (set > 0 && !ldg_i32(&pd.meta[0].changed))) return;
-        ncols = m.dcount;
+        // keeps the support (the test takes it at once); the three flags
+        // and the count are loaded together
+        const int ch = ldg_i32(&pd.meta[set].changed);
+        const int ch0 = ldg_i32(&pd.meta[0].changed);
+        const int dcount = ldg_i32(&pd.meta[set].dcount);
+        if (!ch || !ch0) return;
+        ncols = dcount;
         cols = pd.dlist + static_cast<size_t>(set) * 2 * pd.s;
         wlist = pd.dw + static_cast<size_t>(set) * 2 * pd.s;
     } else {
@@ -467,9 +470,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_wide(const ProbDev* _
     const float* xw = pd.xs;  // G_R: x on the listed columns
     int ncols;
     if (MODE == G_OMEGA) {
-        const CandMeta& m = pd.meta[set];
-        if (!m.changed || (set > 0 && !ldg_i32(&pd.meta[0].changed))) return;  // as in k_gather
-        ncols = m.dcount;
+        const int ch = ldg_i32(&pd.meta[set].changed);  // as in k_gather
+        const int ch0 = ldg_i32(&pd.meta[0].changed);
+        const int dcount = ldg_i32(&pd.meta[set].dcount);
+        if (!ch || !ch0) return;
+        ncols = dcount;
         cols = pd.dlist + static_cast<size_t>(set) * 2 * pd.s;
     } else {
         cols = pd.sup;
