@@ -34,6 +34,24 @@ __device__ __forceinline__ uint32_t quantize_one(double v, double c, double K,
     return static_cast<uint32_t>(fi) + up;
 }
 
+// quantize_one in two parts, for a value shared by several realizations:
+// its floor position fi and threshold f 2^32 (the same operations in the same
+// order), then the coin of one realization.
+__device__ __forceinline__ void position_of(double v, double c, double K, double top,
+                                            double& fi_out, double& th_out) {
+#pragma clang fp contract(off)
+    const double t = v + c;
+    const double p = t * K;
+    double fi = floor(p);
+    fi = fmin(fmax(fi, 0.0), top);
+    const double f = p - fi;
+    fi_out = fi;
+    th_out = f * kTwo32;
+}
+__device__ __forceinline__ uint32_t round_at(double fi, double th, uint32_t u) {
+    return static_cast<uint32_t>(fi) + ((static_cast<double>(u) < th) ? 1u : 0u);
+}
+
 // Element (i, j) of the stacked real view of a row-major matrix.
 template <typename T, int NC>
 __device__ __forceinline__ double load_stacked(const T* src, int64_t m,
@@ -190,11 +208,18 @@ __global__ __launch_bounds__(256) void k_quantize(
             v[q] = static_cast<T>(load_stacked<T, NC>(src, m, ld, min(i0 + q, rows - 1), j));
         const uint64_t b0 = (static_cast<uint64_t>(j) * rows + i0) >> 2;
         const int nlive = static_cast<int>(min<int64_t>(RPC, rows - i0));
-        for (int r = 0; r < R; ++r) {
-            uint32_t w[4] = {0u, 0u, 0u, 0u};
+        // the floor position and the rounding threshold of a value are the
+        // same for both realizations: taken once, then one coin each
+        uint32_t w[2][4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
 #pragma unroll
-            for (int b = 0; b < RPC / 4; ++b) {
-                const uint64_t blk = b0 + b;
+        for (int b = 0; b < RPC / 4; ++b) {
+            double fl[4], th[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) position_of(static_cast<double>(v[4 * b + t]), c, K, top, fl[t], th[t]);
+            const uint64_t blk = b0 + b;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                if (r >= R) break;
                 const uint4 u = philox10(make_uint4(static_cast<uint32_t>(blk), static_cast<uint32_t>(blk >> 32),
                                                     0u, rb + static_cast<uint32_t>(r)),
                                          k0, k1);
@@ -202,12 +227,13 @@ __global__ __launch_bounds__(256) void k_quantize(
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const int q = 4 * b + t;
-                    const uint32_t code = q < nlive ? quantize_one(static_cast<double>(v[q]), c, K, top, uu[t]) : 0u;
-                    w[(q * BITS) >> 5] |= code << ((q * BITS) & 31);
+                    const uint32_t code = q < nlive ? round_at(fl[t], th[t], uu[t]) : 0u;
+                    w[r][(q * BITS) >> 5] |= code << ((q * BITS) & 31);
                 }
             }
-            *reinterpret_cast<uint4*>((r == 0 ? out0 : out1) + off) = make_uint4(w[0], w[1], w[2], w[3]);
         }
+        *reinterpret_cast<uint4*>(out0 + off) = make_uint4(w[0][0], w[0][1], w[0][2], w[0][3]);
+        if (R > 1) *reinterpret_cast<uint4*>(out1 + off) = make_uint4(w[1][0], w[1][1], w[1][2], w[1][3]);
     } else {
         PhiloxStream s0{k0, k1, 0u, rb};
         PhiloxStream s1{k0, k1, 0u, rb + 1u};
