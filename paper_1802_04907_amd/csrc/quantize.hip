@@ -247,9 +247,11 @@ __global__ __launch_bounds__(256) void k_quantize(
             const double v = load_stacked<T, NC>(src, m, ld, i, j);
             const uint64_t e = ebase + i;
             const int bit = q * BITS;
-            w0[bit >> 5] |= quantize_one(v, c, K, top, s0.word(e)) << (bit & 31);
+            double fl, th;
+            position_of(v, c, K, top, fl, th);
+            w0[bit >> 5] |= round_at(fl, th, s0.word(e)) << (bit & 31);
             if (R > 1)
-                w1[bit >> 5] |= quantize_one(v, c, K, top, s1.word(e)) << (bit & 31);
+                w1[bit >> 5] |= round_at(fl, th, s1.word(e)) << (bit & 31);
         }
         *reinterpret_cast<uint4*>(out0 + off) = make_uint4(w0[0], w0[1], w0[2], w0[3]);
         if (R > 1)
